@@ -1,0 +1,507 @@
+/*
+ * Plain FP64 CPU oracle of the energy-based FEM operators.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing on the product path may link or call this
+ * file; only the tests, the smoke check and the CPU-baseline leg of the
+ * benchmark do.  It shares no code with the HIP library.
+ *
+ * What it computes is the plain definition of the discrete energy of Eq. (2)
+ * of the paper and of its exact first and second derivatives, Eq. (1) and the
+ * tangent action of Eq. (3).  The paper obtains these derivatives by automatic
+ * differentiation "up to machine precision" (Sec. 1); here they are written
+ * out in closed form, element by element and quadrature point by quadrature
+ * point, with no blocking, fusion or reordering:
+ *
+ *   Psi(u) = sum_e sum_q  w_q det J_e(xi_q) psi_e(F_eq)                 Eq. (2)
+ *   J_e(xi) = sum_a X_a (x) dN_a/dxi,   grad N_a = J^-T dN_a/dxi
+ *   F_eq    = I + sum_a u_a (x) grad N_a(xi_q)                     Alg. 1 step "Compute"
+ *
+ * Material (the paper names a compressible neo-Hookean law but elides its
+ * formula, Sec. 6.1; the reading used here is the standard form):
+ *   psi = mu/2 (tr F^T F - 3) - mu ln J + lam/2 (ln J)^2,  J = det F
+ *   P   = mu (F - F^-T) + lam ln J F^-T
+ *   A_iJkL = dP_iJ/dF_kL = mu d_ik d_JL + lam Finv_Ji Finv_Lk
+ *                          + (mu - lam ln J) Finv_Jk Finv_Li
+ * The tangent action uses the explicit 81-entry A.  I_1 - 3 and ln J are
+ * evaluated as 2 tr H + H:H and log1p(tr H + ((tr H)^2 - tr H^2)/2 + det H)
+ * with H = F - I, which are the same quantities written without cancellation.
+ *
+ * Elements: Tet4 with the one-point centroid rule (w = 1/6) and trilinear
+ * Hex8 on [-1,1]^3 with the 2x2x2 Gauss rule (points +-1/sqrt 3, w = 1); the
+ * paper leaves the rules unspecified (Eq. 2).
+ *
+ * Assembly: every element writes its own contribution block in parallel
+ * (OpenMP); the blocks are then summed serially in element order, so results
+ * are bitwise identical for any thread count.  Energies are summed with
+ * Neumaier compensation.
+ *
+ * Return codes: 0 ok, -1 bad argument, -4 an element with det J <= 0 or
+ * det F <= 0 was met (energy is then +inf; other outputs are unspecified).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_TET4 0
+#define ORC_HEX8 1
+
+typedef struct {
+    int nen;            /* nodes per element */
+    int nq;             /* quadrature points */
+    double w[8];        /* weights */
+    double dN[8][8][3]; /* dN[q][a][J]: reference gradients at point q */
+} rule_t;
+
+static int make_rule(int type, rule_t *r)
+{
+    if (type == ORC_TET4) {
+        /* N0 = 1 - xi - eta - zeta, N1 = xi, N2 = eta, N3 = zeta */
+        static const double g[4][3] = {{-1, -1, -1}, {1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
+        r->nen = 4;
+        r->nq = 1;
+        r->w[0] = 1.0 / 6.0;
+        for (int a = 0; a < 4; ++a)
+            for (int J = 0; J < 3; ++J) r->dN[0][a][J] = g[a][J];
+        return 0;
+    }
+    if (type == ORC_HEX8) {
+        /* N_a = 1/8 (1 + s_a xi)(1 + t_a eta)(1 + z_a zeta) */
+        static const double c[8][3] = {{-1, -1, -1}, {1, -1, -1}, {1, 1, -1}, {-1, 1, -1},
+                                       {-1, -1, 1},  {1, -1, 1},  {1, 1, 1},  {-1, 1, 1}};
+        const double g = 1.0 / sqrt(3.0);
+        r->nen = 8;
+        r->nq = 8;
+        int q = 0;
+        for (int k = 0; k < 2; ++k)
+            for (int j = 0; j < 2; ++j)
+                for (int i = 0; i < 2; ++i, ++q) {
+                    double p[3] = {(2 * i - 1) * g, (2 * j - 1) * g, (2 * k - 1) * g};
+                    r->w[q] = 1.0;
+                    for (int a = 0; a < 8; ++a) {
+                        double f0 = 1 + c[a][0] * p[0], f1 = 1 + c[a][1] * p[1], f2 = 1 + c[a][2] * p[2];
+                        r->dN[q][a][0] = 0.125 * c[a][0] * f1 * f2;
+                        r->dN[q][a][1] = 0.125 * f0 * c[a][1] * f2;
+                        r->dN[q][a][2] = 0.125 * f0 * f1 * c[a][2];
+                    }
+                }
+        return 0;
+    }
+    return -1;
+}
+
+static double det3(const double M[3][3])
+{
+    return M[0][0] * (M[1][1] * M[2][2] - M[1][2] * M[2][1])
+         - M[0][1] * (M[1][0] * M[2][2] - M[1][2] * M[2][0])
+         + M[0][2] * (M[1][0] * M[2][1] - M[1][1] * M[2][0]);
+}
+
+/* inverse via the adjugate; returns the determinant */
+static double inv3(const double M[3][3], double Mi[3][3])
+{
+    double d = det3(M);
+    Mi[0][0] = (M[1][1] * M[2][2] - M[1][2] * M[2][1]) / d;
+    Mi[0][1] = (M[0][2] * M[2][1] - M[0][1] * M[2][2]) / d;
+    Mi[0][2] = (M[0][1] * M[1][2] - M[0][2] * M[1][1]) / d;
+    Mi[1][0] = (M[1][2] * M[2][0] - M[1][0] * M[2][2]) / d;
+    Mi[1][1] = (M[0][0] * M[2][2] - M[0][2] * M[2][0]) / d;
+    Mi[1][2] = (M[0][2] * M[1][0] - M[0][0] * M[1][2]) / d;
+    Mi[2][0] = (M[1][0] * M[2][1] - M[1][1] * M[2][0]) / d;
+    Mi[2][1] = (M[0][1] * M[2][0] - M[0][0] * M[2][1]) / d;
+    Mi[2][2] = (M[0][0] * M[1][1] - M[0][1] * M[1][0]) / d;
+    return d;
+}
+
+/* Everything the operators need at one quadrature point of one element. */
+typedef struct {
+    double wdetJ;       /* w_q det J */
+    double gN[8][3];    /* grad_X N_a */
+    double F[3][3], Finv[3][3];
+    double H[3][3];     /* F - I */
+    double lnJ;
+    double I1m3;        /* tr(F^T F) - 3 */
+    int ok;             /* det J > 0 and det F > 0 */
+} qp_t;
+
+static void qp_eval(const rule_t *r, int q, const double Xe[8][3], const double ue[8][3], qp_t *s)
+{
+    double Jm[3][3] = {{0}}, Ji[3][3];
+    for (int a = 0; a < r->nen; ++a)
+        for (int i = 0; i < 3; ++i)
+            for (int J = 0; J < 3; ++J) Jm[i][J] += Xe[a][i] * r->dN[q][a][J];
+    double detJ = inv3(Jm, Ji);
+    s->ok = detJ > 0.0;
+    s->wdetJ = r->w[q] * detJ;
+    /* grad N_a = J^-T dN_a/dxi :  (grad N_a)_L = sum_J Ji[J][L] dN[a][J] */
+    for (int a = 0; a < r->nen; ++a)
+        for (int L = 0; L < 3; ++L) {
+            double t = 0;
+            for (int J = 0; J < 3; ++J) t += Ji[J][L] * r->dN[q][a][J];
+            s->gN[a][L] = t;
+        }
+    for (int i = 0; i < 3; ++i)
+        for (int L = 0; L < 3; ++L) {
+            double t = 0;
+            for (int a = 0; a < r->nen; ++a) t += ue[a][i] * s->gN[a][L];
+            s->H[i][L] = t;
+            s->F[i][L] = (i == L ? 1.0 : 0.0) + t;
+        }
+    const double (*H)[3] = (const double (*)[3])s->H;
+    double trH = H[0][0] + H[1][1] + H[2][2];
+    double HH = 0, trH2 = 0;
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            HH += H[i][j] * H[i][j];
+            trH2 += H[i][j] * H[j][i];
+        }
+    double Jm1 = trH + 0.5 * (trH * trH - trH2) + det3(H);   /* det(I+H) - 1 */
+    s->I1m3 = 2.0 * trH + HH;
+    if (!(1.0 + Jm1 > 0.0)) {
+        s->ok = 0;
+        s->lnJ = NAN;
+        return;
+    }
+    s->lnJ = log1p(Jm1);
+    inv3(s->F, s->Finv);
+}
+
+static double psi_of(const qp_t *s, double mu, double lam)
+{
+    return 0.5 * mu * s->I1m3 - mu * s->lnJ + 0.5 * lam * s->lnJ * s->lnJ;
+}
+
+/* first Piola-Kirchhoff stress P_iJ = mu (F - F^-T)_iJ + lam lnJ F^-T_iJ */
+static void piola(const qp_t *s, double mu, double lam, double P[3][3])
+{
+    for (int i = 0; i < 3; ++i)
+        for (int J = 0; J < 3; ++J)
+            P[i][J] = mu * (s->F[i][J] - s->Finv[J][i]) + lam * s->lnJ * s->Finv[J][i];
+}
+
+/* explicit tangent A_iJkL = dP_iJ / dF_kL */
+static void tangent(const qp_t *s, double mu, double lam, double A[3][3][3][3])
+{
+    const double (*Fi)[3] = (const double (*)[3])s->Finv;
+    double c = mu - lam * s->lnJ;
+    for (int i = 0; i < 3; ++i)
+        for (int J = 0; J < 3; ++J)
+            for (int k = 0; k < 3; ++k)
+                for (int L = 0; L < 3; ++L)
+                    A[i][J][k][L] = (i == k && J == L ? mu : 0.0) + lam * Fi[J][i] * Fi[L][k]
+                                  + c * Fi[J][k] * Fi[L][i];
+}
+
+static void gather(const rule_t *r, const double *V, const int32_t *ce, double out[8][3])
+{
+    for (int a = 0; a < r->nen; ++a)
+        for (int i = 0; i < 3; ++i) out[a][i] = V[3 * (int64_t)ce[a] + i];
+}
+
+/* serial scatter of per-element blocks [ne][nen][3] into out [nn][3], element order */
+static void scatter_blocks(const rule_t *r, int64_t nn, int64_t ne, const int32_t *conn,
+                           const double *blk, double *out)
+{
+    memset(out, 0, sizeof(double) * 3 * (size_t)nn);
+    for (int64_t e = 0; e < ne; ++e)
+        for (int a = 0; a < r->nen; ++a)
+            for (int i = 0; i < 3; ++i)
+                out[3 * (int64_t)conn[e * r->nen + a] + i] += blk[(e * r->nen + a) * 3 + i];
+}
+
+static int check_args(int type, int64_t nn, int64_t ne, const int32_t *conn, rule_t *r)
+{
+    if (make_rule(type, r) != 0 || nn <= 0 || ne < 0) return -1;
+    for (int64_t k = 0; k < ne * r->nen; ++k)
+        if (conn[k] < 0 || conn[k] >= nn) return -1;
+    return 0;
+}
+
+/* ------------------------------------------------------------------ energy */
+
+/* Per-element energies psi_e [ne] and their compensated sum (Eq. 2). */
+int orc_energy(int type, int64_t nn, int64_t ne, const double *X, const int32_t *conn,
+               const double *mu, const double *lam, const double *u, double *psi_e, double *total)
+{
+    rule_t r;
+    if (check_args(type, nn, ne, conn, &r)) return -1;
+    int bad = 0;
+#pragma omp parallel for schedule(static) reduction(|| : bad)
+    for (int64_t e = 0; e < ne; ++e) {
+        double Xe[8][3], ue[8][3];
+        gather(&r, X, conn + e * r.nen, Xe);
+        gather(&r, u, conn + e * r.nen, ue);
+        double pe = 0;
+        for (int q = 0; q < r.nq; ++q) {
+            qp_t s;
+            qp_eval(&r, q, Xe, ue, &s);
+            if (!s.ok) { bad = 1; pe = INFINITY; break; }
+            pe += s.wdetJ * psi_of(&s, mu[e], lam[e]);
+        }
+        psi_e[e] = pe;
+    }
+    /* Neumaier summation in element order */
+    double sum = 0, comp = 0;
+    for (int64_t e = 0; e < ne; ++e) {
+        double t = sum + psi_e[e];
+        if (fabs(sum) >= fabs(psi_e[e])) comp += (sum - t) + psi_e[e];
+        else comp += (psi_e[e] - t) + sum;
+        sum = t;
+    }
+    *total = bad ? INFINITY : sum + comp;
+    return bad ? -4 : 0;
+}
+
+/* --------------------------------------------------------------- residual */
+
+/* r_{a,i} = sum_e sum_q w detJ P_iJ grad_J N_a        (Eq. 1, r = grad Psi) */
+int orc_residual(int type, int64_t nn, int64_t ne, const double *X, const int32_t *conn,
+                 const double *mu, const double *lam, const double *u, double *res)
+{
+    rule_t r;
+    if (check_args(type, nn, ne, conn, &r)) return -1;
+    double *blk = (double *)calloc((size_t)(ne * r.nen * 3 + 1), sizeof(double));
+    if (!blk) return -1;
+    int bad = 0;
+#pragma omp parallel for schedule(static) reduction(|| : bad)
+    for (int64_t e = 0; e < ne; ++e) {
+        double Xe[8][3], ue[8][3], P[3][3];
+        gather(&r, X, conn + e * r.nen, Xe);
+        gather(&r, u, conn + e * r.nen, ue);
+        double *f = blk + e * r.nen * 3;
+        for (int q = 0; q < r.nq; ++q) {
+            qp_t s;
+            qp_eval(&r, q, Xe, ue, &s);
+            if (!s.ok) { bad = 1; break; }
+            piola(&s, mu[e], lam[e], P);
+            for (int a = 0; a < r.nen; ++a)
+                for (int i = 0; i < 3; ++i) {
+                    double t = 0;
+                    for (int J = 0; J < 3; ++J) t += P[i][J] * s.gN[a][J];
+                    f[a * 3 + i] += s.wdetJ * t;
+                }
+        }
+    }
+    scatter_blocks(&r, nn, ne, conn, blk, res);
+    free(blk);
+    return bad ? -4 : 0;
+}
+
+/* -------------------------------------------------------------------- hvp */
+
+/* (K v)_{a,i} = sum_e sum_q w detJ A_iJkL (sum_b v_bk grad_L N_b) grad_J N_a   (Eq. 3) */
+int orc_hvp(int type, int64_t nn, int64_t ne, const double *X, const int32_t *conn,
+            const double *mu, const double *lam, const double *u, const double *v, double *y)
+{
+    rule_t r;
+    if (check_args(type, nn, ne, conn, &r)) return -1;
+    double *blk = (double *)calloc((size_t)(ne * r.nen * 3 + 1), sizeof(double));
+    if (!blk) return -1;
+    int bad = 0;
+#pragma omp parallel for schedule(static) reduction(|| : bad)
+    for (int64_t e = 0; e < ne; ++e) {
+        double Xe[8][3], ue[8][3], ve[8][3], A[3][3][3][3];
+        gather(&r, X, conn + e * r.nen, Xe);
+        gather(&r, u, conn + e * r.nen, ue);
+        gather(&r, v, conn + e * r.nen, ve);
+        double *f = blk + e * r.nen * 3;
+        for (int q = 0; q < r.nq; ++q) {
+            qp_t s;
+            qp_eval(&r, q, Xe, ue, &s);
+            if (!s.ok) { bad = 1; break; }
+            tangent(&s, mu[e], lam[e], A);
+            double dF[3][3], dP[3][3];
+            for (int k = 0; k < 3; ++k)
+                for (int L = 0; L < 3; ++L) {
+                    double t = 0;
+                    for (int b = 0; b < r.nen; ++b) t += ve[b][k] * s.gN[b][L];
+                    dF[k][L] = t;
+                }
+            for (int i = 0; i < 3; ++i)
+                for (int J = 0; J < 3; ++J) {
+                    double t = 0;
+                    for (int k = 0; k < 3; ++k)
+                        for (int L = 0; L < 3; ++L) t += A[i][J][k][L] * dF[k][L];
+                    dP[i][J] = t;
+                }
+            for (int a = 0; a < r.nen; ++a)
+                for (int i = 0; i < 3; ++i) {
+                    double t = 0;
+                    for (int J = 0; J < 3; ++J) t += dP[i][J] * s.gN[a][J];
+                    f[a * 3 + i] += s.wdetJ * t;
+                }
+        }
+    }
+    scatter_blocks(&r, nn, ne, conn, blk, y);
+    free(blk);
+    return bad ? -4 : 0;
+}
+
+/* ----------------------------------------------------------- jacobi diag */
+
+/* K_{(a,i),(a,i)} = sum_e sum_q w detJ sum_JL A_iJiL grad_J N_a grad_L N_a */
+int orc_jacobi_diag(int type, int64_t nn, int64_t ne, const double *X, const int32_t *conn,
+                    const double *mu, const double *lam, const double *u, double *d)
+{
+    rule_t r;
+    if (check_args(type, nn, ne, conn, &r)) return -1;
+    double *blk = (double *)calloc((size_t)(ne * r.nen * 3 + 1), sizeof(double));
+    if (!blk) return -1;
+    int bad = 0;
+#pragma omp parallel for schedule(static) reduction(|| : bad)
+    for (int64_t e = 0; e < ne; ++e) {
+        double Xe[8][3], ue[8][3], A[3][3][3][3];
+        gather(&r, X, conn + e * r.nen, Xe);
+        gather(&r, u, conn + e * r.nen, ue);
+        double *f = blk + e * r.nen * 3;
+        for (int q = 0; q < r.nq; ++q) {
+            qp_t s;
+            qp_eval(&r, q, Xe, ue, &s);
+            if (!s.ok) { bad = 1; break; }
+            tangent(&s, mu[e], lam[e], A);
+            for (int a = 0; a < r.nen; ++a)
+                for (int i = 0; i < 3; ++i) {
+                    double t = 0;
+                    for (int J = 0; J < 3; ++J)
+                        for (int L = 0; L < 3; ++L) t += A[i][J][i][L] * s.gN[a][J] * s.gN[a][L];
+                    f[a * 3 + i] += s.wdetJ * t;
+                }
+        }
+    }
+    scatter_blocks(&r, nn, ne, conn, blk, d);
+    free(blk);
+    return bad ? -4 : 0;
+}
+
+/* ------------------------------------------------------ material adjoints */
+
+/* dPsi/dmu_e = sum_q w detJ [ (tr C - 3)/2 - ln J ],  dPsi/dlam_e = sum_q w detJ (ln J)^2 / 2 */
+int orc_grad_material(int type, int64_t nn, int64_t ne, const double *X, const int32_t *conn,
+                      const double *u, double *dmu, double *dlam)
+{
+    rule_t r;
+    if (check_args(type, nn, ne, conn, &r)) return -1;
+    int bad = 0;
+#pragma omp parallel for schedule(static) reduction(|| : bad)
+    for (int64_t e = 0; e < ne; ++e) {
+        double Xe[8][3], ue[8][3];
+        gather(&r, X, conn + e * r.nen, Xe);
+        gather(&r, u, conn + e * r.nen, ue);
+        double gm = 0, gl = 0;
+        for (int q = 0; q < r.nq; ++q) {
+            qp_t s;
+            qp_eval(&r, q, Xe, ue, &s);
+            if (!s.ok) { bad = 1; break; }
+            gm += s.wdetJ * (0.5 * s.I1m3 - s.lnJ);
+            gl += s.wdetJ * 0.5 * s.lnJ * s.lnJ;
+        }
+        dmu[e] = gm;
+        dlam[e] = gl;
+    }
+    return bad ? -4 : 0;
+}
+
+/* w . dr/dmu_e = sum_q w detJ (F - F^-T) : grad w,   w . dr/dlam_e = sum_q w detJ lnJ F^-T : grad w */
+int orc_residual_vjp_material(int type, int64_t nn, int64_t ne, const double *X, const int32_t *conn,
+                              const double *u, const double *wv, double *dmu, double *dlam)
+{
+    rule_t r;
+    if (check_args(type, nn, ne, conn, &r)) return -1;
+    int bad = 0;
+#pragma omp parallel for schedule(static) reduction(|| : bad)
+    for (int64_t e = 0; e < ne; ++e) {
+        double Xe[8][3], ue[8][3], we[8][3];
+        gather(&r, X, conn + e * r.nen, Xe);
+        gather(&r, u, conn + e * r.nen, ue);
+        gather(&r, wv, conn + e * r.nen, we);
+        double gm = 0, gl = 0;
+        for (int q = 0; q < r.nq; ++q) {
+            qp_t s;
+            qp_eval(&r, q, Xe, ue, &s);
+            if (!s.ok) { bad = 1; break; }
+            for (int i = 0; i < 3; ++i)
+                for (int J = 0; J < 3; ++J) {
+                    double gw = 0;
+                    for (int a = 0; a < r.nen; ++a) gw += we[a][i] * s.gN[a][J];
+                    gm += s.wdetJ * (s.F[i][J] - s.Finv[J][i]) * gw;
+                    gl += s.wdetJ * s.lnJ * s.Finv[J][i] * gw;
+                }
+        }
+        dmu[e] = gm;
+        dlam[e] = gl;
+    }
+    return bad ? -4 : 0;
+}
+
+/* ---------------------------------------------------- coordinate adjoint */
+
+/* dPsi/dX_a (at fixed nodal u) = sum_e sum_q w detJ (psi I - H^T P) grad N_a */
+int orc_grad_coords(int type, int64_t nn, int64_t ne, const double *X, const int32_t *conn,
+                    const double *mu, const double *lam, const double *u, double *gX)
+{
+    rule_t r;
+    if (check_args(type, nn, ne, conn, &r)) return -1;
+    double *blk = (double *)calloc((size_t)(ne * r.nen * 3 + 1), sizeof(double));
+    if (!blk) return -1;
+    int bad = 0;
+#pragma omp parallel for schedule(static) reduction(|| : bad)
+    for (int64_t e = 0; e < ne; ++e) {
+        double Xe[8][3], ue[8][3], P[3][3], S[3][3];
+        gather(&r, X, conn + e * r.nen, Xe);
+        gather(&r, u, conn + e * r.nen, ue);
+        double *f = blk + e * r.nen * 3;
+        for (int q = 0; q < r.nq; ++q) {
+            qp_t s;
+            qp_eval(&r, q, Xe, ue, &s);
+            if (!s.ok) { bad = 1; break; }
+            piola(&s, mu[e], lam[e], P);
+            double psi = psi_of(&s, mu[e], lam[e]);
+            for (int m = 0; m < 3; ++m)
+                for (int L = 0; L < 3; ++L) {
+                    double t = (m == L ? psi : 0.0);
+                    for (int i = 0; i < 3; ++i) t -= s.H[i][m] * P[i][L];
+                    S[m][L] = t;
+                }
+            for (int a = 0; a < r.nen; ++a)
+                for (int m = 0; m < 3; ++m) {
+                    double t = 0;
+                    for (int L = 0; L < 3; ++L) t += S[m][L] * s.gN[a][L];
+                    f[a * 3 + m] += s.wdetJ * t;
+                }
+        }
+    }
+    scatter_blocks(&r, nn, ne, conn, blk, gX);
+    free(blk);
+    return bad ? -4 : 0;
+}
+
+/* Element volumes sum_q w detJ, for mesh checks.  Returns -4 if any det J <= 0. */
+int orc_volumes(int type, int64_t nn, int64_t ne, const double *X, const int32_t *conn, double *vol)
+{
+    rule_t r;
+    if (check_args(type, nn, ne, conn, &r)) return -1;
+    int bad = 0;
+    for (int64_t e = 0; e < ne; ++e) {
+        double Xe[8][3], ue[8][3] = {{0}};
+        gather(&r, X, conn + e * r.nen, Xe);
+        double v = 0;
+        for (int q = 0; q < r.nq; ++q) {
+            qp_t s;
+            qp_eval(&r, q, Xe, ue, &s);
+            if (!s.ok) bad = 1;
+            v += s.wdetJ;
+        }
+        vol[e] = v;
+    }
+    return bad ? -4 : 0;
+}
+
+int orc_num_threads(void)
+{
+#ifdef _OPENMP
+    extern int omp_get_max_threads(void);
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}

@@ -1,0 +1,204 @@
+"""Seeded synthetic inputs shared by the HIP path, the tests and the benchmark.
+
+This module holds no arithmetic of the method (no shape functions, no
+quadrature, no material law).  It only builds structured unit-cube meshes and
+draws seeded random fields, with numpy's PCG64 generator, in the layouts the
+C-ABI expects:
+
+* node coordinates ``X``: float64 ``[n_nodes, 3]`` (node-major, the flat DOF
+  vector of Sec. 4 is ``u.reshape(-1)`` with ``dof = 3*node + comp``);
+* connectivity ``conn``: int32 ``[n_elems, n_en]``;
+* per-element material fields ``mu``, ``lam``: float64 ``[n_elems]``;
+* Dirichlet masks: uint8 ``[n_nodes*3]``, 1 = prescribed.
+
+The paper's own meshes are not available; structured cubes stand in for its 3D
+tetrahedral "elasticity" scaling meshes (Sec. 5.1) and for the hexahedral
+meshes of the configurations measured here.
+"""
+from __future__ import annotations
+
+import itertools
+from dataclasses import dataclass
+
+import numpy as np
+
+TET4 = 0
+HEX8 = 1
+N_EN = {TET4: 4, HEX8: 8}
+
+
+@dataclass
+class Mesh:
+    elem: int            # TET4 or HEX8
+    n: int               # hexes per cube edge
+    X: np.ndarray        # float64 [n_nodes, 3]
+    conn: np.ndarray     # int32 [n_elems, n_en]
+
+    @property
+    def n_nodes(self) -> int:
+        return self.X.shape[0]
+
+    @property
+    def n_elems(self) -> int:
+        return self.conn.shape[0]
+
+    @property
+    def n_dofs(self) -> int:
+        return 3 * self.X.shape[0]
+
+
+def grid_nodes(n: int) -> np.ndarray:
+    """Nodes of the unit cube with n hexes per edge; id = i + (n+1)(j + (n+1)k)."""
+    t = np.arange(n + 1, dtype=np.float64) / n
+    k, j, i = np.meshgrid(t, t, t, indexing="ij")
+    return np.stack([i.ravel(), j.ravel(), k.ravel()], axis=1).copy()
+
+
+def _hex_corner_ids(n: int) -> np.ndarray:
+    """[n^3] ids of the (0,0,0) corner of each hex, hexes ordered k, j, i (i fastest)."""
+    m = n + 1
+    k, j, i = np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij")
+    return (i + m * (j + m * k)).ravel().astype(np.int64)
+
+
+def hex_mesh(n: int) -> Mesh:
+    """Q1 hexahedra, local node order: the four z=0 corners counter-clockwise
+    from the origin, then the same four at z=1 (the usual VTK order)."""
+    m = n + 1
+    p = _hex_corner_ids(n)
+    off = [0, 1, 1 + m, m, m * m, 1 + m * m, 1 + m + m * m, m + m * m]
+    conn = np.stack([p + o for o in off], axis=1).astype(np.int32)
+    return Mesh(HEX8, n, grid_nodes(n), conn)
+
+
+def tet_mesh(n: int) -> Mesh:
+    """Each hex split into six tetrahedra along its main diagonal (Kuhn split).
+
+    For the axis permutation (a, b, c) the tetrahedron is
+    [p, p+e_a, p+e_a+e_b, p+(1,1,1)]; its edge matrix has the determinant of
+    the permutation, so for odd permutations the last two local nodes are
+    swapped to keep every tetrahedron positively oriented.  All hexes use the
+    same diagonal, so the split is conforming.
+    """
+    m = n + 1
+    stride = np.array([1, m, m * m], dtype=np.int64)
+    p = _hex_corner_ids(n)
+    tets = []
+    for perm in itertools.permutations(range(3)):
+        a, b, _ = perm
+        # parity of the permutation: number of inversions
+        inv = sum(1 for x in range(3) for y in range(x + 1, 3) if perm[x] > perm[y])
+        n1 = p + stride[a]
+        n2 = n1 + stride[b]
+        n3 = p + stride.sum()
+        if inv % 2 == 0:
+            tets.append(np.stack([p, n1, n2, n3], axis=1))
+        else:
+            tets.append(np.stack([p, n1, n3, n2], axis=1))
+    # six tets per hex, consecutive
+    conn = np.stack(tets, axis=1).reshape(-1, 4).astype(np.int32)
+    return Mesh(TET4, n, grid_nodes(n), conn)
+
+
+def make_mesh(elem: int, n: int) -> Mesh:
+    return tet_mesh(n) if elem == TET4 else hex_mesh(n)
+
+
+# ----------------------------------------------------------------- fields
+
+def rng(seed: int) -> np.random.Generator:
+    return np.random.default_rng(seed)
+
+
+def gaussian_field(n_nodes: int, amplitude: float, seed: int) -> np.ndarray:
+    """u = amplitude * N(0,1) per DOF, float64 [n_nodes, 3]."""
+    return amplitude * rng(seed).standard_normal((n_nodes, 3))
+
+
+def unit_direction(n_nodes: int, seed: int) -> np.ndarray:
+    """v = g / ||g||_2 with g ~ N(0,1) per DOF over all DOFs, float64 [n_nodes, 3]."""
+    g = rng(seed).standard_normal((n_nodes, 3))
+    return g / np.linalg.norm(g)
+
+
+def lognormal_field(n_elems: int, sigma: float, seed: int) -> np.ndarray:
+    """mu_e = exp(sigma * Z_e), Z_e ~ N(0,1) i.i.d. per element."""
+    return np.exp(sigma * rng(seed).standard_normal(n_elems))
+
+
+def constant_field(n_elems: int, value: float) -> np.ndarray:
+    return np.full(n_elems, float(value))
+
+
+def random_rotation(seed: int) -> np.ndarray:
+    """A random proper rotation (QR of a Gaussian matrix with sign fix)."""
+    q, r = np.linalg.qr(rng(seed).standard_normal((3, 3)))
+    q = q * np.sign(np.diag(r))
+    if np.linalg.det(q) < 0:
+        q[:, 0] = -q[:, 0]
+    return q
+
+
+# ------------------------------------------------------------- boundaries
+
+def face_nodes(X: np.ndarray, axis: int, value: float, tol: float = 1e-12) -> np.ndarray:
+    return np.nonzero(np.abs(X[:, axis] - value) < tol)[0]
+
+
+def clamp_top_bottom(X: np.ndarray, top_dz: float, top_all_components: bool = True):
+    """Bottom face z=0 fully clamped; top face z=1 displaced by top_dz in z.
+
+    With ``top_all_components`` the top face is gripped (u_x = u_y = 0 there as
+    well); otherwise only u_z is prescribed on the top face.
+    Returns (mask uint8 [3*n_nodes], u_bc float64 [n_nodes, 3]) where u_bc holds
+    the prescribed values of the final load step (zero on free DOFs).
+    """
+    n_nodes = X.shape[0]
+    mask = np.zeros((n_nodes, 3), dtype=np.uint8)
+    u_bc = np.zeros((n_nodes, 3))
+    bot = face_nodes(X, 2, 0.0)
+    top = face_nodes(X, 2, 1.0)
+    mask[bot, :] = 1
+    if top_all_components:
+        mask[top, :] = 1
+    else:
+        mask[top, 2] = 1
+    u_bc[top, 2] = top_dz
+    return mask.reshape(-1), u_bc
+
+
+# -------------------------------------------------------- named workloads
+
+@dataclass
+class OperatorCase:
+    mesh: Mesh
+    mu: np.ndarray
+    lam: np.ndarray
+    u: np.ndarray
+    v: np.ndarray
+
+
+def operator_case(elem: int, n: int, u_amp: float, u_seed: int = 0, v_seed: int = 1,
+                  mu_sigma: float = 0.0, mu_seed: int = 3, lam_ratio: float | None = None,
+                  lam_const: float = 1.5) -> OperatorCase:
+    """Mesh + material + a state u + a unit direction v.
+
+    mu is 1 when mu_sigma == 0, else lognormal(0, mu_sigma); lam is lam_ratio*mu
+    when lam_ratio is given, else the constant lam_const.
+    """
+    mesh = make_mesh(elem, n)
+    if mu_sigma == 0.0:
+        mu = constant_field(mesh.n_elems, 1.0)
+    else:
+        mu = lognormal_field(mesh.n_elems, mu_sigma, mu_seed)
+    lam = lam_ratio * mu if lam_ratio is not None else constant_field(mesh.n_elems, lam_const)
+    u = gaussian_field(mesh.n_nodes, u_amp, u_seed)
+    v = unit_direction(mesh.n_nodes, v_seed)
+    return OperatorCase(mesh, mu, lam, u, v)
+
+
+def cube_amplitude(n: int, base: float = 0.01, base_n: int = 8) -> float:
+    """Displacement amplitude that keeps the nodal-gradient scale of an n=8
+    cube with amplitude ``base`` (0.01*8/n): at the literal 0.01 a 64^3 Kuhn
+    mesh inverts about a third of its tetrahedra."""
+    return base * base_n / n

@@ -1,0 +1,47 @@
+"""The pins must catch plausible mistakes in the oracle.
+
+Each case plants one mistake (a dropped term, a wrong sign, a transposed
+operand or index) in a copy of the oracle's C source, builds it with gcc on the
+CPU, and runs the pin suite against it in a subprocess; the suite must fail.
+"""
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = os.path.join(ROOT, "oracle", "efem_oracle.c")
+
+MUTATIONS = {
+    "tangent_last_term_transposed": ("+ c * Fi[J][k] * Fi[L][i]", "+ c * Fi[J][i] * Fi[L][k]"),
+    "tangent_lambda_term_transposed": ("lam * Fi[J][i] * Fi[L][k]", "lam * Fi[J][k] * Fi[L][i]"),
+    "tangent_dropped_identity": ("(i == k && J == L ? mu : 0.0)", "0.0"),
+    "stress_transposed_inverse": ("mu * (s->F[i][J] - s->Finv[J][i])", "mu * (s->F[i][J] - s->Finv[i][J])"),
+    "energy_log_sign": ("- mu * s->lnJ +", "+ mu * s->lnJ +"),
+    "gradient_uses_J_inverse_not_transpose": ("t += Ji[J][L] * r->dN[q][a][J]", "t += Ji[L][J] * r->dN[q][a][J]"),
+    "jacobian_dropped_det_term": ("+ 0.5 * (trH * trH - trH2) + det3(H);", "+ 0.5 * (trH * trH - trH2);"),
+    "coords_adjoint_transposed_H": ("t -= s.H[i][m] * P[i][L]", "t -= s.H[m][i] * P[i][L]"),
+    "hex_gauss_point": ("const double g = 1.0 / sqrt(3.0);", "const double g = 0.5;"),
+    "diag_wrong_index": ("A[i][J][i][L] * s.gN[a][J] * s.gN[a][L]", "A[i][J][i][J] * s.gN[a][J] * s.gN[a][L]"),
+    "vjp_mu_transposed": ("(s.F[i][J] - s.Finv[J][i]) * gw", "(s.F[i][J] - s.Finv[i][J]) * gw"),
+    "grad_mu_log_sign": ("(0.5 * s.I1m3 - s.lnJ)", "(0.5 * s.I1m3 + s.lnJ)"),
+    "tet_weight": ("r->w[0] = 1.0 / 6.0;", "r->w[0] = 1.0 / 3.0;"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(MUTATIONS))
+def test_pins_catch_planted_mistake(name, tmp_path):
+    old, new = MUTATIONS[name]
+    src = open(SRC).read()
+    assert src.count(old) == 1, f"mutation anchor not found once: {old!r}"
+    mutated = tmp_path / "mutated.c"
+    mutated.write_text(src.replace(old, new))
+    lib = tmp_path / "libmutated.so"
+    subprocess.run(["gcc", "-O2", "-std=c11", "-fopenmp", "-ffp-contract=off", "-fPIC", "-shared",
+                    str(mutated), "-o", str(lib), "-lm"], check=True)
+    env = dict(os.environ, EFEM_ORACLE_LIB=str(lib), OMP_NUM_THREADS="2")
+    res = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
+                          os.path.join(ROOT, "tests", "test_oracle_pins.py")],
+                         cwd=ROOT, env=env, capture_output=True, text=True, timeout=300)
+    assert res.returncode != 0, f"pins did not catch mutation {name}:\n{res.stdout[-2000:]}"
