@@ -1,0 +1,241 @@
+/*
+ * efem.h -- C-ABI of the energy-based finite-element hot path for AMD MI355X
+ * (gfx950): the global potential energy of a mesh, its gradient (the nodal
+ * residual) and matrix-free tangent actions (Hessian-vector products), their
+ * adjoints with respect to material fields and nodal coordinates, and a
+ * matrix-free Newton-Krylov solve built on them.
+ *
+ * The calls follow the paper's statement of the problem (arXiv 2602.12365):
+ *   - an operator object built from a mesh, an element type and a batch
+ *     (block) size, Sec. 4 ("Geometric Context");
+ *   - the discrete energy Psi_h of a flat DOF vector, Eq. (2) and Alg. 1;
+ *   - the residual r = grad Psi_h, Eq. (1);
+ *   - the tangent action dr = K du, Eq. (3);
+ *   - Dirichlet conditions as a reduced functional over the free DOFs, Sec. 6.1;
+ *   - a matrix-free Newton-Krylov solve, Sec. 6.3.1.
+ *
+ * Element types: 4-node tetrahedra with the one-point centroid rule, 8-node
+ * trilinear hexahedra with the 2x2x2 Gauss rule.  Material: compressible
+ * neo-Hookean, psi = mu/2 (tr F^T F - 3) - mu ln J + lam/2 (ln J)^2, with
+ * per-element (mu, lam).
+ *
+ * Conventions (all calls):
+ *   - Layout: nodal arrays are node-major interleaved, entry 3*node + comp
+ *     (the reshape(-1, 3) of the flat DOF vector, Sec. 4).  Per-element arrays
+ *     are indexed by the caller's element numbering.
+ *   - Ownership: mesh arrays passed to efem_create are HOST pointers and are
+ *     copied.  Every other array argument is a caller-owned DEVICE pointer
+ *     (hipMalloc'd or a contiguous torch CUDA tensor) on the context's device;
+ *     the library never frees it and does not keep it after the call returns,
+ *     except where stated (efem_set_material copies, efem_linearize copies).
+ *   - Streams: operator calls are asynchronous on the context's stream (set at
+ *     creation or with efem_set_stream); results are ready when that stream
+ *     reaches the point of the call.  Calls documented as synchronous wait.
+ *   - Errors: functions return EFEM_OK (0), a warning (> 0) or an error (< 0);
+ *     efem_last_error() gives a message for the calling thread.  No C++
+ *     exception crosses this boundary.
+ *   - Thread safety: a context may be used by one host thread and one stream
+ *     at a time.  Distinct contexts are independent.
+ */
+#ifndef EFEM_H
+#define EFEM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* return codes */
+#define EFEM_OK              0
+#define EFEM_NOT_CONVERGED   1   /* newton_solve stopped at an iteration cap */
+#define EFEM_ERR_INVALID    -1   /* bad argument: null pointer, size, index */
+#define EFEM_ERR_HIP        -2   /* a HIP runtime call failed */
+#define EFEM_ERR_OOM        -3   /* device or host allocation failed */
+#define EFEM_ERR_INVERTED   -4   /* an element with det J <= 0 or det F <= 0 */
+#define EFEM_ERR_STATE      -5   /* call out of order (e.g. hvp before linearize) */
+
+/* element types */
+#define EFEM_TET4 0
+#define EFEM_HEX8 1
+
+/* arithmetic of the tangent action */
+#define EFEM_F64 0
+#define EFEM_F32 1
+
+/* how element contributions are summed into nodal vectors */
+#define EFEM_SCATTER_ATOMIC 0   /* block-aggregated in LDS, then global atomics on
+                                   nodes shared between blocks */
+#define EFEM_SCATTER_COLOR  1   /* blocks coloured so that no two blocks of one
+                                   colour share a node; one pass per colour, no
+                                   global atomics (sums within a block still use
+                                   LDS atomics, so results vary in the last bits) */
+
+typedef struct efem_ctx efem_ctx;
+
+typedef struct {
+    int32_t block_elems;   /* max elements per workgroup block (the paper's batch
+                              size N_B, Alg. 1); 0 = default for the element type */
+    int32_t block_nodes;   /* max distinct nodes per block (<= 600, so that one block
+                              fits 64 KB of LDS); 0 = default */
+    int32_t scatter;       /* EFEM_SCATTER_ATOMIC or EFEM_SCATTER_COLOR */
+    int32_t threads;       /* threads per workgroup (64..256, multiple of 64); 0 = default */
+} efem_options;
+
+/* Build an operator for a mesh (Sec. 4, Operator(mesh, element, batchsize)).
+ *   elem      EFEM_TET4 or EFEM_HEX8
+ *   coords    HOST float64 [n_nodes*3] reference coordinates X
+ *   conn      HOST int32 [n_elems*n_en] connectivity (4 or 8 nodes, element-major;
+ *             hexahedra in the order (0,0,0),(1,0,0),(1,1,0),(0,1,0), then z=1)
+ *   opts      may be NULL (defaults)
+ *   stream    hipStream_t to run on, NULL = the null stream
+ * Elements are reordered internally along a Morton curve and cut into blocks
+ * that each fit one workgroup's LDS.  The material is set to mu = 1, lam = 1.5
+ * until efem_set_material is called.  Synchronous.
+ * Errors: EFEM_ERR_INVALID on a null pointer, n_nodes < 1, n_elems < 1 or a
+ * connectivity entry outside [0, n_nodes); EFEM_ERR_INVERTED if an element of
+ * the reference mesh has det J <= 0 at a quadrature point. */
+int efem_create(efem_ctx **out, int32_t elem, int64_t n_nodes, int64_t n_elems,
+                const double *coords, const int32_t *conn, const efem_options *opts,
+                void *stream);
+
+/* Release every device and host resource of the context.  Synchronizes its stream. */
+void efem_destroy(efem_ctx *ctx);
+
+/* Change the stream later calls run on. */
+int efem_set_stream(efem_ctx *ctx, void *stream);
+
+/* Per-element material (DEVICE float64 [n_elems] each, caller's element order).
+ * Copied into the context; mu, lam must be finite. */
+int efem_set_material(efem_ctx *ctx, const double *mu, const double *lam);
+
+/* Dirichlet mask (DEVICE uint8 [3*n_nodes], 1 = prescribed DOF), or NULL to
+ * clear it.  With a mask set, the residual, the tangent action and the Jacobi
+ * diagonal are those of the reduced functional over the free DOFs (Sec. 6.1):
+ * prescribed entries of the output are 0 and prescribed entries of the
+ * direction v are ignored.  The energy is unaffected (the prescribed values
+ * are part of u).  Copied into the context. */
+int efem_set_dirichlet(efem_ctx *ctx, const uint8_t *mask);
+
+/* Psi_h(u), Eq. (2): u DEVICE float64 [3*n_nodes]; psi DEVICE float64 [1].
+ * A block-wise then compensated FP64 sum, bitwise deterministic.  If an element
+ * has det F <= 0 the result is +inf and the context's inverted flag is set
+ * (see efem_status). */
+int efem_energy(efem_ctx *ctx, const double *u, double *psi);
+
+/* r = grad Psi_h(u), Eq. (1): u, r DEVICE float64 [3*n_nodes]. */
+int efem_residual(efem_ctx *ctx, const double *u, double *r);
+
+/* Fix the linearization point u (DEVICE float64 [3*n_nodes]) of efem_hvp and
+ * its arithmetic prec (EFEM_F64 or EFEM_F32).  u is copied (rounded to float32
+ * for EFEM_F32), so the caller may change u afterwards. */
+int efem_linearize(efem_ctx *ctx, const double *u, int32_t prec);
+
+/* y = K(u) v, Eq. (3), at the point of the last efem_linearize: v, y DEVICE
+ * [3*n_nodes] of the linearize precision (float64 or float32).  y must not
+ * alias v.  EFEM_ERR_STATE if efem_linearize was never called. */
+int efem_hvp(efem_ctx *ctx, const void *v, void *y);
+
+/* y += K(u) v, Eq. (3), in a single kernel launch (efem_hvp needs a second,
+ * small launch to clear the entries that several blocks add into).  Same
+ * arguments and errors as efem_hvp; prescribed entries of y are set to 0. */
+int efem_hvp_acc(efem_ctx *ctx, const void *v, void *y);
+
+/* d = diag K(u), DEVICE float64 [3*n_nodes] (the Jacobi preconditioner);
+ * with a Dirichlet mask, prescribed entries are 1. */
+int efem_jacobi_diag(efem_ctx *ctx, const double *u, double *d);
+
+/* Adjoint with respect to the material at fixed u:
+ *   dmu[e] = dPsi/dmu_e, dlam[e] = dPsi/dlam_e   (DEVICE float64 [n_elems]). */
+int efem_grad_material(efem_ctx *ctx, const double *u, double *dmu, double *dlam);
+
+/* Residual vector-Jacobian product with respect to the material at fixed u:
+ *   dmu[e] = w . dr/dmu_e, dlam[e] = w . dr/dlam_e   (w DEVICE [3*n_nodes];
+ *   outputs DEVICE float64 [n_elems]).  The Dirichlet mask is not applied. */
+int efem_residual_vjp_material(efem_ctx *ctx, const double *u, const double *w,
+                               double *dmu, double *dlam);
+
+/* Adjoint with respect to the reference coordinates at fixed nodal u:
+ *   dX = dPsi/dX, DEVICE float64 [3*n_nodes].  Uses the coordinates given to
+ *   efem_create. */
+int efem_grad_coords(efem_ctx *ctx, const double *u, double *dX);
+
+/* Blocking statistics of a context (host values; synchronous). */
+typedef struct {
+    int32_t n_blocks;         /* workgroup element blocks */
+    int32_t n_colours;        /* colour passes (EFEM_SCATTER_COLOR), else 0 */
+    int32_t max_block_nodes;  /* largest per-block distinct node count */
+    int32_t max_block_elems;
+    int64_t n_shared_nodes;   /* nodes touched by more than one block */
+    int64_t n_block_nodes;    /* sum over blocks of distinct nodes (>= n_nodes) */
+} efem_info;
+
+int efem_get_info(efem_ctx *ctx, efem_info *info);
+
+/* Read and clear the context's device flags (synchronizes the stream):
+ * bit 0 = an element with det F <= 0 was met since the last call. */
+int efem_status(efem_ctx *ctx, int32_t *flags);
+
+/* ------------------------------------------------------------ Newton-Krylov */
+
+typedef struct {
+    int32_t n_steps;          /* load steps; prescribed values ramp as k/n_steps */
+    int32_t hvp_prec;         /* EFEM_F64 or EFEM_F32 for the CG tangent actions */
+    int32_t precond;          /* 0 = Jacobi, 1 = learned (efem_set_mlp) with Jacobi fallback */
+    int32_t max_newton;       /* per load step */
+    int32_t max_cg;           /* per linear solve */
+    int32_t check_every;      /* CG iterations between host convergence checks (>= 1) */
+    double rtol;              /* ||r_free|| <= rtol * ||r_free at step start|| */
+    double atol_floor;        /* absolute floor, times max(1, ||r_free at step start||) */
+    double eta_max, eta_min;  /* Eisenstat-Walker choice 2 forcing bounds */
+    double ew_gamma, ew_alpha;
+    double eta_fixed;         /* > 0: fixed forcing term instead of Eisenstat-Walker */
+    double predictor_rtol;    /* tolerance of the tangent predictor of each load step */
+    double armijo_c;          /* sufficient-decrease constant of the line search */
+    int32_t max_halvings;
+    int32_t verbose;          /* 0 silent, 1 one line per Newton iteration on stderr */
+} efem_solve_opts;
+
+typedef struct {
+    int32_t converged;        /* 1 if every load step met its tolerance */
+    int32_t steps_done;
+    int32_t newton_iters;     /* total */
+    int32_t cg_iters;         /* total, including predictors */
+    int32_t precond_fallbacks;/* learned-preconditioner solves restarted with Jacobi */
+    int32_t line_search_halvings;
+    double final_residual;    /* ||r_free|| at the end (FP64) */
+    double final_energy;
+    double seconds;           /* host wall time of the solve */
+    int32_t newton_per_step[64];
+    int32_t cg_per_step[64];
+} efem_solve_stats;
+
+/* Fill opts with the defaults (n_steps 5, FP64, Jacobi, rtol 1e-8, ...). */
+void efem_solve_opts_default(efem_solve_opts *opts);
+
+/* Matrix-free Newton-Krylov solve of the reduced functional (Sec. 6.1,
+ * Sec. 6.3.1).  Requires efem_set_dirichlet.
+ *   u_inout   DEVICE float64 [3*n_nodes]: initial free values in, solution out
+ *   u_bc      DEVICE float64 [3*n_nodes]: prescribed values of the final load
+ *             step (entries on free DOFs are ignored)
+ * Per load step: prescribed DOFs set to k/n of u_bc, a tangent predictor, then
+ * Newton iterations with PCG (Jacobi or learned), Eisenstat-Walker forcing and
+ * Armijo backtracking on the FP64 energy.  Synchronous.
+ * Returns EFEM_OK, EFEM_NOT_CONVERGED (stats say where) or an error. */
+int efem_newton_solve(efem_ctx *ctx, double *u_inout, const double *u_bc,
+                      const efem_solve_opts *opts, efem_solve_stats *stats);
+
+/* ------------------------------------------------- learned preconditioner */
+
+/* Number of parameters of the per-node MLP preconditioner, and its layout. */
+#define EFEM_MLP_IN   12
+#define EFEM_MLP_HID  64
+#define EFEM_MLP_OUT  3
+
+const char *efem_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* EFEM_H */

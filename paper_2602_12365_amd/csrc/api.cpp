@@ -1,0 +1,568 @@
+// C-ABI entry points: context creation (mesh blocking on the host), material
+// and Dirichlet setup, and the asynchronous operator calls.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "efem_internal.h"
+
+namespace efem {
+
+static thread_local std::string g_error;
+
+void set_error(const std::string &msg) { g_error = msg; }
+
+int hip_fail(hipError_t e, const char *what)
+{
+    set_error(std::string(what) + ": " + hipGetErrorString(e));
+    return e == hipErrorOutOfMemory ? EFEM_ERR_OOM : EFEM_ERR_HIP;
+}
+
+#define HIP_TRY(call)                                    \
+    do {                                                 \
+        hipError_t e_ = (call);                          \
+        if (e_ != hipSuccess) return hip_fail(e_, #call); \
+    } while (0)
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev)
+    {
+        if (hipGetDevice(&prev) == hipSuccess && prev != dev) (void)hipSetDevice(dev);
+        else prev = -1;
+    }
+    ~DeviceGuard()
+    {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+template <class T>
+static int dalloc(Ctx &c, T **p, size_t count)
+{
+    void *q = nullptr;
+    if (count == 0) count = 1;
+    hipError_t e = hipMalloc(&q, count * sizeof(T));
+    if (e != hipSuccess) return hip_fail(e, "hipMalloc");
+    c.owned.push_back(q);
+    *p = static_cast<T *>(q);
+    return EFEM_OK;
+}
+
+template <class T>
+static int upload(Ctx &c, T **p, const std::vector<T> &v)
+{
+    int rc = dalloc(c, p, v.size());
+    if (rc) return rc;
+    if (!v.empty()) HIP_TRY(hipMemcpy(*p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+    return EFEM_OK;
+}
+
+// ------------------------------------------------------------ host geometry
+
+static double det3(const double m[9])
+{
+    return m[0] * (m[4] * m[8] - m[5] * m[7]) - m[1] * (m[3] * m[8] - m[5] * m[6])
+         + m[2] * (m[3] * m[7] - m[4] * m[6]);
+}
+
+// det J of the reference map at every quadrature point must be positive.
+static bool reference_jacobians_positive(int elem, int nen, int64_t ne, const double *X,
+                                         const int32_t *conn)
+{
+    static const int S[8][3] = {{-1, -1, -1}, {1, -1, -1}, {1, 1, -1}, {-1, 1, -1},
+                                {-1, -1, 1},  {1, -1, 1},  {1, 1, 1},  {-1, 1, 1}};
+    const double g = 1.0 / std::sqrt(3.0);
+    for (int64_t e = 0; e < ne; ++e) {
+        const int32_t *ce = conn + e * nen;
+        if (elem == EFEM_TET4) {
+            double E[9];
+            for (int i = 0; i < 3; ++i)
+                for (int c = 0; c < 3; ++c) E[i * 3 + c] = X[3 * ce[c + 1] + i] - X[3 * ce[0] + i];
+            if (!(det3(E) > 0.0)) return false;
+        } else {
+            for (int q = 0; q < 8; ++q) {
+                const double p[3] = {(q & 1) ? g : -g, (q & 2) ? g : -g, (q & 4) ? g : -g};
+                double J[9] = {0};
+                for (int a = 0; a < 8; ++a) {
+                    const double f[3] = {1 + S[a][0] * p[0], 1 + S[a][1] * p[1], 1 + S[a][2] * p[2]};
+                    const double dn[3] = {0.125 * S[a][0] * f[1] * f[2], 0.125 * S[a][1] * f[0] * f[2],
+                                          0.125 * S[a][2] * f[0] * f[1]};
+                    for (int i = 0; i < 3; ++i)
+                        for (int Jj = 0; Jj < 3; ++Jj) J[i * 3 + Jj] += X[3 * ce[a] + i] * dn[Jj];
+                }
+                if (!(det3(J) > 0.0)) return false;
+            }
+        }
+    }
+    return true;
+}
+
+static uint64_t spread3(uint64_t v)   // 21 bits -> every third bit
+{
+    v &= 0x1fffff;
+    v = (v | v << 32) & 0x1f00000000ffffull;
+    v = (v | v << 16) & 0x1f0000ff0000ffull;
+    v = (v | v << 8) & 0x100f00f00f00f00full;
+    v = (v | v << 4) & 0x10c30c30c30c30c3ull;
+    v = (v | v << 2) & 0x1249249249249249ull;
+    return v;
+}
+
+// ---------------------------------------------------------------- blocking
+
+struct HostBlocks {
+    std::vector<int32_t> order;      // internal -> caller element id
+    std::vector<int32_t> estart, nstart;
+    std::vector<uint32_t> bnode;
+    std::vector<uint16_t> lconn;
+    std::vector<int32_t> shared_nodes;
+    std::vector<std::vector<int32_t>> colours;
+    int max_nodes = 0, max_elems = 0;
+};
+
+static void build_blocks(int nen, int64_t nn, int64_t ne, const double *X, const int32_t *conn,
+                         int be, int bn, bool colour, HostBlocks &hb)
+{
+    // Morton order of element centroids
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int64_t i = 0; i < nn; ++i)
+        for (int k = 0; k < 3; ++k) {
+            lo[k] = std::min(lo[k], X[3 * i + k]);
+            hi[k] = std::max(hi[k], X[3 * i + k]);
+        }
+    double ext = std::max({hi[0] - lo[0], hi[1] - lo[1], hi[2] - lo[2], 1e-300});
+    std::vector<std::pair<uint64_t, int32_t>> keys((size_t)ne);
+    for (int64_t e = 0; e < ne; ++e) {
+        double c[3] = {0, 0, 0};
+        for (int a = 0; a < nen; ++a)
+            for (int k = 0; k < 3; ++k) c[k] += X[3 * (int64_t)conn[e * nen + a] + k];
+        uint64_t key = 0;
+        for (int k = 0; k < 3; ++k) {
+            double t = (c[k] / nen - lo[k]) / ext;
+            uint64_t q = (uint64_t)std::min(std::max(t, 0.0) * 2097151.0, 2097151.0);
+            key |= spread3(q) << k;
+        }
+        keys[(size_t)e] = {key, (int32_t)e};
+    }
+    std::sort(keys.begin(), keys.end());
+    hb.order.resize((size_t)ne);
+    for (int64_t e = 0; e < ne; ++e) hb.order[(size_t)e] = keys[(size_t)e].second;
+
+    // greedy cut: at most `be` elements and `bn` distinct nodes per block
+    std::vector<int32_t> mark((size_t)nn, -1);
+    std::vector<int32_t> cut{0};
+    int cur_e = 0, cur_n = 0, blk = 0;
+    for (int64_t k = 0; k < ne; ++k) {
+        const int32_t *ce = conn + (int64_t)hb.order[(size_t)k] * nen;
+        int fresh = 0;
+        for (int a = 0; a < nen; ++a) {
+            bool dup = false;
+            for (int b = 0; b < a; ++b) dup |= ce[b] == ce[a];
+            if (!dup && mark[ce[a]] != blk) ++fresh;
+        }
+        if (cur_e > 0 && (cur_e + 1 > be || cur_n + fresh > bn)) {
+            cut.push_back((int32_t)k);
+            ++blk;
+            cur_e = 0;
+            cur_n = 0;
+            fresh = 0;
+            for (int a = 0; a < nen; ++a) {
+                bool dup = false;
+                for (int b = 0; b < a; ++b) dup |= ce[b] == ce[a];
+                if (!dup) ++fresh;
+            }
+        }
+        for (int a = 0; a < nen; ++a) mark[ce[a]] = blk;
+        cur_e += 1;
+        cur_n += fresh;
+    }
+    cut.push_back((int32_t)ne);
+    const int nb = (int)cut.size() - 1;
+    hb.estart = cut;
+
+    // per-block sorted node lists and local connectivity
+    hb.nstart.assign(1, 0);
+    hb.lconn.resize((size_t)(ne * nen));
+    std::vector<int32_t> nodes;
+    std::vector<int32_t> nblocks((size_t)nn, 0);
+    std::vector<int32_t> local((size_t)nn, -1);
+    for (int b = 0; b < nb; ++b) {
+        nodes.clear();
+        for (int k = cut[b]; k < cut[b + 1]; ++k)
+            for (int a = 0; a < nen; ++a) nodes.push_back(conn[(int64_t)hb.order[k] * nen + a]);
+        std::sort(nodes.begin(), nodes.end());
+        nodes.erase(std::unique(nodes.begin(), nodes.end()), nodes.end());
+        for (size_t i = 0; i < nodes.size(); ++i) {
+            local[nodes[i]] = (int32_t)i;
+            hb.bnode.push_back((uint32_t)nodes[i]);
+            nblocks[nodes[i]] += 1;
+        }
+        for (int k = cut[b]; k < cut[b + 1]; ++k)
+            for (int a = 0; a < nen; ++a)
+                hb.lconn[(size_t)k * nen + a] = (uint16_t)local[conn[(int64_t)hb.order[k] * nen + a]];
+        hb.nstart.push_back((int32_t)hb.bnode.size());
+        hb.max_nodes = std::max(hb.max_nodes, (int)nodes.size());
+        hb.max_elems = std::max(hb.max_elems, cut[b + 1] - cut[b]);
+    }
+    for (size_t i = 0; i < hb.bnode.size(); ++i)
+        if (nblocks[hb.bnode[i]] > 1) hb.bnode[i] |= kShared;
+    for (int64_t g = 0; g < nn; ++g)
+        if (nblocks[(size_t)g] > 1) hb.shared_nodes.push_back((int32_t)g);
+
+    if (!colour) return;
+    // node -> blocks CSR over shared nodes
+    std::vector<int32_t> ptr((size_t)nn + 1, 0);
+    for (size_t i = 0; i < hb.bnode.size(); ++i)
+        if (hb.bnode[i] & kShared) ptr[(hb.bnode[i] & kGidMask) + 1] += 1;
+    for (int64_t g = 0; g < nn; ++g) ptr[(size_t)g + 1] += ptr[(size_t)g];
+    std::vector<int32_t> adj(ptr[(size_t)nn]);
+    std::vector<int32_t> fill(ptr.begin(), ptr.end() - 1);
+    for (int b = 0; b < nb; ++b)
+        for (int i = hb.nstart[b]; i < hb.nstart[b + 1]; ++i)
+            if (hb.bnode[i] & kShared) adj[fill[hb.bnode[i] & kGidMask]++] = b;
+    // greedy colouring of the block graph (blocks sharing a node conflict)
+    std::vector<int32_t> col((size_t)nb, -1);
+    std::vector<int32_t> seen;
+    int ncol = 0;
+    for (int b = 0; b < nb; ++b) {
+        seen.assign((size_t)ncol + 1, 0);
+        for (int i = hb.nstart[b]; i < hb.nstart[b + 1]; ++i) {
+            if (!(hb.bnode[i] & kShared)) continue;
+            const uint32_t g = hb.bnode[i] & kGidMask;
+            for (int j = ptr[g]; j < ptr[g + 1]; ++j)
+                if (col[adj[j]] >= 0) seen[col[adj[j]]] = 1;
+        }
+        int c = 0;
+        while (c < ncol && seen[c]) ++c;
+        col[b] = c;
+        ncol = std::max(ncol, c + 1);
+    }
+    hb.colours.assign((size_t)ncol, {});
+    for (int b = 0; b < nb; ++b) hb.colours[col[b]].push_back(b);
+    // the lowest-coloured block touching a shared node writes it first
+    for (int b = 0; b < nb; ++b)
+        for (int i = hb.nstart[b]; i < hb.nstart[b + 1]; ++i) {
+            if (!(hb.bnode[i] & kShared)) continue;
+            const uint32_t g = hb.bnode[i] & kGidMask;
+            bool first = true;
+            for (int j = ptr[g]; j < ptr[g + 1]; ++j) first &= col[adj[j]] >= col[b];
+            if (first) hb.bnode[i] |= kFirst;
+        }
+}
+
+}  // namespace efem
+
+using namespace efem;
+
+struct efem_ctx : Ctx {};
+
+// ------------------------------------------------------------------- C-ABI
+
+extern "C" {
+
+const char *efem_last_error(void) { return g_error.c_str(); }
+
+void efem_destroy(efem_ctx *ctx)
+{
+    if (!ctx) return;
+    DeviceGuard dg(ctx->device);
+    if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+    else (void)hipDeviceSynchronize();
+    mlp_release(*ctx);
+    for (void *p : ctx->owned) (void)hipFree(p);
+    delete ctx;
+}
+
+int efem_create(efem_ctx **out, int32_t elem, int64_t n_nodes, int64_t n_elems,
+                const double *coords, const int32_t *conn, const efem_options *opts, void *stream)
+{
+    if (!out || !coords || !conn) {
+        set_error("efem_create: null pointer");
+        return EFEM_ERR_INVALID;
+    }
+    *out = nullptr;
+    if (elem != EFEM_TET4 && elem != EFEM_HEX8) {
+        set_error("efem_create: unknown element type");
+        return EFEM_ERR_INVALID;
+    }
+    if (n_nodes < 1 || n_elems < 1 || n_nodes > (int64_t)kGidMask || n_elems > INT32_MAX / 8) {
+        set_error("efem_create: bad mesh sizes");
+        return EFEM_ERR_INVALID;
+    }
+    const int nen = elem == EFEM_TET4 ? 4 : 8;
+    for (int64_t k = 0; k < n_elems * nen; ++k)
+        if (conn[k] < 0 || conn[k] >= n_nodes) {
+            set_error("efem_create: connectivity entry out of range");
+            return EFEM_ERR_INVALID;
+        }
+    if (!reference_jacobians_positive(elem, nen, n_elems, coords, conn)) {
+        set_error("efem_create: reference element with det J <= 0");
+        return EFEM_ERR_INVERTED;
+    }
+    int be = elem == EFEM_TET4 ? 1024 : 256;
+    int bn = 512;
+    int scatter = EFEM_SCATTER_ATOMIC;
+    int threads = 256;
+    if (opts) {
+        if (opts->block_elems > 0) be = opts->block_elems;
+        if (opts->block_nodes > 0) bn = opts->block_nodes;
+        if (opts->scatter == EFEM_SCATTER_COLOR) scatter = EFEM_SCATTER_COLOR;
+        else if (opts->scatter != EFEM_SCATTER_ATOMIC) {
+            set_error("efem_create: unknown scatter mode");
+            return EFEM_ERR_INVALID;
+        }
+        if (opts->threads > 0) threads = opts->threads;
+    }
+    if (bn < nen || bn > 600 || be < 1 || threads < 64 || threads > 256 || threads % 64) {
+        set_error("efem_create: block_nodes must be in [n_en, 600], threads a multiple of 64 in [64, 256]");
+        return EFEM_ERR_INVALID;
+    }
+
+    auto *ctx = new (std::nothrow) efem_ctx();
+    if (!ctx) return EFEM_ERR_OOM;
+    ctx->elem = elem;
+    ctx->nen = nen;
+    ctx->nq = elem == EFEM_TET4 ? 1 : 8;
+    ctx->n_nodes = n_nodes;
+    ctx->n_elems = n_elems;
+    ctx->stream = (hipStream_t)stream;
+    ctx->scatter = scatter == EFEM_SCATTER_COLOR ? Scatter::Color : Scatter::Atomic;
+    ctx->threads = threads;
+    (void)hipGetDevice(&ctx->device);
+
+    HostBlocks hb;
+    build_blocks(nen, n_nodes, n_elems, coords, conn, be, bn, scatter == EFEM_SCATTER_COLOR, hb);
+    ctx->max_block_nodes = hb.max_nodes;
+    ctx->max_block_elems = hb.max_elems;
+
+    auto fail = [&](int rc) {
+        efem_destroy(ctx);
+        return rc;
+    };
+    int rc;
+    BlockMesh &m = ctx->m;
+    m.n_blocks = (int32_t)hb.estart.size() - 1;
+    m.nen = nen;
+    std::vector<double> Xh(coords, coords + 3 * n_nodes);
+    std::vector<float> Xfh(Xh.begin(), Xh.end());
+    int32_t *p_es, *p_ns, *p_eo;
+    uint32_t *p_bn;
+    uint16_t *p_lc;
+    double *p_X;
+    float *p_Xf;
+    if ((rc = upload(*ctx, &p_es, hb.estart)) || (rc = upload(*ctx, &p_ns, hb.nstart))
+        || (rc = upload(*ctx, &p_bn, hb.bnode)) || (rc = upload(*ctx, &p_lc, hb.lconn))
+        || (rc = upload(*ctx, &p_eo, hb.order)) || (rc = upload(*ctx, &p_X, Xh))
+        || (rc = upload(*ctx, &p_Xf, Xfh)) || (rc = upload(*ctx, &ctx->shared_nodes, hb.shared_nodes)))
+        return fail(rc);
+    m.estart = p_es;
+    m.nstart = p_ns;
+    m.bnode = p_bn;
+    m.lconn = p_lc;
+    m.eorig = p_eo;
+    m.X = p_X;
+    m.Xf = p_Xf;
+    ctx->n_shared = (int64_t)hb.shared_nodes.size();
+
+    // default material mu = 1, lam = 1.5
+    std::vector<double> ones((size_t)n_elems, 1.0), lam15((size_t)n_elems, 1.5);
+    if ((rc = upload(*ctx, &ctx->mu, ones)) || (rc = upload(*ctx, &ctx->lam, lam15))) return fail(rc);
+    m.mu = ctx->mu;
+    m.lam = ctx->lam;
+    if ((rc = dalloc(*ctx, &ctx->flags, 1)) || (rc = dalloc(*ctx, &ctx->partials, m.n_blocks))
+        || (rc = dalloc(*ctx, &ctx->counter, 1)))
+        return fail(rc);
+    if (hipMemset(ctx->flags, 0, sizeof(int32_t)) != hipSuccess
+        || hipMemset(ctx->counter, 0, sizeof(uint32_t)) != hipSuccess)
+        return fail(hip_fail(hipGetLastError(), "hipMemset"));
+    m.flags = ctx->flags;
+    m.nmask = nullptr;
+
+    if (scatter == EFEM_SCATTER_COLOR) {
+        for (auto &lst : hb.colours) {
+            int32_t *p;
+            if ((rc = upload(*ctx, &p, lst))) return fail(rc);
+            ctx->passes.push_back({p, (int32_t)lst.size()});
+        }
+    } else {
+        ctx->passes.push_back({nullptr, m.n_blocks});
+    }
+    *out = ctx;
+    return EFEM_OK;
+}
+
+int efem_set_stream(efem_ctx *ctx, void *stream)
+{
+    if (!ctx) return EFEM_ERR_INVALID;
+    ctx->stream = (hipStream_t)stream;
+    return EFEM_OK;
+}
+
+int efem_set_material(efem_ctx *ctx, const double *mu, const double *lam)
+{
+    if (!ctx || !mu || !lam) {
+        set_error("efem_set_material: null pointer");
+        return EFEM_ERR_INVALID;
+    }
+    DeviceGuard dg(ctx->device);
+    HIP_TRY(launch_permute_elems(*ctx, mu, ctx->mu));
+    HIP_TRY(launch_permute_elems(*ctx, lam, ctx->lam));
+    return EFEM_OK;
+}
+
+int efem_set_dirichlet(efem_ctx *ctx, const uint8_t *mask)
+{
+    if (!ctx) return EFEM_ERR_INVALID;
+    DeviceGuard dg(ctx->device);
+    if (!mask) {
+        ctx->m.nmask = nullptr;
+        return EFEM_OK;
+    }
+    if (!ctx->nmask) {
+        int rc = dalloc(*ctx, &ctx->nmask, (size_t)ctx->n_nodes);
+        if (rc) return rc;
+    }
+    HIP_TRY(launch_build_nmask(*ctx, mask, ctx->nmask));
+    ctx->m.nmask = ctx->nmask;
+    return EFEM_OK;
+}
+
+#define CHECK_ARGS(cond, name)                         \
+    do {                                               \
+        if (!ctx || !(cond)) {                         \
+            set_error(name ": null pointer");          \
+            return EFEM_ERR_INVALID;                   \
+        }                                              \
+    } while (0)
+
+int efem_energy(efem_ctx *ctx, const double *u, double *psi)
+{
+    CHECK_ARGS(u && psi, "efem_energy");
+    DeviceGuard dg(ctx->device);
+    HIP_TRY(launch_energy(*ctx, u, psi));
+    return EFEM_OK;
+}
+
+int efem_residual(efem_ctx *ctx, const double *u, double *r)
+{
+    CHECK_ARGS(u && r, "efem_residual");
+    DeviceGuard dg(ctx->device);
+    HIP_TRY(launch_residual(*ctx, u, r));
+    return EFEM_OK;
+}
+
+int efem_linearize(efem_ctx *ctx, const double *u, int32_t prec)
+{
+    CHECK_ARGS(u, "efem_linearize");
+    if (prec != EFEM_F64 && prec != EFEM_F32) {
+        set_error("efem_linearize: unknown precision");
+        return EFEM_ERR_INVALID;
+    }
+    DeviceGuard dg(ctx->device);
+    const size_t n = 3 * (size_t)ctx->n_nodes;
+    int rc;
+    if (prec == EFEM_F64) {
+        if (!ctx->xlin && (rc = dalloc(*ctx, &ctx->xlin, n))) return rc;
+        HIP_TRY(launch_add_x_u(*ctx, u, ctx->xlin));
+    } else {
+        if (!ctx->ulin && (rc = dalloc(*ctx, &ctx->ulin, n))) return rc;
+        HIP_TRY(launch_cast_f32(u, ctx->ulin, (int64_t)n, ctx->stream));
+    }
+    ctx->lin_prec = prec;
+    return EFEM_OK;
+}
+
+static int hvp_impl(efem_ctx *ctx, const void *v, void *y, bool acc, const char *name)
+{
+    if (!ctx || !v || !y) {
+        set_error(std::string(name) + ": null pointer");
+        return EFEM_ERR_INVALID;
+    }
+    if (v == y) {
+        set_error(std::string(name) + ": y aliases v");
+        return EFEM_ERR_INVALID;
+    }
+    if (ctx->lin_prec < 0) {
+        set_error(std::string(name) + ": call efem_linearize first");
+        return EFEM_ERR_STATE;
+    }
+    DeviceGuard dg(ctx->device);
+    if (ctx->lin_prec == EFEM_F64)
+        HIP_TRY(launch_hvp_f64(*ctx, ctx->xlin, (const double *)v, (double *)y, nullptr, acc));
+    else
+        HIP_TRY(launch_hvp_f32(*ctx, ctx->ulin, (const float *)v, (float *)y, nullptr, acc));
+    return EFEM_OK;
+}
+
+int efem_hvp(efem_ctx *ctx, const void *v, void *y) { return hvp_impl(ctx, v, y, false, "efem_hvp"); }
+
+int efem_hvp_acc(efem_ctx *ctx, const void *v, void *y)
+{
+    return hvp_impl(ctx, v, y, true, "efem_hvp_acc");
+}
+
+int efem_jacobi_diag(efem_ctx *ctx, const double *u, double *d)
+{
+    CHECK_ARGS(u && d, "efem_jacobi_diag");
+    DeviceGuard dg(ctx->device);
+    HIP_TRY(launch_diag(*ctx, u, d));
+    return EFEM_OK;
+}
+
+int efem_grad_material(efem_ctx *ctx, const double *u, double *dmu, double *dlam)
+{
+    CHECK_ARGS(u && dmu && dlam, "efem_grad_material");
+    DeviceGuard dg(ctx->device);
+    HIP_TRY(launch_grad_material(*ctx, u, dmu, dlam));
+    return EFEM_OK;
+}
+
+int efem_residual_vjp_material(efem_ctx *ctx, const double *u, const double *w, double *dmu,
+                               double *dlam)
+{
+    CHECK_ARGS(u && w && dmu && dlam, "efem_residual_vjp_material");
+    DeviceGuard dg(ctx->device);
+    HIP_TRY(launch_vjp_material(*ctx, u, w, dmu, dlam));
+    return EFEM_OK;
+}
+
+int efem_grad_coords(efem_ctx *ctx, const double *u, double *dX)
+{
+    CHECK_ARGS(u && dX, "efem_grad_coords");
+    DeviceGuard dg(ctx->device);
+    HIP_TRY(launch_grad_coords(*ctx, u, dX));
+    return EFEM_OK;
+}
+
+int efem_status(efem_ctx *ctx, int32_t *flags)
+{
+    CHECK_ARGS(flags, "efem_status");
+    DeviceGuard dg(ctx->device);
+    HIP_TRY(hipMemcpyAsync(flags, ctx->flags, sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(hipMemsetAsync(ctx->flags, 0, sizeof(int32_t), ctx->stream));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    return EFEM_OK;
+}
+
+int efem_get_info(efem_ctx *ctx, efem_info *info)
+{
+    CHECK_ARGS(info, "efem_get_info");
+    info->n_blocks = ctx->m.n_blocks;
+    info->n_colours = ctx->scatter == Scatter::Color ? (int32_t)ctx->passes.size() : 0;
+    info->max_block_nodes = ctx->max_block_nodes;
+    info->max_block_elems = ctx->max_block_elems;
+    info->n_shared_nodes = ctx->n_shared;
+    info->n_block_nodes = 0;
+    // total block-node entries = nstart[n_blocks]
+    int32_t tot = 0;
+    HIP_TRY(hipMemcpy(&tot, ctx->m.nstart + ctx->m.n_blocks, sizeof(int32_t), hipMemcpyDeviceToHost));
+    info->n_block_nodes = tot;
+    return EFEM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,105 @@
+// Internal declarations shared by the C-ABI host code and the gfx950 kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "efem.h"
+
+namespace efem {
+
+// bnode entries: global node id in the low 30 bits, flags above.
+constexpr uint32_t kGidMask = 0x3fffffffu;
+constexpr uint32_t kShared = 0x80000000u;   // node touched by more than one block
+constexpr uint32_t kFirst = 0x40000000u;    // colour scatter: this block writes first
+
+// Device view of the blocked mesh, passed by value to every element kernel.
+struct BlockMesh {
+    int32_t n_blocks;
+    int32_t nen;
+    const int32_t *estart;    // [n_blocks+1] internal element ranges
+    const int32_t *nstart;    // [n_blocks+1] ranges into bnode
+    const uint32_t *bnode;    // block-local node -> global id | flags
+    const uint16_t *lconn;    // [n_elems*nen] block-local node indices
+    const int32_t *eorig;     // [n_elems] internal -> caller element id
+    const double *X;          // [n_nodes*3]
+    const float *Xf;          // [n_nodes*3]
+    const double *mu, *lam;   // [n_elems] internal order
+    const uint8_t *nmask;     // [n_nodes] bit c = component c prescribed, or null
+    int32_t *flags;           // bit 0: det F <= 0 met
+};
+
+enum class Scatter { Atomic = 0, Color = 1 };
+
+// One launch over a set of blocks: all blocks (list == null) or one colour.
+struct Pass {
+    const int32_t *list;
+    int32_t count;
+};
+
+struct Ctx;
+
+// ---- kernel launchers (kernels_*.hip) -------------------------------------
+// All return hipError_t of the launch.  T = double or float.
+hipError_t launch_energy(const Ctx &c, const double *u, double *psi);
+hipError_t launch_residual(const Ctx &c, const double *u, double *r);
+// acc = false: y = K v (shared nodes zeroed by a pre-pass); acc = true: y += K v, one launch
+hipError_t launch_hvp_f64(const Ctx &c, const double *xlin, const double *v, double *y,
+                          const int32_t *skip, bool acc);
+hipError_t launch_hvp_f32(const Ctx &c, const float *ulin, const float *v, float *y,
+                          const int32_t *skip, bool acc);
+hipError_t launch_diag(const Ctx &c, const double *u, double *d);
+hipError_t launch_grad_material(const Ctx &c, const double *u, double *dmu, double *dlam);
+hipError_t launch_vjp_material(const Ctx &c, const double *u, const double *w, double *dmu,
+                               double *dlam);
+hipError_t launch_grad_coords(const Ctx &c, const double *u, double *g);
+
+// small utility kernels (kernels_util.hip)
+hipError_t launch_permute_elems(const Ctx &c, const double *src, double *dst);
+hipError_t launch_build_nmask(const Ctx &c, const uint8_t *dofmask, uint8_t *nmask);
+hipError_t launch_add_x_u(const Ctx &c, const double *u, double *x);
+hipError_t launch_cast_f32(const double *src, float *dst, int64_t n, hipStream_t s);
+
+// ---- context ---------------------------------------------------------------
+struct Ctx {
+    int elem = 0, nen = 4, nq = 1;
+    int64_t n_nodes = 0, n_elems = 0;
+    int device = 0;
+    hipStream_t stream = nullptr;
+    Scatter scatter = Scatter::Atomic;
+    int threads = 256;
+    int max_block_nodes = 0;        // max nodes over blocks (LDS sizing)
+    int max_block_elems = 0;
+
+    // device buffers owned by the context
+    BlockMesh m{};
+    std::vector<void *> owned;      // every hipMalloc of the context
+    int32_t *shared_nodes = nullptr;    // nodes touched by several blocks
+    int64_t n_shared = 0;
+    std::vector<Pass> passes;           // colour lists (Color) or one pass (Atomic)
+    double *partials = nullptr;         // [n_blocks] per-block energy partials
+    uint32_t *counter = nullptr;        // last-block-done ticket
+    double *mu = nullptr, *lam = nullptr;
+    uint8_t *nmask = nullptr;
+    int32_t *flags = nullptr;
+
+    // linearization point
+    int lin_prec = -1;
+    double *xlin = nullptr;   // X + u  (FP64 tangent)
+    float *ulin = nullptr;    // u in FP32 (FP32 tangent)
+
+    // learned preconditioner state (see precond.cpp)
+    void *mlp = nullptr;
+};
+
+// learned preconditioner resources of a context (precond.cpp)
+void mlp_release(Ctx &c);
+
+// error helpers (api.cpp)
+void set_error(const std::string &msg);
+int hip_fail(hipError_t e, const char *what);
+
+}  // namespace efem

@@ -1,0 +1,947 @@
+// Element kernels of the energy-based FEM hot path for gfx950 (MI355X).
+//
+// Every operator is one pass over element blocks, one workgroup per block:
+//   1. stage the block's distinct nodes (coordinates, state, direction) from
+//      HBM into LDS, once per block (the gather of Alg. 1);
+//   2. one thread per element: reference-space gradients, quadrature-point
+//      math, element forces accumulated into LDS with LDS atomics;
+//   3. write the block's nodal sums out: nodes owned by this block alone with
+//      plain stores, nodes shared with other blocks with global atomics (or,
+//      in the colour scatter, with a plain read-modify-write per colour).
+// The energy reduces per block and the last block to finish sums the block
+// partials in block order, so the energy is bitwise deterministic.
+//
+// Quadrature-point math (Eq. 2 and its exact derivatives, Eqs. 1 and 3) is
+// written in terms of the reference Jacobian Jx = dX/dxi, the deformed one
+// Jd = dx/dxi and the direction's dJ = dv/dxi, so that no 81-entry tangent is
+// ever formed.  With Ae = adj(Jx), De = det Jx, Ad = adj(Jd), Dd = det Jd,
+// J = Dd/De, c1 = mu - lam ln J, S = Ae Ae^T, the element forces are
+// f_a = Q dN_a/dxi with, for the tangent action,
+//   Q = w [ mu/De dJ S + lam De tr(Ad dJ)/Dd^2 Ad^T + c1 De/Dd^2 (Ad dJ Ad)^T ],
+// which is w det Jx dP Jx^-T with dP = mu dF + lam tr(F^-1 dF) F^-T
+// + c1 F^-T dF^T F^-T, F = Jd Jx^-1, dF = dJ Jx^-1.
+#include "efem_internal.h"
+
+namespace efem {
+
+// ------------------------------------------------------------------ helpers
+
+// Workgroup i runs on XCD i % 8.  Give each XCD a contiguous range of
+// (Morton-ordered) blocks so that blocks sharing nodes share an L2.
+__device__ __forceinline__ int xcd_remap(int bid, int n)
+{
+    constexpr int NX = 8;
+    const int q = n / NX, r = n % NX;
+    const int x = bid % NX, k = bid / NX;
+    return x * q + min(x, r) + k;
+}
+
+template <class T>
+__device__ __forceinline__ T adj_det(const T m[9], T a[9])
+{
+    a[0] = m[4] * m[8] - m[5] * m[7];
+    a[1] = m[2] * m[7] - m[1] * m[8];
+    a[2] = m[1] * m[5] - m[2] * m[4];
+    a[3] = m[5] * m[6] - m[3] * m[8];
+    a[4] = m[0] * m[8] - m[2] * m[6];
+    a[5] = m[2] * m[3] - m[0] * m[5];
+    a[6] = m[3] * m[7] - m[4] * m[6];
+    a[7] = m[1] * m[6] - m[0] * m[7];
+    a[8] = m[0] * m[4] - m[1] * m[3];
+    return m[0] * a[0] + m[1] * a[3] + m[2] * a[6];
+}
+
+template <class T> __device__ __forceinline__ T rcp(T x) { return T(1) / x; }
+
+__device__ __forceinline__ double log_(double x) { return log(x); }
+__device__ __forceinline__ float log_(float x) { return __logf(x); }
+
+__device__ __forceinline__ void flag_inverted(int32_t *flags) { atomicOr(flags, 1); }
+
+// ------------------------------------------------------------ element types
+
+// Tet4: N0 = 1 - xi - eta - zeta, N_a = xi_a (a = 1..3); one point, w = 1/6.
+struct Tet4 {
+    static constexpr int NEN = 4, NQ = 1;
+    template <class T> __device__ static constexpr T weight() { return T(1.0 / 6.0); }
+    // G[i*3+J] = d f_i / d xi_J at point q
+    template <class T>
+    __device__ static __forceinline__ void grad(const T f[NEN][3], int, T G[9])
+    {
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int J = 0; J < 3; ++J) G[i * 3 + J] = f[J + 1][i] - f[0][i];
+    }
+    template <class T>
+    __device__ static __forceinline__ void add_forces(const T Q[9], int, T out[NEN][3])
+    {
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            out[1][i] += Q[i * 3 + 0];
+            out[2][i] += Q[i * 3 + 1];
+            out[3][i] += Q[i * 3 + 2];
+            out[0][i] -= Q[i * 3 + 0] + Q[i * 3 + 1] + Q[i * 3 + 2];
+        }
+    }
+    template <class T> __device__ static __forceinline__ T dN(int, int a, int J)
+    {
+        return a == 0 ? T(-1) : (a - 1 == J ? T(1) : T(0));
+    }
+};
+
+// Hex8: trilinear on [-1,1]^3, nodes (0,0,0),(1,0,0),(1,1,0),(0,1,0) then z=1;
+// 2x2x2 Gauss points at +-1/sqrt(3), point q = qx + 2 qy + 4 qz, w = 1.
+__device__ constexpr int kHexS[8][3] = {{-1, -1, -1}, {1, -1, -1}, {1, 1, -1}, {-1, 1, -1},
+                                        {-1, -1, 1},  {1, -1, 1},  {1, 1, 1},  {-1, 1, 1}};
+struct Hex8 {
+    static constexpr int NEN = 8, NQ = 8;
+    template <class T> __device__ static constexpr T weight() { return T(1); }
+    template <class T> __device__ static __forceinline__ T dN(int q, int a, int J)
+    {
+        const T g = T(0.57735026918962576451);
+        const T p0 = (q & 1) ? g : -g, p1 = (q & 2) ? g : -g, p2 = (q & 4) ? g : -g;
+        const T f0 = T(1) + T(kHexS[a][0]) * p0;
+        const T f1 = T(1) + T(kHexS[a][1]) * p1;
+        const T f2 = T(1) + T(kHexS[a][2]) * p2;
+        const T s = T(0.125) * T(kHexS[a][J]);
+        return J == 0 ? s * f1 * f2 : (J == 1 ? s * f0 * f2 : s * f0 * f1);
+    }
+    template <class T>
+    __device__ static __forceinline__ void grad(const T f[NEN][3], int q, T G[9])
+    {
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int J = 0; J < 3; ++J) {
+                T t = T(0);
+#pragma unroll
+                for (int a = 0; a < NEN; ++a) t += f[a][i] * dN<T>(q, a, J);
+                G[i * 3 + J] = t;
+            }
+    }
+    template <class T>
+    __device__ static __forceinline__ void add_forces(const T Q[9], int q, T out[NEN][3])
+    {
+#pragma unroll
+        for (int a = 0; a < NEN; ++a)
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+                out[a][i] += Q[i * 3 + 0] * dN<T>(q, a, 0) + Q[i * 3 + 1] * dN<T>(q, a, 1)
+                           + Q[i * 3 + 2] * dN<T>(q, a, 2);
+    }
+};
+
+// ------------------------------------------------------ quadrature-point math
+
+// Tangent action at one point: Q = w det Jx dP Jx^-T.  Returns false if det Jd <= 0.
+template <class T>
+__device__ __forceinline__ bool qp_hvp(T w, const T Jx[9], const T Jd[9], const T dJ[9], T mu,
+                                       T lam, T Q[9])
+{
+    T Ae[9], Ad[9];
+    const T De = adj_det(Jx, Ae);
+    const T Dd = adj_det(Jd, Ad);
+    // S = Ae Ae^T (symmetric)
+    const T S00 = Ae[0] * Ae[0] + Ae[1] * Ae[1] + Ae[2] * Ae[2];
+    const T S01 = Ae[0] * Ae[3] + Ae[1] * Ae[4] + Ae[2] * Ae[5];
+    const T S02 = Ae[0] * Ae[6] + Ae[1] * Ae[7] + Ae[2] * Ae[8];
+    const T S11 = Ae[3] * Ae[3] + Ae[4] * Ae[4] + Ae[5] * Ae[5];
+    const T S12 = Ae[3] * Ae[6] + Ae[4] * Ae[7] + Ae[5] * Ae[8];
+    const T S22 = Ae[6] * Ae[6] + Ae[7] * Ae[7] + Ae[8] * Ae[8];
+    const T rDe = rcp(De), rDd = rcp(Dd);
+    const T a = w * mu * rDe;
+    const T s2 = w * De * rDd * rDd;
+    const T lnJ = log_(Dd * rDe);
+    const T c1 = mu - lam * lnJ;
+    // W = Ad dJ
+    T W[9];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+            W[i * 3 + j] = Ad[i * 3 + 0] * dJ[0 * 3 + j] + Ad[i * 3 + 1] * dJ[1 * 3 + j]
+                         + Ad[i * 3 + 2] * dJ[2 * 3 + j];
+    const T tr = W[0] + W[4] + W[8];
+    const T b = lam * tr * s2;
+    const T c = c1 * s2;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        const T d0 = dJ[i * 3 + 0], d1 = dJ[i * 3 + 1], d2 = dJ[i * 3 + 2];
+        const T dS0 = d0 * S00 + d1 * S01 + d2 * S02;
+        const T dS1 = d0 * S01 + d1 * S11 + d2 * S12;
+        const T dS2 = d0 * S02 + d1 * S12 + d2 * S22;
+        const T dS[3] = {dS0, dS1, dS2};
+#pragma unroll
+        for (int J = 0; J < 3; ++J) {
+            // M[J][i] = (W Ad)[J][i]
+            const T Mji = W[J * 3 + 0] * Ad[0 * 3 + i] + W[J * 3 + 1] * Ad[1 * 3 + i]
+                        + W[J * 3 + 2] * Ad[2 * 3 + i];
+            Q[i * 3 + J] = a * dS[J] + b * Ad[J * 3 + i] + c * Mji;
+        }
+    }
+    return Dd > T(0);
+}
+
+// Residual at one point: Q = w det Jx P Jx^-T = w [mu/De Jd S + (lam lnJ - mu) De/Dd Ad^T].
+template <class T>
+__device__ __forceinline__ bool qp_residual(T w, const T Jx[9], const T Jd[9], T mu, T lam, T Q[9])
+{
+    T Ae[9], Ad[9];
+    const T De = adj_det(Jx, Ae);
+    const T Dd = adj_det(Jd, Ad);
+    T S[9];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+            S[i * 3 + j] = Ae[i * 3 + 0] * Ae[j * 3 + 0] + Ae[i * 3 + 1] * Ae[j * 3 + 1]
+                         + Ae[i * 3 + 2] * Ae[j * 3 + 2];
+    const T rDe = rcp(De), rDd = rcp(Dd);
+    const T lnJ = log_(Dd * rDe);
+    const T a = w * mu * rDe;
+    const T c = w * (lam * lnJ - mu) * De * rDd;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int J = 0; J < 3; ++J)
+            Q[i * 3 + J] = a * (Jd[i * 3 + 0] * S[0 * 3 + J] + Jd[i * 3 + 1] * S[1 * 3 + J]
+                                + Jd[i * 3 + 2] * S[2 * 3 + J])
+                         + c * Ad[J * 3 + i];
+    return Dd > T(0);
+}
+
+// Kinematics of the displacement gradient H = Hxi Jx^-1 without cancellation:
+// I1 - 3 = 2 tr H + H:H, J - 1 = tr H + ((tr H)^2 - tr H^2)/2 + det H.
+struct Kin {
+    double H[9], wDe, I1m3, Jm1;
+};
+
+__device__ __forceinline__ void kinematics(double w, const double Jx[9], const double Hxi[9], Kin &k)
+{
+    double Ae[9];
+    const double De = adj_det(Jx, Ae);
+    const double rDe = 1.0 / De;
+    k.wDe = w * De;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int L = 0; L < 3; ++L)
+            k.H[i * 3 + L] = (Hxi[i * 3 + 0] * Ae[0 * 3 + L] + Hxi[i * 3 + 1] * Ae[1 * 3 + L]
+                              + Hxi[i * 3 + 2] * Ae[2 * 3 + L]) * rDe;
+    const double *H = k.H;
+    const double trH = H[0] + H[4] + H[8];
+    double HH = 0, trH2 = 0;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            HH += H[i * 3 + j] * H[i * 3 + j];
+            trH2 += H[i * 3 + j] * H[j * 3 + i];
+        }
+    double tmp[9];
+    const double detH = adj_det(H, tmp);
+    k.I1m3 = 2.0 * trH + HH;
+    k.Jm1 = trH + 0.5 * (trH * trH - trH2) + detH;
+}
+
+// ------------------------------------------------------------- LDS staging
+
+// Node record of the FP64 tangent action: X, x = X + u, v (80 B, 16-B aligned).
+struct alignas(16) NodeH64 {
+    double X[3], x[3], v[3], pad;
+};
+// FP32 tangent action: X, u, v.
+struct alignas(16) NodeH32 {
+    float X[3], u[3], v[3], pad[3];
+};
+// X and u (energy, residual, diagonal, adjoints).
+struct alignas(16) NodeXU {
+    double X[3], u[3];
+};
+// X, u and a second nodal field w (residual VJP).
+struct alignas(16) NodeXUW {
+    double X[3], u[3], w[3], pad;
+};
+
+template <class T>
+__device__ __forceinline__ void load3(const T *__restrict__ p, int64_t g, T out[3])
+{
+    out[0] = p[3 * g + 0];
+    out[1] = p[3 * g + 1];
+    out[2] = p[3 * g + 2];
+}
+
+__device__ __forceinline__ bool comp_fixed(const uint8_t *nmask, int64_t g, int c)
+{
+    return nmask && ((nmask[g] >> c) & 1);
+}
+
+// Write the block's nodal sums acc[l*3+c] out; prescribed components get `fixed_val`.
+template <bool ACC, class T>
+__device__ __forceinline__ void write_out(const BlockMesh &m, const uint32_t *bnode, int nn,
+                                          const T *acc, T *__restrict__ y, Scatter mode,
+                                          bool use_mask, T fixed_val)
+{
+    for (int l = threadIdx.x; l < nn; l += blockDim.x) {
+        const uint32_t ent = bnode[l];
+        const int64_t g = ent & kGidMask;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const bool fixed = use_mask && comp_fixed(m.nmask, g, c);
+            T val = acc[l * 3 + c];
+            T *dst = &y[3 * g + c];
+            if (ACC) {
+                // y += K v: plain read-modify-write where no other block writes
+                if (fixed) *dst = fixed_val;
+                else if (!(ent & kShared) || mode == Scatter::Color) *dst += val;
+                else unsafeAtomicAdd(dst, val);
+            } else if (!(ent & kShared)) {
+                *dst = fixed ? fixed_val : val;
+            } else if (mode == Scatter::Atomic) {
+                if (!fixed) unsafeAtomicAdd(dst, val);
+                // prescribed entries were set by the pre-pass
+            } else {
+                if (ent & kFirst) *dst = fixed ? fixed_val : val;
+                else if (!fixed) *dst += val;
+            }
+        }
+    }
+}
+
+// --------------------------------------------------------------- operations
+
+// Every op provides: Node (LDS record), stage(), element<Elem>(), and whether
+// it accumulates nodal vectors.
+
+template <class T> struct HvpOp;
+
+template <> struct HvpOp<double> {
+    using Node = NodeH64;
+    const double *X, *xlin, *v;
+    double *y;
+    __device__ void stage(const BlockMesh &m, Node &n, int64_t g) const
+    {
+        load3(X, g, n.X);
+        load3(xlin, g, n.x);
+        load3(v, g, n.v);
+        if (m.nmask) {
+            const uint8_t b = m.nmask[g];
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+                if ((b >> c) & 1) n.v[c] = 0.0;
+        }
+    }
+    template <class E>
+    __device__ bool element(const Node *sn, const uint16_t *lc, double mu, double lam,
+                            double f[E::NEN][3]) const
+    {
+        double Xe[E::NEN][3], xe[E::NEN][3], ve[E::NEN][3];
+#pragma unroll
+        for (int a = 0; a < E::NEN; ++a) {
+            const Node &n = sn[lc[a]];
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                Xe[a][i] = n.X[i];
+                xe[a][i] = n.x[i];
+                ve[a][i] = n.v[i];
+            }
+        }
+        bool ok = true;
+#pragma unroll
+        for (int q = 0; q < E::NQ; ++q) {
+            double Jx[9], Jd[9], dJ[9], Q[9];
+            E::grad(Xe, q, Jx);
+            E::grad(xe, q, Jd);
+            E::grad(ve, q, dJ);
+            ok &= qp_hvp(E::template weight<double>(), Jx, Jd, dJ, mu, lam, Q);
+            E::add_forces(Q, q, f);
+        }
+        return ok;
+    }
+};
+
+template <> struct HvpOp<float> {
+    using Node = NodeH32;
+    const float *Xf, *ulin, *v;
+    float *y;
+    __device__ void stage(const BlockMesh &m, Node &n, int64_t g) const
+    {
+        load3(Xf, g, n.X);
+        load3(ulin, g, n.u);
+        load3(v, g, n.v);
+        if (m.nmask) {
+            const uint8_t b = m.nmask[g];
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+                if ((b >> c) & 1) n.v[c] = 0.0f;
+        }
+    }
+    template <class E>
+    __device__ bool element(const Node *sn, const uint16_t *lc, float mu, float lam,
+                            float f[E::NEN][3]) const
+    {
+        float Xe[E::NEN][3], ue[E::NEN][3], ve[E::NEN][3];
+#pragma unroll
+        for (int a = 0; a < E::NEN; ++a) {
+            const Node &n = sn[lc[a]];
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                Xe[a][i] = n.X[i];
+                ue[a][i] = n.u[i];
+                ve[a][i] = n.v[i];
+            }
+        }
+        bool ok = true;
+#pragma unroll
+        for (int q = 0; q < E::NQ; ++q) {
+            float Jx[9], Jd[9], dJ[9], Q[9];
+            E::grad(Xe, q, Jx);
+            E::grad(ue, q, Jd);
+#pragma unroll
+            for (int k = 0; k < 9; ++k) Jd[k] += Jx[k];
+            E::grad(ve, q, dJ);
+            ok &= qp_hvp(E::template weight<float>(), Jx, Jd, dJ, mu, lam, Q);
+            E::add_forces(Q, q, f);
+        }
+        return ok;
+    }
+};
+
+template <class E>
+__device__ __forceinline__ void gather_xu(const NodeXU *sn, const uint16_t *lc, double Xe[E::NEN][3],
+                                          double ue[E::NEN][3])
+{
+#pragma unroll
+    for (int a = 0; a < E::NEN; ++a) {
+        const NodeXU &n = sn[lc[a]];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            Xe[a][i] = n.X[i];
+            ue[a][i] = n.u[i];
+        }
+    }
+}
+
+struct XUStage {
+    const double *X, *u;
+    __device__ void stage(const BlockMesh &, NodeXU &n, int64_t g) const
+    {
+        load3(X, g, n.X);
+        load3(u, g, n.u);
+    }
+};
+
+struct ResidualOp : XUStage {
+    using Node = NodeXU;
+    template <class E>
+    __device__ bool element(const Node *sn, const uint16_t *lc, double mu, double lam,
+                            double f[E::NEN][3]) const
+    {
+        double Xe[E::NEN][3], ue[E::NEN][3];
+        gather_xu<E>(sn, lc, Xe, ue);
+        bool ok = true;
+#pragma unroll
+        for (int q = 0; q < E::NQ; ++q) {
+            double Jx[9], Jd[9], Q[9];
+            E::grad(Xe, q, Jx);
+            E::grad(ue, q, Jd);
+#pragma unroll
+            for (int k = 0; k < 9; ++k) Jd[k] += Jx[k];
+            ok &= qp_residual(E::template weight<double>(), Jx, Jd, mu, lam, Q);
+            E::add_forces(Q, q, f);
+        }
+        return ok;
+    }
+};
+
+// diag K: w [ mu/De n^T S n + (lam + c1) De/Dd^2 ((Ad^T n)_i)^2 ], n = dN_a/dxi
+struct DiagOp : XUStage {
+    using Node = NodeXU;
+    template <class E>
+    __device__ bool element(const Node *sn, const uint16_t *lc, double mu, double lam,
+                            double f[E::NEN][3]) const
+    {
+        double Xe[E::NEN][3], ue[E::NEN][3];
+        gather_xu<E>(sn, lc, Xe, ue);
+        bool ok = true;
+#pragma unroll
+        for (int q = 0; q < E::NQ; ++q) {
+            double Jx[9], Jd[9], Ae[9], Ad[9];
+            E::grad(Xe, q, Jx);
+            E::grad(ue, q, Jd);
+#pragma unroll
+            for (int k = 0; k < 9; ++k) Jd[k] += Jx[k];
+            const double De = adj_det(Jx, Ae);
+            const double Dd = adj_det(Jd, Ad);
+            ok &= Dd > 0.0;
+            const double w = E::template weight<double>();
+            const double lnJ = log(Dd / De);
+            const double a = w * mu / De;
+            const double b = w * (lam + mu - lam * lnJ) * De / (Dd * Dd);
+#pragma unroll
+            for (int n = 0; n < E::NEN; ++n) {
+                const double g0 = E::template dN<double>(q, n, 0);
+                const double g1 = E::template dN<double>(q, n, 1);
+                const double g2 = E::template dN<double>(q, n, 2);
+                // Ae^T n, |.|^2 = n^T S n
+                const double t0 = Ae[0] * g0 + Ae[3] * g1 + Ae[6] * g2;
+                const double t1 = Ae[1] * g0 + Ae[4] * g1 + Ae[7] * g2;
+                const double t2 = Ae[2] * g0 + Ae[5] * g1 + Ae[8] * g2;
+                const double nSn = t0 * t0 + t1 * t1 + t2 * t2;
+#pragma unroll
+                for (int i = 0; i < 3; ++i) {
+                    const double k = Ad[0 * 3 + i] * g0 + Ad[1 * 3 + i] * g1 + Ad[2 * 3 + i] * g2;
+                    f[n][i] += a * nSn + b * k * k;
+                }
+            }
+        }
+        return ok;
+    }
+};
+
+// dPsi/dX at fixed nodal u: Q = w det Jx (psi I - H^T P) Jx^-T
+struct GradCoordsOp : XUStage {
+    using Node = NodeXU;
+    template <class E>
+    __device__ bool element(const Node *sn, const uint16_t *lc, double mu, double lam,
+                            double f[E::NEN][3]) const
+    {
+        double Xe[E::NEN][3], ue[E::NEN][3];
+        gather_xu<E>(sn, lc, Xe, ue);
+        bool ok = true;
+#pragma unroll
+        for (int q = 0; q < E::NQ; ++q) {
+            double Jx[9], Hxi[9], Ae[9];
+            E::grad(Xe, q, Jx);
+            E::grad(ue, q, Hxi);
+            Kin k;
+            kinematics(E::template weight<double>(), Jx, Hxi, k);
+            if (!(1.0 + k.Jm1 > 0.0)) {
+                ok = false;
+                continue;
+            }
+            const double lnJ = log1p(k.Jm1);
+            const double psi = 0.5 * mu * k.I1m3 - mu * lnJ + 0.5 * lam * lnJ * lnJ;
+            double F[9], Fa[9];
+#pragma unroll
+            for (int i = 0; i < 9; ++i) F[i] = k.H[i] + ((i % 4) == 0 ? 1.0 : 0.0);
+            const double detF = adj_det(F, Fa);   // F^-1 = Fa / detF
+            const double rdF = 1.0 / detF;
+            double P[9], Sg[9];
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+#pragma unroll
+                for (int J = 0; J < 3; ++J) {
+                    const double FiT = Fa[J * 3 + i] * rdF;   // F^-T_iJ
+                    P[i * 3 + J] = mu * (F[i * 3 + J] - FiT) + lam * lnJ * FiT;
+                }
+#pragma unroll
+            for (int mm = 0; mm < 3; ++mm)
+#pragma unroll
+                for (int L = 0; L < 3; ++L)
+                    Sg[mm * 3 + L] = (mm == L ? psi : 0.0) - (k.H[0 * 3 + mm] * P[0 * 3 + L]
+                                     + k.H[1 * 3 + mm] * P[1 * 3 + L] + k.H[2 * 3 + mm] * P[2 * 3 + L]);
+            // Q = w det Jx Sg Jx^-T = w Sg Ae^T
+            adj_det(Jx, Ae);
+            const double w = E::template weight<double>();
+            double Q[9];
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+#pragma unroll
+                for (int J = 0; J < 3; ++J)
+                    Q[i * 3 + J] = w * (Sg[i * 3 + 0] * Ae[J * 3 + 0] + Sg[i * 3 + 1] * Ae[J * 3 + 1]
+                                        + Sg[i * 3 + 2] * Ae[J * 3 + 2]);
+            E::add_forces(Q, q, f);
+        }
+        return ok;
+    }
+};
+
+// ---------------------------------------------------------- block pass kernel
+
+template <class E, class Op, class T, bool ACC>
+__global__ void __launch_bounds__(256) k_accumulate(BlockMesh m, Op op, T *__restrict__ y,
+                                                    const int32_t *__restrict__ list, int count,
+                                                    Scatter mode, int use_mask, T fixed_val,
+                                                    const int32_t *__restrict__ skip)
+{
+    using Node = typename Op::Node;
+    extern __shared__ __align__(16) unsigned char smem[];
+    if (skip && *skip) return;
+    const int lb = xcd_remap(blockIdx.x, count);
+    const int b = list ? list[lb] : lb;
+    const int n0 = m.nstart[b], nn = m.nstart[b + 1] - n0;
+    const int e0 = m.estart[b], ne = m.estart[b + 1] - e0;
+    Node *sn = reinterpret_cast<Node *>(smem);
+    T *acc = reinterpret_cast<T *>(smem + sizeof(Node) * nn);
+    const uint32_t *bnode = m.bnode + n0;
+    for (int l = threadIdx.x; l < nn; l += blockDim.x) {
+        op.stage(m, sn[l], bnode[l] & kGidMask);
+        acc[3 * l + 0] = T(0);
+        acc[3 * l + 1] = T(0);
+        acc[3 * l + 2] = T(0);
+    }
+    __syncthreads();
+    bool bad = false;
+    for (int k = threadIdx.x; k < ne; k += blockDim.x) {
+        const int e = e0 + k;
+        uint16_t lc[E::NEN];
+#pragma unroll
+        for (int a = 0; a < E::NEN; ++a) lc[a] = m.lconn[(int64_t)e * E::NEN + a];
+        T f[E::NEN][3];
+#pragma unroll
+        for (int a = 0; a < E::NEN; ++a) f[a][0] = f[a][1] = f[a][2] = T(0);
+        bad |= !op.template element<E>(sn, lc, T(m.mu[e]), T(m.lam[e]), f);
+#pragma unroll
+        for (int a = 0; a < E::NEN; ++a)
+#pragma unroll
+            for (int i = 0; i < 3; ++i) atomicAdd(&acc[3 * lc[a] + i], f[a][i]);
+    }
+    if (bad) flag_inverted(m.flags);
+    __syncthreads();
+    write_out<ACC>(m, bnode, nn, acc, y, mode, use_mask != 0, fixed_val);
+}
+
+// Set y = 0 (or the prescribed value) on nodes shared between blocks, before
+// an atomic pass adds into them.
+template <class T>
+__global__ void k_zero_shared(const int32_t *__restrict__ nodes, int64_t n, T *__restrict__ y,
+                              const uint8_t *__restrict__ nmask, T fixed_val)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int64_t g = nodes[i];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) y[3 * g + c] = comp_fixed(nmask, g, c) ? fixed_val : T(0);
+}
+
+// ------------------------------------------------------------------- energy
+
+template <class E>
+__global__ void __launch_bounds__(256) k_energy(BlockMesh m, const double *__restrict__ X,
+                                                const double *__restrict__ u, double *partials,
+                                                uint32_t *counter, double *__restrict__ psi)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ double red[256];
+    __shared__ bool last;
+    const int count = m.n_blocks;
+    const int b = xcd_remap(blockIdx.x, count);
+    const int n0 = m.nstart[b], nn = m.nstart[b + 1] - n0;
+    const int e0 = m.estart[b], ne = m.estart[b + 1] - e0;
+    NodeXU *sn = reinterpret_cast<NodeXU *>(smem);
+    XUStage st{X, u};
+    for (int l = threadIdx.x; l < nn; l += blockDim.x) st.stage(m, sn[l], m.bnode[n0 + l] & kGidMask);
+    __syncthreads();
+    double acc = 0.0;
+    bool bad = false;
+    for (int k = threadIdx.x; k < ne; k += blockDim.x) {
+        const int e = e0 + k;
+        uint16_t lc[E::NEN];
+#pragma unroll
+        for (int a = 0; a < E::NEN; ++a) lc[a] = m.lconn[(int64_t)e * E::NEN + a];
+        double Xe[E::NEN][3], ue[E::NEN][3];
+        gather_xu<E>(sn, lc, Xe, ue);
+        const double mu = m.mu[e], lam = m.lam[e];
+        double pe = 0.0;
+#pragma unroll
+        for (int q = 0; q < E::NQ; ++q) {
+            double Jx[9], Hxi[9];
+            E::grad(Xe, q, Jx);
+            E::grad(ue, q, Hxi);
+            Kin kk;
+            kinematics(E::template weight<double>(), Jx, Hxi, kk);
+            if (!(1.0 + kk.Jm1 > 0.0)) {
+                bad = true;
+                continue;
+            }
+            const double lnJ = log1p(kk.Jm1);
+            pe += kk.wDe * (0.5 * mu * kk.I1m3 - mu * lnJ + 0.5 * lam * lnJ * lnJ);
+        }
+        acc += pe;
+    }
+    if (bad) {
+        flag_inverted(m.flags);
+        acc = INFINITY;
+    }
+    // deterministic tree over the workgroup
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        partials[b] = red[0];
+        __threadfence();
+        const uint32_t t = atomicAdd(counter, 1u);
+        last = (t == (uint32_t)count - 1);
+    }
+    __syncthreads();
+    if (!last) return;
+    __threadfence();
+    // last block: Neumaier sums over a fixed strided assignment, then a fixed tree
+    double s = 0.0, c = 0.0;
+    for (int i = threadIdx.x; i < count; i += blockDim.x) {
+        const double x = __builtin_nontemporal_load(&partials[i]);
+        const double t = s + x;
+        c += (fabs(s) >= fabs(x)) ? ((s - t) + x) : ((x - t) + s);
+        s = t;
+    }
+    red[threadIdx.x] = s + c;
+    __syncthreads();
+    for (int k = blockDim.x / 2; k > 0; k >>= 1) {
+        if ((int)threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        *psi = red[0];
+        *counter = 0u;
+    }
+}
+
+// ------------------------------------------------- per-element adjoint kernels
+
+// dPsi/dmu_e, dPsi/dlam_e at fixed u.
+template <class E>
+__global__ void __launch_bounds__(256) k_grad_material(BlockMesh m, const double *__restrict__ X,
+                                                       const double *__restrict__ u,
+                                                       double *__restrict__ dmu,
+                                                       double *__restrict__ dlam)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int b = xcd_remap(blockIdx.x, m.n_blocks);
+    const int n0 = m.nstart[b], nn = m.nstart[b + 1] - n0;
+    const int e0 = m.estart[b], ne = m.estart[b + 1] - e0;
+    NodeXU *sn = reinterpret_cast<NodeXU *>(smem);
+    XUStage st{X, u};
+    for (int l = threadIdx.x; l < nn; l += blockDim.x) st.stage(m, sn[l], m.bnode[n0 + l] & kGidMask);
+    __syncthreads();
+    bool bad = false;
+    for (int k = threadIdx.x; k < ne; k += blockDim.x) {
+        const int e = e0 + k;
+        uint16_t lc[E::NEN];
+#pragma unroll
+        for (int a = 0; a < E::NEN; ++a) lc[a] = m.lconn[(int64_t)e * E::NEN + a];
+        double Xe[E::NEN][3], ue[E::NEN][3];
+        gather_xu<E>(sn, lc, Xe, ue);
+        double gm = 0.0, gl = 0.0;
+#pragma unroll
+        for (int q = 0; q < E::NQ; ++q) {
+            double Jx[9], Hxi[9];
+            E::grad(Xe, q, Jx);
+            E::grad(ue, q, Hxi);
+            Kin kk;
+            kinematics(E::template weight<double>(), Jx, Hxi, kk);
+            if (!(1.0 + kk.Jm1 > 0.0)) {
+                bad = true;
+                continue;
+            }
+            const double lnJ = log1p(kk.Jm1);
+            gm += kk.wDe * (0.5 * kk.I1m3 - lnJ);
+            gl += kk.wDe * 0.5 * lnJ * lnJ;
+        }
+        const int eo = m.eorig[e];
+        dmu[eo] = gm;
+        dlam[eo] = gl;
+    }
+    if (bad) flag_inverted(m.flags);
+}
+
+// w . dr/dmu_e = sum_q w detJ (F - F^-T) : grad w,  w . dr/dlam_e = sum_q w detJ lnJ F^-T : grad w
+template <class E>
+__global__ void __launch_bounds__(256) k_vjp_material(BlockMesh m, const double *__restrict__ X,
+                                                      const double *__restrict__ u,
+                                                      const double *__restrict__ wv,
+                                                      double *__restrict__ dmu,
+                                                      double *__restrict__ dlam)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int b = xcd_remap(blockIdx.x, m.n_blocks);
+    const int n0 = m.nstart[b], nn = m.nstart[b + 1] - n0;
+    const int e0 = m.estart[b], ne = m.estart[b + 1] - e0;
+    NodeXUW *sn = reinterpret_cast<NodeXUW *>(smem);
+    for (int l = threadIdx.x; l < nn; l += blockDim.x) {
+        const int64_t g = m.bnode[n0 + l] & kGidMask;
+        load3(X, g, sn[l].X);
+        load3(u, g, sn[l].u);
+        load3(wv, g, sn[l].w);
+    }
+    __syncthreads();
+    bool bad = false;
+    for (int k = threadIdx.x; k < ne; k += blockDim.x) {
+        const int e = e0 + k;
+        uint16_t lc[E::NEN];
+#pragma unroll
+        for (int a = 0; a < E::NEN; ++a) lc[a] = m.lconn[(int64_t)e * E::NEN + a];
+        double Xe[E::NEN][3], ue[E::NEN][3], we[E::NEN][3];
+#pragma unroll
+        for (int a = 0; a < E::NEN; ++a)
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                Xe[a][i] = sn[lc[a]].X[i];
+                ue[a][i] = sn[lc[a]].u[i];
+                we[a][i] = sn[lc[a]].w[i];
+            }
+        double gm = 0.0, gl = 0.0;
+#pragma unroll
+        for (int q = 0; q < E::NQ; ++q) {
+            double Jx[9], Hxi[9], Wxi[9], Ae[9];
+            E::grad(Xe, q, Jx);
+            E::grad(ue, q, Hxi);
+            E::grad(we, q, Wxi);
+            Kin kk;
+            kinematics(E::template weight<double>(), Jx, Hxi, kk);
+            if (!(1.0 + kk.Jm1 > 0.0)) {
+                bad = true;
+                continue;
+            }
+            const double lnJ = log1p(kk.Jm1);
+            const double De = adj_det(Jx, Ae);
+            double F[9], Fa[9];
+#pragma unroll
+            for (int i = 0; i < 9; ++i) F[i] = kk.H[i] + ((i % 4) == 0 ? 1.0 : 0.0);
+            const double rdF = 1.0 / adj_det(F, Fa);
+            double sm = 0.0, sl = 0.0;
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+#pragma unroll
+                for (int J = 0; J < 3; ++J) {
+                    const double gw = (Wxi[i * 3 + 0] * Ae[0 * 3 + J] + Wxi[i * 3 + 1] * Ae[1 * 3 + J]
+                                       + Wxi[i * 3 + 2] * Ae[2 * 3 + J]) / De;
+                    const double FiT = Fa[J * 3 + i] * rdF;
+                    sm += (F[i * 3 + J] - FiT) * gw;
+                    sl += lnJ * FiT * gw;
+                }
+            gm += kk.wDe * sm;
+            gl += kk.wDe * sl;
+        }
+        const int eo = m.eorig[e];
+        dmu[eo] = gm;
+        dlam[eo] = gl;
+    }
+    if (bad) flag_inverted(m.flags);
+}
+
+// ---------------------------------------------------------------- launchers
+
+template <class Op>
+static size_t lds_bytes(const Ctx &c, size_t acc_elem)
+{
+    return (sizeof(typename Op::Node) + 3 * acc_elem) * (size_t)c.max_block_nodes;
+}
+
+template <class E, class Op, class T>
+static hipError_t run_accumulate(const Ctx &c, const Op &op, T *y, bool use_mask, T fixed_val,
+                                 const int32_t *skip, bool acc)
+{
+    const size_t lds = lds_bytes<Op>(c, sizeof(T));
+    if (acc) {
+        for (const Pass &p : c.passes) {
+            if (p.count == 0) continue;
+            hipLaunchKernelGGL((k_accumulate<E, Op, T, true>), dim3(p.count), dim3(c.threads), lds,
+                               c.stream, c.m, op, y, p.list, p.count, c.scatter, use_mask ? 1 : 0,
+                               fixed_val, skip);
+        }
+        return hipGetLastError();
+    }
+    if (c.scatter == Scatter::Atomic && c.n_shared > 0) {
+        const int64_t n = c.n_shared;
+        hipLaunchKernelGGL((k_zero_shared<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
+                           c.stream, c.shared_nodes, n, y, use_mask ? c.m.nmask : nullptr,
+                           fixed_val);
+    }
+    for (const Pass &p : c.passes) {
+        if (p.count == 0) continue;
+        hipLaunchKernelGGL((k_accumulate<E, Op, T, false>), dim3(p.count), dim3(c.threads), lds, c.stream,
+                           c.m, op, y, p.list, p.count, c.scatter, use_mask ? 1 : 0, fixed_val,
+                           skip);
+    }
+    return hipGetLastError();
+}
+
+template <class Op, class T>
+static hipError_t dispatch(const Ctx &c, const Op &op, T *y, bool use_mask, T fixed_val,
+                           const int32_t *skip = nullptr, bool acc = false)
+{
+    return c.elem == EFEM_TET4 ? run_accumulate<Tet4>(c, op, y, use_mask, fixed_val, skip, acc)
+                               : run_accumulate<Hex8>(c, op, y, use_mask, fixed_val, skip, acc);
+}
+
+hipError_t launch_residual(const Ctx &c, const double *u, double *r)
+{
+    ResidualOp op;
+    op.X = c.m.X;
+    op.u = u;
+    return dispatch(c, op, r, true, 0.0);
+}
+
+hipError_t launch_diag(const Ctx &c, const double *u, double *d)
+{
+    DiagOp op;
+    op.X = c.m.X;
+    op.u = u;
+    return dispatch(c, op, d, true, 1.0);
+}
+
+hipError_t launch_grad_coords(const Ctx &c, const double *u, double *g)
+{
+    GradCoordsOp op;
+    op.X = c.m.X;
+    op.u = u;
+    return dispatch(c, op, g, false, 0.0);
+}
+
+hipError_t launch_hvp_f64(const Ctx &c, const double *xlin, const double *v, double *y,
+                          const int32_t *skip, bool acc)
+{
+    HvpOp<double> op{c.m.X, xlin, v, y};
+    return dispatch(c, op, y, true, 0.0, skip, acc);
+}
+
+hipError_t launch_hvp_f32(const Ctx &c, const float *ulin, const float *v, float *y,
+                          const int32_t *skip, bool acc)
+{
+    HvpOp<float> op{c.m.Xf, ulin, v, y};
+    return dispatch(c, op, y, true, 0.0f, skip, acc);
+}
+
+hipError_t launch_energy(const Ctx &c, const double *u, double *psi)
+{
+    const size_t lds = sizeof(NodeXU) * (size_t)c.max_block_nodes;
+    if (c.elem == EFEM_TET4)
+        hipLaunchKernelGGL(k_energy<Tet4>, dim3(c.m.n_blocks), dim3(256), lds, c.stream, c.m, c.m.X,
+                           u, c.partials, c.counter, psi);
+    else
+        hipLaunchKernelGGL(k_energy<Hex8>, dim3(c.m.n_blocks), dim3(256), lds, c.stream, c.m, c.m.X,
+                           u, c.partials, c.counter, psi);
+    return hipGetLastError();
+}
+
+hipError_t launch_grad_material(const Ctx &c, const double *u, double *dmu, double *dlam)
+{
+    const size_t lds = sizeof(NodeXU) * (size_t)c.max_block_nodes;
+    if (c.elem == EFEM_TET4)
+        hipLaunchKernelGGL(k_grad_material<Tet4>, dim3(c.m.n_blocks), dim3(c.threads), lds,
+                           c.stream, c.m, c.m.X, u, dmu, dlam);
+    else
+        hipLaunchKernelGGL(k_grad_material<Hex8>, dim3(c.m.n_blocks), dim3(c.threads), lds,
+                           c.stream, c.m, c.m.X, u, dmu, dlam);
+    return hipGetLastError();
+}
+
+hipError_t launch_vjp_material(const Ctx &c, const double *u, const double *w, double *dmu,
+                               double *dlam)
+{
+    const size_t lds = sizeof(NodeXUW) * (size_t)c.max_block_nodes;
+    if (c.elem == EFEM_TET4)
+        hipLaunchKernelGGL(k_vjp_material<Tet4>, dim3(c.m.n_blocks), dim3(c.threads), lds,
+                           c.stream, c.m, c.m.X, u, w, dmu, dlam);
+    else
+        hipLaunchKernelGGL(k_vjp_material<Hex8>, dim3(c.m.n_blocks), dim3(c.threads), lds,
+                           c.stream, c.m, c.m.X, u, w, dmu, dlam);
+    return hipGetLastError();
+}
+
+}  // namespace efem

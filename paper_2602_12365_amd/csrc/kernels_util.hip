@@ -1,0 +1,65 @@
+// Small streaming kernels: material permutation, Dirichlet node masks,
+// linearization caches.
+#include "efem_internal.h"
+
+namespace efem {
+
+__global__ void k_permute_elems(const int32_t *__restrict__ eorig, int64_t n,
+                                const double *__restrict__ src, double *__restrict__ dst)
+{
+    const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (e < n) dst[e] = src[eorig[e]];
+}
+
+__global__ void k_build_nmask(const uint8_t *__restrict__ dofmask, int64_t n_nodes,
+                              uint8_t *__restrict__ nmask)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n_nodes) return;
+    nmask[i] = (uint8_t)((dofmask[3 * i] != 0) | ((dofmask[3 * i + 1] != 0) << 1)
+                         | ((dofmask[3 * i + 2] != 0) << 2));
+}
+
+__global__ void k_add(const double *__restrict__ a, const double *__restrict__ b, int64_t n,
+                      double *__restrict__ out)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) out[i] = a[i] + b[i];
+}
+
+__global__ void k_cast_f32(const double *__restrict__ src, int64_t n, float *__restrict__ dst)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = (float)src[i];
+}
+
+static unsigned grid_for(int64_t n) { return (unsigned)((n + 255) / 256); }
+
+hipError_t launch_permute_elems(const Ctx &c, const double *src, double *dst)
+{
+    hipLaunchKernelGGL(k_permute_elems, dim3(grid_for(c.n_elems)), dim3(256), 0, c.stream,
+                       c.m.eorig, c.n_elems, src, dst);
+    return hipGetLastError();
+}
+
+hipError_t launch_build_nmask(const Ctx &c, const uint8_t *dofmask, uint8_t *nmask)
+{
+    hipLaunchKernelGGL(k_build_nmask, dim3(grid_for(c.n_nodes)), dim3(256), 0, c.stream, dofmask,
+                       c.n_nodes, nmask);
+    return hipGetLastError();
+}
+
+hipError_t launch_add_x_u(const Ctx &c, const double *u, double *x)
+{
+    hipLaunchKernelGGL(k_add, dim3(grid_for(3 * c.n_nodes)), dim3(256), 0, c.stream, c.m.X, u,
+                       3 * c.n_nodes, x);
+    return hipGetLastError();
+}
+
+hipError_t launch_cast_f32(const double *src, float *dst, int64_t n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_cast_f32, dim3(grid_for(n)), dim3(256), 0, s, src, n, dst);
+    return hipGetLastError();
+}
+
+}  // namespace efem

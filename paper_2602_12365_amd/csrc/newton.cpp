@@ -1,0 +1,348 @@
+// Matrix-free Newton-Krylov driver: a host loop over the element kernels
+// (energy, residual, Jacobi diagonal, tangent action) and the streaming CG
+// kernels.  The paper names the method (Sec. 6.3.1) but none of its parts; the
+// reading implemented here:
+//   * load steps k = 1..n: prescribed DOFs ramp to k/n of their final values;
+//   * each step starts with a tangent predictor: the prescribed increment dc
+//     is lifted into the free DOFs by solving K_ff d_f = -(K dc)_f;
+//   * Newton iterations: Jacobi-PCG on K_ff d = -r_f with an Eisenstat-Walker
+//     (choice 2) forcing term, then Armijo backtracking on the FP64 energy
+//     (a step that inverts an element has energy +inf and is rejected);
+//   * stop when ||r_f|| <= rtol ||r_f at the start of the step||.
+// With hvp_prec = EFEM_F32 the CG vectors and tangent actions are float32;
+// the residual, energy, line search and state stay float64.
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <type_traits>
+
+#include "efem_cg.h"
+
+namespace efem {
+
+int precond_solve_f32(Ctx &c, const efem_solve_opts &o, const double *b, double eta, int max_it,
+                      float *x, float *dinv, int *iters, int *fallback);
+
+namespace {
+
+#define TRY(call)                                              \
+    do {                                                       \
+        hipError_t e_ = (call);                                \
+        if (e_ != hipSuccess) return hip_fail(e_, #call);      \
+    } while (0)
+
+template <class T>
+struct Solver {
+    Ctx &c;
+    efem_solve_opts o;
+    int64_t n;
+    std::vector<void *> bufs;
+    double *r = nullptr, *dc = nullptr, *u_old = nullptr, *u_trial = nullptr, *diag = nullptr,
+           *kdc = nullptr, *dscal = nullptr;
+    T *x = nullptr, *rv = nullptr, *p = nullptr, *q = nullptr, *dinv = nullptr;
+    CgScalars *sc = nullptr;
+    CgWorkspace ws;
+    CgScalars *h_sc = nullptr;
+    double *h_scal = nullptr;
+    CgLaunch<T> L{};
+
+    Solver(Ctx &c_, const efem_solve_opts &o_) : c(c_), o(o_), n(3 * c_.n_nodes) {}
+
+    ~Solver()
+    {
+        for (void *b : bufs) (void)hipFree(b);
+        if (h_sc) (void)hipHostFree(h_sc);
+        if (h_scal) (void)hipHostFree(h_scal);
+    }
+
+    template <class U>
+    int alloc(U **ptr, size_t count)
+    {
+        void *q_ = nullptr;
+        hipError_t e = hipMalloc(&q_, std::max<size_t>(count, 1) * sizeof(U));
+        if (e != hipSuccess) return hip_fail(e, "hipMalloc");
+        bufs.push_back(q_);
+        *ptr = static_cast<U *>(q_);
+        return EFEM_OK;
+    }
+
+    int setup()
+    {
+        int rc;
+        if ((rc = alloc(&r, n)) || (rc = alloc(&dc, n)) || (rc = alloc(&u_old, n))
+            || (rc = alloc(&u_trial, n)) || (rc = alloc(&diag, n)) || (rc = alloc(&kdc, n))
+            || (rc = alloc(&dscal, 4)) || (rc = alloc(&x, n)) || (rc = alloc(&rv, n))
+            || (rc = alloc(&p, n)) || (rc = alloc(&q, n)) || (rc = alloc(&dinv, n))
+            || (rc = alloc(&sc, 1)) || (rc = alloc(&ws.partials, 2 * kMaxRedBlocks))
+            || (rc = alloc(&ws.counter, 1)))
+            return rc;
+        TRY(hipMemsetAsync(ws.counter, 0, sizeof(uint32_t), c.stream));
+        if (!c.xlin) {
+            void *q_ = nullptr;
+            TRY(hipMalloc(&q_, n * sizeof(double)));
+            c.owned.push_back(q_);
+            c.xlin = static_cast<double *>(q_);
+        }
+        if (!c.ulin) {
+            void *q_ = nullptr;
+            TRY(hipMalloc(&q_, n * sizeof(float)));
+            c.owned.push_back(q_);
+            c.ulin = static_cast<float *>(q_);
+        }
+        TRY(hipHostMalloc((void **)&h_sc, sizeof(CgScalars), hipHostMallocDefault));
+        TRY(hipHostMalloc((void **)&h_scal, 4 * sizeof(double), hipHostMallocDefault));
+        L = CgLaunch<T>{n, c.stream, ws};
+        return EFEM_OK;
+    }
+
+    int read_scalar(const double *dptr, double &out)
+    {
+        TRY(hipMemcpyAsync(h_scal, dptr, sizeof(double), hipMemcpyDeviceToHost, c.stream));
+        TRY(hipStreamSynchronize(c.stream));
+        out = h_scal[0];
+        return EFEM_OK;
+    }
+
+    int energy(const double *u, double &e)
+    {
+        TRY(launch_energy(c, u, dscal));
+        return read_scalar(dscal, e);
+    }
+
+    int norm(const double *v, double &out)
+    {
+        TRY(launch_dot64(c.stream, ws, n, v, v, dscal + 1));
+        int rc = read_scalar(dscal + 1, out);
+        out = std::sqrt(out);
+        return rc;
+    }
+
+    int linearize(const double *u)
+    {
+        if (std::is_same<T, double>::value) TRY(launch_add_x_u(c, u, c.xlin));
+        else TRY(launch_cast_f32(u, c.ulin, n, c.stream));
+        c.lin_prec = std::is_same<T, double>::value ? EFEM_F64 : EFEM_F32;
+        return EFEM_OK;
+    }
+
+    hipError_t hvp_acc(const T *v, T *y, const int32_t *skip)
+    {
+        if constexpr (std::is_same<T, double>::value)
+            return launch_hvp_f64(c, c.xlin, v, y, skip, true);
+        else
+            return launch_hvp_f32(c, c.ulin, v, y, skip, true);
+    }
+
+    // Jacobi-PCG for K_ff x = sign * b from x = 0; dinv must be set.
+    int pcg(const double *b, double sign, double eta, int max_it, int &iters)
+    {
+        TRY(L.init(b, sign, dinv, c.m.nmask, x, rv, p, q, sc, eta * eta));
+        const int every = std::max(1, o.check_every);
+        for (;;) {
+            for (int j = 0; j < every; ++j) {
+                TRY(hvp_acc(p, q, &sc->done));
+                TRY(L.pq(p, q, sc));
+                TRY(L.update(x, rv, p, q, dinv, sc));
+                TRY(L.dir(p, rv, dinv, sc));
+            }
+            TRY(hipMemcpyAsync(h_sc, sc, sizeof(CgScalars), hipMemcpyDeviceToHost, c.stream));
+            TRY(hipStreamSynchronize(c.stream));
+            if (h_sc->done || h_sc->iter >= max_it) break;
+        }
+        iters = h_sc->iter + (h_sc->breakdown ? 1 : 0);
+        if (h_sc->breakdown && h_sc->iter == 0) TRY(L.scaled(dinv, b, sign, x));
+        return EFEM_OK;
+    }
+
+    int set_dinv(const double *u)
+    {
+        TRY(launch_diag(c, u, diag));
+        TRY(L.dinv_from_diag(diag, c.m.nmask, dinv));
+        return EFEM_OK;
+    }
+
+    int linear_solve(const double *u, const double *b, double eta, int max_it, int &iters,
+                     int &fallbacks)
+    {
+        int rc;
+        if ((rc = set_dinv(u)) || (rc = linearize(u))) return rc;
+        if constexpr (std::is_same<T, float>::value) {
+            if (o.precond == 1 && c.mlp)
+                return precond_solve_f32(c, o, b, eta, max_it, x, dinv, &iters, &fallbacks);
+        }
+        return pcg(b, -1.0, eta, max_it, iters);
+    }
+
+    int run(double *u, const double *u_bc, efem_solve_stats *st)
+    {
+        int rc = setup();
+        if (rc) return rc;
+        const auto t0 = std::chrono::steady_clock::now();
+        const bool f32 = std::is_same<T, float>::value;
+        const double eta_min = f32 ? std::max(o.eta_min, 1e-5) : o.eta_min;
+        st->converged = 1;
+        for (int k = 1; k <= o.n_steps; ++k) {
+            const double frac = (double)k / o.n_steps;
+            int cg_step = 0, nit = 0, fb = 0;
+            // tangent predictor: K_ff d_f = -(K dc)_f, with K dc taken on the unmasked input
+            TRY(launch_bc_increment(c.stream, n, u, u_bc, frac, c.m.nmask, dc, u_old));
+            TRY(launch_add_x_u(c, u, c.xlin));
+            const uint8_t *mask = c.m.nmask;
+            c.m.nmask = nullptr;
+            hipError_t he = launch_hvp_f64(c, c.xlin, dc, kdc, nullptr, false);
+            c.m.nmask = mask;
+            TRY(he);
+            int it = 0;
+            if ((rc = linear_solve(u, kdc, o.predictor_rtol, o.max_cg, it, fb))) return rc;
+            cg_step += it;
+            TRY(L.apply_predictor(u_old, dc, x, c.m.nmask, true, u));
+            double e0;
+            if ((rc = energy(u, e0))) return rc;
+            if (!std::isfinite(e0)) {
+                TRY(L.apply_predictor(u_old, dc, x, c.m.nmask, false, u));
+                if ((rc = energy(u, e0))) return rc;
+                if (!std::isfinite(e0)) {
+                    set_error("efem_newton_solve: the load increment inverts an element");
+                    return EFEM_ERR_INVERTED;
+                }
+            }
+            double rho;
+            TRY(launch_residual(c, u, r));
+            if ((rc = norm(r, rho))) return rc;
+            const double rho0 = rho;
+            const double tol = std::max(o.rtol * rho0, o.atol_floor * std::max(1.0, rho0));
+            double eta_prev = o.eta_max, rho_prev = -1.0;
+            while (rho > tol) {
+                if (nit >= o.max_newton) {
+                    st->converged = 0;
+                    break;
+                }
+                double eta;
+                if (o.eta_fixed > 0) eta = o.eta_fixed;
+                else if (rho_prev < 0) eta = o.eta_max;
+                else {
+                    eta = o.ew_gamma * std::pow(rho / rho_prev, o.ew_alpha);
+                    const double safe = o.ew_gamma * std::pow(eta_prev, o.ew_alpha);
+                    if (safe > 0.1) eta = std::max(eta, safe);
+                    eta = std::min(eta, o.eta_max);
+                    eta = std::max(eta, 0.5 * tol / rho);
+                }
+                if (o.eta_fixed <= 0) eta = std::max(eta, eta_min);
+                if ((rc = linear_solve(u, r, eta, o.max_cg, it, fb))) return rc;
+                cg_step += it;
+                double slope;
+                TRY(L.dot_state(r, x, dscal + 2));
+                if ((rc = read_scalar(dscal + 2, slope))) return rc;
+                double alpha = 1.0, e1 = INFINITY;
+                int h = 0;
+                for (; h <= o.max_halvings; ++h) {
+                    TRY(L.axpy_state(u, alpha, x, u_trial));
+                    if ((rc = energy(u_trial, e1))) return rc;
+                    if (std::isfinite(e1) && e1 <= e0 + o.armijo_c * alpha * slope) break;
+                    alpha *= 0.5;
+                }
+                if (h > o.max_halvings) {
+                    st->converged = 0;
+                    break;
+                }
+                st->line_search_halvings += h;
+                TRY(hipMemcpyAsync(u, u_trial, n * sizeof(double), hipMemcpyDeviceToDevice, c.stream));
+                e0 = e1;
+                rho_prev = rho;
+                eta_prev = eta;
+                TRY(launch_residual(c, u, r));
+                if ((rc = norm(r, rho))) return rc;
+                ++nit;
+                if (o.verbose)
+                    std::fprintf(stderr, "[newton] step %d it %d |r| %.3e (rel %.3e) eta %.2e cg %d alpha %g\n",
+                                 k, nit, rho, rho / rho0, eta, it, alpha);
+            }
+            st->steps_done = k;
+            st->newton_iters += nit;
+            st->cg_iters += cg_step;
+            st->precond_fallbacks += fb;
+            if (k - 1 < 64) {
+                st->newton_per_step[k - 1] = nit;
+                st->cg_per_step[k - 1] = cg_step;
+            }
+            st->final_residual = rho;
+            st->final_energy = e0;
+            if (!st->converged) break;
+        }
+        TRY(hipMemsetAsync(c.flags, 0, sizeof(int32_t), c.stream));
+        TRY(hipStreamSynchronize(c.stream));
+        st->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        return st->converged ? EFEM_OK : EFEM_NOT_CONVERGED;
+    }
+};
+
+}  // namespace
+}  // namespace efem
+
+using namespace efem;
+
+struct efem_ctx : Ctx {};
+
+extern "C" {
+
+void efem_solve_opts_default(efem_solve_opts *o)
+{
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->n_steps = 5;
+    o->hvp_prec = EFEM_F64;
+    o->precond = 0;
+    o->max_newton = 50;
+    o->max_cg = 20000;
+    o->check_every = 8;
+    o->rtol = 1e-8;
+    o->atol_floor = 1e-14;
+    o->eta_max = 0.5;
+    o->eta_min = 1e-10;
+    o->ew_gamma = 0.9;
+    o->ew_alpha = 2.0;
+    o->eta_fixed = 0.0;
+    o->predictor_rtol = 1e-4;
+    o->armijo_c = 1e-4;
+    o->max_halvings = 30;
+    o->verbose = 0;
+}
+
+int efem_newton_solve(efem_ctx *ctx, double *u_inout, const double *u_bc, const efem_solve_opts *opts,
+                      efem_solve_stats *stats)
+{
+    if (!ctx || !u_inout || !u_bc || !opts || !stats) {
+        set_error("efem_newton_solve: null pointer");
+        return EFEM_ERR_INVALID;
+    }
+    if (!ctx->m.nmask) {
+        set_error("efem_newton_solve: set a Dirichlet mask first (efem_set_dirichlet)");
+        return EFEM_ERR_STATE;
+    }
+    if (opts->n_steps < 1 || opts->max_cg < 1 || opts->max_newton < 0 || opts->rtol <= 0
+        || (opts->hvp_prec != EFEM_F64 && opts->hvp_prec != EFEM_F32)) {
+        set_error("efem_newton_solve: bad options");
+        return EFEM_ERR_INVALID;
+    }
+    if (opts->precond == 1 && (!ctx->mlp || opts->hvp_prec != EFEM_F32)) {
+        set_error("efem_newton_solve: the learned preconditioner needs efem_set_mlp and EFEM_F32");
+        return EFEM_ERR_STATE;
+    }
+    std::memset(stats, 0, sizeof(*stats));
+    int dev_prev = -1;
+    (void)hipGetDevice(&dev_prev);
+    if (dev_prev != ctx->device) (void)hipSetDevice(ctx->device);
+    int rc;
+    if (opts->hvp_prec == EFEM_F64) {
+        Solver<double> s(*ctx, *opts);
+        rc = s.run(u_inout, u_bc, stats);
+    } else {
+        Solver<float> s(*ctx, *opts);
+        rc = s.run(u_inout, u_bc, stats);
+    }
+    if (dev_prev >= 0 && dev_prev != ctx->device) (void)hipSetDevice(dev_prev);
+    return rc;
+}
+
+}  // extern "C"

@@ -1,0 +1,290 @@
+"""torch-facing wrapper of the C-ABI: an ``Operator`` built from a mesh (Sec. 4,
+``Operator(mesh, element, batchsize)``) and the ``torch.autograd.Function``s
+whose backward passes are the hand-written adjoint kernels.
+
+PyTorch only supplies device memory and streams: every operator runs in the
+HIP kernels of ``libefem.so``; this module checks shapes, dtypes and devices
+and passes raw pointers.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+_ELEM = {"tet4": L.EFEM_TET4, "hex8": L.EFEM_HEX8, L.EFEM_TET4: L.EFEM_TET4, L.EFEM_HEX8: L.EFEM_HEX8}
+_PREC = {"f64": L.EFEM_F64, "f32": L.EFEM_F32, torch.float64: L.EFEM_F64, torch.float32: L.EFEM_F32}
+_SCATTER = {"atomic": L.EFEM_SCATTER_ATOMIC, "color": L.EFEM_SCATTER_COLOR}
+
+
+def _ptr(t: torch.Tensor):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Operator:
+    """Energy, residual, tangent action and adjoints of one mesh on one GPU.
+
+    Mesh arrays (``X`` float64 [n_nodes, 3], ``conn`` int32 [n_elems, n_en])
+    are host arrays; every state tensor is a contiguous CUDA tensor, float64
+    unless stated, of shape [n_nodes, 3] (or the flat [3*n_nodes]).
+    Calls run on torch's current stream.
+    """
+
+    def __init__(self, elem, X, conn, *, block_elems=0, block_nodes=0, scatter="atomic",
+                 threads=0, device=None):
+        self._lib = L.load()
+        X = np.ascontiguousarray(np.asarray(X, dtype=np.float64))
+        conn = np.ascontiguousarray(np.asarray(conn, dtype=np.int32))
+        if X.ndim != 2 or X.shape[1] != 3:
+            raise ValueError("X must be [n_nodes, 3]")
+        self.elem = _ELEM[elem]
+        self.nen = 4 if self.elem == L.EFEM_TET4 else 8
+        if conn.ndim != 2 or conn.shape[1] != self.nen:
+            raise ValueError(f"conn must be [n_elems, {self.nen}]")
+        self.n_nodes, self.n_elems = X.shape[0], conn.shape[0]
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self.X_host = X
+        opts = L.Options(block_elems, block_nodes, _SCATTER[scatter], threads)
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            self._stream = torch.cuda.current_stream().cuda_stream
+            L.check(self._lib.efem_create(ctypes.byref(h), self.elem, self.n_nodes, self.n_elems,
+                                          X.ctypes.data_as(ctypes.c_void_p),
+                                          conn.ctypes.data_as(ctypes.c_void_p), ctypes.byref(opts),
+                                          ctypes.c_void_p(self._stream)), "efem_create")
+        self._h = h
+        self._lin = None
+        self.X = torch.from_numpy(X).to(self.device)
+
+    # ------------------------------------------------------------- plumbing
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.efem_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _sync_stream(self):
+        s = torch.cuda.current_stream(self.device).cuda_stream
+        if s != self._stream:
+            L.check(self._lib.efem_set_stream(self._h, ctypes.c_void_p(s)), "efem_set_stream")
+            self._stream = s
+
+    def _nodal(self, t, dtype=torch.float64, name="array"):
+        if not isinstance(t, torch.Tensor) or t.device != self.device or t.dtype != dtype:
+            raise TypeError(f"{name} must be a {dtype} tensor on {self.device}")
+        if t.numel() != 3 * self.n_nodes or not t.is_contiguous():
+            raise ValueError(f"{name} must be contiguous with {3 * self.n_nodes} entries")
+        return t
+
+    def _elemwise(self, t, name):
+        if not isinstance(t, torch.Tensor) or t.device != self.device or t.dtype != torch.float64:
+            raise TypeError(f"{name} must be a float64 tensor on {self.device}")
+        if t.numel() != self.n_elems or not t.is_contiguous():
+            raise ValueError(f"{name} must be contiguous with {self.n_elems} entries")
+        return t
+
+    def _new_nodal(self, dtype=torch.float64):
+        return torch.empty((self.n_nodes, 3), dtype=dtype, device=self.device)
+
+    # ---------------------------------------------------------------- setup
+    def set_material(self, mu, lam):
+        self._sync_stream()
+        L.check(self._lib.efem_set_material(self._h, _ptr(self._elemwise(mu, "mu")),
+                                            _ptr(self._elemwise(lam, "lam"))), "efem_set_material")
+
+    def set_dirichlet(self, mask):
+        """mask: uint8 tensor [3*n_nodes] (1 = prescribed) or None."""
+        self._sync_stream()
+        if mask is None:
+            L.check(self._lib.efem_set_dirichlet(self._h, None), "efem_set_dirichlet")
+            return
+        self._mask = self._nodal(mask, torch.uint8, "mask")
+        L.check(self._lib.efem_set_dirichlet(self._h, _ptr(self._mask)), "efem_set_dirichlet")
+
+    def info(self):
+        i = L.Info()
+        L.check(self._lib.efem_get_info(self._h, ctypes.byref(i)), "efem_get_info")
+        return {k: getattr(i, k) for k, _ in L.Info._fields_}
+
+    def status(self):
+        self._sync_stream()
+        f = ctypes.c_int32()
+        L.check(self._lib.efem_status(self._h, ctypes.byref(f)), "efem_status")
+        return f.value
+
+    # ------------------------------------------------------------ operators
+    def energy(self, u, out=None):
+        """Psi_h(u), Eq. (2), as a 0-d float64 device tensor."""
+        self._sync_stream()
+        out = torch.empty((), dtype=torch.float64, device=self.device) if out is None else out
+        L.check(self._lib.efem_energy(self._h, _ptr(self._nodal(u, name="u")), _ptr(out)),
+                "efem_energy")
+        return out
+
+    def residual(self, u, out=None):
+        """r = grad Psi_h(u), Eq. (1)."""
+        self._sync_stream()
+        out = self._new_nodal() if out is None else self._nodal(out, name="out")
+        L.check(self._lib.efem_residual(self._h, _ptr(self._nodal(u, name="u")), _ptr(out)),
+                "efem_residual")
+        return out
+
+    def linearize(self, u, prec="f64"):
+        self._sync_stream()
+        p = _PREC[prec]
+        L.check(self._lib.efem_linearize(self._h, _ptr(self._nodal(u, name="u")), p),
+                "efem_linearize")
+        self._lin = torch.float64 if p == L.EFEM_F64 else torch.float32
+
+    def hvp(self, v, out=None):
+        """y = K(u) v, Eq. (3), at the last linearization point."""
+        self._sync_stream()
+        if self._lin is None:
+            raise RuntimeError("call linearize(u) first")
+        out = self._new_nodal(self._lin) if out is None else self._nodal(out, self._lin, "out")
+        L.check(self._lib.efem_hvp(self._h, _ptr(self._nodal(v, self._lin, "v")), _ptr(out)),
+                "efem_hvp")
+        return out
+
+    def hvp_acc(self, v, out):
+        """out += K(u) v in one kernel launch."""
+        self._sync_stream()
+        if self._lin is None:
+            raise RuntimeError("call linearize(u) first")
+        L.check(self._lib.efem_hvp_acc(self._h, _ptr(self._nodal(v, self._lin, "v")),
+                                       _ptr(self._nodal(out, self._lin, "out"))), "efem_hvp_acc")
+        return out
+
+    def jacobi_diag(self, u, out=None):
+        self._sync_stream()
+        out = self._new_nodal() if out is None else self._nodal(out, name="out")
+        L.check(self._lib.efem_jacobi_diag(self._h, _ptr(self._nodal(u, name="u")), _ptr(out)),
+                "efem_jacobi_diag")
+        return out
+
+    def grad_material(self, u):
+        self._sync_stream()
+        dmu = torch.empty(self.n_elems, dtype=torch.float64, device=self.device)
+        dlam = torch.empty_like(dmu)
+        L.check(self._lib.efem_grad_material(self._h, _ptr(self._nodal(u, name="u")), _ptr(dmu),
+                                             _ptr(dlam)), "efem_grad_material")
+        return dmu, dlam
+
+    def residual_vjp_material(self, u, w):
+        self._sync_stream()
+        dmu = torch.empty(self.n_elems, dtype=torch.float64, device=self.device)
+        dlam = torch.empty_like(dmu)
+        L.check(self._lib.efem_residual_vjp_material(self._h, _ptr(self._nodal(u, name="u")),
+                                                     _ptr(self._nodal(w, name="w")), _ptr(dmu),
+                                                     _ptr(dlam)), "efem_residual_vjp_material")
+        return dmu, dlam
+
+    def grad_coords(self, u, out=None):
+        self._sync_stream()
+        out = self._new_nodal() if out is None else self._nodal(out, name="out")
+        L.check(self._lib.efem_grad_coords(self._h, _ptr(self._nodal(u, name="u")), _ptr(out)),
+                "efem_grad_coords")
+        return out
+
+
+    # -------------------------------------------------------------- solver
+    def newton_solve(self, u, u_bc, **opts):
+        """Matrix-free Newton-Krylov solve (Sec. 6.3.1) of the reduced
+        functional; needs set_dirichlet.  ``u`` (float64 [n_nodes, 3]) is
+        updated in place.  Keyword options are the fields of efem_solve_opts
+        (``hvp_prec`` accepts "f64"/"f32").  Returns (return code, stats dict)."""
+        self._sync_stream()
+        o = L.SolveOpts()
+        self._lib.efem_solve_opts_default(ctypes.byref(o))
+        for k, v in opts.items():
+            if k == "hvp_prec":
+                v = _PREC[v]
+            if not hasattr(o, k):
+                raise KeyError(k)
+            setattr(o, k, v)
+        st = L.SolveStats()
+        rc = L.check(self._lib.efem_newton_solve(self._h, _ptr(self._nodal(u, name="u")),
+                                                 _ptr(self._nodal(u_bc, name="u_bc")),
+                                                 ctypes.byref(o), ctypes.byref(st)),
+                     "efem_newton_solve")
+        k = st.steps_done
+        stats = {f: getattr(st, f) for f, _ in L.SolveStats._fields_
+                 if f not in ("newton_per_step", "cg_per_step")}
+        stats["newton_per_step"] = list(st.newton_per_step[:min(k, 64)])
+        stats["cg_per_step"] = list(st.cg_per_step[:min(k, 64)])
+        return rc, stats
+
+
+# --------------------------------------------------------------- autograd
+
+class EnergyFn(torch.autograd.Function):
+    """Psi(u; mu, lam, X) with the hand-written adjoints as its backward:
+    dPsi/du = r (residual kernel), dPsi/dmu, dPsi/dlam (material kernel),
+    dPsi/dX at fixed nodal u (coordinate kernel).  ``X`` must hold the
+    coordinates the operator was built with; it is an input only so that its
+    gradient can be requested."""
+
+    @staticmethod
+    def forward(ctx, u, mu, lam, X, op: Operator):
+        op.set_material(mu.contiguous(), lam.contiguous())
+        ctx.op = op
+        ctx.save_for_backward(u, mu, lam)
+        return op.energy(u.contiguous()).clone()
+
+    @staticmethod
+    def backward(ctx, g):
+        u, mu, lam = ctx.saved_tensors
+        op = ctx.op
+        op.set_material(mu.contiguous(), lam.contiguous())
+        uc = u.contiguous()
+        du = dmu = dlam = dX = None
+        if ctx.needs_input_grad[0]:
+            du = (g * op.residual(uc)).reshape(u.shape)
+        if ctx.needs_input_grad[1] or ctx.needs_input_grad[2]:
+            gm, gl = op.grad_material(uc)
+            dmu, dlam = g * gm, g * gl
+        if ctx.needs_input_grad[3]:
+            dX = g * op.grad_coords(uc)
+        return du, dmu, dlam, dX, None
+
+
+class ResidualFn(torch.autograd.Function):
+    """r(u; mu, lam) with backward(w) = (K(u) w, w.dr/dmu, w.dr/dlam): the
+    forward-over-adjoint tangent kernel and the residual's material VJP."""
+
+    @staticmethod
+    def forward(ctx, u, mu, lam, op: Operator):
+        op.set_material(mu.contiguous(), lam.contiguous())
+        ctx.op = op
+        ctx.save_for_backward(u, mu, lam)
+        return op.residual(u.contiguous()).reshape(u.shape)
+
+    @staticmethod
+    def backward(ctx, w):
+        u, mu, lam = ctx.saved_tensors
+        op = ctx.op
+        op.set_material(mu.contiguous(), lam.contiguous())
+        uc, wc = u.contiguous(), w.contiguous()
+        du = dmu = dlam = None
+        if ctx.needs_input_grad[0]:
+            op.linearize(uc, "f64")
+            du = op.hvp(wc.reshape(-1, 3)).reshape(u.shape)
+        if ctx.needs_input_grad[1] or ctx.needs_input_grad[2]:
+            dmu, dlam = op.residual_vjp_material(uc, wc.reshape(-1, 3))
+        return du, dmu, dlam, None
+
+
+def energy(op, u, mu, lam, X=None):
+    return EnergyFn.apply(u, mu, lam, op.X if X is None else X, op)
+
+
+def residual(op, u, mu, lam):
+    return ResidualFn.apply(u, mu, lam, op)
