@@ -109,6 +109,13 @@ int efem_set_stream(efem_ctx *ctx, void *stream);
  * Copied into the context; mu, lam must be finite. */
 int efem_set_material(efem_ctx *ctx, const double *mu, const double *lam);
 
+/* Replace the reference coordinates (DEVICE float64 [3*n_nodes]) keeping the
+ * connectivity and the element blocks (e.g. for derivatives with respect to X
+ * by finite differences, or shape updates).  Copied; asynchronous.  The
+ * positivity of the reference Jacobians is not re-checked: an inverted
+ * reference element makes later results undefined. */
+int efem_set_coords(efem_ctx *ctx, const double *coords);
+
 /* Dirichlet mask (DEVICE uint8 [3*n_nodes], 1 = prescribed DOF), or NULL to
  * clear it.  With a mask set, the residual, the tangent action and the Jacobi
  * diagonal are those of the reduced functional over the free DOFs (Sec. 6.1):

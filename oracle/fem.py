@@ -246,7 +246,9 @@ def newton_solve(fem: FEM, mask, u_bc_final, opts: SolveOptions, u0=None):
         lifted into the free DOFs by solving K_ff d_f = -(K d_c)_f;
       * Newton: Jacobi-PCG on K_ff d = -r_f, forcing term by Eisenstat-Walker
         choice 2 with safeguards, then Armijo backtracking on the FP64 energy
-        (steps that invert an element have energy +inf and are rejected);
+        (steps that invert an element have energy +inf and are rejected; the
+        sufficient-decrease test allows 64 eps |Psi| for the energy's rounding,
+        below which a decrease cannot be resolved);
       * stop when ||r_f|| <= rtol ||r_f(step start)||.
     """
     mask = np.asarray(mask).reshape(-1)
@@ -311,7 +313,9 @@ def newton_solve(fem: FEM, mask, u_bc_final, opts: SolveOptions, u0=None):
             alpha = 1.0
             for _ in range(opts.max_halvings + 1):
                 e1 = fem.energy(u + alpha * d, allow_inverted=True)
-                if np.isfinite(e1) and e1 <= e0 + opts.armijo_c * alpha * slope:
+                # sufficient decrease up to the rounding of the energy sum (64 eps |Psi|)
+                noise = 64.0 * np.finfo(np.float64).eps * abs(e0)
+                if np.isfinite(e1) and e1 <= e0 + opts.armijo_c * alpha * slope + noise:
                     break
                 alpha *= 0.5
             else:

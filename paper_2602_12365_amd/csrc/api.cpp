@@ -415,6 +415,21 @@ int efem_set_material(efem_ctx *ctx, const double *mu, const double *lam)
     return EFEM_OK;
 }
 
+int efem_set_coords(efem_ctx *ctx, const double *coords)
+{
+    if (!ctx || !coords) {
+        set_error("efem_set_coords: null pointer");
+        return EFEM_ERR_INVALID;
+    }
+    DeviceGuard dg(ctx->device);
+    const size_t n = 3 * (size_t)ctx->n_nodes;
+    HIP_TRY(hipMemcpyAsync(const_cast<double *>(ctx->m.X), coords, n * sizeof(double),
+                           hipMemcpyDeviceToDevice, ctx->stream));
+    HIP_TRY(launch_cast_f32(ctx->m.X, const_cast<float *>(ctx->m.Xf), (int64_t)n, ctx->stream));
+    ctx->lin_prec = -1;   // a linearization point refers to the old coordinates
+    return EFEM_OK;
+}
+
 int efem_set_dirichlet(efem_ctx *ctx, const uint8_t *mask)
 {
     if (!ctx) return EFEM_ERR_INVALID;

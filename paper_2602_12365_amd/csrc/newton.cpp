@@ -7,7 +7,8 @@
 //     is lifted into the free DOFs by solving K_ff d_f = -(K dc)_f;
 //   * Newton iterations: Jacobi-PCG on K_ff d = -r_f with an Eisenstat-Walker
 //     (choice 2) forcing term, then Armijo backtracking on the FP64 energy
-//     (a step that inverts an element has energy +inf and is rejected);
+//     (a step that inverts an element has energy +inf and is rejected), with a
+//     slack of 64 eps |Psi| for the rounding of the energy sum;
 //   * stop when ||r_f|| <= rtol ||r_f at the start of the step||.
 // With hvp_prec = EFEM_F32 the CG vectors and tangent actions are float32;
 // the residual, energy, line search and state stay float64.
@@ -239,7 +240,10 @@ struct Solver {
                 for (; h <= o.max_halvings; ++h) {
                     TRY(L.axpy_state(u, alpha, x, u_trial));
                     if ((rc = energy(u_trial, e1))) return rc;
-                    if (std::isfinite(e1) && e1 <= e0 + o.armijo_c * alpha * slope) break;
+                    // sufficient decrease, up to the rounding of the FP64 energy sum: near the
+                    // solution the decrease falls below eps |Psi| and cannot be resolved
+                    const double noise = 64.0 * 2.220446049250313e-16 * std::fabs(e0);
+                    if (std::isfinite(e1) && e1 <= e0 + o.armijo_c * alpha * slope + noise) break;
                     alpha *= 0.5;
                 }
                 if (h > o.max_halvings) {

@@ -100,6 +100,15 @@ class Operator:
         L.check(self._lib.efem_set_material(self._h, _ptr(self._elemwise(mu, "mu")),
                                             _ptr(self._elemwise(lam, "lam"))), "efem_set_material")
 
+    def set_coords(self, X):
+        """Replace the reference coordinates (float64 [n_nodes, 3] device tensor),
+        keeping connectivity and blocks."""
+        self._sync_stream()
+        X = self._nodal(X, name="X")
+        L.check(self._lib.efem_set_coords(self._h, _ptr(X)), "efem_set_coords")
+        self.X = X.clone()
+        self._lin = None
+
     def set_dirichlet(self, mask):
         """mask: uint8 tensor [3*n_nodes] (1 = prescribed) or None."""
         self._sync_stream()
