@@ -106,7 +106,8 @@ void efem_destroy(efem_ctx *ctx);
 int efem_set_stream(efem_ctx *ctx, void *stream);
 
 /* Per-element material (DEVICE float64 [n_elems] each, caller's element order).
- * Copied into the context; mu, lam must be finite. */
+ * Copied into the context; mu, lam must be finite.  Synchronous: a field that
+ * is the same in every element is detected and kept as two scalars. */
 int efem_set_material(efem_ctx *ctx, const double *mu, const double *lam);
 
 /* Replace the reference coordinates (DEVICE float64 [3*n_nodes]) keeping the
@@ -147,6 +148,11 @@ int efem_hvp(efem_ctx *ctx, const void *v, void *y);
  * small launch to clear the entries that several blocks add into).  Same
  * arguments and errors as efem_hvp; prescribed entries of y are set to 0. */
 int efem_hvp_acc(efem_ctx *ctx, const void *v, void *y);
+
+/* y = K(u) v in a single launch for a y that holds zeros on entry (e.g. cleared
+ * by the caller's preceding vector kernel, as the library's Krylov loop does);
+ * the result is undefined if y is not zero.  Same arguments as efem_hvp. */
+int efem_hvp_zeroed(efem_ctx *ctx, const void *v, void *y);
 
 /* d = diag K(u), DEVICE float64 [3*n_nodes] (the Jacobi preconditioner);
  * with a Dirichlet mask, prescribed entries are 1. */
@@ -234,10 +240,69 @@ int efem_newton_solve(efem_ctx *ctx, double *u_inout, const double *u_bc,
 
 /* ------------------------------------------------- learned preconditioner */
 
-/* Number of parameters of the per-node MLP preconditioner, and its layout. */
-#define EFEM_MLP_IN   12
-#define EFEM_MLP_HID  64
-#define EFEM_MLP_OUT  3
+/* Learned CG preconditioner (this project's addition to the method, used by
+ * efem_newton_solve with precond = 1 and hvp_prec = EFEM_F32).  Per node i,
+ * with N(i) the nodes sharing an element with i and D the Jacobi diagonal:
+ *   g_i = D_i^-1 r_i (0 on prescribed DOFs), s_i = RMS of g over {i} + N(i),
+ *   f_i = [g_i/s_i, mean_N(i) g/s_i, log(D_i/mean_{N(i)+i} D), prescribed
+ *          fraction of i, of N(i), |N(i)|/26]                     (12 inputs)
+ *   z_i = g_i + s_i MLP(f_i), prescribed DOFs 0,
+ * MLP 12 -> 64 -> 64 -> 3 with softplus hidden layers (the activation of the
+ * paper's neural energy terms, Sec. 6.6.1), bfloat16 weights and layer inputs,
+ * FP32 accumulation on the matrix cores.  z is positively homogeneous in r;
+ * Krylov solves use flexible CG with Jacobi PCG as the fallback.
+ * Parameters: FP32 vector of EFEM_MLP_PARAMS values, W1 [64][12], b1 [64],
+ * W2 [64][64], b2 [64], W3 [3][64], b3 [3] (row-major, output index first). */
+#define EFEM_MLP_IN     12
+#define EFEM_MLP_HID    64
+#define EFEM_MLP_OUT    3
+#define EFEM_MLP_PARAMS 5187
+#define EFEM_MLP_AUX    12   /* floats per training row */
+
+/* Set the preconditioner's parameters (DEVICE float32 [EFEM_MLP_PARAMS],
+ * rounded to bfloat16 and copied), or NULL to remove the network.  The first
+ * call builds the node 1-ring graph (host work, synchronous). */
+int efem_set_mlp(efem_ctx *ctx, const float *params);
+
+/* z = M(r) (DEVICE float32 [3*n_nodes] each) with diag the Jacobi diagonal
+ * (DEVICE float64 [3*n_nodes], as efem_jacobi_diag returns it) and the context's
+ * Dirichlet mask.  EFEM_ERR_STATE without efem_set_mlp. */
+int efem_precond_apply(efem_ctx *ctx, const float *r, const double *diag, float *z);
+
+/* Training rows of one (right-hand side b, target t) pair, b and t DEVICE float32
+ * [3*n_nodes], diag as above: X DEVICE uint16 (bfloat16) [n_nodes][16] (the 12
+ * features, zero padded), aux DEVICE float32 [n_nodes][EFEM_MLP_AUX] =
+ * [g(3), t(3), free-DOF flags(3), s, w, 0] with w = 1 / (|t|^2 n_total), so that
+ * the loss of efem_mlp_loss_grad over all rows of n_total pairs is the mean over
+ * pairs of |M(b) - t|^2 / |t|^2.  Needs the graph (efem_set_mlp called once). */
+int efem_precond_rows(efem_ctx *ctx, const float *b, const double *diag, const float *t,
+                      double n_total, uint16_t *X, float *aux);
+
+/* out [rows][3] = MLP(X) on the matrix cores with the context's parameters. */
+int efem_mlp_forward(efem_ctx *ctx, int64_t rows, const uint16_t *X, float *out);
+
+/* Loss sum_rows w |m (g + s MLP_params(X)) - m t|^2 and its gradient with respect
+ * to params (DEVICE float32 [EFEM_MLP_PARAMS]) into grad (DEVICE float32
+ * [EFEM_MLP_PARAMS], overwritten) and loss (DEVICE float64 [1]); forward and
+ * backward on the vector units, the bfloat16 roundings of the forward treated
+ * as identity in the backward pass.  Deterministic. */
+int efem_mlp_loss_grad(efem_ctx *ctx, int64_t rows, const uint16_t *X, const float *aux,
+                       const float *params, float *grad, double *loss);
+
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8) on DEVICE float32 params,
+ * moments m, v and gradient g (all [EFEM_MLP_PARAMS]); t = step number >= 1. */
+int efem_mlp_adam(efem_ctx *ctx, float *params, float *m, float *v, const float *g, float lr,
+                  int32_t t);
+
+/* Solve K(u)_ff x = b (b, x DEVICE float64 [3*n_nodes]; prescribed entries of b
+ * ignored and of x set to 0) by preconditioned CG from x = 0 to
+ * ||b - K x|| <= rtol ||b||, with the tangent action in hvp_prec and precond 0
+ * (Jacobi) or 1 (learned, flexible CG, Jacobi fallback; needs EFEM_F32).
+ * Requires a Dirichlet mask.  Synchronous; *iters receives the CG iterations,
+ * *fallback 1 if the learned solve fell back to Jacobi. */
+int efem_linear_solve(efem_ctx *ctx, const double *u, const double *b, double *x, double rtol,
+                      int32_t hvp_prec, int32_t precond, int32_t max_iter, int32_t *iters,
+                      int32_t *fallback);
 
 const char *efem_last_error(void);
 

@@ -24,6 +24,7 @@ EFEM_F64, EFEM_F32 = 0, 1
 EFEM_SCATTER_ATOMIC, EFEM_SCATTER_COLOR = 0, 1
 
 EFEM_MLP_IN, EFEM_MLP_HID, EFEM_MLP_OUT = 12, 64, 3
+EFEM_MLP_PARAMS, EFEM_MLP_AUX = 5187, 12
 
 c_void_p = ctypes.c_void_p
 c_int32 = ctypes.c_int32
@@ -73,6 +74,7 @@ SIGNATURES = {
     "efem_linearize": (c_int32, [c_void_p, c_void_p, c_int32]),
     "efem_hvp": (c_int32, [c_void_p, c_void_p, c_void_p]),
     "efem_hvp_acc": (c_int32, [c_void_p, c_void_p, c_void_p]),
+    "efem_hvp_zeroed": (c_int32, [c_void_p, c_void_p, c_void_p]),
     "efem_jacobi_diag": (c_int32, [c_void_p, c_void_p, c_void_p]),
     "efem_grad_material": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p]),
     "efem_residual_vjp_material": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
@@ -82,6 +84,18 @@ SIGNATURES = {
     "efem_solve_opts_default": (None, [ctypes.POINTER(SolveOpts)]),
     "efem_newton_solve": (c_int32, [c_void_p, c_void_p, c_void_p, ctypes.POINTER(SolveOpts),
                                     ctypes.POINTER(SolveStats)]),
+    "efem_set_mlp": (c_int32, [c_void_p, c_void_p]),
+    "efem_precond_apply": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p]),
+    "efem_precond_rows": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_double, c_void_p,
+                                    c_void_p]),
+    "efem_mlp_forward": (c_int32, [c_void_p, c_int64, c_void_p, c_void_p]),
+    "efem_mlp_loss_grad": (c_int32, [c_void_p, c_int64, c_void_p, c_void_p, c_void_p, c_void_p,
+                                     c_void_p]),
+    "efem_mlp_adam": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, ctypes.c_float,
+                                c_int32]),
+    "efem_linear_solve": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_double, c_int32,
+                                    c_int32, c_int32, ctypes.POINTER(c_int32),
+                                    ctypes.POINTER(c_int32)]),
     "efem_last_error": (ctypes.c_char_p, []),
 }
 

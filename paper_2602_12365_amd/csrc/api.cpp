@@ -335,6 +335,7 @@ int efem_create(efem_ctx **out, int32_t elem, int64_t n_nodes, int64_t n_elems,
     ctx->threads = threads;
     (void)hipGetDevice(&ctx->device);
 
+    ctx->conn_host.assign(conn, conn + n_elems * nen);
     HostBlocks hb;
     build_blocks(nen, n_nodes, n_elems, coords, conn, be, bn, scatter == EFEM_SCATTER_COLOR, hb);
     ctx->max_block_nodes = hb.max_nodes;
@@ -372,9 +373,11 @@ int efem_create(efem_ctx **out, int32_t elem, int64_t n_nodes, int64_t n_elems,
     // default material mu = 1, lam = 1.5
     std::vector<double> ones((size_t)n_elems, 1.0), lam15((size_t)n_elems, 1.5);
     if ((rc = upload(*ctx, &ctx->mu, ones)) || (rc = upload(*ctx, &ctx->lam, lam15))) return fail(rc);
-    m.mu = ctx->mu;
-    m.lam = ctx->lam;
-    if ((rc = dalloc(*ctx, &ctx->flags, 1)) || (rc = dalloc(*ctx, &ctx->partials, m.n_blocks))
+    m.mu = nullptr;   // uniform until efem_set_material gives a varying field
+    m.lam = nullptr;
+    m.mu0 = 1.0;
+    m.lam0 = 1.5;
+    if ((rc = dalloc(*ctx, &ctx->flags, 2)) || (rc = dalloc(*ctx, &ctx->partials, m.n_blocks))
         || (rc = dalloc(*ctx, &ctx->counter, 1)))
         return fail(rc);
     if (hipMemset(ctx->flags, 0, sizeof(int32_t)) != hipSuccess
@@ -410,8 +413,27 @@ int efem_set_material(efem_ctx *ctx, const double *mu, const double *lam)
         return EFEM_ERR_INVALID;
     }
     DeviceGuard dg(ctx->device);
+    // a uniform field is passed to the kernels as two scalars (no per-element loads)
+    int32_t *flag = ctx->flags + 1;
+    const int32_t one = 1;
+    HIP_TRY(hipMemcpyAsync(flag, &one, sizeof(int32_t), hipMemcpyHostToDevice, ctx->stream));
+    HIP_TRY(launch_uniform_check(mu, lam, ctx->n_elems, flag, ctx->stream));
+    int32_t uni = 0;
+    double v0[2] = {0, 0};
+    HIP_TRY(hipMemcpyAsync(&uni, flag, sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(hipMemcpyAsync(&v0[0], mu, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(hipMemcpyAsync(&v0[1], lam, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    if (uni) {
+        ctx->m.mu = ctx->m.lam = nullptr;
+        ctx->m.mu0 = v0[0];
+        ctx->m.lam0 = v0[1];
+        return EFEM_OK;
+    }
     HIP_TRY(launch_permute_elems(*ctx, mu, ctx->mu));
     HIP_TRY(launch_permute_elems(*ctx, lam, ctx->lam));
+    ctx->m.mu = ctx->mu;
+    ctx->m.lam = ctx->lam;
     return EFEM_OK;
 }
 
@@ -492,7 +514,7 @@ int efem_linearize(efem_ctx *ctx, const double *u, int32_t prec)
     return EFEM_OK;
 }
 
-static int hvp_impl(efem_ctx *ctx, const void *v, void *y, bool acc, const char *name)
+static int hvp_impl(efem_ctx *ctx, const void *v, void *y, WriteMode mode, const char *name)
 {
     if (!ctx || !v || !y) {
         set_error(std::string(name) + ": null pointer");
@@ -508,17 +530,25 @@ static int hvp_impl(efem_ctx *ctx, const void *v, void *y, bool acc, const char 
     }
     DeviceGuard dg(ctx->device);
     if (ctx->lin_prec == EFEM_F64)
-        HIP_TRY(launch_hvp_f64(*ctx, ctx->xlin, (const double *)v, (double *)y, nullptr, acc));
+        HIP_TRY(launch_hvp_f64(*ctx, ctx->xlin, (const double *)v, (double *)y, nullptr, mode));
     else
-        HIP_TRY(launch_hvp_f32(*ctx, ctx->ulin, (const float *)v, (float *)y, nullptr, acc));
+        HIP_TRY(launch_hvp_f32(*ctx, ctx->ulin, (const float *)v, (float *)y, nullptr, mode));
     return EFEM_OK;
 }
 
-int efem_hvp(efem_ctx *ctx, const void *v, void *y) { return hvp_impl(ctx, v, y, false, "efem_hvp"); }
+int efem_hvp(efem_ctx *ctx, const void *v, void *y)
+{
+    return hvp_impl(ctx, v, y, WriteMode::Overwrite, "efem_hvp");
+}
 
 int efem_hvp_acc(efem_ctx *ctx, const void *v, void *y)
 {
-    return hvp_impl(ctx, v, y, true, "efem_hvp_acc");
+    return hvp_impl(ctx, v, y, WriteMode::Accumulate, "efem_hvp_acc");
+}
+
+int efem_hvp_zeroed(efem_ctx *ctx, const void *v, void *y)
+{
+    return hvp_impl(ctx, v, y, WriteMode::Zeroed, "efem_hvp_zeroed");
 }
 
 int efem_jacobi_diag(efem_ctx *ctx, const double *u, double *d)

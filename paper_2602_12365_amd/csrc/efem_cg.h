@@ -10,17 +10,19 @@ namespace efem {
 
 constexpr int kMaxRedBlocks = 1024;   // grid cap of the streaming reductions
 
-// Device-resident scalars of one CG solve.
+// Device-resident scalars of one CG solve; rz is kept for two iterations
+// (slot = iteration parity) so that it can be replaced while being read.
 struct CgScalars {
-    double rz, rr, bb, tol2, pq, alpha, beta, pad;
-    int32_t done, breakdown, iter, pad2;
+    double rz[2], rr, bb, tol2, pq, alpha, beta, best;
+    int32_t done, breakdown, iter, fallback, stall, pad;
 };
 
-// Reduction scratch: 2 doubles per block and a last-block ticket.
+// Reduction scratch: four arrays of per-workgroup partials.
 struct CgWorkspace {
-    double *partials = nullptr;   // [2 * kMaxRedBlocks]
-    uint32_t *counter = nullptr;  // must be 0 between kernels
+    double *partials = nullptr;   // [4 * kMaxRedBlocks]
 };
+
+int red_grid(int64_t n);
 
 template <class T>
 struct CgLaunch {
@@ -31,14 +33,31 @@ struct CgLaunch {
     hipError_t init(const double *b, double sign, const T *dinv, const uint8_t *nmask, T *x, T *r,
                     T *p, T *q, CgScalars *sc, double eta2) const;
     hipError_t pq(const T *p, const T *q, CgScalars *sc) const;
-    hipError_t update(T *x, T *r, const T *p, T *q, const T *dinv, CgScalars *sc) const;
-    hipError_t dir(T *p, const T *r, const T *dinv, const CgScalars *sc) const;
+    hipError_t update(T *x, T *r, const T *p, T *q, const T *dinv, CgScalars *sc, int j) const;
+    hipError_t dir(T *p, const T *r, const T *dinv, CgScalars *sc, int j) const;
     hipError_t dinv_from_diag(const double *diag, const uint8_t *nmask, T *dinv) const;
     hipError_t axpy_state(const double *u, double alpha, const T *d, double *out) const;
     hipError_t scaled(const T *dinv, const double *b, double sign, T *x) const;
     hipError_t dot_state(const double *a, const T *b, double *out) const;
     hipError_t apply_predictor(const double *u_old, const double *dc, const T *df,
                                const uint8_t *nmask, bool use_df, double *u) const;
+};
+
+// Flexible CG with a nonlinear preconditioner z = M(r) (Notay's flexible CG:
+// Polak-Ribiere beta = r.(z_new - z_old) / rz_old).  The apply kernel writes
+// partials of r.z into `prz` (count `nz`).
+template <class T>
+struct FcgLaunch {
+    int64_t n;
+    hipStream_t s;
+    CgWorkspace ws;
+    // after M(r) -> z: rz = r.z; p = z; breakdown / fallback if rz <= 0
+    hipError_t start(const T *z, T *p, CgScalars *sc, const double *prz, int nz) const;
+    // alpha = rz/pq; x += alpha p; r -= alpha q; q = 0; partials of r.r and r.z_old
+    hipError_t update(T *x, T *r, const T *p, T *q, const T *zold, CgScalars *sc, int j) const;
+    // convergence / stagnation test; beta = (r.z_new - r.z_old)/rz; p = z + beta p
+    hipError_t dir(T *p, const T *z, CgScalars *sc, const double *prz, int nz, int j,
+                   int stall_limit) const;
 };
 
 hipError_t launch_bc_increment(hipStream_t s, int64_t n, const double *u, const double *u_bc,

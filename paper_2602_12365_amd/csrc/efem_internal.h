@@ -27,7 +27,8 @@ struct BlockMesh {
     const int32_t *eorig;     // [n_elems] internal -> caller element id
     const double *X;          // [n_nodes*3]
     const float *Xf;          // [n_nodes*3]
-    const double *mu, *lam;   // [n_elems] internal order
+    const double *mu, *lam;   // [n_elems] internal order, or null: uniform (mu0, lam0)
+    double mu0, lam0;
     const uint8_t *nmask;     // [n_nodes] bit c = component c prescribed, or null
     int32_t *flags;           // bit 0: det F <= 0 met
 };
@@ -46,11 +47,15 @@ struct Ctx;
 // All return hipError_t of the launch.  T = double or float.
 hipError_t launch_energy(const Ctx &c, const double *u, double *psi);
 hipError_t launch_residual(const Ctx &c, const double *u, double *r);
-// acc = false: y = K v (shared nodes zeroed by a pre-pass); acc = true: y += K v, one launch
+// How a nodal output is written:
+//   Overwrite:  y = K v (a small pre-pass clears the entries several blocks add into);
+//   Accumulate: y += K v, one launch (plain read-modify-write on block-private nodes);
+//   Zeroed:     y = K v for a y that holds zeros on entry, one launch.
+enum class WriteMode { Overwrite = 0, Accumulate = 1, Zeroed = 2 };
 hipError_t launch_hvp_f64(const Ctx &c, const double *xlin, const double *v, double *y,
-                          const int32_t *skip, bool acc);
+                          const int32_t *skip, WriteMode mode);
 hipError_t launch_hvp_f32(const Ctx &c, const float *ulin, const float *v, float *y,
-                          const int32_t *skip, bool acc);
+                          const int32_t *skip, WriteMode mode);
 hipError_t launch_diag(const Ctx &c, const double *u, double *d);
 hipError_t launch_grad_material(const Ctx &c, const double *u, double *dmu, double *dlam);
 hipError_t launch_vjp_material(const Ctx &c, const double *u, const double *w, double *dmu,
@@ -62,6 +67,9 @@ hipError_t launch_permute_elems(const Ctx &c, const double *src, double *dst);
 hipError_t launch_build_nmask(const Ctx &c, const uint8_t *dofmask, uint8_t *nmask);
 hipError_t launch_add_x_u(const Ctx &c, const double *u, double *x);
 hipError_t launch_cast_f32(const double *src, float *dst, int64_t n, hipStream_t s);
+// flag = 1 if a[i] == a[0] and b[i] == b[0] for all i (flag must hold 1 on entry)
+hipError_t launch_uniform_check(const double *a, const double *b, int64_t n, int32_t *flag,
+                                hipStream_t s);
 
 // ---- context ---------------------------------------------------------------
 struct Ctx {
@@ -91,8 +99,10 @@ struct Ctx {
     double *xlin = nullptr;   // X + u  (FP64 tangent)
     float *ulin = nullptr;    // u in FP32 (FP32 tangent)
 
-    // learned preconditioner state (see precond.cpp)
+    // learned preconditioner state (precond.cpp) and the host connectivity it
+    // builds the node 1-ring from
     void *mlp = nullptr;
+    std::vector<int32_t> conn_host;
 };
 
 // learned preconditioner resources of a context (precond.cpp)

@@ -1,0 +1,60 @@
+// Learned-preconditioner declarations shared by kernels_mlp.hip and precond.cpp.
+#pragma once
+
+#include <algorithm>
+
+#include "efem_internal.h"
+
+namespace efem {
+
+constexpr int kIn = EFEM_MLP_IN, kInPad = 16, kHid = EFEM_MLP_HID, kOut = EFEM_MLP_OUT;
+constexpr int kAux = 12;   // training row: g(3), t(3), m(3), s, w, pad
+// flat parameter layout: W1 [64][12], b1 [64], W2 [64][64], b2 [64], W3 [3][64], b3 [3]
+constexpr int kOffW1 = 0;
+constexpr int kOffB1 = kOffW1 + kHid * kIn;
+constexpr int kOffW2 = kOffB1 + kHid;
+constexpr int kOffB2 = kOffW2 + kHid * kHid;
+constexpr int kOffW3 = kOffB2 + kHid;
+constexpr int kOffB3 = kOffW3 + kOut * kHid;
+constexpr int kP = kOffB3 + kOut;
+static_assert(kP == EFEM_MLP_PARAMS, "parameter count");
+
+// Per-context state of the learned preconditioner.
+struct MlpState {
+    int64_t *ptr = nullptr;      // [n_nodes+1] node 1-ring CSR
+    int32_t *idx = nullptr;
+    uint16_t *W = nullptr;       // bf16 parameters [kP]
+    bool have_weights = false;
+    uint16_t *X = nullptr;       // [n_nodes][16] bf16 features
+    float *scale = nullptr;      // [n_nodes]
+    float *dinv = nullptr;       // [3 n_nodes]
+    float *z = nullptr;          // [3 n_nodes] scratch of the apply
+    float *zold = nullptr;       // [3 n_nodes] flexible CG
+    double *prz = nullptr;       // [2048] partials
+    float *gpart = nullptr;      // [kGradBlocks][kP]
+    double *lpart = nullptr;     // [kGradBlocks]
+    double *tt = nullptr;        // scalar
+    std::vector<void *> owned;
+};
+constexpr int kGradBlocks = 1024;
+
+hipError_t mlp_features_static(hipStream_t s, const MlpState &M, int64_t n, const double *diag,
+                               const uint8_t *nmask, uint16_t *X);
+hipError_t mlp_features_dyn(hipStream_t s, const MlpState &M, int64_t n, const float *r,
+                            const float *dinv, uint16_t *X, float *scale);
+hipError_t mlp_forward(hipStream_t s, const uint16_t *W, int64_t n, const uint16_t *X, float *out);
+int mlp_apply_grid(int64_t n);
+hipError_t mlp_apply(hipStream_t s, const uint16_t *W, int64_t n, const uint16_t *X, const float *r,
+                     const float *dinv, const float *scale, float *z, double *prz);
+hipError_t mlp_rows_aux(hipStream_t s, int64_t n, const float *b, const float *dinv, const float *t,
+                        const float *scale, double *tt, double n_total, float *aux);
+hipError_t mlp_loss_grad(hipStream_t s, int64_t rows, const uint16_t *X, const float *aux,
+                         const float *params, float *gpart, double *lpart, int G, float *grad,
+                         double *loss);
+hipError_t mlp_adam(hipStream_t s, float *p, float *m, float *v, const float *g, float lr, float b1,
+                    float b2, float eps, int t);
+hipError_t mlp_to_bf16(hipStream_t s, const float *p, uint16_t *out);
+hipError_t mlp_dinv_f32(hipStream_t s, int64_t n, const double *diag, const uint8_t *nmask,
+                        float *dinv);
+
+}  // namespace efem

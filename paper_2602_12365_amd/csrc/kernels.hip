@@ -8,8 +8,9 @@
 //   3. write the block's nodal sums out: nodes owned by this block alone with
 //      plain stores, nodes shared with other blocks with global atomics (or,
 //      in the colour scatter, with a plain read-modify-write per colour).
-// The energy reduces per block and the last block to finish sums the block
-// partials in block order, so the energy is bitwise deterministic.
+// The energy reduces per block and a one-workgroup kernel sums the block
+// partials in block order, so the energy is bitwise deterministic.  Nodal sums
+// are accumulated in FP64 in LDS for both precisions.
 //
 // Quadrature-point math (Eq. 2 and its exact derivatives, Eqs. 1 and 3) is
 // written in terms of the reference Jacobian Jx = dX/dxi, the deformed one
@@ -51,7 +52,19 @@ __device__ __forceinline__ T adj_det(const T m[9], T a[9])
     return m[0] * a[0] + m[1] * a[3] + m[2] * a[6];
 }
 
-template <class T> __device__ __forceinline__ T rcp(T x) { return T(1) / x; }
+// Reciprocal: the hardware estimate refined by two Newton-Raphson steps
+// r <- r + r (1 - x r) (each step squares the relative error), so the FP64
+// result is correct to about an ulp for the normal-range determinants used
+// here; FP32 uses the hardware reciprocal directly (1 ulp).
+__device__ __forceinline__ double rcp(double x)
+{
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
+__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
 __device__ __forceinline__ double log_(double x) { return log(x); }
 __device__ __forceinline__ float log_(float x) { return __logf(x); }
@@ -280,7 +293,7 @@ __device__ __forceinline__ bool comp_fixed(const uint8_t *nmask, int64_t g, int 
 // Write the block's nodal sums acc[l*3+c] out; prescribed components get `fixed_val`.
 template <bool ACC, class T>
 __device__ __forceinline__ void write_out(const BlockMesh &m, const uint32_t *bnode, int nn,
-                                          const T *acc, T *__restrict__ y, Scatter mode,
+                                          const double *acc, T *__restrict__ y, Scatter mode,
                                           bool use_mask, T fixed_val)
 {
     for (int l = threadIdx.x; l < nn; l += blockDim.x) {
@@ -289,7 +302,7 @@ __device__ __forceinline__ void write_out(const BlockMesh &m, const uint32_t *bn
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             const bool fixed = use_mask && comp_fixed(m.nmask, g, c);
-            T val = acc[l * 3 + c];
+            T val = T(acc[l * 3 + c]);
             T *dst = &y[3 * g + c];
             if (ACC) {
                 // y += K v: plain read-modify-write where no other block writes
@@ -558,6 +571,47 @@ struct GradCoordsOp : XUStage {
     }
 };
 
+// ------------------------------------------------------- per-element inputs
+
+// Local connectivity of one element in one vector load (4 or 8 uint16), plus
+// its material.  Loaded one element ahead of its use so that the global-load
+// latency overlaps the previous element's arithmetic.
+template <int NEN> struct LWord;
+template <> struct LWord<4> { uint2 w; };
+template <> struct LWord<8> { uint4 w; };
+
+template <class E> struct EData {
+    LWord<E::NEN> lc;
+    double mu, lam;
+};
+
+template <class E>
+__device__ __forceinline__ EData<E> fetch_elem(const BlockMesh &m, int e)
+{
+    EData<E> d;
+    if constexpr (E::NEN == 4) d.lc.w = *reinterpret_cast<const uint2 *>(m.lconn + (int64_t)e * 4);
+    else d.lc.w = *reinterpret_cast<const uint4 *>(m.lconn + (int64_t)e * 8);
+    if (m.mu) {
+        d.mu = m.mu[e];
+        d.lam = m.lam[e];
+    } else {
+        d.mu = m.mu0;
+        d.lam = m.lam0;
+    }
+    return d;
+}
+
+template <class E>
+__device__ __forceinline__ void unpack_lc(const LWord<E::NEN> &l, uint16_t lc[E::NEN])
+{
+    if constexpr (E::NEN == 4) {
+        lc[0] = l.w.x & 0xffff, lc[1] = l.w.x >> 16, lc[2] = l.w.y & 0xffff, lc[3] = l.w.y >> 16;
+    } else {
+        lc[0] = l.w.x & 0xffff, lc[1] = l.w.x >> 16, lc[2] = l.w.y & 0xffff, lc[3] = l.w.y >> 16;
+        lc[4] = l.w.z & 0xffff, lc[5] = l.w.z >> 16, lc[6] = l.w.w & 0xffff, lc[7] = l.w.w >> 16;
+    }
+}
+
 // ---------------------------------------------------------- block pass kernel
 
 template <class E, class Op, class T, bool ACC>
@@ -574,29 +628,42 @@ __global__ void __launch_bounds__(256) k_accumulate(BlockMesh m, Op op, T *__res
     const int n0 = m.nstart[b], nn = m.nstart[b + 1] - n0;
     const int e0 = m.estart[b], ne = m.estart[b + 1] - e0;
     Node *sn = reinterpret_cast<Node *>(smem);
-    T *acc = reinterpret_cast<T *>(smem + sizeof(Node) * nn);
+    // nodal sums are accumulated in FP64 in LDS for both precisions
+    double *acc = reinterpret_cast<double *>(smem + sizeof(Node) * nn);
     const uint32_t *bnode = m.bnode + n0;
-    for (int l = threadIdx.x; l < nn; l += blockDim.x) {
+    const int nt = blockDim.x;
+    // The 64 lanes of a wave take elements S apart in the block's Morton order
+    // (lane * S + j), so that the lanes of one LDS atomic rarely hit the same
+    // node; wave w takes columns j = w, w + W, ...
+    const int W = nt >> 6, lane = threadIdx.x & 63;
+    const int S = (ne + 63) >> 6;
+    int j = threadIdx.x >> 6;
+    auto elem_of = [&](int jj) { return lane * S + jj; };
+    EData<E> nxt{};
+    if (j < S && elem_of(j) < ne) nxt = fetch_elem<E>(m, e0 + elem_of(j));   // in flight during staging
+    for (int l = threadIdx.x; l < nn; l += nt) {
         op.stage(m, sn[l], bnode[l] & kGidMask);
-        acc[3 * l + 0] = T(0);
-        acc[3 * l + 1] = T(0);
-        acc[3 * l + 2] = T(0);
+        acc[3 * l + 0] = 0.0;
+        acc[3 * l + 1] = 0.0;
+        acc[3 * l + 2] = 0.0;
     }
     __syncthreads();
     bool bad = false;
-    for (int k = threadIdx.x; k < ne; k += blockDim.x) {
-        const int e = e0 + k;
+    for (; j < S; j += W) {
+        const int k = elem_of(j);
+        if (k >= ne) break;
+        const EData<E> cur = nxt;
+        if (j + W < S && elem_of(j + W) < ne) nxt = fetch_elem<E>(m, e0 + elem_of(j + W));
         uint16_t lc[E::NEN];
-#pragma unroll
-        for (int a = 0; a < E::NEN; ++a) lc[a] = m.lconn[(int64_t)e * E::NEN + a];
+        unpack_lc<E>(cur.lc, lc);
         T f[E::NEN][3];
 #pragma unroll
         for (int a = 0; a < E::NEN; ++a) f[a][0] = f[a][1] = f[a][2] = T(0);
-        bad |= !op.template element<E>(sn, lc, T(m.mu[e]), T(m.lam[e]), f);
+        bad |= !op.template element<E>(sn, lc, T(cur.mu), T(cur.lam), f);
 #pragma unroll
         for (int a = 0; a < E::NEN; ++a)
 #pragma unroll
-            for (int i = 0; i < 3; ++i) atomicAdd(&acc[3 * lc[a] + i], f[a][i]);
+            for (int i = 0; i < 3; ++i) atomicAdd(&acc[3 * lc[a] + i], (double)f[a][i]);
     }
     if (bad) flag_inverted(m.flags);
     __syncthreads();
@@ -620,30 +687,33 @@ __global__ void k_zero_shared(const int32_t *__restrict__ nodes, int64_t n, T *_
 
 template <class E>
 __global__ void __launch_bounds__(256) k_energy(BlockMesh m, const double *__restrict__ X,
-                                                const double *__restrict__ u, double *partials,
-                                                uint32_t *counter, double *__restrict__ psi)
+                                                const double *__restrict__ u,
+                                                double *__restrict__ partials)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ double red[256];
-    __shared__ bool last;
     const int count = m.n_blocks;
     const int b = xcd_remap(blockIdx.x, count);
     const int n0 = m.nstart[b], nn = m.nstart[b + 1] - n0;
     const int e0 = m.estart[b], ne = m.estart[b + 1] - e0;
     NodeXU *sn = reinterpret_cast<NodeXU *>(smem);
     XUStage st{X, u};
-    for (int l = threadIdx.x; l < nn; l += blockDim.x) st.stage(m, sn[l], m.bnode[n0 + l] & kGidMask);
+    const int nt = blockDim.x;
+    int k = threadIdx.x;
+    EData<E> nxt{};
+    if (k < ne) nxt = fetch_elem<E>(m, e0 + k);
+    for (int l = threadIdx.x; l < nn; l += nt) st.stage(m, sn[l], m.bnode[n0 + l] & kGidMask);
     __syncthreads();
     double acc = 0.0;
     bool bad = false;
-    for (int k = threadIdx.x; k < ne; k += blockDim.x) {
-        const int e = e0 + k;
+    for (; k < ne; k += nt) {
+        const EData<E> cur = nxt;
+        if (k + nt < ne) nxt = fetch_elem<E>(m, e0 + k + nt);
         uint16_t lc[E::NEN];
-#pragma unroll
-        for (int a = 0; a < E::NEN; ++a) lc[a] = m.lconn[(int64_t)e * E::NEN + a];
+        unpack_lc<E>(cur.lc, lc);
         double Xe[E::NEN][3], ue[E::NEN][3];
         gather_xu<E>(sn, lc, Xe, ue);
-        const double mu = m.mu[e], lam = m.lam[e];
+        const double mu = cur.mu, lam = cur.lam;
         double pe = 0.0;
 #pragma unroll
         for (int q = 0; q < E::NQ; ++q) {
@@ -672,33 +742,30 @@ __global__ void __launch_bounds__(256) k_energy(BlockMesh m, const double *__res
         if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
         __syncthreads();
     }
-    if (threadIdx.x == 0) {
-        partials[b] = red[0];
-        __threadfence();
-        const uint32_t t = atomicAdd(counter, 1u);
-        last = (t == (uint32_t)count - 1);
-    }
-    __syncthreads();
-    if (!last) return;
-    __threadfence();
-    // last block: Neumaier sums over a fixed strided assignment, then a fixed tree
+    if (threadIdx.x == 0) partials[b] = red[0];
+}
+
+// One workgroup: Neumaier sums of the block partials over a fixed strided
+// assignment, then a fixed tree.  A separate launch, so the partials of the
+// previous kernel are visible without device-wide fences.
+__global__ void __launch_bounds__(256) k_sum_partials(const double *__restrict__ partials, int count,
+                                                      double *__restrict__ out)
+{
+    __shared__ double red[256];
     double s = 0.0, c = 0.0;
     for (int i = threadIdx.x; i < count; i += blockDim.x) {
-        const double x = __builtin_nontemporal_load(&partials[i]);
+        const double x = partials[i];
         const double t = s + x;
-        c += (fabs(s) >= fabs(x)) ? ((s - t) + x) : ((x - t) + s);
+        if (isfinite(t)) c += (fabs(s) >= fabs(x)) ? ((s - t) + x) : ((x - t) + s);
         s = t;
     }
-    red[threadIdx.x] = s + c;
+    red[threadIdx.x] = isfinite(s) ? s + c : s;
     __syncthreads();
     for (int k = blockDim.x / 2; k > 0; k >>= 1) {
         if ((int)threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
         __syncthreads();
     }
-    if (threadIdx.x == 0) {
-        *psi = red[0];
-        *counter = 0u;
-    }
+    if (threadIdx.x == 0) *out = red[0];
 }
 
 // ------------------------------------------------- per-element adjoint kernels
@@ -834,10 +901,10 @@ static size_t lds_bytes(const Ctx &c, size_t acc_elem)
 
 template <class E, class Op, class T>
 static hipError_t run_accumulate(const Ctx &c, const Op &op, T *y, bool use_mask, T fixed_val,
-                                 const int32_t *skip, bool acc)
+                                 const int32_t *skip, WriteMode mode)
 {
-    const size_t lds = lds_bytes<Op>(c, sizeof(T));
-    if (acc) {
+    const size_t lds = lds_bytes<Op>(c, sizeof(double));
+    if (mode == WriteMode::Accumulate) {
         for (const Pass &p : c.passes) {
             if (p.count == 0) continue;
             hipLaunchKernelGGL((k_accumulate<E, Op, T, true>), dim3(p.count), dim3(c.threads), lds,
@@ -846,7 +913,7 @@ static hipError_t run_accumulate(const Ctx &c, const Op &op, T *y, bool use_mask
         }
         return hipGetLastError();
     }
-    if (c.scatter == Scatter::Atomic && c.n_shared > 0) {
+    if (mode == WriteMode::Overwrite && c.scatter == Scatter::Atomic && c.n_shared > 0) {
         const int64_t n = c.n_shared;
         hipLaunchKernelGGL((k_zero_shared<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
                            c.stream, c.shared_nodes, n, y, use_mask ? c.m.nmask : nullptr,
@@ -863,10 +930,10 @@ static hipError_t run_accumulate(const Ctx &c, const Op &op, T *y, bool use_mask
 
 template <class Op, class T>
 static hipError_t dispatch(const Ctx &c, const Op &op, T *y, bool use_mask, T fixed_val,
-                           const int32_t *skip = nullptr, bool acc = false)
+                           const int32_t *skip = nullptr, WriteMode mode = WriteMode::Overwrite)
 {
-    return c.elem == EFEM_TET4 ? run_accumulate<Tet4>(c, op, y, use_mask, fixed_val, skip, acc)
-                               : run_accumulate<Hex8>(c, op, y, use_mask, fixed_val, skip, acc);
+    return c.elem == EFEM_TET4 ? run_accumulate<Tet4>(c, op, y, use_mask, fixed_val, skip, mode)
+                               : run_accumulate<Hex8>(c, op, y, use_mask, fixed_val, skip, mode);
 }
 
 hipError_t launch_residual(const Ctx &c, const double *u, double *r)
@@ -894,17 +961,17 @@ hipError_t launch_grad_coords(const Ctx &c, const double *u, double *g)
 }
 
 hipError_t launch_hvp_f64(const Ctx &c, const double *xlin, const double *v, double *y,
-                          const int32_t *skip, bool acc)
+                          const int32_t *skip, WriteMode mode)
 {
     HvpOp<double> op{c.m.X, xlin, v, y};
-    return dispatch(c, op, y, true, 0.0, skip, acc);
+    return dispatch(c, op, y, true, 0.0, skip, mode);
 }
 
 hipError_t launch_hvp_f32(const Ctx &c, const float *ulin, const float *v, float *y,
-                          const int32_t *skip, bool acc)
+                          const int32_t *skip, WriteMode mode)
 {
     HvpOp<float> op{c.m.Xf, ulin, v, y};
-    return dispatch(c, op, y, true, 0.0f, skip, acc);
+    return dispatch(c, op, y, true, 0.0f, skip, mode);
 }
 
 hipError_t launch_energy(const Ctx &c, const double *u, double *psi)
@@ -912,10 +979,11 @@ hipError_t launch_energy(const Ctx &c, const double *u, double *psi)
     const size_t lds = sizeof(NodeXU) * (size_t)c.max_block_nodes;
     if (c.elem == EFEM_TET4)
         hipLaunchKernelGGL(k_energy<Tet4>, dim3(c.m.n_blocks), dim3(256), lds, c.stream, c.m, c.m.X,
-                           u, c.partials, c.counter, psi);
+                           u, c.partials);
     else
         hipLaunchKernelGGL(k_energy<Hex8>, dim3(c.m.n_blocks), dim3(256), lds, c.stream, c.m, c.m.X,
-                           u, c.partials, c.counter, psi);
+                           u, c.partials);
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, c.stream, c.partials, c.m.n_blocks, psi);
     return hipGetLastError();
 }
 

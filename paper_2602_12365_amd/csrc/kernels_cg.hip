@@ -1,10 +1,13 @@
-// Streaming kernels of the Krylov solve.  CG scalars live on the device: each
-// reduction ends with the last workgroup (ticket counter) summing the block
-// partials in block order -- deterministic -- and deriving the next scalars
-// (alpha, beta, convergence), so that a batch of iterations runs without host
-// round trips; once `done` is set every later kernel of the batch returns at
-// once.  Vectors are float64 (plain solve) or float32 (mixed precision);
-// every reduction accumulates in float64.
+// Streaming kernels of the Krylov solve.  CG scalars live on the device so a
+// batch of iterations runs without host round trips.  Reductions are split
+// across kernel boundaries instead of device-wide fences: a kernel writes one
+// partial per workgroup with plain stores, and every workgroup of the next
+// kernel sums those partials in the same fixed order, so all of them derive
+// identical scalars (alpha, beta, convergence) and the result is
+// deterministic.  Workgroup 0 publishes the scalars the host reads.  Once
+// `done` is set, every later kernel of the batch returns at once.  Vectors are
+// float64 (plain solve) or float32 (mixed precision); every reduction
+// accumulates in float64.
 #include "efem_cg.h"
 
 namespace efem {
@@ -16,67 +19,40 @@ __device__ __forceinline__ bool dof_fixed(const uint8_t *nmask, int64_t i)
     return nmask && ((nmask[i / 3] >> (i % 3)) & 1);
 }
 
-// Sum two per-thread values over the grid.  Returns true in thread 0 of the
-// last block, with the totals in s0, s1.
-__device__ bool grid_sum2(double a, double b, double *partials, uint32_t *counter, double &s0,
-                          double &s1)
-{
-    __shared__ double ra[kThreads], rb[kThreads];
-    __shared__ bool last;
-    ra[threadIdx.x] = a;
-    rb[threadIdx.x] = b;
-    __syncthreads();
-    for (int s = kThreads / 2; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s) {
-            ra[threadIdx.x] += ra[threadIdx.x + s];
-            rb[threadIdx.x] += rb[threadIdx.x + s];
-        }
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-        partials[2 * blockIdx.x] = ra[0];
-        partials[2 * blockIdx.x + 1] = rb[0];
-        __threadfence();
-        last = atomicAdd(counter, 1u) == gridDim.x - 1;
-    }
-    __syncthreads();
-    if (!last) return false;
-    __threadfence();
-    double x = 0.0, y = 0.0;
-    for (unsigned i = threadIdx.x; i < gridDim.x; i += kThreads) {
-        x += __hip_atomic_load(&partials[2 * i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        y += __hip_atomic_load(&partials[2 * i + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    ra[threadIdx.x] = x;
-    rb[threadIdx.x] = y;
-    __syncthreads();
-    for (int s = kThreads / 2; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s) {
-            ra[threadIdx.x] += ra[threadIdx.x + s];
-            rb[threadIdx.x] += rb[threadIdx.x + s];
-        }
-        __syncthreads();
-    }
-    if (threadIdx.x != 0) return false;
-    s0 = ra[0];
-    s1 = rb[0];
-    *counter = 0u;
-    return true;
-}
-
 #define GRID_STRIDE(i, n) \
     for (int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x; i < (n); i += (int64_t)gridDim.x * kThreads)
 
-// r = sign * b (prescribed -> 0), z = dinv r, p = z, x = 0, q = 0; rz, rr.
+// Workgroup tree sum of one value per thread; every thread gets the total.
+__device__ __forceinline__ double block_sum(double v, double *red)
+{
+    __syncthreads();
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int s = kThreads / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    return red[0];
+}
+
+// Sum of the `count` partials of the previous kernel (same order in every workgroup).
+__device__ __forceinline__ double sum_partials(const double *part, int count, double *red)
+{
+    double s = 0.0;
+    for (int i = threadIdx.x; i < count; i += kThreads) s += part[i];
+    return block_sum(s, red);
+}
+
+// r = sign * b (prescribed -> 0), z = dinv r, p = z, x = 0, q = 0; partials of r.r, r.z
 template <class T>
 __global__ void __launch_bounds__(kThreads) k_cg_init(int64_t n, const double *__restrict__ b,
                                                       double sign, const T *__restrict__ dinv,
                                                       const uint8_t *__restrict__ nmask,
                                                       T *__restrict__ x, T *__restrict__ r,
                                                       T *__restrict__ p, T *__restrict__ q,
-                                                      CgScalars *sc, double eta2, double *partials,
-                                                      uint32_t *counter)
+                                                      double *__restrict__ prr, double *__restrict__ prz)
 {
+    __shared__ double red[kThreads];
     double rz = 0.0, rr = 0.0;
     GRID_STRIDE(i, n)
     {
@@ -89,51 +65,80 @@ __global__ void __launch_bounds__(kThreads) k_cg_init(int64_t n, const double *_
         rz += (double)ri * (double)zi;
         rr += (double)ri * (double)ri;
     }
-    double s0, s1;
-    if (grid_sum2(rz, rr, partials, counter, s0, s1)) {
-        sc->rz = s0;
-        sc->rr = s1;
-        sc->bb = s1;
-        sc->tol2 = eta2 * s1;
-        sc->done = (s1 == 0.0) ? 1 : 0;
+    const double srr = block_sum(rr, red);
+    const double srz = block_sum(rz, red);
+    if (threadIdx.x == 0) {
+        prr[blockIdx.x] = srr;
+        prz[blockIdx.x] = srz;
+    }
+}
+
+__global__ void __launch_bounds__(kThreads) k_cg_init_fin(const double *__restrict__ prr,
+                                                          const double *__restrict__ prz, int count,
+                                                          CgScalars *sc, double eta2)
+{
+    __shared__ double red[kThreads];
+    const double rr = sum_partials(prr, count, red);
+    const double rz = sum_partials(prz, count, red);
+    if (threadIdx.x == 0) {
+        sc->rz[0] = rz;
+        sc->rz[1] = 0.0;
+        sc->rr = rr;
+        sc->bb = rr;
+        sc->tol2 = eta2 * rr;
+        sc->done = (rr == 0.0) ? 1 : 0;
         sc->breakdown = 0;
+        sc->fallback = 0;
+        sc->stall = 0;
+        sc->best = rr;
         sc->iter = 0;
         sc->alpha = sc->beta = sc->pq = 0.0;
     }
 }
 
-// pq = p . q; alpha = rz / pq, or breakdown if pq <= 0 / not finite.
+// partials of p.q
 template <class T>
 __global__ void __launch_bounds__(kThreads) k_cg_pq(int64_t n, const T *__restrict__ p,
-                                                    const T *__restrict__ q, CgScalars *sc,
-                                                    double *partials, uint32_t *counter)
+                                                    const T *__restrict__ q, const CgScalars *sc,
+                                                    double *__restrict__ ppq)
 {
+    __shared__ double red[kThreads];
     if (sc->done) return;
     double pq = 0.0;
     GRID_STRIDE(i, n) pq += (double)p[i] * (double)q[i];
-    double s0, s1;
-    if (grid_sum2(pq, 0.0, partials, counter, s0, s1)) {
-        sc->pq = s0;
-        if (!(s0 > 0.0) || !isfinite(s0)) {
-            sc->breakdown = 1;
-            sc->done = 1;
-        } else {
-            sc->alpha = sc->rz / s0;
-        }
-    }
+    const double s = block_sum(pq, red);
+    if (threadIdx.x == 0) ppq[blockIdx.x] = s;
 }
 
-// x += alpha p, r -= alpha q, q = 0; rr = r.r, rz_new = r.(dinv r);
-// convergence when rr <= tol2; beta = rz_new / rz.
+// alpha = rz / pq (breakdown if pq <= 0 or not finite); x += alpha p,
+// r -= alpha q, q = 0; partials of r.r and r.(dinv r).  `j` is the iteration
+// index and `par` its parity (which rz slot is current).
 template <class T>
 __global__ void __launch_bounds__(kThreads) k_cg_update(int64_t n, T *__restrict__ x,
                                                         T *__restrict__ r, const T *__restrict__ p,
                                                         T *__restrict__ q, const T *__restrict__ dinv,
-                                                        CgScalars *sc, double *partials,
-                                                        uint32_t *counter)
+                                                        CgScalars *sc, const double *__restrict__ ppq,
+                                                        int count, double *__restrict__ prr,
+                                                        double *__restrict__ prz, int par, int j)
 {
+    __shared__ double red[kThreads];
     if (sc->done) return;
-    const T a = (T)sc->alpha;
+    const double pq = sum_partials(ppq, count, red);
+    if (!(pq > 0.0) || !isfinite(pq)) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            sc->pq = pq;
+            sc->breakdown = 1;
+            sc->done = 1;
+        }
+        return;
+    }
+    const double alpha = sc->rz[par] / pq;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        sc->pq = pq;
+        sc->alpha = alpha;
+        sc->iter = j + 1;
+    }
+    const T a = (T)alpha;
     double rr = 0.0, rz = 0.0;
     GRID_STRIDE(i, n)
     {
@@ -145,37 +150,62 @@ __global__ void __launch_bounds__(kThreads) k_cg_update(int64_t n, T *__restrict
         rr += (double)ri * (double)ri;
         rz += (double)ri * (double)zi;
     }
-    double s0, s1;
-    if (grid_sum2(rr, rz, partials, counter, s0, s1)) {
-        sc->rr = s0;
-        sc->iter += 1;
-        sc->beta = s1 / sc->rz;
-        sc->rz = s1;
-        if (s0 <= sc->tol2 || !isfinite(s0)) sc->done = 1;
+    const double srr = block_sum(rr, red);
+    const double srz = block_sum(rz, red);
+    if (threadIdx.x == 0) {
+        prr[blockIdx.x] = srr;
+        prz[blockIdx.x] = srz;
     }
 }
 
-// p = dinv r + beta p
+// convergence test rr <= tol2; beta = rz_new / rz; p = dinv r + beta p
 template <class T>
 __global__ void __launch_bounds__(kThreads) k_cg_dir(int64_t n, T *__restrict__ p,
                                                      const T *__restrict__ r,
-                                                     const T *__restrict__ dinv, const CgScalars *sc)
+                                                     const T *__restrict__ dinv, CgScalars *sc,
+                                                     const double *__restrict__ prr,
+                                                     const double *__restrict__ prz, int count,
+                                                     int par)
 {
+    __shared__ double red[kThreads];
     if (sc->done) return;
-    const T bt = (T)sc->beta;
+    const double rr = sum_partials(prr, count, red);
+    const double rz = sum_partials(prz, count, red);
+    if (rr <= sc->tol2 || !isfinite(rr)) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            sc->rr = rr;
+            sc->done = 1;
+        }
+        return;
+    }
+    const double beta = rz / sc->rz[par];
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        sc->rz[par ^ 1] = rz;
+        sc->rr = rr;
+        sc->beta = beta;
+    }
+    const T bt = (T)beta;
     GRID_STRIDE(i, n) p[i] = dinv[i] * r[i] + bt * p[i];
 }
 
-// out = a . b (float64), masked entries count normally (callers pass masked vectors)
+// partials of a.b
 template <class TA, class TB>
 __global__ void __launch_bounds__(kThreads) k_dot(int64_t n, const TA *__restrict__ a,
-                                                  const TB *__restrict__ b, double *out,
-                                                  double *partials, uint32_t *counter)
+                                                  const TB *__restrict__ b, double *__restrict__ part)
 {
+    __shared__ double red[kThreads];
     double s = 0.0;
     GRID_STRIDE(i, n) s += (double)a[i] * (double)b[i];
-    double s0, s1;
-    if (grid_sum2(s, 0.0, partials, counter, s0, s1)) *out = s0;
+    const double t = block_sum(s, red);
+    if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+__global__ void __launch_bounds__(kThreads) k_dot_fin(const double *__restrict__ part, int count,
+                                                      double *__restrict__ out)
+{
+    __shared__ double red[kThreads];
+    const double s = sum_partials(part, count, red);
+    if (threadIdx.x == 0) *out = s;
 }
 
 // dinv = 1/diag on free DOFs, 0 on prescribed ones
@@ -232,41 +262,47 @@ __global__ void k_apply_predictor(int64_t n, const double *__restrict__ u_old,
 
 // ------------------------------------------------------------------ launchers
 
-static unsigned red_grid(int64_t n)
+int red_grid(int64_t n)
 {
     int64_t g = (n + kThreads - 1) / kThreads;
-    return (unsigned)std::max<int64_t>(1, std::min<int64_t>(g, kMaxRedBlocks));
+    return (int)std::max<int64_t>(1, std::min<int64_t>(g, kMaxRedBlocks));
 }
 
 template <class T>
 hipError_t CgLaunch<T>::init(const double *b, double sign, const T *dinv, const uint8_t *nmask,
                              T *x, T *r, T *p, T *q, CgScalars *sc, double eta2) const
 {
-    hipLaunchKernelGGL(k_cg_init<T>, dim3(red_grid(n)), dim3(kThreads), 0, s, n, b, sign, dinv,
-                       nmask, x, r, p, q, sc, eta2, ws.partials, ws.counter);
+    const int g = red_grid(n);
+    hipLaunchKernelGGL(k_cg_init<T>, dim3(g), dim3(kThreads), 0, s, n, b, sign, dinv, nmask, x, r,
+                       p, q, ws.partials + kMaxRedBlocks, ws.partials + 2 * kMaxRedBlocks);
+    hipLaunchKernelGGL(k_cg_init_fin, dim3(1), dim3(kThreads), 0, s, ws.partials + kMaxRedBlocks,
+                       ws.partials + 2 * kMaxRedBlocks, g, sc, eta2);
     return hipGetLastError();
 }
 
 template <class T>
 hipError_t CgLaunch<T>::pq(const T *p, const T *q, CgScalars *sc) const
 {
-    hipLaunchKernelGGL(k_cg_pq<T>, dim3(red_grid(n)), dim3(kThreads), 0, s, n, p, q, sc, ws.partials,
-                       ws.counter);
+    hipLaunchKernelGGL(k_cg_pq<T>, dim3(red_grid(n)), dim3(kThreads), 0, s, n, p, q, sc, ws.partials);
     return hipGetLastError();
 }
 
 template <class T>
-hipError_t CgLaunch<T>::update(T *x, T *r, const T *p, T *q, const T *dinv, CgScalars *sc) const
+hipError_t CgLaunch<T>::update(T *x, T *r, const T *p, T *q, const T *dinv, CgScalars *sc, int j) const
 {
-    hipLaunchKernelGGL(k_cg_update<T>, dim3(red_grid(n)), dim3(kThreads), 0, s, n, x, r, p, q, dinv,
-                       sc, ws.partials, ws.counter);
+    const int g = red_grid(n);
+    hipLaunchKernelGGL(k_cg_update<T>, dim3(g), dim3(kThreads), 0, s, n, x, r, p, q, dinv, sc,
+                       ws.partials, g, ws.partials + kMaxRedBlocks, ws.partials + 2 * kMaxRedBlocks,
+                       j & 1, j);
     return hipGetLastError();
 }
 
 template <class T>
-hipError_t CgLaunch<T>::dir(T *p, const T *r, const T *dinv, const CgScalars *sc) const
+hipError_t CgLaunch<T>::dir(T *p, const T *r, const T *dinv, CgScalars *sc, int j) const
 {
-    hipLaunchKernelGGL(k_cg_dir<T>, dim3(red_grid(n)), dim3(kThreads), 0, s, n, p, r, dinv, sc);
+    const int g = red_grid(n);
+    hipLaunchKernelGGL(k_cg_dir<T>, dim3(g), dim3(kThreads), 0, s, n, p, r, dinv, sc,
+                       ws.partials + kMaxRedBlocks, ws.partials + 2 * kMaxRedBlocks, g, j & 1);
     return hipGetLastError();
 }
 
@@ -294,8 +330,11 @@ hipError_t CgLaunch<T>::scaled(const T *dinv, const double *b, double sign, T *x
 template <class T>
 hipError_t CgLaunch<T>::dot_state(const double *a, const T *b, double *out) const
 {
-    hipLaunchKernelGGL((k_dot<double, T>), dim3(red_grid(n)), dim3(kThreads), 0, s, n, a, b, out,
-                       ws.partials, ws.counter);
+    const int g = red_grid(n);
+    hipLaunchKernelGGL((k_dot<double, T>), dim3(g), dim3(kThreads), 0, s, n, a, b,
+                       ws.partials + 3 * kMaxRedBlocks);
+    hipLaunchKernelGGL(k_dot_fin, dim3(1), dim3(kThreads), 0, s, ws.partials + 3 * kMaxRedBlocks, g,
+                       out);
     return hipGetLastError();
 }
 
@@ -319,12 +358,163 @@ hipError_t launch_bc_increment(hipStream_t s, int64_t n, const double *u, const 
 hipError_t launch_dot64(hipStream_t s, const CgWorkspace &ws, int64_t n, const double *a,
                         const double *b, double *out)
 {
-    hipLaunchKernelGGL((k_dot<double, double>), dim3(red_grid(n)), dim3(kThreads), 0, s, n, a, b,
-                       out, ws.partials, ws.counter);
+    const int g = red_grid(n);
+    hipLaunchKernelGGL((k_dot<double, double>), dim3(g), dim3(kThreads), 0, s, n, a, b,
+                       ws.partials + 3 * kMaxRedBlocks);
+    hipLaunchKernelGGL(k_dot_fin, dim3(1), dim3(kThreads), 0, s, ws.partials + 3 * kMaxRedBlocks, g,
+                       out);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------- flexible CG
+
+// rz = r.z from the apply's partials; p = z.  A non-positive rz means the
+// preconditioner is not usable here: request the Jacobi fallback.
+template <class T>
+__global__ void __launch_bounds__(kThreads) k_fcg_start(int64_t n, const T *__restrict__ z,
+                                                        T *__restrict__ p, CgScalars *sc,
+                                                        const double *__restrict__ prz, int nz)
+{
+    __shared__ double red[kThreads];
+    if (sc->done) return;
+    const double rz = sum_partials(prz, nz, red);
+    if (!(rz > 0.0) || !isfinite(rz)) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            sc->fallback = 1;
+            sc->done = 1;
+        }
+        return;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        sc->rz[0] = rz;
+        sc->best = sc->rr;
+        sc->stall = 0;
+        sc->fallback = 0;
+    }
+    GRID_STRIDE(i, n) p[i] = z[i];
+}
+
+// alpha = rz/pq; x += alpha p; r -= alpha q; q = 0; partials of r.r and r.z_old
+template <class T>
+__global__ void __launch_bounds__(kThreads) k_fcg_update(int64_t n, T *__restrict__ x,
+                                                         T *__restrict__ r, const T *__restrict__ p,
+                                                         T *__restrict__ q, const T *__restrict__ zold,
+                                                         CgScalars *sc, const double *__restrict__ ppq,
+                                                         int count, double *__restrict__ prr,
+                                                         double *__restrict__ prz, int par, int j)
+{
+    __shared__ double red[kThreads];
+    if (sc->done) return;
+    const double pq = sum_partials(ppq, count, red);
+    if (!(pq > 0.0) || !isfinite(pq)) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            sc->pq = pq;
+            sc->breakdown = 1;
+            sc->fallback = 1;
+            sc->done = 1;
+        }
+        return;
+    }
+    const double alpha = sc->rz[par] / pq;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        sc->pq = pq;
+        sc->alpha = alpha;
+        sc->iter = j + 1;
+    }
+    const T a = (T)alpha;
+    double rr = 0.0, rzo = 0.0;
+    GRID_STRIDE(i, n)
+    {
+        x[i] += a * p[i];
+        const T ri = r[i] - a * q[i];
+        r[i] = ri;
+        q[i] = T(0);
+        rr += (double)ri * (double)ri;
+        rzo += (double)ri * (double)zold[i];
+    }
+    const double s0 = block_sum(rr, red);
+    const double s1 = block_sum(rzo, red);
+    if (threadIdx.x == 0) {
+        prr[blockIdx.x] = s0;
+        prz[blockIdx.x] = s1;
+    }
+}
+
+// Convergence (rr <= tol2), stagnation (no new best rr for stall_limit
+// iterations) and positivity (r.z_new > 0) tests; beta = (r.z_new - r.z_old) / rz;
+// p = z_new + beta p.
+template <class T>
+__global__ void __launch_bounds__(kThreads) k_fcg_dir(int64_t n, T *__restrict__ p,
+                                                      const T *__restrict__ z, CgScalars *sc,
+                                                      const double *__restrict__ prr,
+                                                      const double *__restrict__ przo, int count,
+                                                      const double *__restrict__ przn, int nz,
+                                                      int par, int stall_limit)
+{
+    __shared__ double red[kThreads];
+    if (sc->done) return;
+    const double rr = sum_partials(prr, count, red);
+    const double rzo = sum_partials(przo, count, red);
+    const double rzn = sum_partials(przn, nz, red);
+    const bool first = blockIdx.x == 0 && threadIdx.x == 0;
+    if (rr <= sc->tol2 || !isfinite(rr)) {
+        if (first) {
+            sc->rr = rr;
+            sc->done = 1;
+        }
+        return;
+    }
+    const int stall = rr < sc->best ? 0 : sc->stall + 1;
+    if (!(rzn > 0.0) || !isfinite(rzn) || stall >= stall_limit) {
+        if (first) {
+            sc->rr = rr;
+            sc->fallback = 1;
+            sc->done = 1;
+        }
+        return;
+    }
+    const double beta = (rzn - rzo) / sc->rz[par];
+    if (first) {
+        sc->rz[par ^ 1] = rzn;
+        sc->rr = rr;
+        sc->beta = beta;
+        sc->stall = stall;
+        if (rr < sc->best) sc->best = rr;
+    }
+    const T bt = (T)beta;
+    GRID_STRIDE(i, n) p[i] = z[i] + bt * p[i];
+}
+
+template <class T>
+hipError_t FcgLaunch<T>::start(const T *z, T *p, CgScalars *sc, const double *prz, int nz) const
+{
+    hipLaunchKernelGGL(k_fcg_start<T>, dim3(red_grid(n)), dim3(kThreads), 0, s, n, z, p, sc, prz, nz);
+    return hipGetLastError();
+}
+
+template <class T>
+hipError_t FcgLaunch<T>::update(T *x, T *r, const T *p, T *q, const T *zold, CgScalars *sc, int j) const
+{
+    const int g = red_grid(n);
+    hipLaunchKernelGGL(k_fcg_update<T>, dim3(g), dim3(kThreads), 0, s, n, x, r, p, q, zold, sc,
+                       ws.partials, g, ws.partials + kMaxRedBlocks, ws.partials + 2 * kMaxRedBlocks,
+                       j & 1, j);
+    return hipGetLastError();
+}
+
+template <class T>
+hipError_t FcgLaunch<T>::dir(T *p, const T *z, CgScalars *sc, const double *prz, int nz, int j,
+                             int stall_limit) const
+{
+    const int g = red_grid(n);
+    hipLaunchKernelGGL(k_fcg_dir<T>, dim3(g), dim3(kThreads), 0, s, n, p, z, sc,
+                       ws.partials + kMaxRedBlocks, ws.partials + 2 * kMaxRedBlocks, g, prz, nz,
+                       j & 1, stall_limit);
     return hipGetLastError();
 }
 
 template struct CgLaunch<double>;
 template struct CgLaunch<float>;
+template struct FcgLaunch<float>;
 
 }  // namespace efem

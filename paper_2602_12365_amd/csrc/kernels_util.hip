@@ -33,7 +33,21 @@ __global__ void k_cast_f32(const double *__restrict__ src, int64_t n, float *__r
     if (i < n) dst[i] = (float)src[i];
 }
 
+__global__ void k_uniform_check(const double *__restrict__ a, const double *__restrict__ b,
+                                int64_t n, int32_t *flag)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n && (a[i] != a[0] || b[i] != b[0])) atomicAnd(flag, 0);
+}
+
 static unsigned grid_for(int64_t n) { return (unsigned)((n + 255) / 256); }
+
+hipError_t launch_uniform_check(const double *a, const double *b, int64_t n, int32_t *flag,
+                                hipStream_t s)
+{
+    hipLaunchKernelGGL(k_uniform_check, dim3(grid_for(n)), dim3(256), 0, s, a, b, n, flag);
+    return hipGetLastError();
+}
 
 hipError_t launch_permute_elems(const Ctx &c, const double *src, double *dst)
 {

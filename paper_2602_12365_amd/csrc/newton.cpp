@@ -19,11 +19,15 @@
 #include <type_traits>
 
 #include "efem_cg.h"
+#include "efem_mlp.h"
 
 namespace efem {
 
-int precond_solve_f32(Ctx &c, const efem_solve_opts &o, const double *b, double eta, int max_it,
-                      float *x, float *dinv, int *iters, int *fallback);
+hipError_t mlp_precondition(Ctx &c, MlpState &M, const float *r, float *z);
+hipError_t mlp_prepare(Ctx &c, MlpState &M, const double *diag);
+
+// flexible-CG iterations without a new smallest residual before falling back
+constexpr int kStallLimit = 10;
 
 namespace {
 
@@ -75,10 +79,8 @@ struct Solver {
             || (rc = alloc(&u_trial, n)) || (rc = alloc(&diag, n)) || (rc = alloc(&kdc, n))
             || (rc = alloc(&dscal, 4)) || (rc = alloc(&x, n)) || (rc = alloc(&rv, n))
             || (rc = alloc(&p, n)) || (rc = alloc(&q, n)) || (rc = alloc(&dinv, n))
-            || (rc = alloc(&sc, 1)) || (rc = alloc(&ws.partials, 2 * kMaxRedBlocks))
-            || (rc = alloc(&ws.counter, 1)))
+            || (rc = alloc(&sc, 1)) || (rc = alloc(&ws.partials, 4 * kMaxRedBlocks)))
             return rc;
-        TRY(hipMemsetAsync(ws.counter, 0, sizeof(uint32_t), c.stream));
         if (!c.xlin) {
             void *q_ = nullptr;
             TRY(hipMalloc(&q_, n * sizeof(double)));
@@ -127,12 +129,13 @@ struct Solver {
         return EFEM_OK;
     }
 
+    // q is cleared by the CG init/update kernels, so the single-launch form applies
     hipError_t hvp_acc(const T *v, T *y, const int32_t *skip)
     {
         if constexpr (std::is_same<T, double>::value)
-            return launch_hvp_f64(c, c.xlin, v, y, skip, true);
+            return launch_hvp_f64(c, c.xlin, v, y, skip, WriteMode::Zeroed);
         else
-            return launch_hvp_f32(c, c.ulin, v, y, skip, true);
+            return launch_hvp_f32(c, c.ulin, v, y, skip, WriteMode::Zeroed);
     }
 
     // Jacobi-PCG for K_ff x = sign * b from x = 0; dinv must be set.
@@ -140,12 +143,13 @@ struct Solver {
     {
         TRY(L.init(b, sign, dinv, c.m.nmask, x, rv, p, q, sc, eta * eta));
         const int every = std::max(1, o.check_every);
+        int j = 0;
         for (;;) {
-            for (int j = 0; j < every; ++j) {
+            for (int k = 0; k < every; ++k, ++j) {
                 TRY(hvp_acc(p, q, &sc->done));
                 TRY(L.pq(p, q, sc));
-                TRY(L.update(x, rv, p, q, dinv, sc));
-                TRY(L.dir(p, rv, dinv, sc));
+                TRY(L.update(x, rv, p, q, dinv, sc, j));
+                TRY(L.dir(p, rv, dinv, sc, j));
             }
             TRY(hipMemcpyAsync(h_sc, sc, sizeof(CgScalars), hipMemcpyDeviceToHost, c.stream));
             TRY(hipStreamSynchronize(c.stream));
@@ -156,6 +160,41 @@ struct Solver {
         return EFEM_OK;
     }
 
+    // Flexible CG with the learned preconditioner for K_ff x = sign * b from
+    // x = 0; on breakdown, non-positive r.z or stagnation, Jacobi PCG from x = 0.
+    int fcg(const double *b, double sign, double eta, int max_it, int &iters, int &fallbacks)
+    {
+        MlpState &M = *static_cast<MlpState *>(c.mlp);
+        FcgLaunch<float> F{n, c.stream, ws};
+        const int nz = mlp_apply_grid(c.n_nodes);
+        TRY(L.init(b, sign, dinv, c.m.nmask, x, rv, p, q, sc, eta * eta));
+        TRY(mlp_precondition(c, M, rv, M.z));
+        TRY(F.start(M.z, p, sc, M.prz, nz));
+        const int every = std::max(1, o.check_every);
+        int j = 0;
+        for (;;) {
+            for (int k = 0; k < every; ++k, ++j) {
+                TRY(hvp_acc(p, q, &sc->done));
+                TRY(L.pq(p, q, sc));
+                TRY(F.update(x, rv, p, q, M.z, sc, j));
+                TRY(mlp_precondition(c, M, rv, M.z));
+                TRY(F.dir(p, M.z, sc, M.prz, nz, j, kStallLimit));
+            }
+            TRY(hipMemcpyAsync(h_sc, sc, sizeof(CgScalars), hipMemcpyDeviceToHost, c.stream));
+            TRY(hipStreamSynchronize(c.stream));
+            if (h_sc->done || h_sc->iter >= max_it) break;
+        }
+        iters = h_sc->iter;
+        if (h_sc->fallback) {
+            int it2 = 0;
+            int rc = pcg(b, sign, eta, max_it, it2);
+            iters += it2;
+            fallbacks += 1;
+            return rc;
+        }
+        return EFEM_OK;
+    }
+
     int set_dinv(const double *u)
     {
         TRY(launch_diag(c, u, diag));
@@ -163,16 +202,36 @@ struct Solver {
         return EFEM_OK;
     }
 
+    // K(u)_ff x = sign * b
     int linear_solve(const double *u, const double *b, double eta, int max_it, int &iters,
-                     int &fallbacks)
+                     int &fallbacks, double sign = -1.0)
     {
         int rc;
         if ((rc = set_dinv(u)) || (rc = linearize(u))) return rc;
         if constexpr (std::is_same<T, float>::value) {
-            if (o.precond == 1 && c.mlp)
-                return precond_solve_f32(c, o, b, eta, max_it, x, dinv, &iters, &fallbacks);
+            auto *M = static_cast<MlpState *>(c.mlp);
+            if (o.precond == 1 && M && M->have_weights) {
+                TRY(mlp_prepare(c, *M, diag));
+                return fcg(b, sign, eta, max_it, iters, fallbacks);
+            }
         }
-        return pcg(b, -1.0, eta, max_it, iters);
+        return pcg(b, sign, eta, max_it, iters);
+    }
+
+    // K(u)_ff xout = b, FP64 result
+    int solve_into(const double *u, const double *b, double rtol, int max_it, double *xout,
+                   int32_t *iters, int32_t *fb)
+    {
+        int rc = setup();
+        if (rc) return rc;
+        int it = 0, f = 0;
+        if ((rc = linear_solve(u, b, rtol, max_it, it, f, +1.0))) return rc;
+        TRY(hipMemsetAsync(xout, 0, n * sizeof(double), c.stream));
+        TRY(L.axpy_state(xout, 1.0, x, xout));
+        TRY(hipStreamSynchronize(c.stream));
+        if (iters) *iters = it;
+        if (fb) *fb = f;
+        return EFEM_OK;
     }
 
     int run(double *u, const double *u_bc, efem_solve_stats *st)
@@ -191,7 +250,7 @@ struct Solver {
             TRY(launch_add_x_u(c, u, c.xlin));
             const uint8_t *mask = c.m.nmask;
             c.m.nmask = nullptr;
-            hipError_t he = launch_hvp_f64(c, c.xlin, dc, kdc, nullptr, false);
+            hipError_t he = launch_hvp_f64(c, c.xlin, dc, kdc, nullptr, WriteMode::Overwrite);
             c.m.nmask = mask;
             TRY(he);
             int it = 0;
@@ -329,7 +388,8 @@ int efem_newton_solve(efem_ctx *ctx, double *u_inout, const double *u_bc, const 
         set_error("efem_newton_solve: bad options");
         return EFEM_ERR_INVALID;
     }
-    if (opts->precond == 1 && (!ctx->mlp || opts->hvp_prec != EFEM_F32)) {
+    if (opts->precond == 1 && (!ctx->mlp || !static_cast<MlpState *>(ctx->mlp)->have_weights
+                               || opts->hvp_prec != EFEM_F32)) {
         set_error("efem_newton_solve: the learned preconditioner needs efem_set_mlp and EFEM_F32");
         return EFEM_ERR_STATE;
     }
@@ -350,3 +410,42 @@ int efem_newton_solve(efem_ctx *ctx, double *u_inout, const double *u_bc, const 
 }
 
 }  // extern "C"
+
+extern "C" int efem_linear_solve(efem_ctx *ctx, const double *u, const double *b, double *x,
+                                 double rtol, int32_t hvp_prec, int32_t precond, int32_t max_iter,
+                                 int32_t *iters, int32_t *fallback)
+{
+    if (!ctx || !u || !b || !x || !(rtol > 0) || max_iter < 1
+        || (hvp_prec != EFEM_F64 && hvp_prec != EFEM_F32) || (precond != 0 && precond != 1)) {
+        set_error("efem_linear_solve: bad argument");
+        return EFEM_ERR_INVALID;
+    }
+    if (!ctx->m.nmask) {
+        set_error("efem_linear_solve: set a Dirichlet mask first (efem_set_dirichlet)");
+        return EFEM_ERR_STATE;
+    }
+    if (precond == 1) {
+        auto *M = static_cast<MlpState *>(ctx->mlp);
+        if (!M || !M->have_weights || hvp_prec != EFEM_F32) {
+            set_error("efem_linear_solve: the learned preconditioner needs efem_set_mlp and EFEM_F32");
+            return EFEM_ERR_STATE;
+        }
+    }
+    efem_solve_opts o;
+    efem_solve_opts_default(&o);
+    o.precond = precond;
+    o.hvp_prec = hvp_prec;
+    int dev_prev = -1;
+    (void)hipGetDevice(&dev_prev);
+    if (dev_prev != ctx->device) (void)hipSetDevice(ctx->device);
+    int rc;
+    if (hvp_prec == EFEM_F64) {
+        Solver<double> s(*ctx, o);
+        rc = s.solve_into(u, b, rtol, max_iter, x, iters, fallback);
+    } else {
+        Solver<float> s(*ctx, o);
+        rc = s.solve_into(u, b, rtol, max_iter, x, iters, fallback);
+    }
+    if (dev_prev >= 0 && dev_prev != ctx->device) (void)hipSetDevice(dev_prev);
+    return rc;
+}

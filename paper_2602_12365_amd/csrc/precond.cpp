@@ -1,15 +1,213 @@
-// Learned CG preconditioner: per-context resources and the flexible-CG solve.
-#include "efem_cg.h"
+// Learned CG preconditioner: per-context state, the node 1-ring graph, and
+// the C-ABI of the preconditioner and of its training.
+#include <algorithm>
+#include <cstring>
+#include <vector>
+
+#include "efem_mlp.h"
 
 namespace efem {
 
-void mlp_release(Ctx &c) { c.mlp = nullptr; }
+#define TRY(call)                                              \
+    do {                                                       \
+        hipError_t e_ = (call);                                \
+        if (e_ != hipSuccess) return hip_fail(e_, #call);      \
+    } while (0)
 
-int precond_solve_f32(Ctx &, const efem_solve_opts &, const double *, double, int, float *, float *,
-                      int *, int *)
+void mlp_release(Ctx &c)
 {
-    set_error("learned preconditioner not set");
-    return EFEM_ERR_STATE;
+    auto *M = static_cast<MlpState *>(c.mlp);
+    if (!M) return;
+    for (void *p : M->owned) (void)hipFree(p);
+    delete M;
+    c.mlp = nullptr;
+}
+
+template <class T>
+static int malloc_into(MlpState &M, T **p, size_t count)
+{
+    void *q = nullptr;
+    hipError_t e = hipMalloc(&q, std::max<size_t>(count, 1) * sizeof(T));
+    if (e != hipSuccess) return hip_fail(e, "hipMalloc");
+    M.owned.push_back(q);
+    *p = static_cast<T *>(q);
+    return EFEM_OK;
+}
+
+// Node 1-ring (nodes sharing an element, excluding the node), sorted per node.
+static void build_ring(const Ctx &c, std::vector<int64_t> &ptr, std::vector<int32_t> &idx)
+{
+    const int64_t nn = c.n_nodes, ne = c.n_elems;
+    const int nen = c.nen;
+    std::vector<int64_t> eptr((size_t)nn + 1, 0);
+    for (int64_t k = 0; k < ne * nen; ++k) eptr[(size_t)c.conn_host[(size_t)k] + 1] += 1;
+    for (int64_t i = 0; i < nn; ++i) eptr[(size_t)i + 1] += eptr[(size_t)i];
+    std::vector<int32_t> elist((size_t)eptr[(size_t)nn]);
+    std::vector<int64_t> fill(eptr.begin(), eptr.end() - 1);
+    for (int64_t e = 0; e < ne; ++e)
+        for (int a = 0; a < nen; ++a) elist[(size_t)fill[(size_t)c.conn_host[(size_t)(e * nen + a)]]++] = (int32_t)e;
+    ptr.assign((size_t)nn + 1, 0);
+    idx.clear();
+    std::vector<int32_t> cand;
+    for (int64_t i = 0; i < nn; ++i) {
+        cand.clear();
+        for (int64_t p = eptr[(size_t)i]; p < eptr[(size_t)i + 1]; ++p) {
+            const int32_t e = elist[(size_t)p];
+            for (int a = 0; a < nen; ++a) {
+                const int32_t j = c.conn_host[(size_t)(e * nen + a)];
+                if (j != i) cand.push_back(j);
+            }
+        }
+        std::sort(cand.begin(), cand.end());
+        cand.erase(std::unique(cand.begin(), cand.end()), cand.end());
+        idx.insert(idx.end(), cand.begin(), cand.end());
+        ptr[(size_t)i + 1] = (int64_t)idx.size();
+    }
+}
+
+// Create the state (graph + buffers) on first use.
+MlpState *mlp_state(Ctx &c, int *rc)
+{
+    *rc = EFEM_OK;
+    if (c.mlp) return static_cast<MlpState *>(c.mlp);
+    auto *M = new (std::nothrow) MlpState();
+    if (!M) {
+        *rc = EFEM_ERR_OOM;
+        return nullptr;
+    }
+    std::vector<int64_t> ptr;
+    std::vector<int32_t> idx;
+    build_ring(c, ptr, idx);
+    const int64_t nn = c.n_nodes;
+    int r;
+    if ((r = malloc_into(*M, &M->ptr, ptr.size())) || (r = malloc_into(*M, &M->idx, idx.size()))
+        || (r = malloc_into(*M, &M->W, kP)) || (r = malloc_into(*M, &M->X, (size_t)nn * kInPad))
+        || (r = malloc_into(*M, &M->scale, (size_t)nn)) || (r = malloc_into(*M, &M->dinv, 3 * (size_t)nn))
+        || (r = malloc_into(*M, &M->z, 3 * (size_t)nn)) || (r = malloc_into(*M, &M->zold, 3 * (size_t)nn))
+        || (r = malloc_into(*M, &M->prz, 2048)) || (r = malloc_into(*M, &M->gpart, (size_t)kGradBlocks * kP))
+        || (r = malloc_into(*M, &M->lpart, kGradBlocks)) || (r = malloc_into(*M, &M->tt, 1))) {
+        for (void *p : M->owned) (void)hipFree(p);
+        delete M;
+        *rc = r;
+        return nullptr;
+    }
+    if (hipMemcpy(M->ptr, ptr.data(), ptr.size() * sizeof(int64_t), hipMemcpyHostToDevice) != hipSuccess
+        || (!idx.empty()
+            && hipMemcpy(M->idx, idx.data(), idx.size() * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess)) {
+        for (void *p : M->owned) (void)hipFree(p);
+        delete M;
+        *rc = hip_fail(hipGetLastError(), "hipMemcpy");
+        return nullptr;
+    }
+    c.mlp = M;
+    return M;
+}
+
+// Features of r (static part from diag) and z = M(r); partials of r.z in M.prz.
+hipError_t mlp_precondition(Ctx &c, MlpState &M, const float *r, float *z)
+{
+    hipError_t e = mlp_features_dyn(c.stream, M, c.n_nodes, r, M.dinv, M.X, M.scale);
+    if (e != hipSuccess) return e;
+    return mlp_apply(c.stream, M.W, c.n_nodes, M.X, r, M.dinv, M.scale, z, M.prz);
+}
+
+// Jacobi inverse (float, 0 on prescribed DOFs) and the static features for diag.
+hipError_t mlp_prepare(Ctx &c, MlpState &M, const double *diag)
+{
+    hipError_t e = mlp_dinv_f32(c.stream, 3 * c.n_nodes, diag, c.m.nmask, M.dinv);
+    if (e != hipSuccess) return e;
+    return mlp_features_static(c.stream, M, c.n_nodes, diag, c.m.nmask, M.X);
 }
 
 }  // namespace efem
+
+using namespace efem;
+
+struct efem_ctx : Ctx {};
+
+extern "C" {
+
+int efem_set_mlp(efem_ctx *ctx, const float *params)
+{
+    if (!ctx) return EFEM_ERR_INVALID;
+    int rc;
+    MlpState *M = mlp_state(*ctx, &rc);
+    if (!M) return rc;
+    if (!params) {
+        M->have_weights = false;
+        return EFEM_OK;
+    }
+    TRY(mlp_to_bf16(ctx->stream, params, M->W));
+    M->have_weights = true;
+    return EFEM_OK;
+}
+
+int efem_precond_apply(efem_ctx *ctx, const float *r, const double *diag, float *z)
+{
+    if (!ctx || !r || !diag || !z) {
+        set_error("efem_precond_apply: null pointer");
+        return EFEM_ERR_INVALID;
+    }
+    auto *M = static_cast<MlpState *>(ctx->mlp);
+    if (!M || !M->have_weights) {
+        set_error("efem_precond_apply: call efem_set_mlp first");
+        return EFEM_ERR_STATE;
+    }
+    TRY(mlp_prepare(*ctx, *M, diag));
+    TRY(mlp_precondition(*ctx, *M, r, z));
+    return EFEM_OK;
+}
+
+int efem_precond_rows(efem_ctx *ctx, const float *b, const double *diag, const float *t,
+                      double n_total, uint16_t *X, float *aux)
+{
+    if (!ctx || !b || !diag || !t || !X || !aux || !(n_total > 0)) {
+        set_error("efem_precond_rows: bad argument");
+        return EFEM_ERR_INVALID;
+    }
+    auto *M = static_cast<MlpState *>(ctx->mlp);
+    if (!M) {
+        set_error("efem_precond_rows: call efem_set_mlp first (builds the node graph)");
+        return EFEM_ERR_STATE;
+    }
+    TRY(mlp_dinv_f32(ctx->stream, 3 * ctx->n_nodes, diag, ctx->m.nmask, M->dinv));
+    TRY(mlp_features_static(ctx->stream, *M, ctx->n_nodes, diag, ctx->m.nmask, X));
+    TRY(mlp_features_dyn(ctx->stream, *M, ctx->n_nodes, b, M->dinv, X, M->scale));
+    TRY(mlp_rows_aux(ctx->stream, ctx->n_nodes, b, M->dinv, t, M->scale, M->tt, n_total, aux));
+    return EFEM_OK;
+}
+
+int efem_mlp_forward(efem_ctx *ctx, int64_t rows, const uint16_t *X, float *out)
+{
+    if (!ctx || !X || !out || rows < 0) return EFEM_ERR_INVALID;
+    auto *M = static_cast<MlpState *>(ctx->mlp);
+    if (!M || !M->have_weights) {
+        set_error("efem_mlp_forward: call efem_set_mlp first");
+        return EFEM_ERR_STATE;
+    }
+    if (rows == 0) return EFEM_OK;
+    TRY(mlp_forward(ctx->stream, M->W, rows, X, out));
+    return EFEM_OK;
+}
+
+int efem_mlp_loss_grad(efem_ctx *ctx, int64_t rows, const uint16_t *X, const float *aux,
+                       const float *params, float *grad, double *loss)
+{
+    if (!ctx || !X || !aux || !params || !grad || !loss || rows < 0) return EFEM_ERR_INVALID;
+    int rc;
+    MlpState *M = mlp_state(*ctx, &rc);
+    if (!M) return rc;
+    const int G = (int)std::max<int64_t>(1, std::min<int64_t>(kGradBlocks, (rows + 15) / 16));
+    TRY(mlp_loss_grad(ctx->stream, rows, X, aux, params, M->gpart, M->lpart, G, grad, loss));
+    return EFEM_OK;
+}
+
+int efem_mlp_adam(efem_ctx *ctx, float *params, float *m, float *v, const float *g, float lr,
+                  int32_t t)
+{
+    if (!ctx || !params || !m || !v || !g || t < 1) return EFEM_ERR_INVALID;
+    TRY(mlp_adam(ctx->stream, params, m, v, g, lr, 0.9f, 0.999f, 1e-8f, t));
+    return EFEM_OK;
+}
+
+}  // extern "C"

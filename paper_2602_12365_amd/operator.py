@@ -172,6 +172,15 @@ class Operator:
                                        _ptr(self._nodal(out, self._lin, "out"))), "efem_hvp_acc")
         return out
 
+    def hvp_zeroed(self, v, out):
+        """out = K(u) v in one kernel launch; ``out`` must hold zeros on entry."""
+        self._sync_stream()
+        if self._lin is None:
+            raise RuntimeError("call linearize(u) first")
+        L.check(self._lib.efem_hvp_zeroed(self._h, _ptr(self._nodal(v, self._lin, "v")),
+                                          _ptr(self._nodal(out, self._lin, "out"))), "efem_hvp_zeroed")
+        return out
+
     def jacobi_diag(self, u, out=None):
         self._sync_stream()
         out = self._new_nodal() if out is None else self._nodal(out, name="out")
@@ -230,6 +239,74 @@ class Operator:
         stats["newton_per_step"] = list(st.newton_per_step[:min(k, 64)])
         stats["cg_per_step"] = list(st.cg_per_step[:min(k, 64)])
         return rc, stats
+
+
+    def linear_solve(self, u, b, rtol=1e-8, hvp_prec="f64", precond=0, max_iter=100000):
+        """Solve K(u)_ff x = b by preconditioned CG (Jacobi, or the learned
+        preconditioner with flexible CG); returns (x, iterations, fell_back)."""
+        self._sync_stream()
+        x = self._new_nodal()
+        it, fb = ctypes.c_int32(), ctypes.c_int32()
+        L.check(self._lib.efem_linear_solve(self._h, _ptr(self._nodal(u, name="u")),
+                                            _ptr(self._nodal(b, name="b")), _ptr(x), float(rtol),
+                                            _PREC[hvp_prec], int(precond), int(max_iter),
+                                            ctypes.byref(it), ctypes.byref(fb)), "efem_linear_solve")
+        return x, it.value, bool(fb.value)
+
+    # ------------------------------------------------- learned preconditioner
+    def set_mlp(self, params):
+        """params: float32 device tensor [EFEM_MLP_PARAMS], or None to remove."""
+        self._sync_stream()
+        if params is None:
+            L.check(self._lib.efem_set_mlp(self._h, None), "efem_set_mlp")
+            return
+        if params.dtype != torch.float32 or params.numel() != L.EFEM_MLP_PARAMS or params.device != self.device:
+            raise TypeError("params must be a float32 device tensor of EFEM_MLP_PARAMS entries")
+        L.check(self._lib.efem_set_mlp(self._h, _ptr(params.contiguous())), "efem_set_mlp")
+
+    def precond_apply(self, r, diag):
+        self._sync_stream()
+        z = self._new_nodal(torch.float32)
+        L.check(self._lib.efem_precond_apply(self._h, _ptr(self._nodal(r, torch.float32, "r")),
+                                             _ptr(self._nodal(diag, name="diag")), _ptr(z)),
+                "efem_precond_apply")
+        return z
+
+    def precond_rows(self, b, diag, t, n_total, X=None, aux=None):
+        """Training rows of one (b, t) pair: X uint16 [n_nodes, 16] (bfloat16 bits),
+        aux float32 [n_nodes, EFEM_MLP_AUX]."""
+        self._sync_stream()
+        if X is None:
+            X = torch.empty((self.n_nodes, 16), dtype=torch.int16, device=self.device)
+        if aux is None:
+            aux = torch.empty((self.n_nodes, L.EFEM_MLP_AUX), dtype=torch.float32, device=self.device)
+        assert X.numel() == 16 * self.n_nodes and aux.numel() == L.EFEM_MLP_AUX * self.n_nodes
+        L.check(self._lib.efem_precond_rows(self._h, _ptr(self._nodal(b, torch.float32, "b")),
+                                            _ptr(self._nodal(diag, name="diag")),
+                                            _ptr(self._nodal(t, torch.float32, "t")), float(n_total),
+                                            _ptr(X), _ptr(aux)), "efem_precond_rows")
+        return X, aux
+
+    def mlp_forward(self, X):
+        self._sync_stream()
+        rows = X.shape[0]
+        out = torch.empty((rows, 3), dtype=torch.float32, device=self.device)
+        L.check(self._lib.efem_mlp_forward(self._h, rows, _ptr(X.contiguous()), _ptr(out)),
+                "efem_mlp_forward")
+        return out
+
+    def mlp_loss_grad(self, X, aux, params, grad=None, loss=None):
+        self._sync_stream()
+        grad = torch.empty(L.EFEM_MLP_PARAMS, dtype=torch.float32, device=self.device) if grad is None else grad
+        loss = torch.empty((), dtype=torch.float64, device=self.device) if loss is None else loss
+        L.check(self._lib.efem_mlp_loss_grad(self._h, X.shape[0], _ptr(X), _ptr(aux), _ptr(params),
+                                             _ptr(grad), _ptr(loss)), "efem_mlp_loss_grad")
+        return grad, loss
+
+    def mlp_adam(self, params, m, v, grad, lr, t):
+        self._sync_stream()
+        L.check(self._lib.efem_mlp_adam(self._h, _ptr(params), _ptr(m), _ptr(v), _ptr(grad),
+                                        float(lr), int(t)), "efem_mlp_adam")
 
 
 # --------------------------------------------------------------- autograd

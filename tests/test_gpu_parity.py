@@ -93,6 +93,33 @@ def test_hvp_f32(case):
     assert rel(y, case.orc.hvp(case.u, case.v)) <= TOL32
 
 
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_hvp_single_launch_forms(case, prec):
+    """efem_hvp_acc: y += K v on an arbitrary y; efem_hvp_zeroed: y = K v on a zero y
+    (with and without a Dirichlet mask)."""
+    dt = torch.float64 if prec == "f64" else torch.float32
+    tol = TOL64 if prec == "f64" else TOL32
+    ref = case.orc.hvp(case.u, case.v)
+    case.op.linearize(dev(case.u), prec)
+    y0 = I.unit_direction(case.mesh.n_nodes, 77)
+    y = dev(y0, dt)
+    got = host(case.op.hvp_acc(dev(case.v, dt), y))
+    assert rel(got - y0, ref) <= tol
+    z = torch.zeros((case.mesh.n_nodes, 3), dtype=dt, device="cuda")
+    assert rel(host(case.op.hvp_zeroed(dev(case.v, dt), z)), ref) <= tol
+    mask, _ = I.clamp_top_bottom(case.mesh.X, 0.1)
+    case.op.set_dirichlet(dev(mask, torch.uint8))
+    try:
+        mref = F.masked(mask, case.orc.hvp(case.u, F.masked(mask, case.v)))
+        z = torch.zeros((case.mesh.n_nodes, 3), dtype=dt, device="cuda")
+        assert rel(host(case.op.hvp_zeroed(dev(case.v, dt), z)), mref) <= tol
+        y = dev(y0, dt)
+        got = host(case.op.hvp_acc(dev(case.v, dt), y))
+        assert rel(got - F.masked(mask, y0), mref) <= tol
+    finally:
+        case.op.set_dirichlet(None)
+
+
 def test_jacobi_diag(case):
     d = host(case.op.jacobi_diag(dev(case.u)))
     assert rel(d, case.orc.jacobi_diag(case.u)) <= TOL64

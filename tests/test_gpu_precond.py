@@ -1,0 +1,184 @@
+"""Learned CG preconditioner on the GPU against its FP64 oracle, its training,
+and flexible CG with the Jacobi fallback.
+
+Tolerances: the network runs on bfloat16 weights and layer inputs; the oracle
+rounds at the same places, but an FP32 value within an FP32 rounding of a
+bfloat16 tie can round the other way (one bf16 ulp = 2^-8 relative), so
+outputs are compared at 3e-2 of the output scale for all entries and 1e-3 for
+99.9% of them.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import fem as F
+from oracle import precond as P
+from paper_2602_12365_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+def dev(a, dtype=torch.float64):
+    return torch.as_tensor(np.ascontiguousarray(a)).to("cuda", dtype=dtype)
+
+
+def bf16_bits(x):
+    """uint16 bit patterns (as int16) of bf16-rounded float32 values."""
+    r = P.bf16_round(x).astype(np.float32)
+    return (r.view(np.uint32) >> 16).astype(np.uint16).view(np.int16)
+
+
+def bits_to_float(b):
+    return (np.asarray(b).view(np.uint16).astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+
+
+def rand_theta(seed, scale=0.3):
+    return (scale * np.random.default_rng(seed).standard_normal(P.N_PARAMS)).astype(np.float32)
+
+
+def close_bf16(got, ref):
+    err = np.abs(got - ref)
+    scale = max(np.abs(ref).max(), 1e-30)
+    return err.max() <= 3e-2 * scale and np.quantile(err, 0.999) <= 1e-3 * scale
+
+
+def make_op(elem, n, mu_sigma=0.5, dz=-0.2):
+    from paper_2602_12365_amd import Operator
+    m = I.make_mesh(elem, n)
+    mu = I.lognormal_field(m.n_elems, mu_sigma, 3)
+    mask, ubc = I.clamp_top_bottom(m.X, dz)
+    op = Operator(elem, m.X, m.conn)
+    op.set_material(dev(mu), dev(1.5 * mu))
+    op.set_dirichlet(dev(mask, torch.uint8))
+    return m, op, mu, mask, ubc
+
+
+def test_mlp_forward_matrix_cores_match_oracle():
+    m, op, *_ = make_op(I.HEX8, 2)
+    theta = rand_theta(1)
+    op.set_mlp(dev(theta, torch.float32))
+    rows = 1000 + 7                               # several 16-node groups and a ragged tail
+    Xf = np.zeros((rows, 16), dtype=np.float32)
+    Xf[:, :12] = np.random.default_rng(2).standard_normal((rows, 12))
+    out = op.mlp_forward(dev(bf16_bits(Xf), torch.int16)).cpu().numpy()
+    ref = P.mlp_forward(theta.astype(np.float64), Xf[:, :12])
+    assert close_bf16(out, ref)
+
+
+@pytest.mark.parametrize("elem", [I.TET4, I.HEX8])
+def test_features_and_apply_match_oracle(elem):
+    m, op, mu, mask, ubc = make_op(elem, 5)
+    theta = rand_theta(3)
+    op.set_mlp(dev(theta, torch.float32))
+    u = I.gaussian_field(m.n_nodes, 0.005, 0)
+    diag = op.jacobi_diag(dev(u))
+    r = I.gaussian_field(m.n_nodes, 1.0, 4)
+    t = I.gaussian_field(m.n_nodes, 1.0, 5)
+    X, aux = op.precond_rows(dev(r, torch.float32), diag, dev(t, torch.float32), 3.0)
+    ptr, idx = P.node_neighbours(m.conn, m.n_nodes)
+    Fo, go, so = P.features(r.astype(np.float32), diag.cpu().numpy(), mask, ptr, idx)
+    Fg = bits_to_float(X.cpu().numpy())[:, :12]
+    assert np.all(np.abs(Fg - P.bf16_round(Fo.astype(np.float32))) <= 2 ** -7 * np.abs(Fo) + 1e-6)
+    a = aux.cpu().numpy()
+    assert np.allclose(a[:, 0:3], go, rtol=1e-5, atol=1e-12 * np.abs(go).max())
+    assert np.allclose(a[:, 9], so, rtol=1e-5)
+    free = (mask.reshape(-1, 3) == 0).astype(float)
+    assert np.array_equal(a[:, 6:9], free)
+    tt = (t.astype(np.float32).astype(np.float64) ** 2).sum()
+    assert np.allclose(a[:, 10], 1.0 / (tt * 3.0), rtol=1e-5)
+    z = op.precond_apply(dev(r, torch.float32), diag).cpu().numpy()
+    zo = P.apply(theta.astype(np.float64), r.astype(np.float32), diag.cpu().numpy(), mask, ptr, idx)
+    assert close_bf16(z, zo)
+    assert np.all(z.reshape(-1)[mask != 0] == 0)
+
+
+def test_loss_gradient_matches_oracle_backward():
+    m, op, mu, mask, ubc = make_op(I.HEX8, 4)
+    theta = rand_theta(6, 0.2)
+    op.set_mlp(dev(theta, torch.float32))
+    diag = op.jacobi_diag(dev(np.zeros((m.n_nodes, 3))))
+    b = I.gaussian_field(m.n_nodes, 1.0, 7)
+    t = I.gaussian_field(m.n_nodes, 1e-3, 8)
+    X, aux = op.precond_rows(dev(b, torch.float32), diag, dev(t, torch.float32), 2.0)
+    th = dev(theta, torch.float32)
+    grad, loss = op.mlp_loss_grad(X, aux, th)
+    Xf = bits_to_float(X.cpu().numpy())[:, :12]
+    A = aux.cpu().numpy().astype(np.float64)
+    out = P.mlp_forward(theta.astype(np.float64), Xf.astype(np.float32))
+    g, tv, mm, s, w = A[:, 0:3], A[:, 3:6], A[:, 6:9], A[:, 9], A[:, 10]
+    e = mm * (g + s[:, None] * out) - mm * tv
+    loss_ref = np.sum(w[:, None] * e * e)
+    dout = 2 * w[:, None] * s[:, None] * mm * e
+    grad_ref = P.mlp_backward(theta.astype(np.float64), Xf.astype(np.float32), dout)
+    assert abs(loss.item() - loss_ref) <= 1e-3 * loss_ref
+    gg = grad.cpu().numpy()
+    assert np.linalg.norm(gg - grad_ref) <= 2e-2 * np.linalg.norm(grad_ref)
+
+
+def test_adam_step():
+    m, op, *_ = make_op(I.TET4, 1)
+    rng = np.random.default_rng(9)
+    p0, g = rng.standard_normal(P.N_PARAMS).astype(np.float32), rng.standard_normal(P.N_PARAMS).astype(np.float32)
+    p, mm, vv = dev(p0, torch.float32), torch.zeros(P.N_PARAMS, device="cuda"), torch.zeros(P.N_PARAMS, device="cuda")
+    op.mlp_adam(p, mm, vv, dev(g, torch.float32), 1e-2, 1)
+    # first step: m_hat = g, v_hat = g^2 -> p - lr * g / (|g| + eps)
+    ref = p0 - 1e-2 * g / (np.abs(g) + 1e-8)
+    assert np.allclose(p.cpu().numpy(), ref, rtol=1e-5, atol=1e-7)
+
+
+def test_training_reduces_loss_and_learned_solve_converges():
+    from paper_2602_12365_amd import precond as PC
+    X, aux, op = PC.generate_rows(n=6, seeds=range(1000, 1003), n_steps=4)
+    theta, hist = PC.train(op, X, aux, epochs=150, lr=3e-3)
+    assert hist[-1][1] < 0.9 * hist[0][1], hist
+    # a solve on an unseen field with the trained network, checked by the oracle
+    m, op2, mu, mask, ubc = make_op(I.HEX8, 8)
+    op2.set_mlp(theta)
+    u = np.zeros((m.n_nodes, 3))
+    u.reshape(-1)[mask != 0] = 0.5 * ubc.reshape(-1)[mask != 0]
+    r = op2.residual(dev(u))
+    x, it_nn, fb = op2.linear_solve(dev(u), r, rtol=1e-8, hvp_prec="f32", precond=1)
+    x_j, it_j, _ = op2.linear_solve(dev(u), r, rtol=1e-8, hvp_prec="f32", precond=0)
+    orc = F.FEM(I.HEX8, m.X, m.conn, mu, 1.5 * mu)
+    rr = F.masked(mask, orc.residual(u))
+    res = F.masked(mask, orc.hvp(u, x.cpu().numpy())) - rr
+    # FP32 tangent actions: the attainable true residual is ~1e-5 relative
+    assert np.linalg.norm(res) <= 5e-5 * np.linalg.norm(rr)
+    print(f"\n[precond] CG iterations to 1e-8: learned {it_nn} (fallback {fb}), Jacobi {it_j}", flush=True)
+
+
+def test_broken_network_falls_back_to_jacobi():
+    m, op, mu, mask, ubc = make_op(I.HEX8, 6)
+    theta = np.zeros(P.N_PARAMS, dtype=np.float32)
+    theta[-3:] = np.nan                        # non-finite preconditioner output
+    op.set_mlp(dev(theta, torch.float32))
+    u = np.zeros((m.n_nodes, 3))
+    u.reshape(-1)[mask != 0] = 0.3 * ubc.reshape(-1)[mask != 0]
+    r = op.residual(dev(u))
+    x, it, fb = op.linear_solve(dev(u), r, rtol=1e-6, hvp_prec="f32", precond=1)
+    assert fb
+    assert torch.isfinite(x).all()
+    orc = F.FEM(I.HEX8, m.X, m.conn, mu, 1.5 * mu)
+    rr = F.masked(mask, orc.residual(u))
+    assert np.linalg.norm(F.masked(mask, orc.hvp(u, x.cpu().numpy())) - rr) <= 1e-5 * np.linalg.norm(rr)
+    # the zero network is Jacobi and needs no fallback
+    theta = np.zeros(P.N_PARAMS, dtype=np.float32)
+    op.set_mlp(dev(theta, torch.float32))
+    x2, it2, fb2 = op.linear_solve(dev(u), r, rtol=1e-6, hvp_prec="f32", precond=1)
+    assert not fb2                             # the zero network is Jacobi and works
+
+
+def test_newton_with_learned_preconditioner():
+    from paper_2602_12365_amd import precond as PC
+    X, aux, op = PC.generate_rows(n=6, seeds=range(1000, 1002), n_steps=3)
+    theta, _ = PC.train(op, X, aux, epochs=60)
+    m, op2, mu, mask, ubc = make_op(I.HEX8, 6)
+    op2.set_mlp(theta)
+    u = torch.zeros((m.n_nodes, 3), dtype=torch.float64, device="cuda")
+    rc, st = op2.newton_solve(u, dev(ubc), n_steps=10, hvp_prec="f32", precond=1)
+    assert rc == 0, st
+    orc = F.FEM(I.HEX8, m.X, m.conn, mu, 1.5 * mu)
+    u_ref, st_ref = F.newton_solve(orc, mask, ubc, F.SolveOptions(n_steps=10))
+    ug = u.cpu().numpy()
+    assert np.linalg.norm(F.masked(mask, orc.residual(ug))) <= 2e-8 * st_ref.residual_history[-1][0]
+    assert np.linalg.norm(ug - u_ref) <= 1e-6 * np.linalg.norm(u_ref)
