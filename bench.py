@@ -9,10 +9,14 @@ DOF/s of the tangent action over the timed steps.
 
 Beside it: the FP32 tangent action, the colour scatter, energy and residual
 times, a roofline object for the dominant kernel (the single-launch FP64
-tangent-action block pass, timed with HIP events on its stream), and the FP64
-CPU oracle timed on a bounded sample on the host cores.
+tangent-action block pass, timed with HIP events on its stream), the Newton
+solves of the metric's second half (plain FP64 Jacobi-CG vs FP32 tangent
+actions with and without the learned preconditioner, on an unseen 96^3 Q1-hex
+compression case, the network trained first on pairs from 32^3 solves), and
+the FP64 CPU oracle timed on a bounded sample on the host cores.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-solve] [--no-cpu]
+    python bench.py --mode kernels     # fixed kernel workload for rocprofv3
 """
 from __future__ import annotations
 
@@ -48,6 +52,102 @@ def event_time(fn, reps, stream):
     return start.elapsed_time(end) / 1e3 / reps   # seconds per call
 
 
+def solve_section(args, dev):
+    """Compression load case (bottom clamped, top -20% z in 10 load steps, Q1
+    hexes, 2x2x2 Gauss, mu ~ lognormal(0, 0.5), lam = 1.5 mu) on an unseen
+    n_test^3 mesh: plain FP64 Newton-CG (Jacobi), mixed FP32-HVP (Jacobi), and
+    mixed FP32-HVP with the learned preconditioner trained on n_train^3 pairs.
+    Wall time from the first load step to the last step's convergence."""
+    import torch
+    from paper_2602_12365_amd import Operator, inputs as I, precond as PC
+
+    res = {"load_case": f"{args.n_test}^3 Q1 hexes, mu~lognormal(0,0.5) seed 2000, lam=1.5mu, "
+                        f"top -20% z in 10 steps, stop at 1e-8 relative residual per step"}
+    t0 = time.time()
+    seeds = range(1000, 1000 + args.train_fields)
+    X, aux, op_tr = PC.generate_rows(n=args.n_train, seeds=seeds, n_steps=10, log=log)
+    t_pairs = time.time() - t0
+    t0 = time.time()
+    theta, hist = PC.train(op_tr, X, aux, epochs=args.epochs, log=log)
+    torch.cuda.synchronize()
+    t_train = time.time() - t0
+    res["training"] = {"mesh": f"{args.n_train}^3 Q1 hexes", "pairs": len(seeds) * 10,
+                       "rows": int(X.shape[0]), "epochs": args.epochs,
+                       "loss_first_last": [hist[0][1], hist[-1][1]],
+                       "pair_generation_s": round(t_pairs, 2), "training_s": round(t_train, 2)}
+    op_tr.close()
+    del X, aux
+
+    mesh, mu, lam, mask, ubc = PC.compression_case(I.HEX8, args.n_test, 2000)
+    op = Operator(I.HEX8, mesh.X, mesh.conn, device=dev)
+    op.set_material(torch.as_tensor(mu, device=dev), torch.as_tensor(lam, device=dev))
+    op.set_dirichlet(torch.as_tensor(mask, device=dev))
+    ubc_t = torch.as_tensor(ubc, device=dev)
+    op.set_mlp(theta)
+    runs = {}
+    u_ref = None
+    for name, kw in [("plain_f64_jacobi", dict(hvp_prec="f64", precond=0)),
+                     ("mixed_f32_jacobi", dict(hvp_prec="f32", precond=0)),
+                     ("mixed_f32_learned", dict(hvp_prec="f32", precond=1))]:
+        u = torch.zeros((mesh.n_nodes, 3), dtype=torch.float64, device=dev)
+        log(f"solve {name}")
+        torch.cuda.synchronize()
+        t0 = time.time()
+        rc, st = op.newton_solve(u, ubc_t, n_steps=10, **kw)
+        torch.cuda.synchronize()
+        wall = time.time() - t0
+        r = op.residual(u)
+        entry = {"rc": rc, "wall_s": round(wall, 3), "solver_s": round(st["seconds"], 3),
+                 "newton_iters": st["newton_iters"], "cg_iters": st["cg_iters"],
+                 "fallbacks": st["precond_fallbacks"], "final_residual_fp64": st["final_residual"],
+                 "newton_per_step": st["newton_per_step"], "cg_per_step": st["cg_per_step"],
+                 "energy": st["final_energy"]}
+        if u_ref is None:
+            u_ref = u.clone()
+        else:
+            entry["rel_diff_to_plain_f64"] = float(torch.linalg.norm(u - u_ref) / torch.linalg.norm(u_ref))
+        entry["residual_norm_check"] = float(torch.linalg.norm(r))
+        runs[name] = entry
+        log(f"{name}: {entry['wall_s']} s, newton {entry['newton_iters']}, cg {entry['cg_iters']}")
+    res["runs"] = runs
+    res["speedup_mixed_learned_vs_plain"] = round(runs["plain_f64_jacobi"]["wall_s"]
+                                                  / runs["mixed_f32_learned"]["wall_s"], 3)
+    res["speedup_mixed_jacobi_vs_plain"] = round(runs["plain_f64_jacobi"]["wall_s"]
+                                                 / runs["mixed_f32_jacobi"]["wall_s"], 3)
+    op.close()
+    return res
+
+
+def kernels_mode(args, dev):
+    """Fixed kernel workload for rocprofv3 (no timing logic): the FP64 and FP32
+    tangent-action block pass on the 64^3 Kuhn mesh, energy, residual, and a
+    plain 256 MiB device copy of known size that calibrates the HBM counters."""
+    import torch
+    from paper_2602_12365_amd import Operator, inputs as I
+    mesh = I.tet_mesh(args.n)
+    u = torch.as_tensor(I.gaussian_field(mesh.n_nodes, I.cube_amplitude(args.n), 0)).to(dev)
+    v = torch.as_tensor(I.unit_direction(mesh.n_nodes, 100)).to(dev)
+    y = torch.zeros_like(u)
+    op = Operator(I.TET4, mesh.X, mesh.conn, device=dev)
+    op.linearize(u, "f64")
+    for _ in range(args.steps):
+        op.hvp_zeroed(v, y)
+    op.linearize(u, "f32")
+    v32, y32 = v.float(), torch.zeros_like(v, dtype=torch.float32)
+    for _ in range(args.steps):
+        op.hvp_zeroed(v32, y32)
+    psi = torch.empty((), dtype=torch.float64, device=dev)
+    for _ in range(args.steps):
+        op.energy(u, out=psi)
+        op.residual(u, out=y)
+    a = torch.empty(256 << 20, dtype=torch.uint8, device=dev)
+    b = torch.empty_like(a)
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    log("kernels mode done")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -56,6 +156,12 @@ def main():
     ap.add_argument("--n", type=int, default=64, help="hexes per cube edge")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-solve", action="store_true")
+    ap.add_argument("--n-train", type=int, default=32)
+    ap.add_argument("--n-test", type=int, default=96)
+    ap.add_argument("--train-fields", type=int, default=20)
+    ap.add_argument("--epochs", type=int, default=400)
+    ap.add_argument("--mode", choices=["bench", "kernels"], default="bench")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU "
@@ -67,6 +173,9 @@ def main():
 
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
+    if args.mode == "kernels":
+        kernels_mode(args, dev)
+        return
     n = args.n
     log(f"mesh n={n}")
     mesh = I.tet_mesh(n)
@@ -179,6 +288,9 @@ def main():
         "setup_s": round(setup_s, 3),
         "paper_context": "matrix-free JVP ~13 MDoF/s, 3D linear tets, NVIDIA A100 (JAX), precision unstated",
     }
+
+    if not args.no_solve:
+        out["newton"] = solve_section(args, dev)
 
     if not args.no_cpu:
         from oracle import fem as F

@@ -80,6 +80,10 @@ typedef struct {
                               fits 64 KB of LDS); 0 = default */
     int32_t scatter;       /* EFEM_SCATTER_ATOMIC or EFEM_SCATTER_COLOR */
     int32_t threads;       /* threads per workgroup (64..256, multiple of 64); 0 = default */
+    int32_t no_pairs;      /* EFEM_TET4: nonzero = one tetrahedron per work item; by
+                              default two tetrahedra that share a face form one item
+                              (5 nodes instead of 8), which results do not depend on
+                              beyond rounding */
 } efem_options;
 
 /* Build an operator for a mesh (Sec. 4, Operator(mesh, element, batchsize)).
@@ -181,6 +185,7 @@ typedef struct {
     int32_t max_block_elems;
     int64_t n_shared_nodes;   /* nodes touched by more than one block */
     int64_t n_block_nodes;    /* sum over blocks of distinct nodes (>= n_nodes) */
+    int64_t n_items;          /* work items: face-sharing tetrahedron pairs count once */
 } efem_info;
 
 int efem_get_info(efem_ctx *ctx, efem_info *info);

@@ -1,6 +1,7 @@
 // C-ABI entry points: context creation (mesh blocking on the host), material
 // and Dirichlet setup, and the asynchronous operator calls.
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -117,17 +118,115 @@ static uint64_t spread3(uint64_t v)   // 21 bits -> every third bit
 
 struct HostBlocks {
     std::vector<int32_t> order;      // internal -> caller element id
-    std::vector<int32_t> estart, nstart;
+    std::vector<int32_t> estart, istart, nstart;
     std::vector<uint32_t> bnode;
-    std::vector<uint16_t> lconn;
+    std::vector<uint32_t> items;     // packed local connectivity, kItemWords[elem] words per item
     std::vector<int32_t> shared_nodes;
     std::vector<std::vector<int32_t>> colours;
     int max_nodes = 0, max_elems = 0;
 };
 
-static void build_blocks(int nen, int64_t nn, int64_t ne, const double *X, const int32_t *conn,
-                         int be, int bn, bool colour, HostBlocks &hb)
+static double orient(const double *X, int32_t a, int32_t b, int32_t c, int32_t d)
 {
+    double E[9];
+    for (int i = 0; i < 3; ++i) {
+        E[i * 3 + 0] = X[3 * (int64_t)b + i] - X[3 * (int64_t)a + i];
+        E[i * 3 + 1] = X[3 * (int64_t)c + i] - X[3 * (int64_t)a + i];
+        E[i * 3 + 2] = X[3 * (int64_t)d + i] - X[3 * (int64_t)a + i];
+    }
+    return det3(E);
+}
+
+// Pair the tetrahedra el[0..n) of one block that share a face: a greedy
+// maximal matching in the block's (Morton) order.  On return el holds the
+// pairs first (partners adjacent), then the unpaired elements, and pw the
+// node tuples (a, b, c, d1, d2) of the pairs with (a, b, c, d1) and
+// (a, c, b, d2) both positively oriented.  Returns the number of pairs.
+static int pair_tets(const double *X, const int32_t *conn, std::vector<int32_t> &el,
+                     std::vector<std::array<int32_t, 5>> &pw)
+{
+    const int n = (int)el.size();
+    struct Face {
+        int32_t v[3];
+        int32_t k;
+        bool operator<(const Face &o) const
+        {
+            if (v[0] != o.v[0]) return v[0] < o.v[0];
+            if (v[1] != o.v[1]) return v[1] < o.v[1];
+            if (v[2] != o.v[2]) return v[2] < o.v[2];
+            return k < o.k;
+        }
+        bool same(const Face &o) const { return v[0] == o.v[0] && v[1] == o.v[1] && v[2] == o.v[2]; }
+    };
+    std::vector<Face> faces;
+    faces.reserve((size_t)n * 4);
+    for (int k = 0; k < n; ++k) {
+        const int32_t *ce = conn + 4 * (int64_t)el[(size_t)k];
+        for (int skip = 0; skip < 4; ++skip) {
+            Face f{};
+            int t = 0;
+            for (int a = 0; a < 4; ++a)
+                if (a != skip) f.v[t++] = ce[a];
+            std::sort(f.v, f.v + 3);
+            f.k = k;
+            faces.push_back(f);
+        }
+    }
+    std::sort(faces.begin(), faces.end());
+    // up to 4 face neighbours per element, in increasing block order
+    std::vector<std::array<int32_t, 4>> nb((size_t)n);
+    std::vector<int> cnt((size_t)n, 0);
+    for (size_t i = 0; i + 1 < faces.size(); ++i)
+        if (faces[i].same(faces[i + 1]) && (i + 2 >= faces.size() || !faces[i + 1].same(faces[i + 2]))
+            && (i == 0 || !faces[i - 1].same(faces[i]))) {
+            const int p = faces[i].k, q = faces[i + 1].k;
+            if (p == q) continue;
+            if (cnt[(size_t)p] < 4) nb[(size_t)p][(size_t)cnt[(size_t)p]++] = q;
+            if (cnt[(size_t)q] < 4) nb[(size_t)q][(size_t)cnt[(size_t)q]++] = p;
+        }
+    for (int k = 0; k < n; ++k) std::sort(nb[(size_t)k].begin(), nb[(size_t)k].begin() + cnt[(size_t)k]);
+    std::vector<int32_t> mate((size_t)n, -1);
+    std::vector<int32_t> paired, single;
+    pw.clear();
+    for (int k = 0; k < n; ++k) {
+        if (mate[(size_t)k] >= 0) continue;
+        for (int t = 0; t < cnt[(size_t)k]; ++t) {
+            const int j = nb[(size_t)k][(size_t)t];
+            if (mate[(size_t)j] >= 0) continue;
+            const int32_t *ck = conn + 4 * (int64_t)el[(size_t)k];
+            const int32_t *cj = conn + 4 * (int64_t)el[(size_t)j];
+            int32_t fa[3], d1 = -1, d2 = -1;
+            int nf = 0;
+            for (int a = 0; a < 4; ++a) {
+                const bool in = ck[a] == cj[0] || ck[a] == cj[1] || ck[a] == cj[2] || ck[a] == cj[3];
+                if (in && nf < 3) fa[nf++] = ck[a];
+                else d1 = ck[a];
+            }
+            for (int a = 0; a < 4; ++a)
+                if (cj[a] != fa[0] && cj[a] != fa[1] && cj[a] != fa[2]) d2 = cj[a];
+            if (nf != 3 || d1 < 0 || d2 < 0) continue;
+            if (!(orient(X, fa[0], fa[1], fa[2], d1) > 0.0)) std::swap(fa[1], fa[2]);
+            if (!(orient(X, fa[0], fa[1], fa[2], d1) > 0.0) || !(orient(X, fa[0], fa[2], fa[1], d2) > 0.0))
+                continue;
+            mate[(size_t)k] = j;
+            mate[(size_t)j] = k;
+            paired.push_back(el[(size_t)k]);
+            paired.push_back(el[(size_t)j]);
+            pw.push_back({fa[0], fa[1], fa[2], d1, d2});
+            break;
+        }
+        if (mate[(size_t)k] < 0) single.push_back(el[(size_t)k]);
+    }
+    const int np = (int)pw.size();
+    el = paired;
+    el.insert(el.end(), single.begin(), single.end());
+    return np;
+}
+
+static void build_blocks(int elem, int64_t nn, int64_t ne, const double *X, const int32_t *conn,
+                         int be, int bn, bool colour, bool pairs, HostBlocks &hb)
+{
+    const int nen = elem == EFEM_TET4 ? 4 : 8;
     // Morton order of element centroids
     double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
     for (int64_t i = 0; i < nn; ++i)
@@ -185,10 +284,11 @@ static void build_blocks(int nen, int64_t nn, int64_t ne, const double *X, const
     const int nb = (int)cut.size() - 1;
     hb.estart = cut;
 
-    // per-block sorted node lists and local connectivity
+    // per-block sorted node lists, tetrahedron pairs and packed local connectivity
     hb.nstart.assign(1, 0);
-    hb.lconn.resize((size_t)(ne * nen));
-    std::vector<int32_t> nodes;
+    hb.istart.assign(1, 0);
+    std::vector<int32_t> nodes, el;
+    std::vector<std::array<int32_t, 5>> pw;
     std::vector<int32_t> nblocks((size_t)nn, 0);
     std::vector<int32_t> local((size_t)nn, -1);
     for (int b = 0; b < nb; ++b) {
@@ -202,9 +302,32 @@ static void build_blocks(int nen, int64_t nn, int64_t ne, const double *X, const
             hb.bnode.push_back((uint32_t)nodes[i]);
             nblocks[nodes[i]] += 1;
         }
-        for (int k = cut[b]; k < cut[b + 1]; ++k)
-            for (int a = 0; a < nen; ++a)
-                hb.lconn[(size_t)k * nen + a] = (uint16_t)local[conn[(int64_t)hb.order[k] * nen + a]];
+        el.assign(hb.order.begin() + cut[b], hb.order.begin() + cut[b + 1]);
+        if (elem == EFEM_TET4) {
+            const int np = pairs ? pair_tets(X, conn, el, pw) : 0;
+            std::copy(el.begin(), el.end(), hb.order.begin() + cut[b]);
+            // item words: a | b << 10 | c << 20, then d1 | d2 << 10 (local ids < 1024)
+            for (int p = 0; p < np; ++p) {
+                const auto &t = pw[(size_t)p];
+                hb.items.push_back((uint32_t)local[t[0]] | (uint32_t)local[t[1]] << 10
+                                   | (uint32_t)local[t[2]] << 20);
+                hb.items.push_back((uint32_t)local[t[3]] | (uint32_t)local[t[4]] << 10);
+            }
+            for (size_t k = 2 * (size_t)np; k < el.size(); ++k) {
+                const int32_t *ce = conn + 4 * (int64_t)el[k];
+                hb.items.push_back((uint32_t)local[ce[0]] | (uint32_t)local[ce[1]] << 10
+                                   | (uint32_t)local[ce[2]] << 20);
+                hb.items.push_back((uint32_t)local[ce[3]] | (uint32_t)local[ce[3]] << 10);
+            }
+            hb.istart.push_back(hb.istart.back() + (int32_t)el.size() - np);
+        } else {
+            for (int32_t e : el) {
+                const int32_t *ce = conn + 8 * (int64_t)e;
+                for (int a = 0; a < 8; a += 2)
+                    hb.items.push_back((uint32_t)local[ce[a]] | (uint32_t)local[ce[a + 1]] << 16);
+            }
+            hb.istart.push_back(hb.istart.back() + (int32_t)el.size());
+        }
         hb.nstart.push_back((int32_t)hb.bnode.size());
         hb.max_nodes = std::max(hb.max_nodes, (int)nodes.size());
         hb.max_elems = std::max(hb.max_elems, cut[b + 1] - cut[b]);
@@ -337,7 +460,8 @@ int efem_create(efem_ctx **out, int32_t elem, int64_t n_nodes, int64_t n_elems,
 
     ctx->conn_host.assign(conn, conn + n_elems * nen);
     HostBlocks hb;
-    build_blocks(nen, n_nodes, n_elems, coords, conn, be, bn, scatter == EFEM_SCATTER_COLOR, hb);
+    build_blocks(elem, n_nodes, n_elems, coords, conn, be, bn, scatter == EFEM_SCATTER_COLOR,
+                 !(opts && opts->no_pairs), hb);
     ctx->max_block_nodes = hb.max_nodes;
     ctx->max_block_elems = hb.max_elems;
 
@@ -348,23 +472,24 @@ int efem_create(efem_ctx **out, int32_t elem, int64_t n_nodes, int64_t n_elems,
     int rc;
     BlockMesh &m = ctx->m;
     m.n_blocks = (int32_t)hb.estart.size() - 1;
-    m.nen = nen;
     std::vector<double> Xh(coords, coords + 3 * n_nodes);
     std::vector<float> Xfh(Xh.begin(), Xh.end());
-    int32_t *p_es, *p_ns, *p_eo;
-    uint32_t *p_bn;
-    uint16_t *p_lc;
+    int32_t *p_es, *p_is, *p_ns, *p_eo;
+    uint32_t *p_bn, *p_it;
     double *p_X;
     float *p_Xf;
-    if ((rc = upload(*ctx, &p_es, hb.estart)) || (rc = upload(*ctx, &p_ns, hb.nstart))
-        || (rc = upload(*ctx, &p_bn, hb.bnode)) || (rc = upload(*ctx, &p_lc, hb.lconn))
-        || (rc = upload(*ctx, &p_eo, hb.order)) || (rc = upload(*ctx, &p_X, Xh))
-        || (rc = upload(*ctx, &p_Xf, Xfh)) || (rc = upload(*ctx, &ctx->shared_nodes, hb.shared_nodes)))
+    if ((rc = upload(*ctx, &p_es, hb.estart)) || (rc = upload(*ctx, &p_is, hb.istart))
+        || (rc = upload(*ctx, &p_ns, hb.nstart)) || (rc = upload(*ctx, &p_bn, hb.bnode))
+        || (rc = upload(*ctx, &p_it, hb.items)) || (rc = upload(*ctx, &p_eo, hb.order))
+        || (rc = upload(*ctx, &p_X, Xh)) || (rc = upload(*ctx, &p_Xf, Xfh))
+        || (rc = upload(*ctx, &ctx->shared_nodes, hb.shared_nodes)))
         return fail(rc);
+    ctx->n_items = hb.istart.back();
     m.estart = p_es;
+    m.istart = p_is;
     m.nstart = p_ns;
     m.bnode = p_bn;
-    m.lconn = p_lc;
+    m.items = p_it;
     m.eorig = p_eo;
     m.X = p_X;
     m.Xf = p_Xf;
@@ -602,6 +727,7 @@ int efem_get_info(efem_ctx *ctx, efem_info *info)
     info->max_block_nodes = ctx->max_block_nodes;
     info->max_block_elems = ctx->max_block_elems;
     info->n_shared_nodes = ctx->n_shared;
+    info->n_items = ctx->n_items;
     info->n_block_nodes = 0;
     // total block-node entries = nstart[n_blocks]
     int32_t tot = 0;

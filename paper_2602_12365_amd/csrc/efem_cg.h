@@ -10,11 +10,14 @@ namespace efem {
 
 constexpr int kMaxRedBlocks = 1024;   // grid cap of the streaming reductions
 
-// Device-resident scalars of one CG solve; rz is kept for two iterations
-// (slot = iteration parity) so that it can be replaced while being read.
+// Device-resident scalars of one CG solve.  Every workgroup of a kernel reads
+// the scalars the previous iteration left while workgroup 0 publishes the
+// new ones, so whatever is both read and replaced within one kernel (rz, the
+// best residual and the stall count) is kept in two slots indexed by the
+// iteration parity.
 struct CgScalars {
-    double rz[2], rr, bb, tol2, pq, alpha, beta, best;
-    int32_t done, breakdown, iter, fallback, stall, pad;
+    double rz[2], rr, bb, tol2, pq, alpha, beta, best[2];
+    int32_t done, breakdown, iter, fallback, stall[2];
 };
 
 // Reduction scratch: four arrays of per-workgroup partials.

@@ -17,13 +17,19 @@ constexpr uint32_t kShared = 0x80000000u;   // node touched by more than one blo
 constexpr uint32_t kFirst = 0x40000000u;    // colour scatter: this block writes first
 
 // Device view of the blocked mesh, passed by value to every element kernel.
+// A block's elements are its work items' elements: tetrahedron pairs first
+// (partners adjacent in the internal order), then single elements, so item k of
+// a block with np pairs covers internal elements e0 + k + min(k, np) (+1 for the
+// second tetrahedron of a pair).
 struct BlockMesh {
     int32_t n_blocks;
-    int32_t nen;
+    int32_t pad;
     const int32_t *estart;    // [n_blocks+1] internal element ranges
+    const int32_t *istart;    // [n_blocks+1] work item ranges (np = elements - items)
     const int32_t *nstart;    // [n_blocks+1] ranges into bnode
     const uint32_t *bnode;    // block-local node -> global id | flags
-    const uint16_t *lconn;    // [n_elems*nen] block-local node indices
+    const uint32_t *items;    // packed block-local node ids: Tet4 2 words per item
+                              // (a | b<<10 | c<<20, d1 | d2<<10), Hex8 4 words (2 x 16 bit)
     const int32_t *eorig;     // [n_elems] internal -> caller element id
     const double *X;          // [n_nodes*3]
     const float *Xf;          // [n_nodes*3]
@@ -74,7 +80,7 @@ hipError_t launch_uniform_check(const double *a, const double *b, int64_t n, int
 // ---- context ---------------------------------------------------------------
 struct Ctx {
     int elem = 0, nen = 4, nq = 1;
-    int64_t n_nodes = 0, n_elems = 0;
+    int64_t n_nodes = 0, n_elems = 0, n_items = 0;
     int device = 0;
     hipStream_t stream = nullptr;
     Scatter scatter = Scatter::Atomic;

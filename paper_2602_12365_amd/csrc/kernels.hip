@@ -66,40 +66,125 @@ __device__ __forceinline__ double rcp(double x)
 }
 __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
-__device__ __forceinline__ double log_(double x) { return log(x); }
+// Natural logarithms for the material law.  The device library's FP64 log
+// costs about 100 instructions (general special-case handling); these cost
+// about 25.  Method: the exponent split y = 2^k m with m in [1/sqrt2, sqrt2),
+// then ln m = 2 atanh(s), s = (m - 1)/(m + 1), |s| <= 3 - 2 sqrt2 = 0.1716,
+// by its odd power series 2 (s + s^3/3 + ... + s^19/19); the first omitted
+// term, s^21/21, is below 2.4e-17 of the sum.  m - 1 is exact (Sterbenz), and
+// the quotient gets one residual correction, so the result is within a few
+// ulp.  Arguments must be positive and finite (the callers flag det F <= 0
+// before the value is used).
+__device__ __forceinline__ double two_atanh(double s)
+{
+    const double z = s * s;
+    double p = 1.0 / 19.0;
+    p = fma(p, z, 1.0 / 17.0);
+    p = fma(p, z, 1.0 / 15.0);
+    p = fma(p, z, 1.0 / 13.0);
+    p = fma(p, z, 1.0 / 11.0);
+    p = fma(p, z, 1.0 / 9.0);
+    p = fma(p, z, 1.0 / 7.0);
+    p = fma(p, z, 1.0 / 5.0);
+    p = fma(p, z, 1.0 / 3.0);
+    const double s2 = s + s;
+    return fma(s2 * z, p, s2);
+}
+
+// t / d to within about half an ulp: the refined reciprocal, then one
+// residual step on the quotient.
+__device__ __forceinline__ double quot(double t, double d)
+{
+    const double r = rcp(d);
+    const double q = t * r;
+    return fma(fma(-q, d, t), r, q);
+}
+
+constexpr double kLn2 = 0.69314718055994530942;   // rounded once to double
+constexpr double kSqrtHalf = 0.70710678118654752440;
+
+// y = 2^k m, m in [1/sqrt2, sqrt2)
+__device__ __forceinline__ double split_exp(double y, int &k)
+{
+    double m = __builtin_amdgcn_frexp_mant(y);   // [0.5, 1)
+    k = __builtin_amdgcn_frexp_exp(y);
+    const bool lo = m < kSqrtHalf;
+    m = lo ? m + m : m;
+    k = lo ? k - 1 : k;
+    return m;
+}
+
+__device__ __forceinline__ double log_(double x)
+{
+    int k;
+    const double m = split_exp(x, k);
+    return fma((double)k, kLn2, two_atanh(quot(m - 1.0, m + 1.0)));
+}
+
+// ln(1 + x) for x > -1.  When 1 + x lies in [1/sqrt2, sqrt2) the argument
+// s = x / (2 + x) is formed from x itself, so the rounding of 1 + x never
+// enters (this is where ln J is small and the energy cancels to second order).
+__device__ __forceinline__ double log1p_(double x)
+{
+    int k;
+    const double m = split_exp(1.0 + x, k);
+    const bool near = k == 0;
+    const double t = near ? x : m - 1.0;
+    const double d = near ? 2.0 + x : m + 1.0;
+    return fma((double)k, kLn2, two_atanh(quot(t, d)));
+}
+
 __device__ __forceinline__ float log_(float x) { return __logf(x); }
 
 __device__ __forceinline__ void flag_inverted(int32_t *flags) { atomicOr(flags, 1); }
 
 // ------------------------------------------------------------ element types
 
-// Tet4: N0 = 1 - xi - eta - zeta, N_a = xi_a (a = 1..3); one point, w = 1/6.
-struct Tet4 {
-    static constexpr int NEN = 4, NQ = 1;
+// Work items.  An item is what one thread computes: a pair of tetrahedra that
+// share a face, or one hexahedron.  NEN nodes per item, NQ quadrature points
+// per item, NSUB elements per item (sub(q) is the element of point q).
+//
+// Tet4 pair: nodes (a, b, c, d1, d2) with tet 1 = (a, b, c, d1) positively
+// oriented and tet 2 = (a, c, b, d2), also positive since d2 lies on the
+// other side of the shared face.  A tetrahedron without a partner is stored as
+// (n0, n1, n2, n3, n3) and its second point skipped.
+// Each tetrahedron: N0 = 1 - xi - eta - zeta, N_k = xi_k; one point, w = 1/6.
+struct Tet4Pair {
+    static constexpr int NEN = 5, NQ = 2, NSUB = 2;
     template <class T> __device__ static constexpr T weight() { return T(1.0 / 6.0); }
+    __device__ static constexpr int sub(int q) { return q; }
+    // the second point of an unpaired tetrahedron is skipped
+    __device__ static constexpr bool skip(int q, bool pair) { return q > 0 && !pair; }
+    // pair node of local tet node k (k = 0..3) of tet q
+    __device__ static constexpr int node(int q, int k)
+    {
+        return q == 0 ? k : (k == 1 ? 2 : (k == 2 ? 1 : (k == 3 ? 4 : 0)));
+    }
     // G[i*3+J] = d f_i / d xi_J at point q
     template <class T>
-    __device__ static __forceinline__ void grad(const T f[NEN][3], int, T G[9])
+    __device__ static __forceinline__ void grad(const T f[NEN][3], int q, T G[9])
     {
 #pragma unroll
         for (int i = 0; i < 3; ++i)
 #pragma unroll
-            for (int J = 0; J < 3; ++J) G[i * 3 + J] = f[J + 1][i] - f[0][i];
+            for (int J = 0; J < 3; ++J) G[i * 3 + J] = f[node(q, J + 1)][i] - f[0][i];
     }
     template <class T>
-    __device__ static __forceinline__ void add_forces(const T Q[9], int, T out[NEN][3])
+    __device__ static __forceinline__ void add_forces(const T Q[9], int q, T out[NEN][3])
     {
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
-            out[1][i] += Q[i * 3 + 0];
-            out[2][i] += Q[i * 3 + 1];
-            out[3][i] += Q[i * 3 + 2];
+            out[node(q, 1)][i] += Q[i * 3 + 0];
+            out[node(q, 2)][i] += Q[i * 3 + 1];
+            out[node(q, 3)][i] += Q[i * 3 + 2];
             out[0][i] -= Q[i * 3 + 0] + Q[i * 3 + 1] + Q[i * 3 + 2];
         }
     }
-    template <class T> __device__ static __forceinline__ T dN(int, int a, int J)
+    // d N_a / d xi_J of pair node a at point q (0 for the node outside tet q)
+    template <class T> __device__ static __forceinline__ T dN(int q, int a, int J)
     {
-        return a == 0 ? T(-1) : (a - 1 == J ? T(1) : T(0));
+        if (a == 0) return T(-1);
+        return node(q, J + 1) == a ? T(1) : T(0);
     }
 };
 
@@ -108,8 +193,10 @@ struct Tet4 {
 __device__ constexpr int kHexS[8][3] = {{-1, -1, -1}, {1, -1, -1}, {1, 1, -1}, {-1, 1, -1},
                                         {-1, -1, 1},  {1, -1, 1},  {1, 1, 1},  {-1, 1, 1}};
 struct Hex8 {
-    static constexpr int NEN = 8, NQ = 8;
+    static constexpr int NEN = 8, NQ = 8, NSUB = 1;
     template <class T> __device__ static constexpr T weight() { return T(1); }
+    __device__ static constexpr int sub(int) { return 0; }
+    __device__ static constexpr bool skip(int, bool) { return false; }
     template <class T> __device__ static __forceinline__ T dN(int q, int a, int J)
     {
         const T g = T(0.57735026918962576451);
@@ -346,8 +433,8 @@ template <> struct HvpOp<double> {
         }
     }
     template <class E>
-    __device__ bool element(const Node *sn, const uint16_t *lc, double mu, double lam,
-                            double f[E::NEN][3]) const
+    __device__ __forceinline__ bool element(const Node *sn, const uint16_t *lc, const double *mu,
+                                            const double *lam, bool pair, double f[E::NEN][3]) const
     {
         double Xe[E::NEN][3], xe[E::NEN][3], ve[E::NEN][3];
 #pragma unroll
@@ -363,11 +450,12 @@ template <> struct HvpOp<double> {
         bool ok = true;
 #pragma unroll
         for (int q = 0; q < E::NQ; ++q) {
+            if (E::skip(q, pair)) continue;
             double Jx[9], Jd[9], dJ[9], Q[9];
             E::grad(Xe, q, Jx);
             E::grad(xe, q, Jd);
             E::grad(ve, q, dJ);
-            ok &= qp_hvp(E::template weight<double>(), Jx, Jd, dJ, mu, lam, Q);
+            ok &= qp_hvp(E::template weight<double>(), Jx, Jd, dJ, mu[E::sub(q)], lam[E::sub(q)], Q);
             E::add_forces(Q, q, f);
         }
         return ok;
@@ -391,8 +479,8 @@ template <> struct HvpOp<float> {
         }
     }
     template <class E>
-    __device__ bool element(const Node *sn, const uint16_t *lc, float mu, float lam,
-                            float f[E::NEN][3]) const
+    __device__ __forceinline__ bool element(const Node *sn, const uint16_t *lc, const float *mu,
+                                            const float *lam, bool pair, float f[E::NEN][3]) const
     {
         float Xe[E::NEN][3], ue[E::NEN][3], ve[E::NEN][3];
 #pragma unroll
@@ -408,13 +496,14 @@ template <> struct HvpOp<float> {
         bool ok = true;
 #pragma unroll
         for (int q = 0; q < E::NQ; ++q) {
+            if (E::skip(q, pair)) continue;
             float Jx[9], Jd[9], dJ[9], Q[9];
             E::grad(Xe, q, Jx);
             E::grad(ue, q, Jd);
 #pragma unroll
             for (int k = 0; k < 9; ++k) Jd[k] += Jx[k];
             E::grad(ve, q, dJ);
-            ok &= qp_hvp(E::template weight<float>(), Jx, Jd, dJ, mu, lam, Q);
+            ok &= qp_hvp(E::template weight<float>(), Jx, Jd, dJ, mu[E::sub(q)], lam[E::sub(q)], Q);
             E::add_forces(Q, q, f);
         }
         return ok;
@@ -448,20 +537,21 @@ struct XUStage {
 struct ResidualOp : XUStage {
     using Node = NodeXU;
     template <class E>
-    __device__ bool element(const Node *sn, const uint16_t *lc, double mu, double lam,
-                            double f[E::NEN][3]) const
+    __device__ __forceinline__ bool element(const Node *sn, const uint16_t *lc, const double *mu,
+                                            const double *lam, bool pair, double f[E::NEN][3]) const
     {
         double Xe[E::NEN][3], ue[E::NEN][3];
         gather_xu<E>(sn, lc, Xe, ue);
         bool ok = true;
 #pragma unroll
         for (int q = 0; q < E::NQ; ++q) {
+            if (E::skip(q, pair)) continue;
             double Jx[9], Jd[9], Q[9];
             E::grad(Xe, q, Jx);
             E::grad(ue, q, Jd);
 #pragma unroll
             for (int k = 0; k < 9; ++k) Jd[k] += Jx[k];
-            ok &= qp_residual(E::template weight<double>(), Jx, Jd, mu, lam, Q);
+            ok &= qp_residual(E::template weight<double>(), Jx, Jd, mu[E::sub(q)], lam[E::sub(q)], Q);
             E::add_forces(Q, q, f);
         }
         return ok;
@@ -472,14 +562,16 @@ struct ResidualOp : XUStage {
 struct DiagOp : XUStage {
     using Node = NodeXU;
     template <class E>
-    __device__ bool element(const Node *sn, const uint16_t *lc, double mu, double lam,
-                            double f[E::NEN][3]) const
+    __device__ __forceinline__ bool element(const Node *sn, const uint16_t *lc, const double *mu,
+                                            const double *lam, bool pair, double f[E::NEN][3]) const
     {
         double Xe[E::NEN][3], ue[E::NEN][3];
         gather_xu<E>(sn, lc, Xe, ue);
         bool ok = true;
 #pragma unroll
         for (int q = 0; q < E::NQ; ++q) {
+            if (E::skip(q, pair)) continue;
+            const double mq = mu[E::sub(q)], lq = lam[E::sub(q)];
             double Jx[9], Jd[9], Ae[9], Ad[9];
             E::grad(Xe, q, Jx);
             E::grad(ue, q, Jd);
@@ -489,9 +581,9 @@ struct DiagOp : XUStage {
             const double Dd = adj_det(Jd, Ad);
             ok &= Dd > 0.0;
             const double w = E::template weight<double>();
-            const double lnJ = log(Dd / De);
-            const double a = w * mu / De;
-            const double b = w * (lam + mu - lam * lnJ) * De / (Dd * Dd);
+            const double lnJ = log_(Dd / De);
+            const double a = w * mq / De;
+            const double b = w * (lq + mq - lq * lnJ) * De / (Dd * Dd);
 #pragma unroll
             for (int n = 0; n < E::NEN; ++n) {
                 const double g0 = E::template dN<double>(q, n, 0);
@@ -517,14 +609,16 @@ struct DiagOp : XUStage {
 struct GradCoordsOp : XUStage {
     using Node = NodeXU;
     template <class E>
-    __device__ bool element(const Node *sn, const uint16_t *lc, double mu, double lam,
-                            double f[E::NEN][3]) const
+    __device__ __forceinline__ bool element(const Node *sn, const uint16_t *lc, const double *mu,
+                                            const double *lam, bool pair, double f[E::NEN][3]) const
     {
         double Xe[E::NEN][3], ue[E::NEN][3];
         gather_xu<E>(sn, lc, Xe, ue);
         bool ok = true;
 #pragma unroll
         for (int q = 0; q < E::NQ; ++q) {
+            if (E::skip(q, pair)) continue;
+            const double mu_ = mu[E::sub(q)], lam_ = lam[E::sub(q)];
             double Jx[9], Hxi[9], Ae[9];
             E::grad(Xe, q, Jx);
             E::grad(ue, q, Hxi);
@@ -534,8 +628,8 @@ struct GradCoordsOp : XUStage {
                 ok = false;
                 continue;
             }
-            const double lnJ = log1p(k.Jm1);
-            const double psi = 0.5 * mu * k.I1m3 - mu * lnJ + 0.5 * lam * lnJ * lnJ;
+            const double lnJ = log1p_(k.Jm1);
+            const double psi = 0.5 * mu_ * k.I1m3 - mu_ * lnJ + 0.5 * lam_ * lnJ * lnJ;
             double F[9], Fa[9];
 #pragma unroll
             for (int i = 0; i < 9; ++i) F[i] = k.H[i] + ((i % 4) == 0 ? 1.0 : 0.0);
@@ -547,7 +641,7 @@ struct GradCoordsOp : XUStage {
 #pragma unroll
                 for (int J = 0; J < 3; ++J) {
                     const double FiT = Fa[J * 3 + i] * rdF;   // F^-T_iJ
-                    P[i * 3 + J] = mu * (F[i * 3 + J] - FiT) + lam * lnJ * FiT;
+                    P[i * 3 + J] = mu_ * (F[i * 3 + J] - FiT) + lam_ * lnJ * FiT;
                 }
 #pragma unroll
             for (int mm = 0; mm < 3; ++mm)
@@ -571,51 +665,99 @@ struct GradCoordsOp : XUStage {
     }
 };
 
-// ------------------------------------------------------- per-element inputs
+// ------------------------------------------------------------ per-item inputs
 
-// Local connectivity of one element in one vector load (4 or 8 uint16), plus
-// its material.  Loaded one element ahead of its use so that the global-load
-// latency overlaps the previous element's arithmetic.
-template <int NEN> struct LWord;
-template <> struct LWord<4> { uint2 w; };
-template <> struct LWord<8> { uint4 w; };
+// Work items of one block.  Pairs come first; item k covers the internal
+// elements e0 + k + min(k, np) (+ s for sub-element s of a pair).
+struct ItemRange {
+    int i0, ni, e0, np;
+    __device__ __forceinline__ int elem(int k, int s) const { return e0 + k + min(k, np) + s; }
+};
 
-template <class E> struct EData {
-    LWord<E::NEN> lc;
-    double mu, lam;
+__device__ __forceinline__ ItemRange item_range(const BlockMesh &m, int b)
+{
+    ItemRange r;
+    r.i0 = m.istart[b];
+    r.ni = m.istart[b + 1] - r.i0;
+    r.e0 = m.estart[b];
+    r.np = (m.estart[b + 1] - r.e0) - r.ni;
+    return r;
+}
+
+// Packed local connectivity of one item in one vector load, plus its
+// materials.  Loaded one item ahead of its use so that the global-load latency
+// overlaps the previous item's arithmetic.
+template <class E> struct ItemWord;
+template <> struct ItemWord<Tet4Pair> { uint2 w; };
+template <> struct ItemWord<Hex8> { uint4 w; };
+
+template <class E> struct IData {
+    ItemWord<E> lc;
+    double mu[E::NSUB], lam[E::NSUB];
 };
 
 template <class E>
-__device__ __forceinline__ EData<E> fetch_elem(const BlockMesh &m, int e)
+__device__ __forceinline__ IData<E> fetch_item(const BlockMesh &m, const ItemRange &r, int k)
 {
-    EData<E> d;
-    if constexpr (E::NEN == 4) d.lc.w = *reinterpret_cast<const uint2 *>(m.lconn + (int64_t)e * 4);
-    else d.lc.w = *reinterpret_cast<const uint4 *>(m.lconn + (int64_t)e * 8);
-    if (m.mu) {
-        d.mu = m.mu[e];
-        d.lam = m.lam[e];
-    } else {
-        d.mu = m.mu0;
-        d.lam = m.lam0;
+    IData<E> d;
+    const int64_t i = r.i0 + k;
+    if constexpr (E::NEN == 5) d.lc.w = *reinterpret_cast<const uint2 *>(m.items + 2 * i);
+    else d.lc.w = *reinterpret_cast<const uint4 *>(m.items + 4 * i);
+#pragma unroll
+    for (int s = 0; s < E::NSUB; ++s) {
+        if (m.mu) {
+            // an unpaired tetrahedron has no second element: repeat the first
+            const int e = r.elem(k, (s > 0 && k >= r.np) ? 0 : s);
+            d.mu[s] = m.mu[e];
+            d.lam[s] = m.lam[e];
+        } else {
+            d.mu[s] = m.mu0;
+            d.lam[s] = m.lam0;
+        }
     }
     return d;
 }
 
 template <class E>
-__device__ __forceinline__ void unpack_lc(const LWord<E::NEN> &l, uint16_t lc[E::NEN])
+__device__ __forceinline__ void unpack_lc(const ItemWord<E> &l, uint16_t lc[E::NEN])
 {
-    if constexpr (E::NEN == 4) {
-        lc[0] = l.w.x & 0xffff, lc[1] = l.w.x >> 16, lc[2] = l.w.y & 0xffff, lc[3] = l.w.y >> 16;
+    if constexpr (E::NEN == 5) {
+        lc[0] = l.w.x & 1023u, lc[1] = (l.w.x >> 10) & 1023u, lc[2] = (l.w.x >> 20) & 1023u;
+        lc[3] = l.w.y & 1023u, lc[4] = (l.w.y >> 10) & 1023u;
     } else {
         lc[0] = l.w.x & 0xffff, lc[1] = l.w.x >> 16, lc[2] = l.w.y & 0xffff, lc[3] = l.w.y >> 16;
         lc[4] = l.w.z & 0xffff, lc[5] = l.w.z >> 16, lc[6] = l.w.w & 0xffff, lc[7] = l.w.w >> 16;
     }
 }
 
+template <class E, class T>
+__device__ __forceinline__ void materials(const IData<E> &d, T mu[E::NSUB], T lam[E::NSUB])
+{
+#pragma unroll
+    for (int s = 0; s < E::NSUB; ++s) {
+        mu[s] = T(d.mu[s]);
+        lam[s] = T(d.lam[s]);
+    }
+}
+
 // ---------------------------------------------------------- block pass kernel
 
+// Waves per SIMD the register allocator must leave room for.  The FP64 Tet4
+// pair pass needs about 186 VGPRs unconstrained (2 waves); the other item
+// kernels keep the compiler's choice.
+#ifndef EFEM_TET64_MIN_WAVES
+#define EFEM_TET64_MIN_WAVES 1
+#endif
+template <class E, class T> struct MinWaves {
+    static constexpr int value = 1;
+};
+template <> struct MinWaves<Tet4Pair, double> {
+    static constexpr int value = EFEM_TET64_MIN_WAVES;
+};
+
 template <class E, class Op, class T, bool ACC>
-__global__ void __launch_bounds__(256) k_accumulate(BlockMesh m, Op op, T *__restrict__ y,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MinWaves<E, T>::value, 8)))
+k_accumulate(BlockMesh m, Op op, T *__restrict__ y,
                                                     const int32_t *__restrict__ list, int count,
                                                     Scatter mode, int use_mask, T fixed_val,
                                                     const int32_t *__restrict__ skip)
@@ -626,21 +768,21 @@ __global__ void __launch_bounds__(256) k_accumulate(BlockMesh m, Op op, T *__res
     const int lb = xcd_remap(blockIdx.x, count);
     const int b = list ? list[lb] : lb;
     const int n0 = m.nstart[b], nn = m.nstart[b + 1] - n0;
-    const int e0 = m.estart[b], ne = m.estart[b + 1] - e0;
+    const ItemRange r = item_range(m, b);
     Node *sn = reinterpret_cast<Node *>(smem);
     // nodal sums are accumulated in FP64 in LDS for both precisions
     double *acc = reinterpret_cast<double *>(smem + sizeof(Node) * nn);
     const uint32_t *bnode = m.bnode + n0;
     const int nt = blockDim.x;
-    // The 64 lanes of a wave take elements S apart in the block's Morton order
+    // The 64 lanes of a wave take items S apart in the block's Morton order
     // (lane * S + j), so that the lanes of one LDS atomic rarely hit the same
     // node; wave w takes columns j = w, w + W, ...
     const int W = nt >> 6, lane = threadIdx.x & 63;
-    const int S = (ne + 63) >> 6;
+    const int S = (r.ni + 63) >> 6;
     int j = threadIdx.x >> 6;
-    auto elem_of = [&](int jj) { return lane * S + jj; };
-    EData<E> nxt{};
-    if (j < S && elem_of(j) < ne) nxt = fetch_elem<E>(m, e0 + elem_of(j));   // in flight during staging
+    auto item_of = [&](int jj) { return lane * S + jj; };
+    IData<E> nxt{};
+    if (j < S && item_of(j) < r.ni) nxt = fetch_item<E>(m, r, item_of(j));   // in flight during staging
     for (int l = threadIdx.x; l < nn; l += nt) {
         op.stage(m, sn[l], bnode[l] & kGidMask);
         acc[3 * l + 0] = 0.0;
@@ -650,16 +792,18 @@ __global__ void __launch_bounds__(256) k_accumulate(BlockMesh m, Op op, T *__res
     __syncthreads();
     bool bad = false;
     for (; j < S; j += W) {
-        const int k = elem_of(j);
-        if (k >= ne) break;
-        const EData<E> cur = nxt;
-        if (j + W < S && elem_of(j + W) < ne) nxt = fetch_elem<E>(m, e0 + elem_of(j + W));
+        const int k = item_of(j);
+        if (k >= r.ni) break;
+        const IData<E> cur = nxt;
+        if (j + W < S && item_of(j + W) < r.ni) nxt = fetch_item<E>(m, r, item_of(j + W));
         uint16_t lc[E::NEN];
         unpack_lc<E>(cur.lc, lc);
+        T mu[E::NSUB], lam[E::NSUB];
+        materials<E>(cur, mu, lam);
         T f[E::NEN][3];
 #pragma unroll
         for (int a = 0; a < E::NEN; ++a) f[a][0] = f[a][1] = f[a][2] = T(0);
-        bad |= !op.template element<E>(sn, lc, T(cur.mu), T(cur.lam), f);
+        bad |= !op.template element<E>(sn, lc, mu, lam, k < r.np, f);
 #pragma unroll
         for (int a = 0; a < E::NEN; ++a)
 #pragma unroll
@@ -695,28 +839,30 @@ __global__ void __launch_bounds__(256) k_energy(BlockMesh m, const double *__res
     const int count = m.n_blocks;
     const int b = xcd_remap(blockIdx.x, count);
     const int n0 = m.nstart[b], nn = m.nstart[b + 1] - n0;
-    const int e0 = m.estart[b], ne = m.estart[b + 1] - e0;
+    const ItemRange r = item_range(m, b);
     NodeXU *sn = reinterpret_cast<NodeXU *>(smem);
     XUStage st{X, u};
     const int nt = blockDim.x;
     int k = threadIdx.x;
-    EData<E> nxt{};
-    if (k < ne) nxt = fetch_elem<E>(m, e0 + k);
+    IData<E> nxt{};
+    if (k < r.ni) nxt = fetch_item<E>(m, r, k);
     for (int l = threadIdx.x; l < nn; l += nt) st.stage(m, sn[l], m.bnode[n0 + l] & kGidMask);
     __syncthreads();
     double acc = 0.0;
     bool bad = false;
-    for (; k < ne; k += nt) {
-        const EData<E> cur = nxt;
-        if (k + nt < ne) nxt = fetch_elem<E>(m, e0 + k + nt);
+    for (; k < r.ni; k += nt) {
+        const IData<E> cur = nxt;
+        if (k + nt < r.ni) nxt = fetch_item<E>(m, r, k + nt);
         uint16_t lc[E::NEN];
         unpack_lc<E>(cur.lc, lc);
         double Xe[E::NEN][3], ue[E::NEN][3];
         gather_xu<E>(sn, lc, Xe, ue);
-        const double mu = cur.mu, lam = cur.lam;
+        const bool pair = k < r.np;
         double pe = 0.0;
 #pragma unroll
         for (int q = 0; q < E::NQ; ++q) {
+            if (E::skip(q, pair)) continue;
+            const double mu = cur.mu[E::sub(q)], lam = cur.lam[E::sub(q)];
             double Jx[9], Hxi[9];
             E::grad(Xe, q, Jx);
             E::grad(ue, q, Hxi);
@@ -726,7 +872,7 @@ __global__ void __launch_bounds__(256) k_energy(BlockMesh m, const double *__res
                 bad = true;
                 continue;
             }
-            const double lnJ = log1p(kk.Jm1);
+            const double lnJ = log1p_(kk.Jm1);
             pe += kk.wDe * (0.5 * mu * kk.I1m3 - mu * lnJ + 0.5 * lam * lnJ * lnJ);
         }
         acc += pe;
@@ -768,7 +914,7 @@ __global__ void __launch_bounds__(256) k_sum_partials(const double *__restrict__
     if (threadIdx.x == 0) *out = red[0];
 }
 
-// ------------------------------------------------- per-element adjoint kernels
+// ---------------------------------------------------- per-element adjoint kernels
 
 // dPsi/dmu_e, dPsi/dlam_e at fixed u.
 template <class E>
@@ -780,22 +926,23 @@ __global__ void __launch_bounds__(256) k_grad_material(BlockMesh m, const double
     extern __shared__ __align__(16) unsigned char smem[];
     const int b = xcd_remap(blockIdx.x, m.n_blocks);
     const int n0 = m.nstart[b], nn = m.nstart[b + 1] - n0;
-    const int e0 = m.estart[b], ne = m.estart[b + 1] - e0;
+    const ItemRange r = item_range(m, b);
     NodeXU *sn = reinterpret_cast<NodeXU *>(smem);
     XUStage st{X, u};
     for (int l = threadIdx.x; l < nn; l += blockDim.x) st.stage(m, sn[l], m.bnode[n0 + l] & kGidMask);
     __syncthreads();
     bool bad = false;
-    for (int k = threadIdx.x; k < ne; k += blockDim.x) {
-        const int e = e0 + k;
+    for (int k = threadIdx.x; k < r.ni; k += blockDim.x) {
+        const IData<E> d = fetch_item<E>(m, r, k);
         uint16_t lc[E::NEN];
-#pragma unroll
-        for (int a = 0; a < E::NEN; ++a) lc[a] = m.lconn[(int64_t)e * E::NEN + a];
+        unpack_lc<E>(d.lc, lc);
         double Xe[E::NEN][3], ue[E::NEN][3];
         gather_xu<E>(sn, lc, Xe, ue);
-        double gm = 0.0, gl = 0.0;
+        const bool pair = k < r.np;
+        double gm[E::NSUB] = {}, gl[E::NSUB] = {};
 #pragma unroll
         for (int q = 0; q < E::NQ; ++q) {
+            if (E::skip(q, pair)) continue;
             double Jx[9], Hxi[9];
             E::grad(Xe, q, Jx);
             E::grad(ue, q, Hxi);
@@ -805,13 +952,17 @@ __global__ void __launch_bounds__(256) k_grad_material(BlockMesh m, const double
                 bad = true;
                 continue;
             }
-            const double lnJ = log1p(kk.Jm1);
-            gm += kk.wDe * (0.5 * kk.I1m3 - lnJ);
-            gl += kk.wDe * 0.5 * lnJ * lnJ;
+            const double lnJ = log1p_(kk.Jm1);
+            gm[E::sub(q)] += kk.wDe * (0.5 * kk.I1m3 - lnJ);
+            gl[E::sub(q)] += kk.wDe * 0.5 * lnJ * lnJ;
         }
-        const int eo = m.eorig[e];
-        dmu[eo] = gm;
-        dlam[eo] = gl;
+#pragma unroll
+        for (int s = 0; s < E::NSUB; ++s) {
+            if (s > 0 && !pair) break;
+            const int eo = m.eorig[r.elem(k, s)];
+            dmu[eo] = gm[s];
+            dlam[eo] = gl[s];
+        }
     }
     if (bad) flag_inverted(m.flags);
 }
@@ -827,7 +978,7 @@ __global__ void __launch_bounds__(256) k_vjp_material(BlockMesh m, const double 
     extern __shared__ __align__(16) unsigned char smem[];
     const int b = xcd_remap(blockIdx.x, m.n_blocks);
     const int n0 = m.nstart[b], nn = m.nstart[b + 1] - n0;
-    const int e0 = m.estart[b], ne = m.estart[b + 1] - e0;
+    const ItemRange r = item_range(m, b);
     NodeXUW *sn = reinterpret_cast<NodeXUW *>(smem);
     for (int l = threadIdx.x; l < nn; l += blockDim.x) {
         const int64_t g = m.bnode[n0 + l] & kGidMask;
@@ -837,11 +988,10 @@ __global__ void __launch_bounds__(256) k_vjp_material(BlockMesh m, const double 
     }
     __syncthreads();
     bool bad = false;
-    for (int k = threadIdx.x; k < ne; k += blockDim.x) {
-        const int e = e0 + k;
+    for (int k = threadIdx.x; k < r.ni; k += blockDim.x) {
+        const IData<E> d = fetch_item<E>(m, r, k);
         uint16_t lc[E::NEN];
-#pragma unroll
-        for (int a = 0; a < E::NEN; ++a) lc[a] = m.lconn[(int64_t)e * E::NEN + a];
+        unpack_lc<E>(d.lc, lc);
         double Xe[E::NEN][3], ue[E::NEN][3], we[E::NEN][3];
 #pragma unroll
         for (int a = 0; a < E::NEN; ++a)
@@ -851,9 +1001,11 @@ __global__ void __launch_bounds__(256) k_vjp_material(BlockMesh m, const double 
                 ue[a][i] = sn[lc[a]].u[i];
                 we[a][i] = sn[lc[a]].w[i];
             }
-        double gm = 0.0, gl = 0.0;
+        const bool pair = k < r.np;
+        double gm[E::NSUB] = {}, gl[E::NSUB] = {};
 #pragma unroll
         for (int q = 0; q < E::NQ; ++q) {
+            if (E::skip(q, pair)) continue;
             double Jx[9], Hxi[9], Wxi[9], Ae[9];
             E::grad(Xe, q, Jx);
             E::grad(ue, q, Hxi);
@@ -864,7 +1016,7 @@ __global__ void __launch_bounds__(256) k_vjp_material(BlockMesh m, const double 
                 bad = true;
                 continue;
             }
-            const double lnJ = log1p(kk.Jm1);
+            const double lnJ = log1p_(kk.Jm1);
             const double De = adj_det(Jx, Ae);
             double F[9], Fa[9];
 #pragma unroll
@@ -881,12 +1033,16 @@ __global__ void __launch_bounds__(256) k_vjp_material(BlockMesh m, const double 
                     sm += (F[i * 3 + J] - FiT) * gw;
                     sl += lnJ * FiT * gw;
                 }
-            gm += kk.wDe * sm;
-            gl += kk.wDe * sl;
+            gm[E::sub(q)] += kk.wDe * sm;
+            gl[E::sub(q)] += kk.wDe * sl;
         }
-        const int eo = m.eorig[e];
-        dmu[eo] = gm;
-        dlam[eo] = gl;
+#pragma unroll
+        for (int s = 0; s < E::NSUB; ++s) {
+            if (s > 0 && !pair) break;
+            const int eo = m.eorig[r.elem(k, s)];
+            dmu[eo] = gm[s];
+            dlam[eo] = gl[s];
+        }
     }
     if (bad) flag_inverted(m.flags);
 }
@@ -932,7 +1088,7 @@ template <class Op, class T>
 static hipError_t dispatch(const Ctx &c, const Op &op, T *y, bool use_mask, T fixed_val,
                            const int32_t *skip = nullptr, WriteMode mode = WriteMode::Overwrite)
 {
-    return c.elem == EFEM_TET4 ? run_accumulate<Tet4>(c, op, y, use_mask, fixed_val, skip, mode)
+    return c.elem == EFEM_TET4 ? run_accumulate<Tet4Pair>(c, op, y, use_mask, fixed_val, skip, mode)
                                : run_accumulate<Hex8>(c, op, y, use_mask, fixed_val, skip, mode);
 }
 
@@ -978,7 +1134,7 @@ hipError_t launch_energy(const Ctx &c, const double *u, double *psi)
 {
     const size_t lds = sizeof(NodeXU) * (size_t)c.max_block_nodes;
     if (c.elem == EFEM_TET4)
-        hipLaunchKernelGGL(k_energy<Tet4>, dim3(c.m.n_blocks), dim3(256), lds, c.stream, c.m, c.m.X,
+        hipLaunchKernelGGL(k_energy<Tet4Pair>, dim3(c.m.n_blocks), dim3(256), lds, c.stream, c.m, c.m.X,
                            u, c.partials);
     else
         hipLaunchKernelGGL(k_energy<Hex8>, dim3(c.m.n_blocks), dim3(256), lds, c.stream, c.m, c.m.X,
@@ -991,7 +1147,7 @@ hipError_t launch_grad_material(const Ctx &c, const double *u, double *dmu, doub
 {
     const size_t lds = sizeof(NodeXU) * (size_t)c.max_block_nodes;
     if (c.elem == EFEM_TET4)
-        hipLaunchKernelGGL(k_grad_material<Tet4>, dim3(c.m.n_blocks), dim3(c.threads), lds,
+        hipLaunchKernelGGL(k_grad_material<Tet4Pair>, dim3(c.m.n_blocks), dim3(c.threads), lds,
                            c.stream, c.m, c.m.X, u, dmu, dlam);
     else
         hipLaunchKernelGGL(k_grad_material<Hex8>, dim3(c.m.n_blocks), dim3(c.threads), lds,
@@ -1004,7 +1160,7 @@ hipError_t launch_vjp_material(const Ctx &c, const double *u, const double *w, d
 {
     const size_t lds = sizeof(NodeXUW) * (size_t)c.max_block_nodes;
     if (c.elem == EFEM_TET4)
-        hipLaunchKernelGGL(k_vjp_material<Tet4>, dim3(c.m.n_blocks), dim3(c.threads), lds,
+        hipLaunchKernelGGL(k_vjp_material<Tet4Pair>, dim3(c.m.n_blocks), dim3(c.threads), lds,
                            c.stream, c.m, c.m.X, u, w, dmu, dlam);
     else
         hipLaunchKernelGGL(k_vjp_material<Hex8>, dim3(c.m.n_blocks), dim3(c.threads), lds,

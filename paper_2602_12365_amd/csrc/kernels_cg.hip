@@ -89,8 +89,8 @@ __global__ void __launch_bounds__(kThreads) k_cg_init_fin(const double *__restri
         sc->done = (rr == 0.0) ? 1 : 0;
         sc->breakdown = 0;
         sc->fallback = 0;
-        sc->stall = 0;
-        sc->best = rr;
+        sc->stall[0] = sc->stall[1] = 0;
+        sc->best[0] = sc->best[1] = rr;
         sc->iter = 0;
         sc->alpha = sc->beta = sc->pq = 0.0;
     }
@@ -387,8 +387,8 @@ __global__ void __launch_bounds__(kThreads) k_fcg_start(int64_t n, const T *__re
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         sc->rz[0] = rz;
-        sc->best = sc->rr;
-        sc->stall = 0;
+        sc->best[0] = sc->rr;
+        sc->stall[0] = 0;
         sc->fallback = 0;
     }
     GRID_STRIDE(i, n) p[i] = z[i];
@@ -464,7 +464,8 @@ __global__ void __launch_bounds__(kThreads) k_fcg_dir(int64_t n, T *__restrict__
         }
         return;
     }
-    const int stall = rr < sc->best ? 0 : sc->stall + 1;
+    const double best = sc->best[par];
+    const int stall = rr < best ? 0 : sc->stall[par] + 1;
     if (!(rzn > 0.0) || !isfinite(rzn) || stall >= stall_limit) {
         if (first) {
             sc->rr = rr;
@@ -478,8 +479,8 @@ __global__ void __launch_bounds__(kThreads) k_fcg_dir(int64_t n, T *__restrict__
         sc->rz[par ^ 1] = rzn;
         sc->rr = rr;
         sc->beta = beta;
-        sc->stall = stall;
-        if (rr < sc->best) sc->best = rr;
+        sc->stall[par ^ 1] = stall;
+        sc->best[par ^ 1] = rr < best ? rr : best;
     }
     const T bt = (T)beta;
     GRID_STRIDE(i, n) p[i] = z[i] + bt * p[i];

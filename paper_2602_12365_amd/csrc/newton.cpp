@@ -27,7 +27,7 @@ hipError_t mlp_precondition(Ctx &c, MlpState &M, const float *r, float *z);
 hipError_t mlp_prepare(Ctx &c, MlpState &M, const double *diag);
 
 // flexible-CG iterations without a new smallest residual before falling back
-constexpr int kStallLimit = 10;
+constexpr int kStallLimit = 30;
 
 namespace {
 

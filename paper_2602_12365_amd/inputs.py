@@ -104,6 +104,32 @@ def make_mesh(elem: int, n: int) -> Mesh:
     return tet_mesh(n) if elem == TET4 else hex_mesh(n)
 
 
+# the twelve even permutations of four local nodes (orientation-preserving)
+_EVEN4 = np.array([p for p in itertools.permutations(range(4))
+                   if sum(1 for x in range(4) for y in range(x + 1, 4) if p[x] > p[y]) % 2 == 0],
+                  dtype=np.int64)
+
+
+def scrambled_mesh(mesh: Mesh, seed: int, jitter: float = 0.1) -> Mesh:
+    """The same cube with shuffled node ids and element order, interior nodes
+    moved by up to ``jitter`` grid spacings per coordinate, and (tetrahedra)
+    each element's local nodes rotated by a random even permutation, so no
+    regular structure of the generator survives."""
+    g = rng(seed)
+    nn, ne = mesh.n_nodes, mesh.n_elems
+    X = mesh.X.copy()
+    interior = np.all((X > 1e-12) & (X < 1 - 1e-12), axis=1)
+    X[interior] += (jitter / mesh.n) * g.uniform(-1.0, 1.0, size=(int(interior.sum()), 3))
+    new_id = g.permutation(nn)
+    Xs = np.empty_like(X)
+    Xs[new_id] = X
+    conn = new_id[mesh.conn.astype(np.int64)]
+    conn = conn[g.permutation(ne)]
+    if mesh.elem == TET4:
+        conn = np.take_along_axis(conn, _EVEN4[g.integers(0, len(_EVEN4), size=ne)], axis=1)
+    return Mesh(mesh.elem, mesh.n, Xs, conn.astype(np.int32))
+
+
 # ----------------------------------------------------------------- fields
 
 def rng(seed: int) -> np.random.Generator:

@@ -34,7 +34,7 @@ class Operator:
     """
 
     def __init__(self, elem, X, conn, *, block_elems=0, block_nodes=0, scatter="atomic",
-                 threads=0, device=None):
+                 threads=0, pairs=True, device=None):
         self._lib = L.load()
         X = np.ascontiguousarray(np.asarray(X, dtype=np.float64))
         conn = np.ascontiguousarray(np.asarray(conn, dtype=np.int32))
@@ -45,9 +45,13 @@ class Operator:
         if conn.ndim != 2 or conn.shape[1] != self.nen:
             raise ValueError(f"conn must be [n_elems, {self.nen}]")
         self.n_nodes, self.n_elems = X.shape[0], conn.shape[0]
-        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        dev = torch.device(device) if device is not None else torch.device("cuda")
+        if dev.type != "cuda":
+            raise ValueError("the operator runs on a GPU device")
+        self.device = torch.device("cuda", dev.index if dev.index is not None else torch.cuda.current_device())
         self.X_host = X
-        opts = L.Options(block_elems, block_nodes, _SCATTER[scatter], threads)
+        self.pairs = bool(pairs)
+        opts = L.Options(block_elems, block_nodes, _SCATTER[scatter], threads, 0 if pairs else 1)
         h = ctypes.c_void_p()
         with torch.cuda.device(self.device):
             self._stream = torch.cuda.current_stream().cuda_stream

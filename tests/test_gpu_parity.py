@@ -26,11 +26,16 @@ CASES = [
     ("tet_5_color_small", I.TET4, 5, dict(block_elems=100, block_nodes=64, scatter="color",
                                            threads=64)),
     ("tet_9_ragged", I.TET4, 9, dict(block_elems=301, block_nodes=97, threads=128)),
+    ("tet_6_no_pairs", I.TET4, 6, dict(pairs=False)),
+    ("tet_7_odd_blocks", I.TET4, 7, dict(block_elems=63, block_nodes=50)),
+    ("tet_6_scrambled", I.TET4, 6, dict(scramble=11)),
+    ("tet_5_scrambled_color", I.TET4, 5, dict(scramble=12, scatter="color", block_elems=200)),
     ("hex_1", I.HEX8, 1, {}),
     ("hex_3_small_blocks", I.HEX8, 3, dict(block_elems=5, block_nodes=27)),
     ("hex_6", I.HEX8, 6, {}),
     ("hex_6_color", I.HEX8, 6, dict(scatter="color")),
     ("hex_7_ragged", I.HEX8, 7, dict(block_elems=45, block_nodes=100, threads=64)),
+    ("hex_5_scrambled", I.HEX8, 5, dict(scramble=13)),
 ]
 
 
@@ -51,7 +56,11 @@ def host(t):
 class Case:
     def __init__(self, elem, n, opts, mu_sigma=0.3):
         from paper_2602_12365_amd import Operator
+        opts = dict(opts)
+        scramble = opts.pop("scramble", None)
         self.mesh = I.make_mesh(elem, n)
+        if scramble is not None:
+            self.mesh = I.scrambled_mesh(self.mesh, scramble)
         m = self.mesh
         self.mu = I.lognormal_field(m.n_elems, mu_sigma, 3)
         self.lam = 1.5 * self.mu
@@ -176,6 +185,36 @@ def test_repeat_calls(case):
     y1 = host(case.op.hvp(dev(case.v)))
     y2 = host(case.op.hvp(dev(case.v)))
     assert rel(y1, y2) <= 1e-14
+
+
+@pytest.mark.parametrize("stretch", [(2.5, 0.6, 1.3), (0.5, 0.7, 0.9)], ids=["J1.95", "J0.315"])
+def test_large_strain(case, stretch):
+    """Affine stretches plus small noise: det F far from 1 on both sides (the
+    logarithm's exponent split)."""
+    m = case.mesh
+    u = (m.X - 0.5) * (np.asarray(stretch) - 1.0)
+    u = u + I.gaussian_field(m.n_nodes, 1e-3 / m.n, 5)
+    psi = host(case.op.energy(dev(u)))
+    ref = case.orc.energy(u)
+    assert abs(psi - ref) <= TOL_E * abs(ref)
+    assert rel(host(case.op.residual(dev(u))), case.orc.residual(u)) <= TOL64
+    case.op.linearize(dev(u), "f64")
+    assert rel(host(case.op.hvp(dev(case.v))), case.orc.hvp(u, case.v)) <= TOL64
+    assert rel(host(case.op.jacobi_diag(dev(u))), case.orc.jacobi_diag(u)) <= TOL64
+
+
+def test_work_items(case):
+    """Face-sharing tetrahedra are paired into work items (a maximal matching
+    inside each block); one element per item without pairing or for hexahedra."""
+    info = case.op.info()
+    ne = case.mesh.n_elems
+    assert info["n_items"] <= ne
+    if case.mesh.elem == I.HEX8 or not case.op.pairs:
+        assert info["n_items"] == ne
+    else:
+        # every element is in exactly one item and most are paired
+        assert info["n_items"] >= ne // 2
+        assert info["n_items"] <= 0.6 * ne + 2 * info["n_blocks"]
 
 
 def test_inverted_element_flags_and_inf():

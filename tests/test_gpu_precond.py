@@ -131,11 +131,14 @@ def test_training_reduces_loss_and_learned_solve_converges():
     X, aux, op = PC.generate_rows(n=6, seeds=range(1000, 1003), n_steps=4)
     theta, hist = PC.train(op, X, aux, epochs=150, lr=3e-3)
     assert hist[-1][1] < 0.9 * hist[0][1], hist
-    # a solve on an unseen field with the trained network, checked by the oracle
+    # a solve on an unseen field with the trained network, checked by the oracle;
+    # the linearization point is one tenth of the top displacement applied as a
+    # jump (16% compression of the top layer, where the tangent is still
+    # positive definite)
     m, op2, mu, mask, ubc = make_op(I.HEX8, 8)
     op2.set_mlp(theta)
     u = np.zeros((m.n_nodes, 3))
-    u.reshape(-1)[mask != 0] = 0.5 * ubc.reshape(-1)[mask != 0]
+    u.reshape(-1)[mask != 0] = 0.1 * ubc.reshape(-1)[mask != 0]
     r = op2.residual(dev(u))
     x, it_nn, fb = op2.linear_solve(dev(u), r, rtol=1e-8, hvp_prec="f32", precond=1)
     x_j, it_j, _ = op2.linear_solve(dev(u), r, rtol=1e-8, hvp_prec="f32", precond=0)
