@@ -251,7 +251,9 @@ int efem_newton_solve(efem_ctx *ctx, double *u_inout, const double *u_bc,
  *   g_i = D_i^-1 r_i (0 on prescribed DOFs), s_i = RMS of g over {i} + N(i),
  *   f_i = [g_i/s_i, mean_N(i) g/s_i, log(D_i/mean_{N(i)+i} D), prescribed
  *          fraction of i, of N(i), |N(i)|/26]                     (12 inputs)
- *   z_i = g_i + s_i MLP(f_i), prescribed DOFs 0,
+ *   z_i = g_i + gamma_i s_i MLP(f_i), prescribed DOFs 0, where gamma_i = 1
+ *         unless r_i.z_i would fall below r_i.g_i / 2; then gamma_i in [0, 1)
+ *         makes it exactly half (so r.z >= r.D^-1 r / 2 > 0 for any network),
  * MLP 12 -> 64 -> 64 -> 3 with softplus hidden layers (the activation of the
  * paper's neural energy terms, Sec. 6.6.1), bfloat16 weights and layer inputs,
  * FP32 accumulation on the matrix cores.  z is positively homogeneous in r;
@@ -298,6 +300,36 @@ int efem_mlp_loss_grad(efem_ctx *ctx, int64_t rows, const uint16_t *X, const flo
  * moments m, v and gradient g (all [EFEM_MLP_PARAMS]); t = step number >= 1. */
 int efem_mlp_adam(efem_ctx *ctx, float *params, float *m, float *v, const float *g, float lr,
                   int32_t t);
+
+/* Energy-norm training of the preconditioner, one sample (the objective is the
+ * K-norm error of one preconditioned step, sum over samples of
+ * w (z.Kz - 2 r.z) = w (|K^-1 r - z|_K^2 - |K^-1 r|_K^2), z = m (g + s MLP),
+ * which needs no solves).  At the context's current FP32 linearization
+ * (efem_linearize(u, EFEM_F32)) and Dirichlet mask, for a residual r (DEVICE
+ * float32 [3*n_nodes]) whose rows efem_precond_rows built into aux, and the
+ * network outputs out (DEVICE float32 [n_nodes][3], efem_mlp_forward of
+ * those rows):
+ *   z = m (g + s out)             -> z  (DEVICE float32 [3*n_nodes])
+ *   K z                           -> kz (DEVICE float32 [3*n_nodes])
+ *   w = 1 / (n_samples r.g)       -> aux[:, 10]
+ *   t = (g + s out) - (K z - r)   -> aux[:, 3:6]
+ *   energy += w (z.Kz - 2 r.z)    (DEVICE float64 scalar, accumulated)
+ * With these t and w, efem_mlp_loss_grad over the rows returns the gradient of
+ * the energy objective at the current parameters (its loss value is then
+ * sum w |K z - r|^2 on free DOFs).  EFEM_ERR_STATE without an FP32
+ * linearization. */
+int efem_mlp_energy_rows(efem_ctx *ctx, const float *r, const float *out, double n_samples,
+                         float *aux, float *z, float *kz, double *energy);
+
+/* Residuals that Jacobi-preconditioned CG meets on K(u)_ff x = sign b from
+ * x = 0 (FP32 tangent actions; the training samples of the preconditioner).
+ * sign = +1 or -1; iters HOST int32 [n_snap], ascending; R DEVICE float32
+ * [n_snap][3*n_nodes] receives the CG residual after iters[k] iterations.
+ * *taken = snapshots reached before CG stopped (exact zero residual or
+ * breakdown); later ones repeat the last residual.  Requires a Dirichlet
+ * mask; synchronous. */
+int efem_cg_snapshots(efem_ctx *ctx, const double *u, const double *b, double sign, int32_t n_snap,
+                      const int32_t *iters, float *R, int32_t *taken);
 
 /* Solve K(u)_ff x = b (b, x DEVICE float64 [3*n_nodes]; prescribed entries of b
  * ignored and of x set to 0) by preconditioned CG from x = 0 to

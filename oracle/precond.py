@@ -142,10 +142,20 @@ def features(r, diag, mask, ptr, idx):
 
 
 def apply(theta, r, diag, mask, ptr, idx):
-    """z = g + s * MLP(features), prescribed DOFs 0."""
+    """z = g + gamma * s * MLP(features), prescribed DOFs 0, with the node-wise
+    safeguard gamma in (0, 1]: where the correction c = s * MLP would leave
+    r_i . z_i below half of r_i . g_i (the Jacobi step's share), it is scaled
+    back to exactly half, so that r . z >= r . D^-1 r / 2 > 0 for r != 0."""
     F, g, s = features(r, diag, mask, ptr, idx)
     out = mlp_forward(theta, F.astype(np.float32))
-    z = g + s[:, None] * out
-    z[s == 0] = 0.0
-    z[np.asarray(mask).reshape(-1, 3) != 0] = 0.0
-    return z
+    fixed = np.asarray(mask).reshape(-1, 3) != 0
+    c = s[:, None] * out
+    c[s == 0] = 0.0
+    c[fixed] = 0.0
+    R = np.asarray(r, dtype=np.float64).reshape(-1, 3)
+    a = (R * g).sum(axis=1)
+    b = (R * c).sum(axis=1)
+    low = a + b < 0.5 * a
+    gamma = np.ones_like(a)
+    gamma[low] = -0.5 * a[low] / b[low]
+    return g + gamma[:, None] * c

@@ -93,6 +93,10 @@ SIGNATURES = {
                                      c_void_p]),
     "efem_mlp_adam": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, ctypes.c_float,
                                 c_int32]),
+    "efem_mlp_energy_rows": (c_int32, [c_void_p, c_void_p, c_void_p, c_double, c_void_p, c_void_p,
+                                       c_void_p, c_void_p]),
+    "efem_cg_snapshots": (c_int32, [c_void_p, c_void_p, c_void_p, c_double, c_int32, c_void_p,
+                                    c_void_p, ctypes.POINTER(c_int32)]),
     "efem_linear_solve": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_double, c_int32,
                                     c_int32, c_int32, ctypes.POINTER(c_int32),
                                     ctypes.POINTER(c_int32)]),

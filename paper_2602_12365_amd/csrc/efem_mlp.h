@@ -33,10 +33,12 @@ struct MlpState {
     double *prz = nullptr;       // [2048] partials
     float *gpart = nullptr;      // [kGradBlocks][kP]
     double *lpart = nullptr;     // [kGradBlocks]
+    double *epart = nullptr;     // [2 kEnergyBlocks] energy-row partials
     double *tt = nullptr;        // scalar
     std::vector<void *> owned;
 };
 constexpr int kGradBlocks = 1024;
+constexpr int kEnergyBlocks = 512;
 
 hipError_t mlp_features_static(hipStream_t s, const MlpState &M, int64_t n, const double *diag,
                                const uint8_t *nmask, uint16_t *X);
@@ -51,6 +53,14 @@ hipError_t mlp_rows_aux(hipStream_t s, int64_t n, const float *b, const float *d
 hipError_t mlp_loss_grad(hipStream_t s, int64_t rows, const uint16_t *X, const float *aux,
                          const float *params, float *gpart, double *lpart, int G, float *grad,
                          double *loss);
+// energy-norm training rows of one sample: z = m (g + s out) and partials of
+// r.g (G blocks), then, with K z in kz, the pseudo-targets, the weights and
+// energy += w (z.Kz - 2 r.z); `part` holds 2 G doubles
+hipError_t mlp_energy_z(hipStream_t s, int64_t n, const float *r, const float *out, const float *aux,
+                        float *z, double *part, int G);
+hipError_t mlp_energy_target(hipStream_t s, int64_t n, const float *r, const float *out, const float *z,
+                             const float *kz, float *aux, const double *rgpart, double n_samples,
+                             double *part, int G, double *energy);
 hipError_t mlp_adam(hipStream_t s, float *p, float *m, float *v, const float *g, float lr, float b1,
                     float b2, float eps, int t);
 hipError_t mlp_to_bf16(hipStream_t s, const float *p, uint16_t *out);

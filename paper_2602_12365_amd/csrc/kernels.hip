@@ -144,6 +144,15 @@ __device__ __forceinline__ void flag_inverted(int32_t *flags) { atomicOr(flags, 
 // share a face, or one hexahedron.  NEN nodes per item, NQ quadrature points
 // per item, NSUB elements per item (sub(q) is the element of point q).
 //
+// Interface of an item type E:
+//   Field<T>, prep(f, F)      what the gradients are formed from, given the
+//                             NEN nodal values f of one field;
+//   grad(F, q, G)             G[i*3+J] = d f_i / d xi_J at point q;
+//   Acc<T>, add_forces<FIRST>(Q, q, A), finish(A, out)
+//                             nodal forces out_a = sum_q Q_q dN_a/dxi(q)
+//                             (FIRST: the first point, which initialises A);
+//   dN(q, a, J)               the shape-function derivatives themselves.
+//
 // Tet4 pair: nodes (a, b, c, d1, d2) with tet 1 = (a, b, c, d1) positively
 // oriented and tet 2 = (a, c, b, d2), also positive since d2 lies on the
 // other side of the shared face.  A tetrahedron without a partner is stored as
@@ -151,6 +160,7 @@ __device__ __forceinline__ void flag_inverted(int32_t *flags) { atomicOr(flags, 
 // Each tetrahedron: N0 = 1 - xi - eta - zeta, N_k = xi_k; one point, w = 1/6.
 struct Tet4Pair {
     static constexpr int NEN = 5, NQ = 2, NSUB = 2;
+    using Lean = Tet4Pair;   // the form with the fewest live registers
     template <class T> __device__ static constexpr T weight() { return T(1.0 / 6.0); }
     __device__ static constexpr int sub(int q) { return q; }
     // the second point of an unpaired tetrahedron is skipped
@@ -160,25 +170,66 @@ struct Tet4Pair {
     {
         return q == 0 ? k : (k == 1 ? 2 : (k == 2 ? 1 : (k == 3 ? 4 : 0)));
     }
-    // G[i*3+J] = d f_i / d xi_J at point q
+    template <class T> struct Field {
+        T f[NEN][3];
+    };
     template <class T>
-    __device__ static __forceinline__ void grad(const T f[NEN][3], int q, T G[9])
+    __device__ static __forceinline__ void prep(const T f[NEN][3], Field<T> &F)
+    {
+#pragma unroll
+        for (int a = 0; a < NEN; ++a)
+#pragma unroll
+            for (int i = 0; i < 3; ++i) F.f[a][i] = f[a][i];
+    }
+    template <class T>
+    __device__ static __forceinline__ void grad(const Field<T> &F, int q, T G[9])
     {
 #pragma unroll
         for (int i = 0; i < 3; ++i)
 #pragma unroll
-            for (int J = 0; J < 3; ++J) G[i * 3 + J] = f[node(q, J + 1)][i] - f[0][i];
+            for (int J = 0; J < 3; ++J) G[i * 3 + J] = F.f[node(q, J + 1)][i] - F.f[0][i];
     }
-    template <class T>
-    __device__ static __forceinline__ void add_forces(const T Q[9], int q, T out[NEN][3])
+    template <class T> struct Acc {
+        T f[NEN][3];
+    };
+    template <class T> __device__ static __forceinline__ void zero(Acc<T> &A)
+    {
+#pragma unroll
+        for (int a = 0; a < NEN; ++a) A.f[a][0] = A.f[a][1] = A.f[a][2] = T(0);
+    }
+    // node forms accumulate straight into the caller's nodal array
+    template <bool FIRST, class T>
+    __device__ static __forceinline__ void add_forces_to(const T Q[9], int q, T out[NEN][3])
     {
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
-            out[node(q, 1)][i] += Q[i * 3 + 0];
-            out[node(q, 2)][i] += Q[i * 3 + 1];
-            out[node(q, 3)][i] += Q[i * 3 + 2];
-            out[0][i] -= Q[i * 3 + 0] + Q[i * 3 + 1] + Q[i * 3 + 2];
+            const T s = -(Q[i * 3 + 0] + Q[i * 3 + 1] + Q[i * 3 + 2]);
+            if (FIRST) {   // point 0 of tet 1 touches nodes 0..3 only
+                out[node(q, 1)][i] = Q[i * 3 + 0];
+                out[node(q, 2)][i] = Q[i * 3 + 1];
+                out[node(q, 3)][i] = Q[i * 3 + 2];
+                out[0][i] = s;
+                out[4][i] = T(0);
+            } else {
+                out[node(q, 1)][i] += Q[i * 3 + 0];
+                out[node(q, 2)][i] += Q[i * 3 + 1];
+                out[node(q, 3)][i] += Q[i * 3 + 2];
+                out[0][i] += s;
+            }
         }
+    }
+    template <bool FIRST, class T>
+    __device__ static __forceinline__ void add_forces(const T Q[9], int q, Acc<T> &A)
+    {
+        add_forces_to<FIRST>(Q, q, A.f);
+    }
+    template <class T>
+    __device__ static __forceinline__ void finish(const Acc<T> &A, T out[NEN][3])
+    {
+#pragma unroll
+        for (int a = 0; a < NEN; ++a)
+#pragma unroll
+            for (int i = 0; i < 3; ++i) out[a][i] = A.f[a][i];
     }
     // d N_a / d xi_J of pair node a at point q (0 for the node outside tet q)
     template <class T> __device__ static __forceinline__ T dN(int q, int a, int J)
@@ -188,27 +239,37 @@ struct Tet4Pair {
     }
 };
 
-// Hex8: trilinear on [-1,1]^3, nodes (0,0,0),(1,0,0),(1,1,0),(0,1,0) then z=1;
-// 2x2x2 Gauss points at +-1/sqrt(3), point q = qx + 2 qy + 4 qz, w = 1.
-__device__ constexpr int kHexS[8][3] = {{-1, -1, -1}, {1, -1, -1}, {1, 1, -1}, {-1, 1, -1},
-                                        {-1, -1, 1},  {1, -1, 1},  {1, 1, 1},  {-1, 1, 1}};
-struct Hex8 {
-    static constexpr int NEN = 8, NQ = 8, NSUB = 1;
-    template <class T> __device__ static constexpr T weight() { return T(1); }
-    __device__ static constexpr int sub(int) { return 0; }
-    __device__ static constexpr bool skip(int, bool) { return false; }
+// Hex8 in node form: the same element with gradients and forces as sums over
+// the 8 nodes (8 terms per entry).  It keeps 24 values per field live instead
+// of 36, which is what the three-field FP64 tangent action needs to stay out
+// of scratch memory.
+__device__ constexpr int kHexSgn[8][3] = {{-1, -1, -1}, {1, -1, -1}, {1, 1, -1}, {-1, 1, -1},
+                                          {-1, -1, 1},  {1, -1, 1},  {1, 1, 1},  {-1, 1, 1}};
+struct Hex8Nodes {
+    static constexpr int NEN = 8;
     template <class T> __device__ static __forceinline__ T dN(int q, int a, int J)
     {
         const T g = T(0.57735026918962576451);
         const T p0 = (q & 1) ? g : -g, p1 = (q & 2) ? g : -g, p2 = (q & 4) ? g : -g;
-        const T f0 = T(1) + T(kHexS[a][0]) * p0;
-        const T f1 = T(1) + T(kHexS[a][1]) * p1;
-        const T f2 = T(1) + T(kHexS[a][2]) * p2;
-        const T s = T(0.125) * T(kHexS[a][J]);
+        const T f0 = T(1) + T(kHexSgn[a][0]) * p0;
+        const T f1 = T(1) + T(kHexSgn[a][1]) * p1;
+        const T f2 = T(1) + T(kHexSgn[a][2]) * p2;
+        const T s = T(0.125) * T(kHexSgn[a][J]);
         return J == 0 ? s * f1 * f2 : (J == 1 ? s * f0 * f2 : s * f0 * f1);
     }
+    template <class T> struct Field {
+        T f[NEN][3];
+    };
     template <class T>
-    __device__ static __forceinline__ void grad(const T f[NEN][3], int q, T G[9])
+    __device__ static __forceinline__ void prep(const T f[NEN][3], Field<T> &F)
+    {
+#pragma unroll
+        for (int a = 0; a < NEN; ++a)
+#pragma unroll
+            for (int i = 0; i < 3; ++i) F.f[a][i] = f[a][i];
+    }
+    template <class T>
+    __device__ static __forceinline__ void grad(const Field<T> &F, int q, T G[9])
     {
 #pragma unroll
         for (int i = 0; i < 3; ++i)
@@ -216,19 +277,160 @@ struct Hex8 {
             for (int J = 0; J < 3; ++J) {
                 T t = T(0);
 #pragma unroll
-                for (int a = 0; a < NEN; ++a) t += f[a][i] * dN<T>(q, a, J);
+                for (int a = 0; a < NEN; ++a) t += F.f[a][i] * dN<T>(q, a, J);
                 G[i * 3 + J] = t;
             }
     }
-    template <class T>
-    __device__ static __forceinline__ void add_forces(const T Q[9], int q, T out[NEN][3])
+    template <class T> struct Acc {
+        T f[NEN][3];
+    };
+    template <class T> __device__ static __forceinline__ void zero(Acc<T> &A)
+    {
+#pragma unroll
+        for (int a = 0; a < NEN; ++a) A.f[a][0] = A.f[a][1] = A.f[a][2] = T(0);
+    }
+    template <bool FIRST, class T>
+    __device__ static __forceinline__ void add_forces_to(const T Q[9], int q, T out[NEN][3])
     {
 #pragma unroll
         for (int a = 0; a < NEN; ++a)
 #pragma unroll
-            for (int i = 0; i < 3; ++i)
+            for (int i = 0; i < 3; ++i) {
+                if (FIRST) out[a][i] = T(0);
                 out[a][i] += Q[i * 3 + 0] * dN<T>(q, a, 0) + Q[i * 3 + 1] * dN<T>(q, a, 1)
                            + Q[i * 3 + 2] * dN<T>(q, a, 2);
+            }
+    }
+    template <bool FIRST, class T>
+    __device__ static __forceinline__ void add_forces(const T Q[9], int q, Acc<T> &A)
+    {
+        add_forces_to<FIRST>(Q, q, A.f);
+    }
+    template <class T>
+    __device__ static __forceinline__ void finish(const Acc<T> &A, T out[NEN][3])
+    {
+#pragma unroll
+        for (int a = 0; a < NEN; ++a)
+#pragma unroll
+            for (int i = 0; i < 3; ++i) out[a][i] = A.f[a][i];
+    }
+};
+
+// Hex8: trilinear on [-1,1]^3, nodes (0,0,0),(1,0,0),(1,1,0),(0,1,0) then z=1;
+// 2x2x2 Gauss points at +-1/sqrt(3), point q = qx + 2 qy + 4 qz, w = 1.
+//
+// The derivative of a trilinear field along one reference direction depends
+// only on the differences along the four element edges of that direction,
+// interpolated bilinearly in the other two coordinates:
+//   d f / d xi_J (q) = sum_e w_J(e, q) (f[e+] - f[e-]),
+//   w_J(e, q) = (1 + s1_e p1_q)(1 + s2_e p2_q) / 8,
+// with (s1_e, s2_e) the signs of edge e in the two other directions and p_q
+// the point's coordinates.  So the gradient is formed from 12 edge
+// differences per field (36 subtractions per element, shared by the 8
+// points) and 4 terms per entry instead of 8; the nodal forces take the
+// transposed route through 12 edge accumulators.
+__device__ constexpr int kHexS[8][3] = {{-1, -1, -1}, {1, -1, -1}, {1, 1, -1}, {-1, 1, -1},
+                                        {-1, -1, 1},  {1, -1, 1},  {1, 1, 1},  {-1, 1, 1}};
+// edges (e-, e+) of each direction J, ordered by the signs of the other two
+// directions (the lower-numbered one varies fastest)
+__device__ constexpr int kHexEdge[3][4][2] = {{{0, 1}, {3, 2}, {4, 5}, {7, 6}},
+                                              {{0, 3}, {1, 2}, {4, 7}, {5, 6}},
+                                              {{0, 4}, {1, 5}, {3, 7}, {2, 6}}};
+struct Hex8 {
+    static constexpr int NEN = 8, NQ = 8, NSUB = 1;
+    using Lean = Hex8Nodes;   // the form with the fewest live registers
+    template <class T> __device__ static constexpr T weight() { return T(1); }
+    __device__ static constexpr int sub(int) { return 0; }
+    __device__ static constexpr bool skip(int, bool) { return false; }
+    static constexpr double kG = 0.57735026918962576451;   // 1/sqrt(3)
+    // w_J(e, q)
+    __device__ static constexpr double ew(int J, int e, int q)
+    {
+        const int o1 = J == 0 ? 1 : 0, o2 = J == 2 ? 1 : 2;   // the other two directions
+        const double s1 = (e & 1) ? 1.0 : -1.0, s2 = (e & 2) ? 1.0 : -1.0;
+        const double p1 = ((q >> o1) & 1) ? kG : -kG, p2 = ((q >> o2) & 1) ? kG : -kG;
+        return 0.125 * (1.0 + s1 * p1) * (1.0 + s2 * p2);
+    }
+    // index of the edge of direction J that node a ends
+    __device__ static constexpr int edge_of(int J, int a)
+    {
+        const int o1 = J == 0 ? 1 : 0, o2 = J == 2 ? 1 : 2;
+        return (kHexS[a][o1] > 0 ? 1 : 0) + (kHexS[a][o2] > 0 ? 2 : 0);
+    }
+    template <class T> struct Field {
+        T d[3][4][3];   // [direction][edge][component]
+    };
+    template <class T>
+    __device__ static __forceinline__ void prep(const T f[NEN][3], Field<T> &F)
+    {
+#pragma unroll
+        for (int J = 0; J < 3; ++J)
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+#pragma unroll
+                for (int i = 0; i < 3; ++i)
+                    F.d[J][e][i] = f[kHexEdge[J][e][1]][i] - f[kHexEdge[J][e][0]][i];
+    }
+    template <class T>
+    __device__ static __forceinline__ void grad(const Field<T> &F, int q, T G[9])
+    {
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int J = 0; J < 3; ++J) {
+                T t = T(ew(J, 0, q)) * F.d[J][0][i];
+#pragma unroll
+                for (int e = 1; e < 4; ++e) t = fma(T(ew(J, e, q)), F.d[J][e][i], t);
+                G[i * 3 + J] = t;
+            }
+    }
+    template <class T> struct Acc {
+        T d[3][4][3];   // edge forces: +d to e+, -d to e-
+    };
+    template <class T> __device__ static __forceinline__ void zero(Acc<T> &A)
+    {
+#pragma unroll
+        for (int J = 0; J < 3; ++J)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) A.d[J][e][0] = A.d[J][e][1] = A.d[J][e][2] = T(0);
+    }
+    template <bool FIRST, class T>
+    __device__ static __forceinline__ void add_forces(const T Q[9], int q, Acc<T> &A)
+    {
+#pragma unroll
+        for (int J = 0; J < 3; ++J)
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+#pragma unroll
+                for (int i = 0; i < 3; ++i) {
+                    if (FIRST) A.d[J][e][i] = T(ew(J, e, q)) * Q[i * 3 + J];
+                    else A.d[J][e][i] = fma(T(ew(J, e, q)), Q[i * 3 + J], A.d[J][e][i]);
+                }
+    }
+    template <class T>
+    __device__ static __forceinline__ void finish(const Acc<T> &A, T out[NEN][3])
+    {
+        // every node ends exactly one edge of each direction: its + end where
+        // its sign in that direction is +, else its - end
+#pragma unroll
+        for (int a = 0; a < NEN; ++a)
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                const int e0 = edge_of(0, a), e1 = edge_of(1, a), e2 = edge_of(2, a);
+                const T t0 = kHexS[a][0] > 0 ? A.d[0][e0][i] : -A.d[0][e0][i];
+                const T t1 = kHexS[a][1] > 0 ? t0 + A.d[1][e1][i] : t0 - A.d[1][e1][i];
+                out[a][i] = kHexS[a][2] > 0 ? t1 + A.d[2][e2][i] : t1 - A.d[2][e2][i];
+            }
+    }
+    template <class T> __device__ static __forceinline__ T dN(int q, int a, int J)
+    {
+        const T g = T(kG);
+        const T p0 = (q & 1) ? g : -g, p1 = (q & 2) ? g : -g, p2 = (q & 4) ? g : -g;
+        const T f0 = T(1) + T(kHexS[a][0]) * p0;
+        const T f1 = T(1) + T(kHexS[a][1]) * p1;
+        const T f2 = T(1) + T(kHexS[a][2]) * p2;
+        const T s = T(0.125) * T(kHexS[a][J]);
+        return J == 0 ? s * f1 * f2 : (J == 1 ? s * f0 * f2 : s * f0 * f1);
     }
 };
 
@@ -447,16 +649,23 @@ template <> struct HvpOp<double> {
                 ve[a][i] = n.v[i];
             }
         }
+        // three fields: the register-lean form (node sums for Hex8)
+        using G = typename E::Lean;
+        typename G::template Field<double> FX, Fx, Fv;
+        G::prep(Xe, FX);
+        G::prep(xe, Fx);
+        G::prep(ve, Fv);
         bool ok = true;
 #pragma unroll
         for (int q = 0; q < E::NQ; ++q) {
             if (E::skip(q, pair)) continue;
             double Jx[9], Jd[9], dJ[9], Q[9];
-            E::grad(Xe, q, Jx);
-            E::grad(xe, q, Jd);
-            E::grad(ve, q, dJ);
+            G::grad(FX, q, Jx);
+            G::grad(Fx, q, Jd);
+            G::grad(Fv, q, dJ);
             ok &= qp_hvp(E::template weight<double>(), Jx, Jd, dJ, mu[E::sub(q)], lam[E::sub(q)], Q);
-            E::add_forces(Q, q, f);
+            if (q == 0) G::template add_forces_to<true>(Q, q, f);
+            else G::template add_forces_to<false>(Q, q, f);
         }
         return ok;
     }
@@ -493,27 +702,37 @@ template <> struct HvpOp<float> {
                 ve[a][i] = n.v[i];
             }
         }
+        typename E::template Field<float> FX, Fu, Fv;
+        E::prep(Xe, FX);
+        E::prep(ue, Fu);
+        E::prep(ve, Fv);
+        typename E::template Acc<float> A;
         bool ok = true;
 #pragma unroll
         for (int q = 0; q < E::NQ; ++q) {
             if (E::skip(q, pair)) continue;
             float Jx[9], Jd[9], dJ[9], Q[9];
-            E::grad(Xe, q, Jx);
-            E::grad(ue, q, Jd);
+            E::grad(FX, q, Jx);
+            E::grad(Fu, q, Jd);
 #pragma unroll
             for (int k = 0; k < 9; ++k) Jd[k] += Jx[k];
-            E::grad(ve, q, dJ);
+            E::grad(Fv, q, dJ);
             ok &= qp_hvp(E::template weight<float>(), Jx, Jd, dJ, mu[E::sub(q)], lam[E::sub(q)], Q);
-            E::add_forces(Q, q, f);
+            if (q == 0) E::template add_forces<true>(Q, q, A);
+            else E::template add_forces<false>(Q, q, A);
         }
+        E::finish(A, f);
         return ok;
     }
 };
 
+// X and u of an item's nodes from LDS, in the item type's gradient form
 template <class E>
-__device__ __forceinline__ void gather_xu(const NodeXU *sn, const uint16_t *lc, double Xe[E::NEN][3],
-                                          double ue[E::NEN][3])
+__device__ __forceinline__ void gather_xu(const NodeXU *sn, const uint16_t *lc,
+                                          typename E::template Field<double> &FX,
+                                          typename E::template Field<double> &Fu)
 {
+    double Xe[E::NEN][3], ue[E::NEN][3];
 #pragma unroll
     for (int a = 0; a < E::NEN; ++a) {
         const NodeXU &n = sn[lc[a]];
@@ -523,6 +742,8 @@ __device__ __forceinline__ void gather_xu(const NodeXU *sn, const uint16_t *lc, 
             ue[a][i] = n.u[i];
         }
     }
+    E::prep(Xe, FX);
+    E::prep(ue, Fu);
 }
 
 struct XUStage {
@@ -540,20 +761,23 @@ struct ResidualOp : XUStage {
     __device__ __forceinline__ bool element(const Node *sn, const uint16_t *lc, const double *mu,
                                             const double *lam, bool pair, double f[E::NEN][3]) const
     {
-        double Xe[E::NEN][3], ue[E::NEN][3];
-        gather_xu<E>(sn, lc, Xe, ue);
+        typename E::template Field<double> FX, Fu;
+        gather_xu<E>(sn, lc, FX, Fu);
+        typename E::template Acc<double> A;
         bool ok = true;
 #pragma unroll
         for (int q = 0; q < E::NQ; ++q) {
             if (E::skip(q, pair)) continue;
             double Jx[9], Jd[9], Q[9];
-            E::grad(Xe, q, Jx);
-            E::grad(ue, q, Jd);
+            E::grad(FX, q, Jx);
+            E::grad(Fu, q, Jd);
 #pragma unroll
             for (int k = 0; k < 9; ++k) Jd[k] += Jx[k];
             ok &= qp_residual(E::template weight<double>(), Jx, Jd, mu[E::sub(q)], lam[E::sub(q)], Q);
-            E::add_forces(Q, q, f);
+            if (q == 0) E::template add_forces<true>(Q, q, A);
+            else E::template add_forces<false>(Q, q, A);
         }
+        E::finish(A, f);
         return ok;
     }
 };
@@ -565,16 +789,18 @@ struct DiagOp : XUStage {
     __device__ __forceinline__ bool element(const Node *sn, const uint16_t *lc, const double *mu,
                                             const double *lam, bool pair, double f[E::NEN][3]) const
     {
-        double Xe[E::NEN][3], ue[E::NEN][3];
-        gather_xu<E>(sn, lc, Xe, ue);
+        typename E::template Field<double> FX, Fu;
+        gather_xu<E>(sn, lc, FX, Fu);
+#pragma unroll
+        for (int a = 0; a < E::NEN; ++a) f[a][0] = f[a][1] = f[a][2] = 0.0;
         bool ok = true;
 #pragma unroll
         for (int q = 0; q < E::NQ; ++q) {
             if (E::skip(q, pair)) continue;
             const double mq = mu[E::sub(q)], lq = lam[E::sub(q)];
             double Jx[9], Jd[9], Ae[9], Ad[9];
-            E::grad(Xe, q, Jx);
-            E::grad(ue, q, Jd);
+            E::grad(FX, q, Jx);
+            E::grad(Fu, q, Jd);
 #pragma unroll
             for (int k = 0; k < 9; ++k) Jd[k] += Jx[k];
             const double De = adj_det(Jx, Ae);
@@ -612,16 +838,18 @@ struct GradCoordsOp : XUStage {
     __device__ __forceinline__ bool element(const Node *sn, const uint16_t *lc, const double *mu,
                                             const double *lam, bool pair, double f[E::NEN][3]) const
     {
-        double Xe[E::NEN][3], ue[E::NEN][3];
-        gather_xu<E>(sn, lc, Xe, ue);
+        typename E::template Field<double> FX, Fu;
+        gather_xu<E>(sn, lc, FX, Fu);
+        typename E::template Acc<double> A;
+        E::zero(A);   // a point may be skipped (inverted), so no point initialises
         bool ok = true;
 #pragma unroll
         for (int q = 0; q < E::NQ; ++q) {
             if (E::skip(q, pair)) continue;
             const double mu_ = mu[E::sub(q)], lam_ = lam[E::sub(q)];
             double Jx[9], Hxi[9], Ae[9];
-            E::grad(Xe, q, Jx);
-            E::grad(ue, q, Hxi);
+            E::grad(FX, q, Jx);
+            E::grad(Fu, q, Hxi);
             Kin k;
             kinematics(E::template weight<double>(), Jx, Hxi, k);
             if (!(1.0 + k.Jm1 > 0.0)) {
@@ -659,8 +887,9 @@ struct GradCoordsOp : XUStage {
                 for (int J = 0; J < 3; ++J)
                     Q[i * 3 + J] = w * (Sg[i * 3 + 0] * Ae[J * 3 + 0] + Sg[i * 3 + 1] * Ae[J * 3 + 1]
                                         + Sg[i * 3 + 2] * Ae[J * 3 + 2]);
-            E::add_forces(Q, q, f);
+            E::template add_forces<false>(Q, q, A);
         }
+        E::finish(A, f);
         return ok;
     }
 };
@@ -800,9 +1029,7 @@ k_accumulate(BlockMesh m, Op op, T *__restrict__ y,
         unpack_lc<E>(cur.lc, lc);
         T mu[E::NSUB], lam[E::NSUB];
         materials<E>(cur, mu, lam);
-        T f[E::NEN][3];
-#pragma unroll
-        for (int a = 0; a < E::NEN; ++a) f[a][0] = f[a][1] = f[a][2] = T(0);
+        T f[E::NEN][3];   // written in full by element()
         bad |= !op.template element<E>(sn, lc, mu, lam, k < r.np, f);
 #pragma unroll
         for (int a = 0; a < E::NEN; ++a)
@@ -855,8 +1082,8 @@ __global__ void __launch_bounds__(256) k_energy(BlockMesh m, const double *__res
         if (k + nt < r.ni) nxt = fetch_item<E>(m, r, k + nt);
         uint16_t lc[E::NEN];
         unpack_lc<E>(cur.lc, lc);
-        double Xe[E::NEN][3], ue[E::NEN][3];
-        gather_xu<E>(sn, lc, Xe, ue);
+        typename E::template Field<double> FX, Fu;
+        gather_xu<E>(sn, lc, FX, Fu);
         const bool pair = k < r.np;
         double pe = 0.0;
 #pragma unroll
@@ -864,8 +1091,8 @@ __global__ void __launch_bounds__(256) k_energy(BlockMesh m, const double *__res
             if (E::skip(q, pair)) continue;
             const double mu = cur.mu[E::sub(q)], lam = cur.lam[E::sub(q)];
             double Jx[9], Hxi[9];
-            E::grad(Xe, q, Jx);
-            E::grad(ue, q, Hxi);
+            E::grad(FX, q, Jx);
+            E::grad(Fu, q, Hxi);
             Kin kk;
             kinematics(E::template weight<double>(), Jx, Hxi, kk);
             if (!(1.0 + kk.Jm1 > 0.0)) {
@@ -936,16 +1163,16 @@ __global__ void __launch_bounds__(256) k_grad_material(BlockMesh m, const double
         const IData<E> d = fetch_item<E>(m, r, k);
         uint16_t lc[E::NEN];
         unpack_lc<E>(d.lc, lc);
-        double Xe[E::NEN][3], ue[E::NEN][3];
-        gather_xu<E>(sn, lc, Xe, ue);
+        typename E::template Field<double> FX, Fu;
+        gather_xu<E>(sn, lc, FX, Fu);
         const bool pair = k < r.np;
         double gm[E::NSUB] = {}, gl[E::NSUB] = {};
 #pragma unroll
         for (int q = 0; q < E::NQ; ++q) {
             if (E::skip(q, pair)) continue;
             double Jx[9], Hxi[9];
-            E::grad(Xe, q, Jx);
-            E::grad(ue, q, Hxi);
+            E::grad(FX, q, Jx);
+            E::grad(Fu, q, Hxi);
             Kin kk;
             kinematics(E::template weight<double>(), Jx, Hxi, kk);
             if (!(1.0 + kk.Jm1 > 0.0)) {
@@ -992,24 +1219,30 @@ __global__ void __launch_bounds__(256) k_vjp_material(BlockMesh m, const double 
         const IData<E> d = fetch_item<E>(m, r, k);
         uint16_t lc[E::NEN];
         unpack_lc<E>(d.lc, lc);
-        double Xe[E::NEN][3], ue[E::NEN][3], we[E::NEN][3];
+        typename E::template Field<double> FX, Fu, Fw;
+        {
+            double Xe[E::NEN][3], ue[E::NEN][3], we[E::NEN][3];
 #pragma unroll
-        for (int a = 0; a < E::NEN; ++a)
+            for (int a = 0; a < E::NEN; ++a)
 #pragma unroll
-            for (int i = 0; i < 3; ++i) {
-                Xe[a][i] = sn[lc[a]].X[i];
-                ue[a][i] = sn[lc[a]].u[i];
-                we[a][i] = sn[lc[a]].w[i];
-            }
+                for (int i = 0; i < 3; ++i) {
+                    Xe[a][i] = sn[lc[a]].X[i];
+                    ue[a][i] = sn[lc[a]].u[i];
+                    we[a][i] = sn[lc[a]].w[i];
+                }
+            E::prep(Xe, FX);
+            E::prep(ue, Fu);
+            E::prep(we, Fw);
+        }
         const bool pair = k < r.np;
         double gm[E::NSUB] = {}, gl[E::NSUB] = {};
 #pragma unroll
         for (int q = 0; q < E::NQ; ++q) {
             if (E::skip(q, pair)) continue;
             double Jx[9], Hxi[9], Wxi[9], Ae[9];
-            E::grad(Xe, q, Jx);
-            E::grad(ue, q, Hxi);
-            E::grad(we, q, Wxi);
+            E::grad(FX, q, Jx);
+            E::grad(Fu, q, Hxi);
+            E::grad(Fw, q, Wxi);
             Kin kk;
             kinematics(E::template weight<double>(), Jx, Hxi, kk);
             if (!(1.0 + kk.Jm1 > 0.0)) {

@@ -202,13 +202,25 @@ __global__ void __launch_bounds__(256) k_mlp_apply(int64_t n, const uint16_t *__
         const int64_t node = g0 + (lane & 15);
         const f4 o = mlp16(R, load_x(X, node, n));
         if (lane < 16 && node < n) {
+            // z = g + gamma c with g = D^-1 r, c = s MLP; gamma < 1 only where
+            // r_i.z_i would fall below half of r_i.g_i, so r.z >= r.D^-1 r / 2
             const float si = s[node];
+            float ri[3], gi[3], ci[3], a = 0.f, b = 0.f;
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                const float di = dinv[3 * node + c], ri = r[3 * node + c];
-                const float zi = (di == 0.f || si == 0.f) ? 0.f : ri * di + si * o[c];
+                const float di = dinv[3 * node + c];
+                ri[c] = r[3 * node + c];
+                gi[c] = ri[c] * di;
+                ci[c] = (di == 0.f || si == 0.f) ? 0.f : si * o[c];
+                a += ri[c] * gi[c];
+                b += ri[c] * ci[c];
+            }
+            const float gam = (a + b < 0.5f * a) ? (-0.5f * a) / b : 1.f;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const float zi = gi[c] + gam * ci[c];
                 z[3 * node + c] = zi;
-                rz += (double)ri * (double)zi;
+                rz += (double)ri[c] * (double)zi;
             }
         }
     }
@@ -219,6 +231,85 @@ __global__ void __launch_bounds__(256) k_mlp_apply(int64_t n, const uint16_t *__
         __syncthreads();
     }
     if (threadIdx.x == 0) prz[blockIdx.x] = red[0];
+}
+
+// ------------------------------------------------- energy-norm training rows
+
+// Block sum of one double per thread (256 threads); thread 0 gets the total.
+__device__ __forceinline__ double block_sum256(double v, double *red)
+{
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) {
+        if ((int)threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+        __syncthreads();
+    }
+    const double t = red[0];
+    __syncthreads();
+    return t;
+}
+
+// z = m (g + s out) for one sample's rows aux = [g(3), t(3), m(3), s, w, 0];
+// partials of r . g (the Jacobi share, which normalises the sample).
+__global__ void __launch_bounds__(256) k_energy_z(int64_t n, const float *__restrict__ r,
+                                                  const float *__restrict__ out,
+                                                  const float *__restrict__ aux, float *__restrict__ z,
+                                                  double *__restrict__ part)
+{
+    __shared__ double red[256];
+    double rg = 0.0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const float *a = aux + i * kAux;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            z[3 * i + c] = a[6 + c] * (a[c] + a[9] * out[3 * i + c]);
+            rg += (double)r[3 * i + c] * (double)a[c];
+        }
+    }
+    const double t = block_sum256(rg, red);
+    if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+// With w = 1 / (n_samples r.g): aux w = w, aux t = (g + s out) - (K z - r), so
+// that the target-fit loss gradient of the rows equals the gradient of
+// w (z.Kz - 2 r.z); partials of that energy term.
+__global__ void __launch_bounds__(256) k_energy_target(int64_t n, const float *__restrict__ r,
+                                                       const float *__restrict__ out,
+                                                       const float *__restrict__ z,
+                                                       const float *__restrict__ kz, float *__restrict__ aux,
+                                                       const double *__restrict__ rgpart, int G,
+                                                       double n_samples, double *__restrict__ part)
+{
+    __shared__ double red[256];
+    double rg = 0.0;
+    for (int k = threadIdx.x; k < G; k += blockDim.x) rg += rgpart[k];
+    rg = block_sum256(rg, red);
+    const double w = rg > 0.0 ? 1.0 / (n_samples * rg) : 0.0;
+    double e = 0.0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        float *a = aux + i * kAux;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const float ri = r[3 * i + c], zi = z[3 * i + c], ki = kz[3 * i + c];
+            a[3 + c] = (a[c] + a[9] * out[3 * i + c]) - (ki - ri);
+            e += (double)zi * (double)ki - 2.0 * (double)ri * (double)zi;
+        }
+        a[10] = (float)w;
+    }
+    const double t = block_sum256(e, red);
+    if (threadIdx.x == 0) part[blockIdx.x] = w * t;
+}
+
+__global__ void __launch_bounds__(256) k_energy_acc(const double *__restrict__ part, int G,
+                                                    double *__restrict__ energy)
+{
+    __shared__ double red[256];
+    double e = 0.0;
+    for (int k = threadIdx.x; k < G; k += blockDim.x) e += part[k];
+    e = block_sum256(e, red);
+    if (threadIdx.x == 0) *energy += e;
 }
 
 // ------------------------------------------------------------------ training
@@ -487,6 +578,23 @@ hipError_t mlp_loss_grad(hipStream_t s, int64_t rows, const uint16_t *X, const f
 {
     hipLaunchKernelGGL(k_mlp_grad, dim3(G), dim3(256), 0, s, rows, X, aux, params, gpart, lpart);
     hipLaunchKernelGGL(k_grad_reduce, dim3(g256(kP)), dim3(256), 0, s, G, gpart, lpart, grad, loss);
+    return hipGetLastError();
+}
+
+hipError_t mlp_energy_z(hipStream_t s, int64_t n, const float *r, const float *out, const float *aux,
+                        float *z, double *part, int G)
+{
+    hipLaunchKernelGGL(k_energy_z, dim3(G), dim3(256), 0, s, n, r, out, aux, z, part);
+    return hipGetLastError();
+}
+
+hipError_t mlp_energy_target(hipStream_t s, int64_t n, const float *r, const float *out, const float *z,
+                             const float *kz, float *aux, const double *rgpart, double n_samples,
+                             double *part, int G, double *energy)
+{
+    hipLaunchKernelGGL(k_energy_target, dim3(G), dim3(256), 0, s, n, r, out, z, kz, aux, rgpart, G,
+                       n_samples, part);
+    hipLaunchKernelGGL(k_energy_acc, dim3(1), dim3(256), 0, s, part, G, energy);
     return hipGetLastError();
 }
 

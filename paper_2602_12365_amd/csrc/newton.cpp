@@ -218,6 +218,38 @@ struct Solver {
         return pcg(b, sign, eta, max_it, iters);
     }
 
+    // Jacobi-PCG on K(u)_ff x = sign b from x = 0, keeping the CG residual after
+    // its[k] iterations in R + k n (ascending its); returns how many were
+    // reached before CG stopped (later ones repeat the last residual).
+    int snapshots(const double *u, const double *b, double sign, int nsnap, const int32_t *its,
+                  T *R, int32_t *taken)
+    {
+        int rc = setup();
+        if (rc) return rc;
+        if ((rc = set_dinv(u)) || (rc = linearize(u))) return rc;
+        TRY(L.init(b, sign, dinv, c.m.nmask, x, rv, p, q, sc, 0.0));
+        int k = 0;
+        for (int j = 0;; ++j) {
+            while (k < nsnap && its[k] == j) {
+                TRY(hipMemcpyAsync(R + (int64_t)k * n, rv, n * sizeof(T), hipMemcpyDeviceToDevice,
+                                   c.stream));
+                ++k;
+            }
+            if (k == nsnap) break;
+            TRY(hvp_acc(p, q, &sc->done));
+            TRY(L.pq(p, q, sc));
+            TRY(L.update(x, rv, p, q, dinv, sc, j));
+            TRY(L.dir(p, rv, dinv, sc, j));
+        }
+        TRY(hipMemcpyAsync(h_sc, sc, sizeof(CgScalars), hipMemcpyDeviceToHost, c.stream));
+        TRY(hipStreamSynchronize(c.stream));
+        int got = 0;
+        for (int i = 0; i < nsnap; ++i)
+            if (!h_sc->done || its[i] <= h_sc->iter) ++got;
+        *taken = got;
+        return EFEM_OK;
+    }
+
     // K(u)_ff xout = b, FP64 result
     int solve_into(const double *u, const double *b, double rtol, int max_it, double *xout,
                    int32_t *iters, int32_t *fb)
@@ -446,6 +478,34 @@ extern "C" int efem_linear_solve(efem_ctx *ctx, const double *u, const double *b
         Solver<float> s(*ctx, o);
         rc = s.solve_into(u, b, rtol, max_iter, x, iters, fallback);
     }
+    if (dev_prev >= 0 && dev_prev != ctx->device) (void)hipSetDevice(dev_prev);
+    return rc;
+}
+
+extern "C" int efem_cg_snapshots(efem_ctx *ctx, const double *u, const double *b, double sign,
+                                 int32_t n_snap, const int32_t *iters, float *R, int32_t *taken)
+{
+    if (!ctx || !u || !b || !iters || !R || !taken || n_snap < 1 || !(sign == 1.0 || sign == -1.0)) {
+        set_error("efem_cg_snapshots: bad argument");
+        return EFEM_ERR_INVALID;
+    }
+    for (int k = 0; k < n_snap; ++k)
+        if (iters[k] < 0 || iters[k] > 1000000 || (k > 0 && iters[k] < iters[k - 1])) {
+            set_error("efem_cg_snapshots: iters must be ascending and in [0, 1e6]");
+            return EFEM_ERR_INVALID;
+        }
+    if (!ctx->m.nmask) {
+        set_error("efem_cg_snapshots: set a Dirichlet mask first (efem_set_dirichlet)");
+        return EFEM_ERR_STATE;
+    }
+    efem_solve_opts o;
+    efem_solve_opts_default(&o);
+    o.hvp_prec = EFEM_F32;
+    int dev_prev = -1;
+    (void)hipGetDevice(&dev_prev);
+    if (dev_prev != ctx->device) (void)hipSetDevice(ctx->device);
+    Solver<float> s(*ctx, o);
+    const int rc = s.snapshots(u, b, sign, n_snap, iters, R, taken);
     if (dev_prev >= 0 && dev_prev != ctx->device) (void)hipSetDevice(dev_prev);
     return rc;
 }

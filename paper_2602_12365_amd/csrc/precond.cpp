@@ -85,7 +85,8 @@ MlpState *mlp_state(Ctx &c, int *rc)
         || (r = malloc_into(*M, &M->scale, (size_t)nn)) || (r = malloc_into(*M, &M->dinv, 3 * (size_t)nn))
         || (r = malloc_into(*M, &M->z, 3 * (size_t)nn)) || (r = malloc_into(*M, &M->zold, 3 * (size_t)nn))
         || (r = malloc_into(*M, &M->prz, 2048)) || (r = malloc_into(*M, &M->gpart, (size_t)kGradBlocks * kP))
-        || (r = malloc_into(*M, &M->lpart, kGradBlocks)) || (r = malloc_into(*M, &M->tt, 1))) {
+        || (r = malloc_into(*M, &M->lpart, kGradBlocks)) || (r = malloc_into(*M, &M->tt, 1))
+        || (r = malloc_into(*M, &M->epart, 2 * kEnergyBlocks))) {
         for (void *p : M->owned) (void)hipFree(p);
         delete M;
         *rc = r;
@@ -199,6 +200,29 @@ int efem_mlp_loss_grad(efem_ctx *ctx, int64_t rows, const uint16_t *X, const flo
     if (!M) return rc;
     const int G = (int)std::max<int64_t>(1, std::min<int64_t>(kGradBlocks, (rows + 15) / 16));
     TRY(mlp_loss_grad(ctx->stream, rows, X, aux, params, M->gpart, M->lpart, G, grad, loss));
+    return EFEM_OK;
+}
+
+int efem_mlp_energy_rows(efem_ctx *ctx, const float *r, const float *out, double n_samples,
+                         float *aux, float *z, float *kz, double *energy)
+{
+    if (!ctx || !r || !out || !aux || !z || !kz || !energy || !(n_samples > 0)) {
+        set_error("efem_mlp_energy_rows: bad argument");
+        return EFEM_ERR_INVALID;
+    }
+    if (ctx->lin_prec != EFEM_F32 || !ctx->ulin) {
+        set_error("efem_mlp_energy_rows: linearize with EFEM_F32 first");
+        return EFEM_ERR_STATE;
+    }
+    int rc;
+    MlpState *M = mlp_state(*ctx, &rc);
+    if (!M) return rc;
+    const int64_t n = ctx->n_nodes;
+    const int G = (int)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, kEnergyBlocks));
+    TRY(mlp_energy_z(ctx->stream, n, r, out, aux, z, M->epart, G));
+    TRY(launch_hvp_f32(*ctx, ctx->ulin, z, kz, nullptr, WriteMode::Overwrite));
+    TRY(mlp_energy_target(ctx->stream, n, r, out, z, kz, aux, M->epart, n_samples,
+                          M->epart + kEnergyBlocks, G, energy));
     return EFEM_OK;
 }
 

@@ -307,6 +307,30 @@ class Operator:
                                              _ptr(grad), _ptr(loss)), "efem_mlp_loss_grad")
         return grad, loss
 
+    def mlp_energy_rows(self, r, out, n_samples, aux, z, kz, energy):
+        """One sample of the energy-norm objective at the current FP32
+        linearization: fills z, kz, the rows' weights and pseudo-targets in aux,
+        and adds the sample's energy term into the device scalar ``energy``."""
+        self._sync_stream()
+        L.check(self._lib.efem_mlp_energy_rows(self._h, _ptr(self._nodal(r, torch.float32, "r")),
+                                               _ptr(out), float(n_samples), _ptr(aux),
+                                               _ptr(self._nodal(z, torch.float32, "z")),
+                                               _ptr(self._nodal(kz, torch.float32, "kz")), _ptr(energy)),
+                "efem_mlp_energy_rows")
+
+    def cg_snapshots(self, u, b, iters, sign=1.0, R=None):
+        """Residuals of FP32 Jacobi-PCG on K(u)_ff x = sign b after each of
+        ``iters`` iterations: (R float32 [len(iters), n_nodes, 3], number reached)."""
+        self._sync_stream()
+        its = (ctypes.c_int32 * len(iters))(*[int(i) for i in iters])
+        if R is None:
+            R = torch.empty((len(iters), self.n_nodes, 3), dtype=torch.float32, device=self.device)
+        taken = ctypes.c_int32()
+        L.check(self._lib.efem_cg_snapshots(self._h, _ptr(self._nodal(u, name="u")),
+                                            _ptr(self._nodal(b, name="b")), float(sign), len(iters),
+                                            its, _ptr(R), ctypes.byref(taken)), "efem_cg_snapshots")
+        return R, taken.value
+
     def mlp_adam(self, params, m, v, grad, lr, t):
         self._sync_stream()
         L.check(self._lib.efem_mlp_adam(self._h, _ptr(params), _ptr(m), _ptr(v), _ptr(grad),

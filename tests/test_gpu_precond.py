@@ -185,3 +185,89 @@ def test_newton_with_learned_preconditioner():
     ug = u.cpu().numpy()
     assert np.linalg.norm(F.masked(mask, orc.residual(ug))) <= 2e-8 * st_ref.residual_history[-1][0]
     assert np.linalg.norm(ug - u_ref) <= 1e-6 * np.linalg.norm(u_ref)
+
+
+def test_cg_snapshots_match_oracle_pcg():
+    """Residual snapshots of the FP32 Jacobi-PCG against the oracle's FP64 PCG
+    (first iterations, before rounding drifts the two apart) and the
+    D^-1-orthogonality of PCG residuals."""
+    m, op, mu, mask, ubc = make_op(I.HEX8, 5)
+    u = np.zeros((m.n_nodes, 3))
+    u.reshape(-1)[mask != 0] = 0.05 * ubc.reshape(-1)[mask != 0]
+    b = I.gaussian_field(m.n_nodes, 1.0, 21)
+    R, taken = op.cg_snapshots(dev(u), dev(b), [0, 1, 2, 3, 3, 6], sign=-1.0)
+    assert taken == 6
+    R = R.cpu().numpy().reshape(6, -1).astype(np.float64)
+    orc = F.FEM(I.HEX8, m.X, m.conn, mu, 1.5 * mu)
+    bb = F.masked(mask, -b).reshape(-1)
+    assert np.allclose(R[0], bb.astype(np.float32), rtol=0, atol=0)
+    assert np.array_equal(R[3], R[4])
+    D = orc.jacobi_diag(u).reshape(-1)
+    dinv = np.where(mask != 0, 0.0, 1.0 / D)
+    K = lambda v: F.masked(mask, orc.hvp(u, F.masked(mask, v.reshape(-1, 3)))).reshape(-1)
+    for k, j in ((1, 1), (2, 2), (3, 3)):
+        x, _ = F.pcg(K, bb, dinv, 0.0, j)
+        rj = bb - K(x)
+        assert np.linalg.norm(R[k] - rj) <= 1e-4 * np.linalg.norm(bb), (j, np.linalg.norm(R[k] - rj))
+    G = R[[0, 1, 2, 3, 5]]
+    for i in range(5):
+        for j in range(i):
+            c = abs(G[i] @ (dinv * G[j])) / np.sqrt((G[i] @ (dinv * G[i])) * (G[j] @ (dinv * G[j])))
+            assert c <= 1e-3, (i, j, c)
+
+
+def test_energy_rows_and_gradient_match_oracle():
+    """z, K z, pseudo-targets, weights and the energy term of one sample against
+    the oracle's tangent action, and the resulting parameter gradient against
+    the oracle's MLP backward of dE/dout = 2 w s m (K z - r)."""
+    m, op, mu, mask, ubc = make_op(I.HEX8, 4)
+    theta = rand_theta(31, 0.2)
+    op.set_mlp(dev(theta, torch.float32))
+    u = np.zeros((m.n_nodes, 3))
+    u.reshape(-1)[mask != 0] = 0.05 * ubc.reshape(-1)[mask != 0]
+    r = F.masked(mask, I.gaussian_field(m.n_nodes, 1.0, 32))
+    diag = op.jacobi_diag(dev(u))
+    r32 = dev(r, torch.float32)
+    X, aux = op.precond_rows(r32, diag, r32, 1.0)
+    out = op.mlp_forward(X)
+    op.linearize(dev(u), "f32")
+    z = torch.empty((m.n_nodes, 3), dtype=torch.float32, device="cuda")
+    kz = torch.empty_like(z)
+    energy = torch.zeros((), dtype=torch.float64, device="cuda")
+    n_samples = 3.0
+    op.mlp_energy_rows(r32, out, n_samples, aux, z, kz, energy)
+    A = aux.cpu().numpy().astype(np.float64)
+    o = out.cpu().numpy().astype(np.float64)
+    g, mm, s = A[:, 0:3], A[:, 6:9], A[:, 9]
+    zr = g + s[:, None] * o
+    z_ref = mm * zr
+    assert np.allclose(z.cpu().numpy(), z_ref, rtol=1e-6, atol=1e-7 * np.abs(z_ref).max())
+    orc = F.FEM(I.HEX8, m.X, m.conn, mu, 1.5 * mu)
+    zz = z.cpu().numpy().astype(np.float64)
+    Kz = F.masked(mask, orc.hvp(u, zz))
+    scale = np.abs(Kz).max()
+    assert np.abs(kz.cpu().numpy() - Kz).max() <= 5e-5 * scale
+    rr = r.astype(np.float32).astype(np.float64)
+    w = 1.0 / (n_samples * (rr * g).sum())
+    assert np.allclose(A[:, 10], w, rtol=1e-6)
+    assert np.abs(A[:, 3:6] - (zr - (Kz - rr))).max() <= 5e-5 * scale
+    e_ref = w * ((zz * Kz).sum() - 2.0 * (rr * zz).sum())
+    assert abs(energy.item() - e_ref) <= 1e-4 * abs(e_ref)
+    # gradient through the pseudo-targets
+    th = dev(theta, torch.float32)
+    grad, _ = op.mlp_loss_grad(X, aux, th)
+    Xf = bits_to_float(X.cpu().numpy())[:, :12]
+    dout = 2.0 * w * s[:, None] * mm * (Kz - rr)
+    grad_ref = P.mlp_backward(theta.astype(np.float64), Xf.astype(np.float32), dout)
+    gg = grad.cpu().numpy()
+    assert np.linalg.norm(gg - grad_ref) <= 2e-2 * np.linalg.norm(grad_ref)
+
+
+def test_energy_training_lowers_the_objective_below_jacobi():
+    from paper_2602_12365_amd import precond as PC
+    S = PC.generate_samples(n=6, seeds=range(1000, 1002), n_steps=3, snaps=(0, 3, 10))
+    assert S.n_samples == 2 * 3 * 3
+    theta, hist = PC.train_energy(S, epochs=80, lr=2e-3)
+    assert hist[0][1] < 0.0                       # the Jacobi step already lowers the energy
+    assert hist[-1][1] < 1.2 * hist[0][1], hist   # and the trained network lowers it further
+    print(f"\n[precond] energy objective Jacobi {hist[0][1]:.4f} -> trained {hist[-1][1]:.4f}", flush=True)

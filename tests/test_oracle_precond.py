@@ -109,3 +109,27 @@ def test_apply_is_positively_homogeneous_and_masked():
     # the zero network is Jacobi
     zj = P.apply(np.zeros(P.N_PARAMS), r, D, mask, ptr, idx)
     assert np.allclose(zj, np.where(mask.reshape(-1, 3) != 0, 0, r / D))
+
+
+def test_apply_safeguard_keeps_half_the_jacobi_share_per_node():
+    """r_i . z_i >= r_i . g_i / 2 at every node, with equality exactly where the
+    correction was scaled back; elsewhere z = g + s MLP unchanged."""
+    m = I.hex_mesh(3)
+    rng = np.random.default_rng(11)
+    r = rng.standard_normal((m.n_nodes, 3))
+    D = rng.uniform(0.5, 2.0, (m.n_nodes, 3))
+    mask, _ = I.clamp_top_bottom(m.X, 0.1)
+    ptr, idx = P.node_neighbours(m.conn, m.n_nodes)
+    th = rand_theta(12, 1.0)                    # large weights: many nodes need the safeguard
+    z = P.apply(th, r, D, mask, ptr, idx)
+    F, g, s = P.features(r, D, mask, ptr, idx)
+    c = s[:, None] * P.mlp_forward(th, F.astype(np.float32))
+    c[mask.reshape(-1, 3) != 0] = 0.0
+    a = (r * g).sum(axis=1)
+    rz = (r * z).sum(axis=1)
+    low = a + (r * c).sum(axis=1) < 0.5 * a
+    assert low.sum() > 5 and (~low).sum() > 5
+    assert np.all(rz >= 0.5 * a - 1e-12 * np.abs(a).max())
+    assert np.allclose(rz[low], 0.5 * a[low], rtol=1e-12, atol=1e-14)
+    assert np.allclose(z[~low], (g + c)[~low], rtol=0, atol=0)
+    assert (r * z).sum() >= 0.5 * (r * g).sum()
