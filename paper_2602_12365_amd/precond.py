@@ -143,10 +143,12 @@ class SampleSet:
 
 def generate_samples(n=32, seeds=range(1000, 1020), n_steps=10, snaps=(0, 5, 20, 60, 150),
                      elem=I.HEX8, device="cuda", log=None):
-    """Residual snapshots of FP32 Jacobi-PCG on K(u_k) d = -r(u_k with the
-    prescribed values of step k+1), u_k the equilibrium of step k (u_0 = 0),
-    for k = 0..n_steps-1 and each material field; the state advances with
-    efem_newton_solve."""
+    """Residual snapshots of FP32 Jacobi-PCG on the first system of each load
+    step, the tangent predictor K(u_k)_ff d_f = -(K(u_k) dc)_f with dc the
+    increment of the prescribed values and u_k the equilibrium of step k
+    (u_0 = 0), for k = 0..n_steps-1 and each material field; the state
+    advances with efem_newton_solve.  Snapshots CG did not reach, or that are
+    zero or not finite, are dropped."""
     S = SampleSet()
     for seed in seeds:
         mesh, mu, lam, mask, ubc = compression_case(elem, n, seed)
@@ -164,9 +166,17 @@ def generate_samples(n=32, seeds=range(1000, 1020), n_steps=10, snaps=(0, 5, 20,
                 if rc != 0:
                     raise RuntimeError(f"training solve did not converge (seed {seed}, step {k}): {st}")
             uk = u.clone()
-            rhs = op.residual(torch.where(fixed, ((k + 1) / n_steps) * ubc_t, uk).contiguous())
-            R, taken = op.cg_snapshots(uk, rhs, snaps, sign=-1.0)
-            S.add(op, uk, op.jacobi_diag(uk), R[:max(taken, 1)])
+            dc = torch.where(fixed, ubc_t / n_steps, torch.zeros_like(ubc_t)).contiguous()
+            op.set_dirichlet(None)                  # K dc on the unmasked increment
+            op.linearize(uk, "f64")
+            kdc = op.hvp(dc)
+            op.set_dirichlet(m)
+            R, taken = op.cg_snapshots(uk, kdc, snaps, sign=-1.0)
+            R = R[:taken]
+            flat = R.reshape(R.shape[0], -1)
+            keep = torch.isfinite(flat).all(dim=1) & (flat.abs().amax(dim=1) > 0)
+            if bool(keep.any()):
+                S.add(op, uk, op.jacobi_diag(uk), R[keep].contiguous())
         if log:
             log(f"samples from mu seed {seed} done")
     return S.finish()
