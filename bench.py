@@ -11,10 +11,10 @@ Beside it: the FP32 tangent action, the colour scatter, energy and residual
 times, a roofline object for the dominant kernel (the single-launch FP64
 tangent-action block pass, timed with HIP events on its stream), the Newton
 solves of the metric's second half (plain FP64 Jacobi-CG vs FP32 tangent
-actions with and without the learned preconditioner, on an unseen 96^3 Q1-hex
-compression case, the network trained first in the energy norm on CG
-residuals from 32^3 solves), and
-the FP64 CPU oracle timed on a bounded sample on the host cores.
+actions with and without the learned preconditioner, on the 128^3 Q1-hex
+compression case and on the unseen 96^3 test mesh of the preconditioner,
+the network trained first in the energy norm on CG residuals from 32^3
+solves), and the FP64 CPU oracle timed on a bounded sample on the host cores.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-solve] [--no-cpu]
     python bench.py --mode kernels     # fixed kernel workload for rocprofv3
@@ -98,15 +98,15 @@ def measured_traffic():
 
 def solve_section(args, dev):
     """Compression load case (bottom clamped, top -20% z in 10 load steps, Q1
-    hexes, 2x2x2 Gauss, mu ~ lognormal(0, 0.5), lam = 1.5 mu) on an unseen
-    n_test^3 mesh: plain FP64 Newton-CG (Jacobi), mixed FP32-HVP (Jacobi), and
-    mixed FP32-HVP with the learned preconditioner trained on n_train^3 pairs.
+    hexes, 2x2x2 Gauss, mu ~ lognormal(0, 0.5), lam = 1.5 mu) on the 128^3
+    mesh (mu seed 3) and on the unseen 96^3 test mesh of the preconditioner
+    (mu seed 2000): plain FP64 Newton-CG (Jacobi), mixed FP32-HVP (Jacobi), and
+    mixed FP32-HVP with the learned preconditioner trained on 32^3 samples.
     Wall time from the first load step to the last step's convergence."""
     import torch
     from paper_2602_12365_amd import Operator, inputs as I, precond as PC
 
-    res = {"load_case": f"{args.n_test}^3 Q1 hexes, mu~lognormal(0,0.5) seed 2000, lam=1.5mu, "
-                        f"top -20% z in 10 steps, stop at 1e-8 relative residual per step"}
+    res = {}
     t0 = time.time()
     seeds = range(1000, 1000 + args.train_fields)
     S = PC.generate_samples(n=args.n_train, seeds=seeds, n_steps=10, log=log)
@@ -125,7 +125,30 @@ def solve_section(args, dev):
         st[0].close()
     del S
 
-    mesh, mu, lam, mask, ubc = PC.compression_case(I.HEX8, args.n_test, 2000)
+    res["solves"] = {}
+    for tag, n, seed in (("cfg3", args.n_cfg3, 3), ("cfg5_test", args.n_test, 2000)):
+        if n <= 0:
+            continue
+        res["solves"][tag] = compression_solves(dev, n, seed, theta)
+    # the metric's headline pair: plain FP64 vs mixed FP32 + learned, and mixed
+    # FP32 + Jacobi, on the largest configuration run
+    main = res["solves"].get("cfg3") or res["solves"].get("cfg5_test")
+    runs = main["runs"]
+    res["speedup_mixed_learned_vs_plain"] = round(runs["plain_f64_jacobi"]["wall_s"]
+                                                  / runs["mixed_f32_learned"]["wall_s"], 3)
+    res["speedup_mixed_jacobi_vs_plain"] = round(runs["plain_f64_jacobi"]["wall_s"]
+                                                 / runs["mixed_f32_jacobi"]["wall_s"], 3)
+    return res
+
+
+def compression_solves(dev, n, seed, theta):
+    """Compression case on n^3 Q1 hexes (mu seed `seed`): plain FP64 Jacobi,
+    mixed FP32 Jacobi and mixed FP32 with the learned preconditioner."""
+    import torch
+    from paper_2602_12365_amd import Operator, inputs as I, precond as PC
+    mesh, mu, lam, mask, ubc = PC.compression_case(I.HEX8, n, seed)
+    res = {"load_case": f"{n}^3 Q1 hexes ({mesh.n_dofs} DOF), mu~lognormal(0,0.5) seed {seed}, "
+                        f"lam=1.5mu, top -20% z in 10 steps, stop at 1e-8 relative residual per step"}
     op = Operator(I.HEX8, mesh.X, mesh.conn, device=dev)
     op.set_material(torch.as_tensor(mu, device=dev), torch.as_tensor(lam, device=dev))
     op.set_dirichlet(torch.as_tensor(mask, device=dev))
@@ -205,7 +228,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-solve", action="store_true")
     ap.add_argument("--n-train", type=int, default=32)
-    ap.add_argument("--n-test", type=int, default=96)
+    ap.add_argument("--n-test", type=int, default=96, help="learned-preconditioner test mesh (0 = skip)")
+    ap.add_argument("--n-cfg3", type=int, default=128, help="compression-solve mesh (0 = skip)")
     ap.add_argument("--train-fields", type=int, default=20)
     ap.add_argument("--epochs", type=int, default=300)
     ap.add_argument("--lr", type=float, default=1e-3)
@@ -294,6 +318,23 @@ def main():
     n_col = opc.info()["n_colours"]
     opc.close()
 
+    # sparse tangent by colouring (Alg. 2): K(u) from n_colours tangent
+    # actions, then CSR products against the matrix-free one
+    sp_info = op.sparse_setup()
+    vals = op.sparse_assemble(u)
+    t_asm = event_time(lambda: op.sparse_assemble(u, values=vals), 3, stream)
+    t_spmv = event_time(lambda: op.sparse_spmv(vals, V[0], out=Y), 50, stream)
+    spmv_bytes = sp_info["nnz"] * (8 + 4) + (sp_info["n_rows"] + 1) * 8 + 2 * ndof * 8
+    sparse = {"n_colours": sp_info["n_colours"], "nnz": sp_info["nnz"],
+              "setup_s": round(sp_info["setup_seconds"], 3), "assemble_ms": round(t_asm * 1e3, 3),
+              "assemble_gdofs": round(ndof / t_asm / 1e9, 4),
+              "spmv_us": round(t_spmv * 1e6, 3), "spmv_gbs": round(spmv_bytes / t_spmv / 1e9, 1),
+              "spmv_pct_hbm": round(100 * spmv_bytes / t_spmv / 1e9 / HBM_PEAK_GBS, 2),
+              "paper_context": "sparse differentiation ~0.5 MDoF/s in 3D, 80-90 colours, A100 (JAX)"}
+    log(f"sparse: {sp_info['n_colours']} colours, nnz {sp_info['nnz']}, assemble {t_asm*1e3:.2f} ms, "
+        f"spmv {t_spmv*1e6:.1f} us")
+    del vals
+
     t_hvp = t_step / N_DIRS
     out = {
         "metric": "HVP Gdof/s & %HBM peak; Newton solve s to 1e-8 resid, plain vs mixed+NN",
@@ -342,6 +383,7 @@ def main():
         "residual_us": round(t_res * 1e6, 3),
         "energy_us": round(t_en * 1e6, 3),
         "setup_s": round(setup_s, 3),
+        "sparse_tangent": sparse,
         "paper_context": "matrix-free JVP ~13 MDoF/s, 3D linear tets, NVIDIA A100 (JAX), precision unstated",
     }
 

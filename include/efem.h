@@ -341,6 +341,39 @@ int efem_linear_solve(efem_ctx *ctx, const double *u, const double *b, double *x
                       int32_t hvp_prec, int32_t precond, int32_t max_iter, int32_t *iters,
                       int32_t *fallback);
 
+/* ------------------------------------------ sparse tangent by colouring
+ * The paper's second technique (Alg. 2): the tangent K(u) as a sparse matrix,
+ * recovered from n_colours tangent actions.  Its pattern is the node 1-ring in
+ * 3x3 blocks (CSR over DOFs, columns sorted).  DOF colours come from a greedy
+ * distance-2 colouring of the node graph, times 3 components, so no row has
+ * two columns of one colour; K times the indicator vector of a colour holds,
+ * in each row, that row's entry of the colour.  With a Dirichlet mask the
+ * rows and columns of prescribed DOFs are zero (the reduced K_ff, as
+ * efem_hvp applies it). */
+typedef struct {
+    int64_t n_rows;           /* 3 n_nodes */
+    int64_t nnz;
+    int32_t n_colours;
+    int32_t max_row;          /* most nonzeros in a row */
+    double setup_seconds;     /* host time of the pattern and the colouring */
+} efem_sparse_info;
+
+/* Build the pattern and the colouring (host work, synchronous; the first call
+ * builds, later calls only report).  EFEM_ERR_INVALID beyond 2^31 nonzeros. */
+int efem_sparse_setup(efem_ctx *ctx, efem_sparse_info *info);
+
+/* Copy the pattern out: row_ptr DEVICE int64 [n_rows+1], col DEVICE int32
+ * [nnz], dof_colour DEVICE int32 [n_rows].  EFEM_ERR_STATE before setup. */
+int efem_sparse_pattern(efem_ctx *ctx, int64_t *row_ptr, int32_t *col, int32_t *dof_colour);
+
+/* values (DEVICE float64 [nnz], in pattern order) = K(u) from n_colours FP64
+ * tangent actions at u (DEVICE float64 [3*n_nodes]; the context's FP64
+ * linearization is set to u). */
+int efem_sparse_assemble(efem_ctx *ctx, const double *u, double *values);
+
+/* y = K x with the assembled values (x, y DEVICE float64 [3*n_nodes]). */
+int efem_sparse_spmv(efem_ctx *ctx, const double *values, const double *x, double *y);
+
 const char *efem_last_error(void);
 
 #ifdef __cplusplus

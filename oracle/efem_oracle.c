@@ -337,6 +337,47 @@ int orc_hvp(int type, int64_t nn, int64_t ne, const double *X, const int32_t *co
     return bad ? -4 : 0;
 }
 
+/* ------------------------------------------------------- element tangents */
+
+/* Element tangent matrices, the matrix form of Eq. (3):
+ *   K_e[(a,i),(b,k)] = sum_q w detJ sum_{J,L} A_iJkL grad_J N_a grad_L N_b
+ * written to Ke [ne][nen*3][nen*3] (row (a,i) = 3a + i).  The global tangent
+ * is their sum over the connectivity; its sparsity pattern is the node 1-ring
+ * in 3x3 blocks.  Used to check the colouring-based sparse assembly. */
+int orc_element_tangents(int type, int64_t nn, int64_t ne, const double *X, const int32_t *conn,
+                         const double *mu, const double *lam, const double *u, double *Ke)
+{
+    rule_t r;
+    if (check_args(type, nn, ne, conn, &r)) return -1;
+    const int m = r.nen * 3;
+    int bad = 0;
+#pragma omp parallel for schedule(static) reduction(|| : bad)
+    for (int64_t e = 0; e < ne; ++e) {
+        double Xe[8][3], ue[8][3], A[3][3][3][3];
+        gather(&r, X, conn + e * r.nen, Xe);
+        gather(&r, u, conn + e * r.nen, ue);
+        double *K = Ke + e * (int64_t)m * m;
+        memset(K, 0, sizeof(double) * (size_t)(m * m));
+        for (int q = 0; q < r.nq; ++q) {
+            qp_t s;
+            qp_eval(&r, q, Xe, ue, &s);
+            if (!s.ok) { bad = 1; break; }
+            tangent(&s, mu[e], lam[e], A);
+            for (int a = 0; a < r.nen; ++a)
+                for (int i = 0; i < 3; ++i)
+                    for (int b = 0; b < r.nen; ++b)
+                        for (int k = 0; k < 3; ++k) {
+                            double t = 0;
+                            for (int J = 0; J < 3; ++J)
+                                for (int L = 0; L < 3; ++L)
+                                    t += A[i][J][k][L] * s.gN[a][J] * s.gN[b][L];
+                            K[(3 * a + i) * m + 3 * b + k] += s.wdetJ * t;
+                        }
+        }
+    }
+    return bad ? -4 : 0;
+}
+
 /* ----------------------------------------------------------- jacobi diag */
 
 /* K_{(a,i),(a,i)} = sum_e sum_q w detJ sum_JL A_iJiL grad_J N_a grad_L N_a */

@@ -35,6 +35,7 @@ def lib():
             ("orc_energy", [_dp, _dp, _dp, _dp, _dp]),
             ("orc_residual", [_dp, _dp, _dp, _dp]),
             ("orc_hvp", [_dp, _dp, _dp, _dp, _dp]),
+            ("orc_element_tangents", [_dp, _dp, _dp, _dp]),
             ("orc_jacobi_diag", [_dp, _dp, _dp, _dp]),
             ("orc_grad_material", [_dp, _dp, _dp]),
             ("orc_residual_vjp_material", [_dp, _dp, _dp, _dp]),
@@ -130,6 +131,27 @@ class FEM:
         _check(lib().orc_hvp(*self._head(), _d(self.mu), _d(self.lam), _d(u), _d(v), _d(y)),
                "hvp")
         return y
+
+    def element_tangents(self, u):
+        """K_e [n_elems, 3 n_en, 3 n_en], the matrix form of Eq. (3) per element."""
+        u = self._vec(u)
+        m = 3 * self.conn.shape[1]
+        Ke = np.empty((self.n_elems, m, m))
+        _check(lib().orc_element_tangents(*self._head(), _d(self.mu), _d(self.lam), _d(u), _d(Ke)),
+               "element_tangents")
+        return Ke
+
+    def tangent_matrix(self, u):
+        """The global tangent K(u) as a scipy CSR matrix [3 n_nodes]^2: the sum of
+        the element tangents over the connectivity (duplicates added)."""
+        import scipy.sparse as sp
+        Ke = self.element_tangents(u)
+        dofs = (3 * self.conn[:, :, None] + np.arange(3)[None, None, :]).reshape(self.n_elems, -1)
+        m = dofs.shape[1]
+        rows = np.repeat(dofs, m, axis=1).reshape(-1)
+        cols = np.tile(dofs, (1, m)).reshape(-1)
+        n = 3 * self.X.shape[0]
+        return sp.coo_matrix((Ke.reshape(-1), (rows, cols)), shape=(n, n)).tocsr()
 
     def jacobi_diag(self, u):
         """diag K(u), the Jacobi preconditioner of the Newton-CG solve."""

@@ -43,6 +43,11 @@ class Info(ctypes.Structure):
                 ("n_block_nodes", c_int64), ("n_items", c_int64)]
 
 
+class SparseInfo(ctypes.Structure):
+    _fields_ = [("n_rows", c_int64), ("nnz", c_int64), ("n_colours", c_int32), ("max_row", c_int32),
+                ("setup_seconds", c_double)]
+
+
 class SolveOpts(ctypes.Structure):
     _fields_ = [("n_steps", c_int32), ("hvp_prec", c_int32), ("precond", c_int32),
                 ("max_newton", c_int32), ("max_cg", c_int32), ("check_every", c_int32),
@@ -97,6 +102,10 @@ SIGNATURES = {
                                        c_void_p, c_void_p]),
     "efem_cg_snapshots": (c_int32, [c_void_p, c_void_p, c_void_p, c_double, c_int32, c_void_p,
                                     c_void_p, ctypes.POINTER(c_int32)]),
+    "efem_sparse_setup": (c_int32, [c_void_p, c_void_p]),
+    "efem_sparse_pattern": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p]),
+    "efem_sparse_assemble": (c_int32, [c_void_p, c_void_p, c_void_p]),
+    "efem_sparse_spmv": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p]),
     "efem_linear_solve": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_double, c_int32,
                                     c_int32, c_int32, ctypes.POINTER(c_int32),
                                     ctypes.POINTER(c_int32)]),

@@ -397,6 +397,7 @@ void efem_destroy(efem_ctx *ctx)
     if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
     else (void)hipDeviceSynchronize();
     mlp_release(*ctx);
+    sparse_release(*ctx);
     for (void *p : ctx->owned) (void)hipFree(p);
     delete ctx;
 }
@@ -483,8 +484,7 @@ int efem_create(efem_ctx **out, int32_t elem, int64_t n_nodes, int64_t n_elems,
     if ((rc = upload(*ctx, &p_es, hb.estart)) || (rc = upload(*ctx, &p_is, hb.istart))
         || (rc = upload(*ctx, &p_ns, hb.nstart)) || (rc = upload(*ctx, &p_bn, hb.bnode))
         || (rc = upload(*ctx, &p_it, hb.items)) || (rc = upload(*ctx, &p_eo, hb.order))
-        || (rc = upload(*ctx, &p_X, Xh)) || (rc = upload(*ctx, &p_Xf, Xfh))
-        || (rc = upload(*ctx, &ctx->shared_nodes, hb.shared_nodes)))
+        || (rc = upload(*ctx, &p_X, Xh)) || (rc = upload(*ctx, &p_Xf, Xfh)))
         return fail(rc);
     ctx->n_items = hb.istart.back();
     m.estart = p_es;

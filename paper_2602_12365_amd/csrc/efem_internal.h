@@ -54,7 +54,8 @@ struct Ctx;
 hipError_t launch_energy(const Ctx &c, const double *u, double *psi);
 hipError_t launch_residual(const Ctx &c, const double *u, double *r);
 // How a nodal output is written:
-//   Overwrite:  y = K v (a small pre-pass clears the entries several blocks add into);
+//   Overwrite:  y = K v (a fill pre-pass clears y, prescribed components to
+//               their value, before the block pass adds into shared nodes);
 //   Accumulate: y += K v, one launch (plain read-modify-write on block-private nodes);
 //   Zeroed:     y = K v for a y that holds zeros on entry, one launch.
 enum class WriteMode { Overwrite = 0, Accumulate = 1, Zeroed = 2 };
@@ -91,8 +92,7 @@ struct Ctx {
     // device buffers owned by the context
     BlockMesh m{};
     std::vector<void *> owned;      // every hipMalloc of the context
-    int32_t *shared_nodes = nullptr;    // nodes touched by several blocks
-    int64_t n_shared = 0;
+    int64_t n_shared = 0;               // nodes touched by several blocks
     std::vector<Pass> passes;           // colour lists (Color) or one pass (Atomic)
     double *partials = nullptr;         // [n_blocks] per-block energy partials
     uint32_t *counter = nullptr;        // last-block-done ticket
@@ -108,11 +108,15 @@ struct Ctx {
     // learned preconditioner state (precond.cpp) and the host connectivity it
     // builds the node 1-ring from
     void *mlp = nullptr;
+    // sparse tangent by colouring (sparse.cpp), built on first use
+    void *sparse = nullptr;
     std::vector<int32_t> conn_host;
 };
 
 // learned preconditioner resources of a context (precond.cpp)
 void mlp_release(Ctx &c);
+// sparse-tangent resources of a context (sparse.cpp)
+void sparse_release(Ctx &c);
 
 // error helpers (api.cpp)
 void set_error(const std::string &msg);

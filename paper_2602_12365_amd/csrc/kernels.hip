@@ -148,9 +148,12 @@ __device__ __forceinline__ void flag_inverted(int32_t *flags) { atomicOr(flags, 
 //   Field<T>, prep(f, F)      what the gradients are formed from, given the
 //                             NEN nodal values f of one field;
 //   grad(F, q, G)             G[i*3+J] = d f_i / d xi_J at point q;
-//   Acc<T>, add_forces<FIRST>(Q, q, A), finish(A, out)
+//   Acc<T>, add_forces<INIT>(Q, q, A), finish(A, out)
 //                             nodal forces out_a = sum_q Q_q dN_a/dxi(q)
-//                             (FIRST: the first point, which initialises A);
+//                             (INIT: the points arrive in ascending order and
+//                             none is skipped but possibly the last, starting
+//                             from an uninitialised A; otherwise A was zeroed
+//                             and every point adds);
 //   dN(q, a, J)               the shape-function derivatives themselves.
 //
 // Tet4 pair: nodes (a, b, c, d1, d2) with tet 1 = (a, b, c, d1) positively
@@ -197,14 +200,16 @@ struct Tet4Pair {
 #pragma unroll
         for (int a = 0; a < NEN; ++a) A.f[a][0] = A.f[a][1] = A.f[a][2] = T(0);
     }
-    // node forms accumulate straight into the caller's nodal array
-    template <bool FIRST, class T>
+    // Node forms accumulate straight into the caller's nodal array.  INIT:
+    // points arrive in ascending order from an uninitialised accumulator (the
+    // first point assigns); otherwise every point adds.
+    template <bool INIT, class T>
     __device__ static __forceinline__ void add_forces_to(const T Q[9], int q, T out[NEN][3])
     {
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
             const T s = -(Q[i * 3 + 0] + Q[i * 3 + 1] + Q[i * 3 + 2]);
-            if (FIRST) {   // point 0 of tet 1 touches nodes 0..3 only
+            if (INIT && q == 0) {   // point 0 of tet 1 touches nodes 0..3 only
                 out[node(q, 1)][i] = Q[i * 3 + 0];
                 out[node(q, 2)][i] = Q[i * 3 + 1];
                 out[node(q, 3)][i] = Q[i * 3 + 2];
@@ -218,10 +223,10 @@ struct Tet4Pair {
             }
         }
     }
-    template <bool FIRST, class T>
+    template <bool INIT, class T>
     __device__ static __forceinline__ void add_forces(const T Q[9], int q, Acc<T> &A)
     {
-        add_forces_to<FIRST>(Q, q, A.f);
+        add_forces_to<INIT>(Q, q, A.f);
     }
     template <class T>
     __device__ static __forceinline__ void finish(const Acc<T> &A, T out[NEN][3])
@@ -289,22 +294,22 @@ struct Hex8Nodes {
 #pragma unroll
         for (int a = 0; a < NEN; ++a) A.f[a][0] = A.f[a][1] = A.f[a][2] = T(0);
     }
-    template <bool FIRST, class T>
+    template <bool INIT, class T>
     __device__ static __forceinline__ void add_forces_to(const T Q[9], int q, T out[NEN][3])
     {
 #pragma unroll
         for (int a = 0; a < NEN; ++a)
 #pragma unroll
             for (int i = 0; i < 3; ++i) {
-                if (FIRST) out[a][i] = T(0);
+                if (INIT && q == 0) out[a][i] = T(0);
                 out[a][i] += Q[i * 3 + 0] * dN<T>(q, a, 0) + Q[i * 3 + 1] * dN<T>(q, a, 1)
                            + Q[i * 3 + 2] * dN<T>(q, a, 2);
             }
     }
-    template <bool FIRST, class T>
+    template <bool INIT, class T>
     __device__ static __forceinline__ void add_forces(const T Q[9], int q, Acc<T> &A)
     {
-        add_forces_to<FIRST>(Q, q, A.f);
+        add_forces_to<INIT>(Q, q, A.f);
     }
     template <class T>
     __device__ static __forceinline__ void finish(const Acc<T> &A, T out[NEN][3])
@@ -343,22 +348,32 @@ struct Hex8 {
     __device__ static constexpr int sub(int) { return 0; }
     __device__ static constexpr bool skip(int, bool) { return false; }
     static constexpr double kG = 0.57735026918962576451;   // 1/sqrt(3)
-    // w_J(e, q)
-    __device__ static constexpr double ew(int J, int e, int q)
+    // the two directions other than J
+    __device__ static constexpr int oth1(int J) { return J == 0 ? 1 : 0; }
+    __device__ static constexpr int oth2(int J) { return J == 2 ? 1 : 2; }
+    // which of the 4 columns of direction J point q uses: its coordinate
+    // signs in the two other directions
+    __device__ static constexpr int col(int J, int q)
     {
-        const int o1 = J == 0 ? 1 : 0, o2 = J == 2 ? 1 : 2;   // the other two directions
-        const double s1 = (e & 1) ? 1.0 : -1.0, s2 = (e & 2) ? 1.0 : -1.0;
-        const double p1 = ((q >> o1) & 1) ? kG : -kG, p2 = ((q >> o2) & 1) ? kG : -kG;
-        return 0.125 * (1.0 + s1 * p1) * (1.0 + s2 * p2);
+        return ((q >> oth1(J)) & 1) + 2 * ((q >> oth2(J)) & 1);
     }
+    // (1 + s p g) for edge sign s and point coordinate sign p, and its eighth
+    __device__ static constexpr double lw(int s_pos, int p_pos)
+    {
+        return 1.0 + ((s_pos == p_pos) ? kG : -kG);
+    }
+    __device__ static constexpr double lw8(int s_pos, int p_pos) { return 0.125 * lw(s_pos, p_pos); }
     // index of the edge of direction J that node a ends
     __device__ static constexpr int edge_of(int J, int a)
     {
-        const int o1 = J == 0 ? 1 : 0, o2 = J == 2 ? 1 : 2;
-        return (kHexS[a][o1] > 0 ? 1 : 0) + (kHexS[a][o2] > 0 ? 2 : 0);
+        return (kHexS[a][oth1(J)] > 0 ? 1 : 0) + (kHexS[a][oth2(J)] > 0 ? 2 : 0);
     }
+    // The 12 distinct gradient columns of a field: c[J][k] = d f / d xi_J at
+    // the points whose other two coordinates have signs k (4 combinations),
+    // from the 4 edge differences of direction J by one interpolation along
+    // each of the two other directions.
     template <class T> struct Field {
-        T d[3][4][3];   // [direction][edge][component]
+        T c[3][4][3];   // [direction][column][component]
     };
     template <class T>
     __device__ static __forceinline__ void prep(const T f[NEN][3], Field<T> &F)
@@ -366,10 +381,23 @@ struct Hex8 {
 #pragma unroll
         for (int J = 0; J < 3; ++J)
 #pragma unroll
-            for (int e = 0; e < 4; ++e)
+            for (int i = 0; i < 3; ++i) {
+                T d[4];
 #pragma unroll
-                for (int i = 0; i < 3; ++i)
-                    F.d[J][e][i] = f[kHexEdge[J][e][1]][i] - f[kHexEdge[J][e][0]][i];
+                for (int e = 0; e < 4; ++e) d[e] = f[kHexEdge[J][e][1]][i] - f[kHexEdge[J][e][0]][i];
+                // along the first other direction: A[p1][lev], lev = edge sign in the second
+                T A[2][2];
+#pragma unroll
+                for (int p1 = 0; p1 < 2; ++p1)
+#pragma unroll
+                    for (int lev = 0; lev < 2; ++lev)
+                        A[p1][lev] = fma(T(lw(1, p1)), d[1 + 2 * lev], T(lw(0, p1)) * d[2 * lev]);
+#pragma unroll
+                for (int p1 = 0; p1 < 2; ++p1)
+#pragma unroll
+                    for (int p2 = 0; p2 < 2; ++p2)
+                        F.c[J][p1 + 2 * p2][i] = fma(T(lw8(1, p2)), A[p1][1], T(lw8(0, p2)) * A[p1][0]);
+            }
     }
     template <class T>
     __device__ static __forceinline__ void grad(const Field<T> &F, int q, T G[9])
@@ -377,39 +405,53 @@ struct Hex8 {
 #pragma unroll
         for (int i = 0; i < 3; ++i)
 #pragma unroll
-            for (int J = 0; J < 3; ++J) {
-                T t = T(ew(J, 0, q)) * F.d[J][0][i];
-#pragma unroll
-                for (int e = 1; e < 4; ++e) t = fma(T(ew(J, e, q)), F.d[J][e][i], t);
-                G[i * 3 + J] = t;
-            }
+            for (int J = 0; J < 3; ++J) G[i * 3 + J] = F.c[J][col(J, q)][i];
     }
+    // forces: the transposed route, columns -> edges -> nodes
     template <class T> struct Acc {
-        T d[3][4][3];   // edge forces: +d to e+, -d to e-
+        T c[3][4][3];
     };
     template <class T> __device__ static __forceinline__ void zero(Acc<T> &A)
     {
 #pragma unroll
         for (int J = 0; J < 3; ++J)
 #pragma unroll
-            for (int e = 0; e < 4; ++e) A.d[J][e][0] = A.d[J][e][1] = A.d[J][e][2] = T(0);
+            for (int k = 0; k < 4; ++k) A.c[J][k][0] = A.c[J][k][1] = A.c[J][k][2] = T(0);
     }
-    template <bool FIRST, class T>
+    // INIT: points arrive in ascending order from an uninitialised accumulator,
+    // so a column is assigned at its first point (coordinate J negative)
+    template <bool INIT, class T>
     __device__ static __forceinline__ void add_forces(const T Q[9], int q, Acc<T> &A)
     {
 #pragma unroll
         for (int J = 0; J < 3; ++J)
 #pragma unroll
-            for (int e = 0; e < 4; ++e)
-#pragma unroll
-                for (int i = 0; i < 3; ++i) {
-                    if (FIRST) A.d[J][e][i] = T(ew(J, e, q)) * Q[i * 3 + J];
-                    else A.d[J][e][i] = fma(T(ew(J, e, q)), Q[i * 3 + J], A.d[J][e][i]);
-                }
+            for (int i = 0; i < 3; ++i) {
+                T &a = A.c[J][col(J, q)][i];
+                if (INIT && !((q >> J) & 1)) a = Q[i * 3 + J];
+                else a += Q[i * 3 + J];
+            }
     }
     template <class T>
     __device__ static __forceinline__ void finish(const Acc<T> &A, T out[NEN][3])
     {
+        T E[3][4][3];   // edge forces: +E to the edge's + end, -E to its - end
+#pragma unroll
+        for (int J = 0; J < 3; ++J)
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                T B[2][2];   // [p1][lev]
+#pragma unroll
+                for (int p1 = 0; p1 < 2; ++p1)
+#pragma unroll
+                    for (int lev = 0; lev < 2; ++lev)
+                        B[p1][lev] = fma(T(lw8(lev, 1)), A.c[J][p1 + 2][i], T(lw8(lev, 0)) * A.c[J][p1][i]);
+#pragma unroll
+                for (int s1 = 0; s1 < 2; ++s1)
+#pragma unroll
+                    for (int lev = 0; lev < 2; ++lev)
+                        E[J][s1 + 2 * lev][i] = fma(T(lw(s1, 1)), B[1][lev], T(lw(s1, 0)) * B[0][lev]);
+            }
         // every node ends exactly one edge of each direction: its + end where
         // its sign in that direction is +, else its - end
 #pragma unroll
@@ -417,9 +459,9 @@ struct Hex8 {
 #pragma unroll
             for (int i = 0; i < 3; ++i) {
                 const int e0 = edge_of(0, a), e1 = edge_of(1, a), e2 = edge_of(2, a);
-                const T t0 = kHexS[a][0] > 0 ? A.d[0][e0][i] : -A.d[0][e0][i];
-                const T t1 = kHexS[a][1] > 0 ? t0 + A.d[1][e1][i] : t0 - A.d[1][e1][i];
-                out[a][i] = kHexS[a][2] > 0 ? t1 + A.d[2][e2][i] : t1 - A.d[2][e2][i];
+                const T t0 = kHexS[a][0] > 0 ? E[0][e0][i] : -E[0][e0][i];
+                const T t1 = kHexS[a][1] > 0 ? t0 + E[1][e1][i] : t0 - E[1][e1][i];
+                out[a][i] = kHexS[a][2] > 0 ? t1 + E[2][e2][i] : t1 - E[2][e2][i];
             }
     }
     template <class T> __device__ static __forceinline__ T dN(int q, int a, int J)
@@ -664,8 +706,7 @@ template <> struct HvpOp<double> {
             G::grad(Fx, q, Jd);
             G::grad(Fv, q, dJ);
             ok &= qp_hvp(E::template weight<double>(), Jx, Jd, dJ, mu[E::sub(q)], lam[E::sub(q)], Q);
-            if (q == 0) G::template add_forces_to<true>(Q, q, f);
-            else G::template add_forces_to<false>(Q, q, f);
+            G::template add_forces_to<true>(Q, q, f);
         }
         return ok;
     }
@@ -718,8 +759,7 @@ template <> struct HvpOp<float> {
             for (int k = 0; k < 9; ++k) Jd[k] += Jx[k];
             E::grad(Fv, q, dJ);
             ok &= qp_hvp(E::template weight<float>(), Jx, Jd, dJ, mu[E::sub(q)], lam[E::sub(q)], Q);
-            if (q == 0) E::template add_forces<true>(Q, q, A);
-            else E::template add_forces<false>(Q, q, A);
+            E::template add_forces<true>(Q, q, A);
         }
         E::finish(A, f);
         return ok;
@@ -774,8 +814,7 @@ struct ResidualOp : XUStage {
 #pragma unroll
             for (int k = 0; k < 9; ++k) Jd[k] += Jx[k];
             ok &= qp_residual(E::template weight<double>(), Jx, Jd, mu[E::sub(q)], lam[E::sub(q)], Q);
-            if (q == 0) E::template add_forces<true>(Q, q, A);
-            else E::template add_forces<false>(Q, q, A);
+            E::template add_forces<true>(Q, q, A);
         }
         E::finish(A, f);
         return ok;
@@ -1041,17 +1080,17 @@ k_accumulate(BlockMesh m, Op op, T *__restrict__ y,
     write_out<ACC>(m, bnode, nn, acc, y, mode, use_mask != 0, fixed_val);
 }
 
-// Set y = 0 (or the prescribed value) on nodes shared between blocks, before
-// an atomic pass adds into them.
+// y = 0, prescribed components = fixed_val, before an atomic pass adds into
+// the nodes that several blocks share (the block-private ones it overwrites).
+// A contiguous fill of the whole vector: cheaper than an indexed one over the
+// shared nodes alone.
 template <class T>
-__global__ void k_zero_shared(const int32_t *__restrict__ nodes, int64_t n, T *__restrict__ y,
-                              const uint8_t *__restrict__ nmask, T fixed_val)
+__global__ void __launch_bounds__(256) k_fill_nodal(int64_t n, T *__restrict__ y,
+                                                    const uint8_t *__restrict__ nmask, T fixed_val)
 {
-    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const int64_t g = nodes[i];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) y[3 * g + c] = comp_fixed(nmask, g, c) ? fixed_val : T(0);
+    const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;   // DOF index
+    if (j >= n) return;
+    y[j] = (nmask && ((nmask[j / 3] >> (j % 3)) & 1)) ? fixed_val : T(0);
 }
 
 // ------------------------------------------------------------------- energy
@@ -1303,10 +1342,9 @@ static hipError_t run_accumulate(const Ctx &c, const Op &op, T *y, bool use_mask
         return hipGetLastError();
     }
     if (mode == WriteMode::Overwrite && c.scatter == Scatter::Atomic && c.n_shared > 0) {
-        const int64_t n = c.n_shared;
-        hipLaunchKernelGGL((k_zero_shared<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
-                           c.stream, c.shared_nodes, n, y, use_mask ? c.m.nmask : nullptr,
-                           fixed_val);
+        const int64_t n = 3 * c.n_nodes;
+        hipLaunchKernelGGL((k_fill_nodal<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
+                           c.stream, n, y, use_mask ? c.m.nmask : nullptr, fixed_val);
     }
     for (const Pass &p : c.passes) {
         if (p.count == 0) continue;

@@ -245,6 +245,41 @@ class Operator:
         return rc, stats
 
 
+    # ------------------------------------------------------ sparse tangent
+    def sparse_setup(self):
+        """Pattern and distance-2 colouring of K (Alg. 2); returns the info dict."""
+        self._sync_stream()
+        i = L.SparseInfo()
+        L.check(self._lib.efem_sparse_setup(self._h, ctypes.byref(i)), "efem_sparse_setup")
+        self._sparse = {k: getattr(i, k) for k, _ in L.SparseInfo._fields_}
+        return dict(self._sparse)
+
+    def sparse_pattern(self):
+        """(row_ptr int64 [n_rows+1], col int32 [nnz], dof_colour int32 [n_rows])."""
+        info = self._sparse if getattr(self, "_sparse", None) else self.sparse_setup()
+        rp = torch.empty(info["n_rows"] + 1, dtype=torch.int64, device=self.device)
+        col = torch.empty(info["nnz"], dtype=torch.int32, device=self.device)
+        dc = torch.empty(info["n_rows"], dtype=torch.int32, device=self.device)
+        L.check(self._lib.efem_sparse_pattern(self._h, _ptr(rp), _ptr(col), _ptr(dc)), "efem_sparse_pattern")
+        return rp, col, dc
+
+    def sparse_assemble(self, u, values=None):
+        """K(u) values (float64 [nnz], pattern order) from n_colours tangent actions."""
+        info = self._sparse if getattr(self, "_sparse", None) else self.sparse_setup()
+        if values is None:
+            values = torch.empty(info["nnz"], dtype=torch.float64, device=self.device)
+        L.check(self._lib.efem_sparse_assemble(self._h, _ptr(self._nodal(u, name="u")), _ptr(values)),
+                "efem_sparse_assemble")
+        self._lin = torch.float64
+        return values
+
+    def sparse_spmv(self, values, x, out=None):
+        self._sync_stream()
+        out = self._new_nodal() if out is None else self._nodal(out, name="out")
+        L.check(self._lib.efem_sparse_spmv(self._h, _ptr(values), _ptr(self._nodal(x, name="x")), _ptr(out)),
+                "efem_sparse_spmv")
+        return out
+
     def linear_solve(self, u, b, rtol=1e-8, hvp_prec="f64", precond=0, max_iter=100000):
         """Solve K(u)_ff x = b by preconditioned CG (Jacobi, or the learned
         preconditioner with flexible CG); returns (x, iterations, fell_back)."""
