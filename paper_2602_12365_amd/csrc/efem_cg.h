@@ -1,5 +1,5 @@
 // Declarations of the Krylov-solve kernels (kernels_cg.hip) used by the host
-// Newton driver (newton.cpp).
+// Newton solver (newton.cpp).
 #pragma once
 
 #include <algorithm>

@@ -1085,12 +1085,14 @@ k_accumulate(BlockMesh m, Op op, T *__restrict__ y,
 // A contiguous fill of the whole vector: cheaper than an indexed one over the
 // shared nodes alone.
 template <class T>
-__global__ void __launch_bounds__(256) k_fill_nodal(int64_t n, T *__restrict__ y,
+__global__ void __launch_bounds__(256) k_fill_nodal(int64_t n_nodes, T *__restrict__ y,
                                                     const uint8_t *__restrict__ nmask, T fixed_val)
 {
-    const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;   // DOF index
-    if (j >= n) return;
-    y[j] = (nmask && ((nmask[j / 3] >> (j % 3)) & 1)) ? fixed_val : T(0);
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;   // node
+    if (i >= n_nodes) return;
+    const uint8_t b = nmask ? nmask[i] : 0;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) y[3 * i + c] = ((b >> c) & 1) ? fixed_val : T(0);
 }
 
 // ------------------------------------------------------------------- energy
@@ -1342,7 +1344,7 @@ static hipError_t run_accumulate(const Ctx &c, const Op &op, T *y, bool use_mask
         return hipGetLastError();
     }
     if (mode == WriteMode::Overwrite && c.scatter == Scatter::Atomic && c.n_shared > 0) {
-        const int64_t n = 3 * c.n_nodes;
+        const int64_t n = c.n_nodes;
         hipLaunchKernelGGL((k_fill_nodal<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
                            c.stream, n, y, use_mask ? c.m.nmask : nullptr, fixed_val);
     }

@@ -1,4 +1,4 @@
-// Matrix-free Newton-Krylov driver: a host loop over the element kernels
+// Matrix-free Newton-Krylov solver: a host loop over the element kernels
 // (energy, residual, Jacobi diagonal, tangent action) and the streaming CG
 // kernels.  The paper names the method (Sec. 6.3.1) but none of its parts; the
 // reading implemented here:

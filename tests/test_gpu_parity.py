@@ -263,3 +263,17 @@ def test_full_size_64cube_tets():
         op.linearize(dev(u), "f32")
         assert rel(host(op.hvp(dev(v, torch.float32))), ref) <= TOL32
         op.close()
+
+
+def test_zero_state(case):
+    """u = 0: the energy is exactly zero (psi(I) = 0 term by term), the residual
+    vanishes to rounding, and the tangent action is the small-strain
+    stiffness action (the oracle's tangent at u = 0)."""
+    m = case.mesh
+    z = np.zeros((m.n_nodes, 3))
+    assert host(case.op.energy(dev(z))) == 0.0
+    r = host(case.op.residual(dev(z)))
+    scale = np.abs(case.orc.residual(case.u)).max()
+    assert np.abs(r).max() <= 1e-13 * scale
+    case.op.linearize(dev(z), "f64")
+    assert rel(host(case.op.hvp(dev(case.v))), case.orc.hvp(z, case.v)) <= TOL64
