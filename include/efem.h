@@ -2,8 +2,9 @@
  * efem.h -- C-ABI of the energy-based finite-element hot path for AMD MI355X
  * (gfx950): the global potential energy of a mesh, its gradient (the nodal
  * residual) and matrix-free tangent actions (Hessian-vector products), their
- * adjoints with respect to material fields and nodal coordinates, and a
- * matrix-free Newton-Krylov solve built on them.
+ * adjoints with respect to material fields and nodal coordinates, a
+ * matrix-free Newton-Krylov solve built on them, the sparse tangent matrix by
+ * colouring, and a learned CG preconditioner.
  *
  * The calls follow the paper's statement of the problem (arXiv 2602.12365):
  *   - an operator object built from a mesh, an element type and a batch
@@ -12,7 +13,8 @@
  *   - the residual r = grad Psi_h, Eq. (1);
  *   - the tangent action dr = K du, Eq. (3);
  *   - Dirichlet conditions as a reduced functional over the free DOFs, Sec. 6.1;
- *   - a matrix-free Newton-Krylov solve, Sec. 6.3.1.
+ *   - a matrix-free Newton-Krylov solve, Sec. 6.3.1;
+ *   - the sparse tangent recovered from tangent actions by colouring, Alg. 2.
  *
  * Element types: 4-node tetrahedra with the one-point centroid rule, 8-node
  * trilinear hexahedra with the 2x2x2 Gauss rule.  Material: compressible
