@@ -7,9 +7,10 @@ neo-Hookean mu = 1, lam = 1.5, linearization point u = 0.00125 N(0,1) (seed 0),
 linearization plus 100 FP64 tangent actions y = K(u) v (efem_hvp).  `value` is
 DOF/s of the tangent action over the timed steps.
 
-Beside it: the FP32 tangent action, the colour scatter, energy and residual
-times, a roofline object for the dominant kernel (the single-launch FP64
-tangent-action block pass, timed with HIP events on its stream), the Newton
+Beside it: the FP32 tangent action, the colour and atomic scatters, energy
+and residual times, a roofline object for the dominant kernel (the FP64
+tangent action's block pass with its halo gather, timed with HIP events on
+its stream), the Newton
 solves of the metric's second half (plain FP64 Jacobi-CG vs FP32 tangent
 actions with and without the learned preconditioner, on the 128^3 Q1-hex
 compression case and on the unseen 96^3 test mesh of the preconditioner,
@@ -75,9 +76,9 @@ def kernel_source_hash():
 
 
 def measured_traffic():
-    """HBM bytes per launch of the FP64 tangent-action block pass from the
-    committed rocprofv3 counter summary, or None if it is missing or was taken
-    on different kernel sources."""
+    """HBM bytes of one FP64 tangent action (block pass + halo gather) from
+    the committed rocprofv3 counter summary, or None if it is missing or was
+    taken on different kernel sources."""
     try:
         with open(COUNTERS_MD) as f:
             lines = f.read().splitlines()
@@ -190,7 +191,8 @@ def compression_solves(dev, n, seed, theta):
 
 def kernels_mode(args, dev):
     """Fixed kernel workload for rocprofv3 (no timing logic): the FP64 and FP32
-    tangent-action block pass on the 64^3 Kuhn mesh, energy, residual, and a
+    tangent actions (block pass + halo gather) on the 64^3 Kuhn mesh, energy,
+    residual, and a
     plain 256 MiB device copy of known size that calibrates the HBM counters."""
     import torch
     from paper_2602_12365_amd import Operator, inputs as I
@@ -279,9 +281,9 @@ def main():
     value = N_DIRS * ndof / t_step / 1e9
     log(f"f64 step {t_step*1e3:.3f} ms -> {value:.2f} GDoF/s")
 
-    # dominant kernel alone: the single-launch block pass (efem_hvp_zeroed, the
-    # form the Krylov loop uses); y is not re-cleared between timing calls, which
-    # changes its values but not the work
+    # dominant kernel: the block pass and its halo gather (efem_hvp_zeroed, the
+    # form the Krylov loop uses); y is not re-cleared between timing calls,
+    # which changes its values but not the work
     op.linearize(u, "f64")
     Y.zero_()
     reps = N_DIRS * max(args.steps // 4, 2)
@@ -292,7 +294,7 @@ def main():
     alg_flops = mesh.n_elems * FLOPS_PER_TET_HVP
     achieved = alg_hvp / t_acc / 1e9
     achieved_tf = alg_flops / t_acc / 1e12
-    log(f"hvp block-pass kernel {t_acc*1e6:.2f} us -> {achieved:.0f} GB/s, {achieved_tf:.2f} TFLOP/s")
+    log(f"hvp block pass + gather {t_acc*1e6:.2f} us -> {achieved:.0f} GB/s, {achieved_tf:.2f} TFLOP/s")
 
     # FP32 tangent action
     op.linearize(u, "f32")
@@ -310,13 +312,16 @@ def main():
     psi = torch.empty((), dtype=torch.float64, device=dev)
     t_en = event_time(lambda: op.energy(u, out=psi), 50, stream)
 
-    # colour scatter
-    opc = Operator(I.TET4, mesh.X, mesh.conn, scatter="color", device=dev)
-    opc.linearize(u, "f64")
-    opc.hvp(V[0], out=Y)
-    t_col = event_time(lambda: opc.hvp(V[0], out=Y), 200, stream)
-    n_col = opc.info()["n_colours"]
-    opc.close()
+    # the other two ways of summing over nodes shared between blocks
+    t_scatter, n_col = {}, 0
+    for mode in ("color", "atomic"):
+        opc = Operator(I.TET4, mesh.X, mesh.conn, scatter=mode, device=dev)
+        opc.linearize(u, "f64")
+        opc.hvp(V[0], out=Y)
+        t_scatter[mode] = event_time(lambda: opc.hvp(V[0], out=Y), 200, stream)
+        if mode == "color":
+            n_col = opc.info()["n_colours"]
+        opc.close()
 
     # sparse tangent by colouring (Alg. 2): K(u) from n_colours tangent
     # actions, then CSR products against the matrix-free one
@@ -353,7 +358,7 @@ def main():
             "workload": f"unit cube {n}^3 hexes x 6 Kuhn tets: {mesh.n_elems} Tet4, "
                         f"{mesh.n_nodes} nodes, {ndof} DOF; neo-Hookean mu=1 lam=1.5; "
                         f"u=0.00125*N(0,1); step = linearize + {N_DIRS} FP64 HVPs",
-            "scatter": "atomic",
+            "scatter": "halo",
             "blocks": info["n_blocks"],
         },
         # the FP64 roofline of the formulation (alg_flops / 78.6 TFLOP/s) is the
@@ -366,7 +371,8 @@ def main():
             "unit": "TFLOP/s",
             "frac": round(achieved_tf / FP64_PEAK_TFLOPS, 4),
             "traffic": measured_traffic(),
-            "kernel": "k_accumulate<Tet4Pair, HvpOp<double>, double, false> (efem_hvp_zeroed)",
+            "kernel": "k_accumulate<Tet4Pair, HvpOp<double>, double, false> + "
+                      "k_halo_gather<double, false> (efem_hvp_zeroed)",
             "kernel_us": round(t_acc * 1e6, 3),
             "alg_flops": alg_flops,
             "alg_bytes": alg_hvp,
@@ -378,8 +384,9 @@ def main():
         "hvp_f32_us": round(t32 * 1e6, 3),
         "hvp_f32_gdofs": round(ndof / t32 / 1e9, 3),
         "hvp_f32_pct_hbm": round(100 * alg32 / t32 / 1e9 / HBM_PEAK_GBS, 2),
-        "hvp_f64_color_us": round(t_col * 1e6, 3),
+        "hvp_f64_color_us": round(t_scatter["color"] * 1e6, 3),
         "color_passes": n_col,
+        "hvp_f64_atomic_us": round(t_scatter["atomic"] * 1e6, 3),
         "residual_us": round(t_res * 1e6, 3),
         "energy_us": round(t_en * 1e6, 3),
         "setup_s": round(setup_s, 3),

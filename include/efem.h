@@ -65,13 +65,16 @@ extern "C" {
 #define EFEM_F64 0
 #define EFEM_F32 1
 
-/* how element contributions are summed into nodal vectors */
-#define EFEM_SCATTER_ATOMIC 0   /* block-aggregated in LDS, then global atomics on
-                                   nodes shared between blocks */
+/* how element contributions are summed into nodal vectors (within a block
+ * always in LDS, with LDS atomics, so results vary in the last bits) */
+#define EFEM_SCATTER_HALO   0   /* default: block sums of nodes shared between
+                                   blocks are stored per (block, node) and a
+                                   second kernel adds each node's entries in block
+                                   order; no global atomics */
 #define EFEM_SCATTER_COLOR  1   /* blocks coloured so that no two blocks of one
-                                   colour share a node; one pass per colour, no
-                                   global atomics (sums within a block still use
-                                   LDS atomics, so results vary in the last bits) */
+                                   colour share a node; one pass per colour */
+#define EFEM_SCATTER_ATOMIC 2   /* global atomic adds on shared nodes (after a
+                                   clearing fill of the output) */
 
 typedef struct efem_ctx efem_ctx;
 
@@ -80,7 +83,7 @@ typedef struct {
                               size N_B, Alg. 1); 0 = default for the element type */
     int32_t block_nodes;   /* max distinct nodes per block (<= 600, so that one block
                               fits 64 KB of LDS); 0 = default */
-    int32_t scatter;       /* EFEM_SCATTER_ATOMIC or EFEM_SCATTER_COLOR */
+    int32_t scatter;       /* EFEM_SCATTER_HALO (0, default), _COLOR or _ATOMIC */
     int32_t threads;       /* threads per workgroup (64..256, multiple of 64); 0 = default */
     int32_t no_pairs;      /* EFEM_TET4: nonzero = one tetrahedron per work item; by
                               default two tetrahedra that share a face form one item

@@ -21,7 +21,7 @@ EFEM_ERR_STATE = -5
 
 EFEM_TET4, EFEM_HEX8 = 0, 1
 EFEM_F64, EFEM_F32 = 0, 1
-EFEM_SCATTER_ATOMIC, EFEM_SCATTER_COLOR = 0, 1
+EFEM_SCATTER_HALO, EFEM_SCATTER_COLOR, EFEM_SCATTER_ATOMIC = 0, 1, 2
 
 EFEM_MLP_IN, EFEM_MLP_HID, EFEM_MLP_OUT = 12, 64, 3
 EFEM_MLP_PARAMS, EFEM_MLP_AUX = 5187, 12

@@ -432,13 +432,13 @@ int efem_create(efem_ctx **out, int32_t elem, int64_t n_nodes, int64_t n_elems,
     // nodes, or 256 hexes within 512 nodes, per block
     int be = elem == EFEM_TET4 ? 1536 : 256;
     int bn = elem == EFEM_TET4 ? 600 : 512;
-    int scatter = EFEM_SCATTER_ATOMIC;
+    int scatter = EFEM_SCATTER_HALO;
     int threads = 256;
     if (opts) {
         if (opts->block_elems > 0) be = opts->block_elems;
         if (opts->block_nodes > 0) bn = opts->block_nodes;
-        if (opts->scatter == EFEM_SCATTER_COLOR) scatter = EFEM_SCATTER_COLOR;
-        else if (opts->scatter != EFEM_SCATTER_ATOMIC) {
+        scatter = opts->scatter;
+        if (scatter != EFEM_SCATTER_HALO && scatter != EFEM_SCATTER_COLOR && scatter != EFEM_SCATTER_ATOMIC) {
             set_error("efem_create: unknown scatter mode");
             return EFEM_ERR_INVALID;
         }
@@ -457,7 +457,9 @@ int efem_create(efem_ctx **out, int32_t elem, int64_t n_nodes, int64_t n_elems,
     ctx->n_nodes = n_nodes;
     ctx->n_elems = n_elems;
     ctx->stream = (hipStream_t)stream;
-    ctx->scatter = scatter == EFEM_SCATTER_COLOR ? Scatter::Color : Scatter::Atomic;
+    ctx->scatter = scatter == EFEM_SCATTER_COLOR ? Scatter::Color
+                   : scatter == EFEM_SCATTER_ATOMIC ? Scatter::Atomic
+                                                    : Scatter::Halo;
     ctx->threads = threads;
     (void)hipGetDevice(&ctx->device);
 
@@ -496,6 +498,31 @@ int efem_create(efem_ctx **out, int32_t elem, int64_t n_nodes, int64_t n_elems,
     m.X = p_X;
     m.Xf = p_Xf;
     ctx->n_shared = (int64_t)hb.shared_nodes.size();
+    m.halo = nullptr;
+    m.hslot = nullptr;
+    if (ctx->scatter == Scatter::Halo && ctx->n_shared > 0) {
+        // each shared node's block-node entries, in block order
+        const int32_t ns = (int32_t)ctx->n_shared;
+        std::vector<int32_t> slot((size_t)n_nodes, -1);
+        for (int32_t s = 0; s < ns; ++s) slot[(size_t)hb.shared_nodes[(size_t)s]] = s;
+        std::vector<int32_t> hptr((size_t)ns + 1, 0);
+        for (uint32_t ent : hb.bnode)
+            if (ent & kShared) hptr[(size_t)slot[ent & kGidMask] + 1] += 1;
+        for (int32_t s = 0; s < ns; ++s) hptr[(size_t)s + 1] += hptr[(size_t)s];
+        // entry i of a shared node gets the next halo slot of that node, so a
+        // node's slots are consecutive and in block order
+        std::vector<int32_t> hslot(hb.bnode.size(), -1), fill(hptr.begin(), hptr.end() - 1);
+        for (size_t i = 0; i < hb.bnode.size(); ++i)
+            if (hb.bnode[i] & kShared) hslot[i] = fill[(size_t)slot[hb.bnode[i] & kGidMask]]++;
+        double *p_h;
+        int32_t *p_hs;
+        if ((rc = upload(*ctx, &ctx->halo_ptr, hptr)) || (rc = upload(*ctx, &p_hs, hslot))
+            || (rc = upload(*ctx, &ctx->halo_node, hb.shared_nodes))
+            || (rc = dalloc(*ctx, &p_h, 3 * (size_t)hptr[(size_t)ns])))
+            return fail(rc);
+        m.halo = p_h;
+        m.hslot = p_hs;
+    }
 
     // default material mu = 1, lam = 1.5
     std::vector<double> ones((size_t)n_elems, 1.0), lam15((size_t)n_elems, 1.5);

@@ -37,9 +37,18 @@ struct BlockMesh {
     double mu0, lam0;
     const uint8_t *nmask;     // [n_nodes] bit c = component c prescribed, or null
     int32_t *flags;           // bit 0: det F <= 0 met
+    // halo scatter: block-node entry i of a shared node stores its block sum
+    // at halo[3 * hslot[i] + c]; the entries of one node are consecutive
+    double *halo;             // [3 * number of shared entries]
+    const int32_t *hslot;     // [n_block_nodes]
 };
 
-enum class Scatter { Atomic = 0, Color = 1 };
+// How block sums reach nodes shared between blocks:
+//   Halo:   plain stores into a per-entry buffer, then a gather kernel sums each
+//           shared node's entries in block order (no device atomics);
+//   Color:  one pass per block colour, read-modify-write;
+//   Atomic: device-scope atomic adds.
+enum class Scatter { Halo = 0, Color = 1, Atomic = 2 };
 
 // One launch over a set of blocks: all blocks (list == null) or one colour.
 struct Pass {
@@ -54,10 +63,12 @@ struct Ctx;
 hipError_t launch_energy(const Ctx &c, const double *u, double *psi);
 hipError_t launch_residual(const Ctx &c, const double *u, double *r);
 // How a nodal output is written:
-//   Overwrite:  y = K v (a fill pre-pass clears y, prescribed components to
-//               their value, before the block pass adds into shared nodes);
-//   Accumulate: y += K v, one launch (plain read-modify-write on block-private nodes);
-//   Zeroed:     y = K v for a y that holds zeros on entry, one launch.
+//   Overwrite:  y = K v (halo scatter: block pass, then the gather of shared
+//               nodes; atomic scatter: a fill pre-pass clears y, prescribed
+//               components to their value, before the block pass adds into
+//               shared nodes);
+//   Accumulate: y += K v (plain read-modify-write on block-private nodes);
+//   Zeroed:     y = K v for a y that holds zeros on entry (no fill pre-pass).
 enum class WriteMode { Overwrite = 0, Accumulate = 1, Zeroed = 2 };
 hipError_t launch_hvp_f64(const Ctx &c, const double *xlin, const double *v, double *y,
                           const int32_t *skip, WriteMode mode);
@@ -84,7 +95,7 @@ struct Ctx {
     int64_t n_nodes = 0, n_elems = 0, n_items = 0;
     int device = 0;
     hipStream_t stream = nullptr;
-    Scatter scatter = Scatter::Atomic;
+    Scatter scatter = Scatter::Halo;
     int threads = 256;
     int max_block_nodes = 0;        // max nodes over blocks (LDS sizing)
     int max_block_elems = 0;
@@ -93,6 +104,9 @@ struct Ctx {
     BlockMesh m{};
     std::vector<void *> owned;      // every hipMalloc of the context
     int64_t n_shared = 0;               // nodes touched by several blocks
+    // halo scatter: shared node i = halo_node[i] sums the halo entries
+    // halo_ptr[i] .. halo_ptr[i+1]-1 (its blocks in block order)
+    int32_t *halo_ptr = nullptr, *halo_node = nullptr;
     std::vector<Pass> passes;           // colour lists (Color) or one pass (Atomic)
     double *partials = nullptr;         // [n_blocks] per-block energy partials
     uint32_t *counter = nullptr;        // last-block-done ticket

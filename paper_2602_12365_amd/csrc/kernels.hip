@@ -621,15 +621,26 @@ __device__ __forceinline__ bool comp_fixed(const uint8_t *nmask, int64_t g, int 
     return nmask && ((nmask[g] >> c) & 1);
 }
 
-// Write the block's nodal sums acc[l*3+c] out; prescribed components get `fixed_val`.
+// Write the block's nodal sums acc[l*3+c] out; prescribed components get
+// `fixed_val`.  Under the halo scatter a node shared with other blocks is not
+// written here: its sum goes to its halo slot (hslot[l]), and k_halo_gather
+// adds each node's slots up afterwards.
 template <bool ACC, class T>
 __device__ __forceinline__ void write_out(const BlockMesh &m, const uint32_t *bnode, int nn,
                                           const double *acc, T *__restrict__ y, Scatter mode,
-                                          bool use_mask, T fixed_val)
+                                          bool use_mask, T fixed_val, T *__restrict__ halo,
+                                          const int32_t *__restrict__ hslot)
 {
     for (int l = threadIdx.x; l < nn; l += blockDim.x) {
         const uint32_t ent = bnode[l];
         const int64_t g = ent & kGidMask;
+        if ((ent & kShared) && mode == Scatter::Halo) {
+            T *h = halo + 3 * (int64_t)hslot[l];
+            h[0] = T(acc[l * 3 + 0]);
+            h[1] = T(acc[l * 3 + 1]);
+            h[2] = T(acc[l * 3 + 2]);
+            continue;
+        }
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             const bool fixed = use_mask && comp_fixed(m.nmask, g, c);
@@ -1077,7 +1088,40 @@ k_accumulate(BlockMesh m, Op op, T *__restrict__ y,
     }
     if (bad) flag_inverted(m.flags);
     __syncthreads();
-    write_out<ACC>(m, bnode, nn, acc, y, mode, use_mask != 0, fixed_val);
+    write_out<ACC>(m, bnode, nn, acc, y, mode, use_mask != 0, fixed_val,
+                   reinterpret_cast<T *>(m.halo), m.hslot ? m.hslot + n0 : nullptr);
+}
+
+// Second half of the halo scatter: shared node i = node[i] sums its slots
+// halo[ptr[i] .. ptr[i+1]-1] (its blocks in block order; in FP64, so the
+// result does not depend on the schedule), then y = sum (ACC: y += sum);
+// prescribed components get fixed_val.  Consecutive nodes own consecutive
+// slots, so the reads stream.
+template <class T, bool ACC>
+__global__ void __launch_bounds__(256) k_halo_gather(int32_t n, const int32_t *__restrict__ ptr,
+                                                     const int32_t *__restrict__ node,
+                                                     const T *__restrict__ halo, T *__restrict__ y,
+                                                     const uint8_t *__restrict__ nmask, T fixed_val,
+                                                     const int32_t *__restrict__ skip)
+{
+    if (skip && *skip) return;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int64_t g = node[i];
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+    for (int64_t k = ptr[i], ke = ptr[i + 1]; k < ke; ++k) {
+        s0 += (double)halo[3 * k + 0];
+        s1 += (double)halo[3 * k + 1];
+        s2 += (double)halo[3 * k + 2];
+    }
+    const uint8_t b = nmask ? nmask[g] : 0;
+    const double s[3] = {s0, s1, s2};
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        T *dst = &y[3 * g + c];
+        if ((b >> c) & 1) *dst = fixed_val;
+        else *dst = ACC ? *dst + T(s[c]) : T(s[c]);
+    }
 }
 
 // y = 0, prescribed components = fixed_val, before an atomic pass adds into
@@ -1334,6 +1378,9 @@ static hipError_t run_accumulate(const Ctx &c, const Op &op, T *y, bool use_mask
                                  const int32_t *skip, WriteMode mode)
 {
     const size_t lds = lds_bytes<Op>(c, sizeof(double));
+    const bool halo = c.scatter == Scatter::Halo && c.n_shared > 0;
+    const unsigned gather_blocks = (unsigned)((c.n_shared + 255) / 256);
+    const uint8_t *gmask = use_mask ? c.m.nmask : nullptr;
     if (mode == WriteMode::Accumulate) {
         for (const Pass &p : c.passes) {
             if (p.count == 0) continue;
@@ -1341,6 +1388,10 @@ static hipError_t run_accumulate(const Ctx &c, const Op &op, T *y, bool use_mask
                                c.stream, c.m, op, y, p.list, p.count, c.scatter, use_mask ? 1 : 0,
                                fixed_val, skip);
         }
+        if (halo)
+            hipLaunchKernelGGL((k_halo_gather<T, true>), dim3(gather_blocks), dim3(256), 0, c.stream,
+                               (int32_t)c.n_shared, c.halo_ptr, c.halo_node,
+                               reinterpret_cast<const T *>(c.m.halo), y, gmask, fixed_val, skip);
         return hipGetLastError();
     }
     if (mode == WriteMode::Overwrite && c.scatter == Scatter::Atomic && c.n_shared > 0) {
@@ -1354,6 +1405,10 @@ static hipError_t run_accumulate(const Ctx &c, const Op &op, T *y, bool use_mask
                            c.m, op, y, p.list, p.count, c.scatter, use_mask ? 1 : 0, fixed_val,
                            skip);
     }
+    if (halo)
+        hipLaunchKernelGGL((k_halo_gather<T, false>), dim3(gather_blocks), dim3(256), 0, c.stream,
+                           (int32_t)c.n_shared, c.halo_ptr, c.halo_node,
+                           reinterpret_cast<const T *>(c.m.halo), y, gmask, fixed_val, skip);
     return hipGetLastError();
 }
 

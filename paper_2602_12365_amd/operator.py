@@ -17,7 +17,7 @@ from . import _lib as L
 
 _ELEM = {"tet4": L.EFEM_TET4, "hex8": L.EFEM_HEX8, L.EFEM_TET4: L.EFEM_TET4, L.EFEM_HEX8: L.EFEM_HEX8}
 _PREC = {"f64": L.EFEM_F64, "f32": L.EFEM_F32, torch.float64: L.EFEM_F64, torch.float32: L.EFEM_F32}
-_SCATTER = {"atomic": L.EFEM_SCATTER_ATOMIC, "color": L.EFEM_SCATTER_COLOR}
+_SCATTER = {"halo": L.EFEM_SCATTER_HALO, "color": L.EFEM_SCATTER_COLOR, "atomic": L.EFEM_SCATTER_ATOMIC}
 
 
 def _ptr(t: torch.Tensor):
@@ -33,7 +33,7 @@ class Operator:
     Calls run on torch's current stream.
     """
 
-    def __init__(self, elem, X, conn, *, block_elems=0, block_nodes=0, scatter="atomic",
+    def __init__(self, elem, X, conn, *, block_elems=0, block_nodes=0, scatter="halo",
                  threads=0, pairs=True, device=None):
         self._lib = L.load()
         X = np.ascontiguousarray(np.asarray(X, dtype=np.float64))

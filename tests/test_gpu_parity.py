@@ -23,6 +23,8 @@ CASES = [
     ("tet_3_small_blocks", I.TET4, 3, dict(block_elems=37, block_nodes=40)),
     ("tet_8", I.TET4, 8, {}),
     ("tet_8_color", I.TET4, 8, dict(scatter="color")),
+    ("tet_8_atomic", I.TET4, 8, dict(scatter="atomic")),
+    ("tet_3_small_blocks_atomic", I.TET4, 3, dict(block_elems=37, block_nodes=40, scatter="atomic")),
     ("tet_5_color_small", I.TET4, 5, dict(block_elems=100, block_nodes=64, scatter="color",
                                            threads=64)),
     ("tet_9_ragged", I.TET4, 9, dict(block_elems=301, block_nodes=97, threads=128)),
@@ -34,6 +36,7 @@ CASES = [
     ("hex_3_small_blocks", I.HEX8, 3, dict(block_elems=5, block_nodes=27)),
     ("hex_6", I.HEX8, 6, {}),
     ("hex_6_color", I.HEX8, 6, dict(scatter="color")),
+    ("hex_6_atomic", I.HEX8, 6, dict(scatter="atomic")),
     ("hex_7_ragged", I.HEX8, 7, dict(block_elems=45, block_nodes=100, threads=64)),
     ("hex_5_scrambled", I.HEX8, 5, dict(scramble=13)),
 ]
@@ -253,7 +256,7 @@ def test_full_size_64cube_tets():
     v = I.unit_direction(m.n_nodes, 100)
     mu, lam = np.ones(m.n_elems), 1.5 * np.ones(m.n_elems)
     orc = F.FEM(I.TET4, m.X, m.conn, mu, lam)
-    for scatter in ("atomic", "color"):
+    for scatter in ("halo", "atomic", "color"):
         op = Operator(I.TET4, m.X, m.conn, scatter=scatter)
         assert abs(host(op.energy(dev(u))) - orc.energy(u)) <= TOL_E * orc.energy(u)
         assert rel(host(op.residual(dev(u))), orc.residual(u)) <= TOL64
