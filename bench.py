@@ -8,7 +8,7 @@ linearization plus 100 FP64 tangent actions y = K(u) v (efem_hvp).  `value` is
 DOF/s of the tangent action over the timed steps.
 
 Beside it: the FP32 tangent action, the colour and atomic scatters, energy
-and residual times, a roofline object for the dominant kernel (the FP64
+and residual times, the same operators under the small-strain linear model, a roofline object for the dominant kernel (the FP64
 tangent action's block pass with its halo gather, timed with HIP events on
 its stream), the Newton
 solves of the metric's second half (plain FP64 Jacobi-CG vs FP32 tangent
@@ -323,6 +323,35 @@ def main():
             n_col = opc.info()["n_colours"]
         opc.close()
 
+    # the small-strain linear model on the same mesh (the density of the
+    # paper's linear-elastic example): its tangent has no state, so one
+    # action reads X and v and writes y
+    opl = Operator(I.TET4, mesh.X, mesh.conn, model="linear", device=dev)
+    opl.linearize(u, "f64")
+    opl.hvp(V[0], out=Y)
+    t_l64 = event_time(lambda: opl.hvp(V[0], out=Y), 200, stream)
+    opl.linearize(u, "f32")
+    opl.hvp(V32[0], out=Y32)
+    t_l32 = event_time(lambda: opl.hvp(V32[0], out=Y32), 200, stream)
+    t_lres = event_time(lambda: opl.residual(u, out=R), 50, stream)
+    t_len = event_time(lambda: opl.energy(u, out=psi), 50, stream)
+    opl.close()
+    b_l64 = conn_b + 3 * node_b
+    b_l32 = conn_b + 3 * node_b // 2
+    linear = {
+        "hvp_f64_us": round(t_l64 * 1e6, 3), "hvp_f64_gdofs": round(ndof / t_l64 / 1e9, 3),
+        "hvp_f64_pct_hbm": round(100 * b_l64 / t_l64 / 1e9 / HBM_PEAK_GBS, 2),
+        "hvp_f32_us": round(t_l32 * 1e6, 3), "hvp_f32_gdofs": round(ndof / t_l32 / 1e9, 3),
+        "hvp_f32_pct_hbm": round(100 * b_l32 / t_l32 / 1e9 / HBM_PEAK_GBS, 2),
+        "residual_us": round(t_lres * 1e6, 3),
+        "residual_pct_hbm": round(100 * (conn_b + 3 * node_b) / t_lres / 1e9 / HBM_PEAK_GBS, 2),
+        "energy_us": round(t_len * 1e6, 3),
+        "energy_pct_hbm": round(100 * (conn_b + 2 * node_b) / t_len / 1e9 / HBM_PEAK_GBS, 2),
+        "alg_bytes_hvp_f64": b_l64,
+    }
+    log(f"linear model: hvp f64 {t_l64*1e6:.2f} us ({linear['hvp_f64_pct_hbm']}% HBM), "
+        f"f32 {t_l32*1e6:.2f} us, residual {t_lres*1e6:.2f} us, energy {t_len*1e6:.2f} us")
+
     # sparse tangent by colouring (Alg. 2): K(u) from n_colours tangent
     # actions, then CSR products against the matrix-free one
     sp_info = op.sparse_setup()
@@ -391,6 +420,7 @@ def main():
         "energy_us": round(t_en * 1e6, 3),
         "setup_s": round(setup_s, 3),
         "sparse_tangent": sparse,
+        "linear_model": linear,
         "paper_context": "matrix-free JVP ~13 MDoF/s, 3D linear tets, NVIDIA A100 (JAX), precision unstated",
     }
 

@@ -17,9 +17,11 @@
  *   - the sparse tangent recovered from tangent actions by colouring, Alg. 2.
  *
  * Element types: 4-node tetrahedra with the one-point centroid rule, 8-node
- * trilinear hexahedra with the 2x2x2 Gauss rule.  Material: compressible
- * neo-Hookean, psi = mu/2 (tr F^T F - 3) - mu ln J + lam/2 (ln J)^2, with
- * per-element (mu, lam).
+ * trilinear hexahedra with the 2x2x2 Gauss rule.  Material (per-element mu,
+ * lam): compressible neo-Hookean, psi = mu/2 (tr F^T F - 3) - mu ln J +
+ * lam/2 (ln J)^2 (Sec. 6.1), or small-strain linear elasticity, psi = mu
+ * eps:eps + lam/2 (tr eps)^2 with eps = sym grad u (the density of the
+ * paper's first example, Sec. 6.1), chosen with efem_set_model.
  *
  * Conventions (all calls):
  *   - Layout: nodal arrays are node-major interleaved, entry 3*node + comp
@@ -61,6 +63,10 @@ extern "C" {
 #define EFEM_TET4 0
 #define EFEM_HEX8 1
 
+/* material models (efem_set_model) */
+#define EFEM_MODEL_NEO_HOOKE 0
+#define EFEM_MODEL_LINEAR    1
+
 /* arithmetic of the tangent action */
 #define EFEM_F64 0
 #define EFEM_F32 1
@@ -81,8 +87,8 @@ typedef struct efem_ctx efem_ctx;
 typedef struct {
     int32_t block_elems;   /* max elements per workgroup block (the paper's batch
                               size N_B, Alg. 1); 0 = default for the element type */
-    int32_t block_nodes;   /* max distinct nodes per block (<= 600, so that one block
-                              fits 64 KB of LDS); 0 = default */
+    int32_t block_nodes;   /* max distinct nodes per block (<= 768, so that two
+                              blocks fit a CU's 160 KB of LDS); 0 = default */
     int32_t scatter;       /* EFEM_SCATTER_HALO (0, default), _COLOR or _ATOMIC */
     int32_t threads;       /* threads per workgroup (64..256, multiple of 64); 0 = default */
     int32_t no_pairs;      /* EFEM_TET4: nonzero = one tetrahedron per work item; by
@@ -118,6 +124,15 @@ int efem_set_stream(efem_ctx *ctx, void *stream);
  * Copied into the context; mu, lam must be finite.  Synchronous: a field that
  * is the same in every element is detected and kept as two scalars. */
 int efem_set_material(efem_ctx *ctx, const double *mu, const double *lam);
+
+/* Material model of the strain energy density: EFEM_MODEL_NEO_HOOKE (the
+ * default) or EFEM_MODEL_LINEAR.  Every later operator call (energy,
+ * residual, tangent action, diagonal, adjoints, solves, sparse tangent) uses
+ * it.  Under the linear model the tangent does not depend on u, so the state
+ * given to efem_linearize is not read by efem_hvp (linearize is still required
+ * first), and there is no det F condition.  Returns EFEM_ERR_INVALID for an
+ * unknown model. */
+int efem_set_model(efem_ctx *ctx, int32_t model);
 
 /* Replace the reference coordinates (DEVICE float64 [3*n_nodes]) keeping the
  * connectivity and the element blocks (e.g. for derivatives with respect to X

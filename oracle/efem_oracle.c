@@ -26,6 +26,15 @@
  * evaluated as 2 tr H + H:H and log1p(tr H + ((tr H)^2 - tr H^2)/2 + det H)
  * with H = F - I, which are the same quantities written without cancellation.
  *
+ * Second material (model ORC_LINEAR): small-strain linear elasticity, the
+ * density of the paper's linear-elastic example (Sec. 6.1), in 3D:
+ *   eps = (H + H^T)/2,  psi = mu eps:eps + lam/2 (tr eps)^2
+ *   P   = sigma = 2 mu eps + lam tr(eps) I
+ *   A_iJkL = mu (d_ik d_JL + d_iL d_Jk) + lam d_iJ d_kL   (constant)
+ * It has no det F condition; only det J <= 0 is an error.
+ *
+ * Every entry point takes the element type and the material model first.
+ *
  * Elements: Tet4 with the one-point centroid rule (w = 1/6) and trilinear
  * Hex8 on [-1,1]^3 with the 2x2x2 Gauss rule (points +-1/sqrt 3, w = 1); the
  * paper leaves the rules unspecified (Eq. 2).
@@ -45,6 +54,9 @@
 
 #define ORC_TET4 0
 #define ORC_HEX8 1
+
+#define ORC_NEO_HOOKE 0
+#define ORC_LINEAR 1
 
 typedef struct {
     int nen;            /* nodes per element */
@@ -121,10 +133,14 @@ typedef struct {
     double H[3][3];     /* F - I */
     double lnJ;
     double I1m3;        /* tr(F^T F) - 3 */
-    int ok;             /* det J > 0 and det F > 0 */
+    double eps[3][3];   /* (H + H^T)/2 */
+    double treps;
+    int model;
+    int ok;             /* det J > 0, and det F > 0 for the neo-Hookean model */
 } qp_t;
 
-static void qp_eval(const rule_t *r, int q, const double Xe[8][3], const double ue[8][3], qp_t *s)
+static void qp_eval(const rule_t *r, int q, const double Xe[8][3], const double ue[8][3], int model,
+                    qp_t *s)
 {
     double Jm[3][3] = {{0}}, Ji[3][3];
     for (int a = 0; a < r->nen; ++a)
@@ -149,6 +165,15 @@ static void qp_eval(const rule_t *r, int q, const double Xe[8][3], const double 
         }
     const double (*H)[3] = (const double (*)[3])s->H;
     double trH = H[0][0] + H[1][1] + H[2][2];
+    s->model = model;
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) s->eps[i][j] = 0.5 * (H[i][j] + H[j][i]);
+    s->treps = trH;
+    if (model == ORC_LINEAR) {
+        s->lnJ = 0.0;
+        s->I1m3 = 0.0;
+        return;
+    }
     double HH = 0, trH2 = 0;
     for (int i = 0; i < 3; ++i)
         for (int j = 0; j < 3; ++j) {
@@ -166,22 +191,71 @@ static void qp_eval(const rule_t *r, int q, const double Xe[8][3], const double 
     inv3(s->F, s->Finv);
 }
 
-static double psi_of(const qp_t *s, double mu, double lam)
+static double eps_dot(const qp_t *s)
 {
-    return 0.5 * mu * s->I1m3 - mu * s->lnJ + 0.5 * lam * s->lnJ * s->lnJ;
+    double t = 0;
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) t += s->eps[i][j] * s->eps[i][j];
+    return t;
 }
 
-/* first Piola-Kirchhoff stress P_iJ = mu (F - F^-T)_iJ + lam lnJ F^-T_iJ */
-static void piola(const qp_t *s, double mu, double lam, double P[3][3])
+/* dpsi/dmu and dpsi/dlam (psi is linear in both, for both models) */
+static void psi_parts(const qp_t *s, double *dmu, double *dlam)
+{
+    if (s->model == ORC_LINEAR) {
+        *dmu = eps_dot(s);
+        *dlam = 0.5 * s->treps * s->treps;
+    } else {
+        *dmu = 0.5 * s->I1m3 - s->lnJ;
+        *dlam = 0.5 * s->lnJ * s->lnJ;
+    }
+}
+
+static double psi_of(const qp_t *s, double mu, double lam)
+{
+    double pm, pl;
+    psi_parts(s, &pm, &pl);
+    return mu * pm + lam * pl;
+}
+
+/* dP/dmu and dP/dlam (P is linear in both):
+ *   neo-Hookean: F - F^-T and ln J F^-T;   linear: 2 eps and tr(eps) I */
+static void piola_parts(const qp_t *s, double Pm[3][3], double Pl[3][3])
 {
     for (int i = 0; i < 3; ++i)
-        for (int J = 0; J < 3; ++J)
-            P[i][J] = mu * (s->F[i][J] - s->Finv[J][i]) + lam * s->lnJ * s->Finv[J][i];
+        for (int J = 0; J < 3; ++J) {
+            if (s->model == ORC_LINEAR) {
+                Pm[i][J] = 2.0 * s->eps[i][J];
+                Pl[i][J] = i == J ? s->treps : 0.0;
+            } else {
+                Pm[i][J] = s->F[i][J] - s->Finv[J][i];
+                Pl[i][J] = s->lnJ * s->Finv[J][i];
+            }
+        }
+}
+
+/* first Piola-Kirchhoff stress P = mu dP/dmu + lam dP/dlam:
+ * neo-Hookean mu (F - F^-T) + lam lnJ F^-T, linear sigma */
+static void piola(const qp_t *s, double mu, double lam, double P[3][3])
+{
+    double Pm[3][3], Pl[3][3];
+    piola_parts(s, Pm, Pl);
+    for (int i = 0; i < 3; ++i)
+        for (int J = 0; J < 3; ++J) P[i][J] = mu * Pm[i][J] + lam * Pl[i][J];
 }
 
 /* explicit tangent A_iJkL = dP_iJ / dF_kL */
 static void tangent(const qp_t *s, double mu, double lam, double A[3][3][3][3])
 {
+    if (s->model == ORC_LINEAR) {
+        for (int i = 0; i < 3; ++i)
+            for (int J = 0; J < 3; ++J)
+                for (int k = 0; k < 3; ++k)
+                    for (int L = 0; L < 3; ++L)
+                        A[i][J][k][L] = mu * ((i == k && J == L ? 1.0 : 0.0) + (i == L && J == k ? 1.0 : 0.0))
+                                      + (i == J && k == L ? lam : 0.0);
+        return;
+    }
     const double (*Fi)[3] = (const double (*)[3])s->Finv;
     double c = mu - lam * s->lnJ;
     for (int i = 0; i < 3; ++i)
@@ -209,9 +283,10 @@ static void scatter_blocks(const rule_t *r, int64_t nn, int64_t ne, const int32_
                 out[3 * (int64_t)conn[e * r->nen + a] + i] += blk[(e * r->nen + a) * 3 + i];
 }
 
-static int check_args(int type, int64_t nn, int64_t ne, const int32_t *conn, rule_t *r)
+static int check_args(int type, int model, int64_t nn, int64_t ne, const int32_t *conn, rule_t *r)
 {
     if (make_rule(type, r) != 0 || nn <= 0 || ne < 0) return -1;
+    if (model != ORC_NEO_HOOKE && model != ORC_LINEAR) return -1;
     for (int64_t k = 0; k < ne * r->nen; ++k)
         if (conn[k] < 0 || conn[k] >= nn) return -1;
     return 0;
@@ -220,11 +295,11 @@ static int check_args(int type, int64_t nn, int64_t ne, const int32_t *conn, rul
 /* ------------------------------------------------------------------ energy */
 
 /* Per-element energies psi_e [ne] and their compensated sum (Eq. 2). */
-int orc_energy(int type, int64_t nn, int64_t ne, const double *X, const int32_t *conn,
+int orc_energy(int type, int model, int64_t nn, int64_t ne, const double *X, const int32_t *conn,
                const double *mu, const double *lam, const double *u, double *psi_e, double *total)
 {
     rule_t r;
-    if (check_args(type, nn, ne, conn, &r)) return -1;
+    if (check_args(type, model, nn, ne, conn, &r)) return -1;
     int bad = 0;
 #pragma omp parallel for schedule(static) reduction(|| : bad)
     for (int64_t e = 0; e < ne; ++e) {
@@ -234,7 +309,7 @@ int orc_energy(int type, int64_t nn, int64_t ne, const double *X, const int32_t 
         double pe = 0;
         for (int q = 0; q < r.nq; ++q) {
             qp_t s;
-            qp_eval(&r, q, Xe, ue, &s);
+            qp_eval(&r, q, Xe, ue, model, &s);
             if (!s.ok) { bad = 1; pe = INFINITY; break; }
             pe += s.wdetJ * psi_of(&s, mu[e], lam[e]);
         }
@@ -255,11 +330,11 @@ int orc_energy(int type, int64_t nn, int64_t ne, const double *X, const int32_t 
 /* --------------------------------------------------------------- residual */
 
 /* r_{a,i} = sum_e sum_q w detJ P_iJ grad_J N_a        (Eq. 1, r = grad Psi) */
-int orc_residual(int type, int64_t nn, int64_t ne, const double *X, const int32_t *conn,
+int orc_residual(int type, int model, int64_t nn, int64_t ne, const double *X, const int32_t *conn,
                  const double *mu, const double *lam, const double *u, double *res)
 {
     rule_t r;
-    if (check_args(type, nn, ne, conn, &r)) return -1;
+    if (check_args(type, model, nn, ne, conn, &r)) return -1;
     double *blk = (double *)calloc((size_t)(ne * r.nen * 3 + 1), sizeof(double));
     if (!blk) return -1;
     int bad = 0;
@@ -271,7 +346,7 @@ int orc_residual(int type, int64_t nn, int64_t ne, const double *X, const int32_
         double *f = blk + e * r.nen * 3;
         for (int q = 0; q < r.nq; ++q) {
             qp_t s;
-            qp_eval(&r, q, Xe, ue, &s);
+            qp_eval(&r, q, Xe, ue, model, &s);
             if (!s.ok) { bad = 1; break; }
             piola(&s, mu[e], lam[e], P);
             for (int a = 0; a < r.nen; ++a)
@@ -290,11 +365,11 @@ int orc_residual(int type, int64_t nn, int64_t ne, const double *X, const int32_
 /* -------------------------------------------------------------------- hvp */
 
 /* (K v)_{a,i} = sum_e sum_q w detJ A_iJkL (sum_b v_bk grad_L N_b) grad_J N_a   (Eq. 3) */
-int orc_hvp(int type, int64_t nn, int64_t ne, const double *X, const int32_t *conn,
+int orc_hvp(int type, int model, int64_t nn, int64_t ne, const double *X, const int32_t *conn,
             const double *mu, const double *lam, const double *u, const double *v, double *y)
 {
     rule_t r;
-    if (check_args(type, nn, ne, conn, &r)) return -1;
+    if (check_args(type, model, nn, ne, conn, &r)) return -1;
     double *blk = (double *)calloc((size_t)(ne * r.nen * 3 + 1), sizeof(double));
     if (!blk) return -1;
     int bad = 0;
@@ -307,7 +382,7 @@ int orc_hvp(int type, int64_t nn, int64_t ne, const double *X, const int32_t *co
         double *f = blk + e * r.nen * 3;
         for (int q = 0; q < r.nq; ++q) {
             qp_t s;
-            qp_eval(&r, q, Xe, ue, &s);
+            qp_eval(&r, q, Xe, ue, model, &s);
             if (!s.ok) { bad = 1; break; }
             tangent(&s, mu[e], lam[e], A);
             double dF[3][3], dP[3][3];
@@ -344,11 +419,11 @@ int orc_hvp(int type, int64_t nn, int64_t ne, const double *X, const int32_t *co
  * written to Ke [ne][nen*3][nen*3] (row (a,i) = 3a + i).  The global tangent
  * is their sum over the connectivity; its sparsity pattern is the node 1-ring
  * in 3x3 blocks.  Used to check the colouring-based sparse assembly. */
-int orc_element_tangents(int type, int64_t nn, int64_t ne, const double *X, const int32_t *conn,
+int orc_element_tangents(int type, int model, int64_t nn, int64_t ne, const double *X, const int32_t *conn,
                          const double *mu, const double *lam, const double *u, double *Ke)
 {
     rule_t r;
-    if (check_args(type, nn, ne, conn, &r)) return -1;
+    if (check_args(type, model, nn, ne, conn, &r)) return -1;
     const int m = r.nen * 3;
     int bad = 0;
 #pragma omp parallel for schedule(static) reduction(|| : bad)
@@ -360,7 +435,7 @@ int orc_element_tangents(int type, int64_t nn, int64_t ne, const double *X, cons
         memset(K, 0, sizeof(double) * (size_t)(m * m));
         for (int q = 0; q < r.nq; ++q) {
             qp_t s;
-            qp_eval(&r, q, Xe, ue, &s);
+            qp_eval(&r, q, Xe, ue, model, &s);
             if (!s.ok) { bad = 1; break; }
             tangent(&s, mu[e], lam[e], A);
             for (int a = 0; a < r.nen; ++a)
@@ -381,11 +456,11 @@ int orc_element_tangents(int type, int64_t nn, int64_t ne, const double *X, cons
 /* ----------------------------------------------------------- jacobi diag */
 
 /* K_{(a,i),(a,i)} = sum_e sum_q w detJ sum_JL A_iJiL grad_J N_a grad_L N_a */
-int orc_jacobi_diag(int type, int64_t nn, int64_t ne, const double *X, const int32_t *conn,
+int orc_jacobi_diag(int type, int model, int64_t nn, int64_t ne, const double *X, const int32_t *conn,
                     const double *mu, const double *lam, const double *u, double *d)
 {
     rule_t r;
-    if (check_args(type, nn, ne, conn, &r)) return -1;
+    if (check_args(type, model, nn, ne, conn, &r)) return -1;
     double *blk = (double *)calloc((size_t)(ne * r.nen * 3 + 1), sizeof(double));
     if (!blk) return -1;
     int bad = 0;
@@ -397,7 +472,7 @@ int orc_jacobi_diag(int type, int64_t nn, int64_t ne, const double *X, const int
         double *f = blk + e * r.nen * 3;
         for (int q = 0; q < r.nq; ++q) {
             qp_t s;
-            qp_eval(&r, q, Xe, ue, &s);
+            qp_eval(&r, q, Xe, ue, model, &s);
             if (!s.ok) { bad = 1; break; }
             tangent(&s, mu[e], lam[e], A);
             for (int a = 0; a < r.nen; ++a)
@@ -416,12 +491,13 @@ int orc_jacobi_diag(int type, int64_t nn, int64_t ne, const double *X, const int
 
 /* ------------------------------------------------------ material adjoints */
 
-/* dPsi/dmu_e = sum_q w detJ [ (tr C - 3)/2 - ln J ],  dPsi/dlam_e = sum_q w detJ (ln J)^2 / 2 */
-int orc_grad_material(int type, int64_t nn, int64_t ne, const double *X, const int32_t *conn,
+/* dPsi/dmu_e = sum_q w detJ dpsi/dmu,  dPsi/dlam_e = sum_q w detJ dpsi/dlam:
+ * neo-Hookean (tr C - 3)/2 - ln J and (ln J)^2 / 2; linear eps:eps and (tr eps)^2 / 2 */
+int orc_grad_material(int type, int model, int64_t nn, int64_t ne, const double *X, const int32_t *conn,
                       const double *u, double *dmu, double *dlam)
 {
     rule_t r;
-    if (check_args(type, nn, ne, conn, &r)) return -1;
+    if (check_args(type, model, nn, ne, conn, &r)) return -1;
     int bad = 0;
 #pragma omp parallel for schedule(static) reduction(|| : bad)
     for (int64_t e = 0; e < ne; ++e) {
@@ -431,10 +507,12 @@ int orc_grad_material(int type, int64_t nn, int64_t ne, const double *X, const i
         double gm = 0, gl = 0;
         for (int q = 0; q < r.nq; ++q) {
             qp_t s;
-            qp_eval(&r, q, Xe, ue, &s);
+            qp_eval(&r, q, Xe, ue, model, &s);
             if (!s.ok) { bad = 1; break; }
-            gm += s.wdetJ * (0.5 * s.I1m3 - s.lnJ);
-            gl += s.wdetJ * 0.5 * s.lnJ * s.lnJ;
+            double pm, pl;
+            psi_parts(&s, &pm, &pl);
+            gm += s.wdetJ * pm;
+            gl += s.wdetJ * pl;
         }
         dmu[e] = gm;
         dlam[e] = gl;
@@ -442,12 +520,12 @@ int orc_grad_material(int type, int64_t nn, int64_t ne, const double *X, const i
     return bad ? -4 : 0;
 }
 
-/* w . dr/dmu_e = sum_q w detJ (F - F^-T) : grad w,   w . dr/dlam_e = sum_q w detJ lnJ F^-T : grad w */
-int orc_residual_vjp_material(int type, int64_t nn, int64_t ne, const double *X, const int32_t *conn,
+/* w . dr/dmu_e = sum_q w detJ dP/dmu : grad w,   w . dr/dlam_e = sum_q w detJ dP/dlam : grad w */
+int orc_residual_vjp_material(int type, int model, int64_t nn, int64_t ne, const double *X, const int32_t *conn,
                               const double *u, const double *wv, double *dmu, double *dlam)
 {
     rule_t r;
-    if (check_args(type, nn, ne, conn, &r)) return -1;
+    if (check_args(type, model, nn, ne, conn, &r)) return -1;
     int bad = 0;
 #pragma omp parallel for schedule(static) reduction(|| : bad)
     for (int64_t e = 0; e < ne; ++e) {
@@ -458,14 +536,16 @@ int orc_residual_vjp_material(int type, int64_t nn, int64_t ne, const double *X,
         double gm = 0, gl = 0;
         for (int q = 0; q < r.nq; ++q) {
             qp_t s;
-            qp_eval(&r, q, Xe, ue, &s);
+            qp_eval(&r, q, Xe, ue, model, &s);
             if (!s.ok) { bad = 1; break; }
+            double Pm[3][3], Pl[3][3];
+            piola_parts(&s, Pm, Pl);
             for (int i = 0; i < 3; ++i)
                 for (int J = 0; J < 3; ++J) {
                     double gw = 0;
                     for (int a = 0; a < r.nen; ++a) gw += we[a][i] * s.gN[a][J];
-                    gm += s.wdetJ * (s.F[i][J] - s.Finv[J][i]) * gw;
-                    gl += s.wdetJ * s.lnJ * s.Finv[J][i] * gw;
+                    gm += s.wdetJ * Pm[i][J] * gw;
+                    gl += s.wdetJ * Pl[i][J] * gw;
                 }
         }
         dmu[e] = gm;
@@ -477,11 +557,11 @@ int orc_residual_vjp_material(int type, int64_t nn, int64_t ne, const double *X,
 /* ---------------------------------------------------- coordinate adjoint */
 
 /* dPsi/dX_a (at fixed nodal u) = sum_e sum_q w detJ (psi I - H^T P) grad N_a */
-int orc_grad_coords(int type, int64_t nn, int64_t ne, const double *X, const int32_t *conn,
+int orc_grad_coords(int type, int model, int64_t nn, int64_t ne, const double *X, const int32_t *conn,
                     const double *mu, const double *lam, const double *u, double *gX)
 {
     rule_t r;
-    if (check_args(type, nn, ne, conn, &r)) return -1;
+    if (check_args(type, model, nn, ne, conn, &r)) return -1;
     double *blk = (double *)calloc((size_t)(ne * r.nen * 3 + 1), sizeof(double));
     if (!blk) return -1;
     int bad = 0;
@@ -493,7 +573,7 @@ int orc_grad_coords(int type, int64_t nn, int64_t ne, const double *X, const int
         double *f = blk + e * r.nen * 3;
         for (int q = 0; q < r.nq; ++q) {
             qp_t s;
-            qp_eval(&r, q, Xe, ue, &s);
+            qp_eval(&r, q, Xe, ue, model, &s);
             if (!s.ok) { bad = 1; break; }
             piola(&s, mu[e], lam[e], P);
             double psi = psi_of(&s, mu[e], lam[e]);
@@ -517,10 +597,10 @@ int orc_grad_coords(int type, int64_t nn, int64_t ne, const double *X, const int
 }
 
 /* Element volumes sum_q w detJ, for mesh checks.  Returns -4 if any det J <= 0. */
-int orc_volumes(int type, int64_t nn, int64_t ne, const double *X, const int32_t *conn, double *vol)
+int orc_volumes(int type, int model, int64_t nn, int64_t ne, const double *X, const int32_t *conn, double *vol)
 {
     rule_t r;
-    if (check_args(type, nn, ne, conn, &r)) return -1;
+    if (check_args(type, model, nn, ne, conn, &r)) return -1;
     int bad = 0;
     for (int64_t e = 0; e < ne; ++e) {
         double Xe[8][3], ue[8][3] = {{0}};
@@ -528,7 +608,7 @@ int orc_volumes(int type, int64_t nn, int64_t ne, const double *X, const int32_t
         double v = 0;
         for (int q = 0; q < r.nq; ++q) {
             qp_t s;
-            qp_eval(&r, q, Xe, ue, &s);
+            qp_eval(&r, q, Xe, ue, model, &s);
             if (!s.ok) bad = 1;
             v += s.wdetJ;
         }

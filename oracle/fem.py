@@ -17,6 +17,10 @@ import numpy as np
 from . import build as _build
 
 TET4, HEX8 = 0, 1
+# material models: compressible neo-Hookean (Sec. 6.1) and small-strain
+# linear elasticity (the density of the paper's first example)
+NEO_HOOKE, LINEAR = 0, 1
+MODELS = {"neo_hookean": NEO_HOOKE, "linear": LINEAR}
 _lib = None
 
 _dp = ctypes.POINTER(ctypes.c_double)
@@ -30,7 +34,7 @@ def lib():
         path = os.environ.get("EFEM_ORACLE_LIB") or _build.build()
         _lib = ctypes.CDLL(path)
         i64, c_int = ctypes.c_int64, ctypes.c_int
-        common = [c_int, i64, i64, _dp, _ip]
+        common = [c_int, c_int, i64, i64, _dp, _ip]
         for name, extra in [
             ("orc_energy", [_dp, _dp, _dp, _dp, _dp]),
             ("orc_residual", [_dp, _dp, _dp, _dp]),
@@ -70,14 +74,18 @@ def _check(rc, what):
 
 @dataclass
 class FEM:
-    """Mesh + per-element material: the geometric context of Sec. 4 (Operator)."""
+    """Mesh + per-element material: the geometric context of Sec. 4 (Operator).
+    `model` is "neo_hookean" (default) or "linear"."""
     elem: int
     X: np.ndarray
     conn: np.ndarray
     mu: np.ndarray
     lam: np.ndarray
+    model: str = "neo_hookean"
 
     def __post_init__(self):
+        if self.model not in MODELS:
+            raise ValueError(f"unknown material model {self.model!r}")
         self.X = np.ascontiguousarray(self.X, dtype=np.float64)
         self.conn = np.ascontiguousarray(self.conn, dtype=np.int32)
         self.mu = np.ascontiguousarray(self.mu, dtype=np.float64)
@@ -92,7 +100,7 @@ class FEM:
         return self.conn.shape[0]
 
     def _head(self):
-        return (self.elem, self.n_nodes, self.n_elems, _d(self.X),
+        return (self.elem, MODELS[self.model], self.n_nodes, self.n_elems, _d(self.X),
                 self.conn.ctypes.data_as(_ip))
 
     @staticmethod

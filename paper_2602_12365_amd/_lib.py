@@ -21,6 +21,7 @@ EFEM_ERR_STATE = -5
 
 EFEM_TET4, EFEM_HEX8 = 0, 1
 EFEM_F64, EFEM_F32 = 0, 1
+EFEM_MODEL_NEO_HOOKE, EFEM_MODEL_LINEAR = 0, 1
 EFEM_SCATTER_HALO, EFEM_SCATTER_COLOR, EFEM_SCATTER_ATOMIC = 0, 1, 2
 
 EFEM_MLP_IN, EFEM_MLP_HID, EFEM_MLP_OUT = 12, 64, 3
@@ -72,6 +73,7 @@ SIGNATURES = {
     "efem_destroy": (None, [c_void_p]),
     "efem_set_stream": (c_int32, [c_void_p, c_void_p]),
     "efem_set_material": (c_int32, [c_void_p, c_void_p, c_void_p]),
+    "efem_set_model": (c_int32, [c_void_p, c_int32]),
     "efem_set_dirichlet": (c_int32, [c_void_p, c_void_p]),
     "efem_set_coords": (c_int32, [c_void_p, c_void_p]),
     "efem_energy": (c_int32, [c_void_p, c_void_p, c_void_p]),

@@ -429,9 +429,9 @@ int efem_create(efem_ctx **out, int32_t elem, int64_t n_nodes, int64_t n_elems,
         return EFEM_ERR_INVERTED;
     }
     // defaults measured on the 64^3 workloads: 1536 tets (768 pairs) within 600
-    // nodes, or 256 hexes within 512 nodes, per block
-    int be = elem == EFEM_TET4 ? 1536 : 256;
-    int bn = elem == EFEM_TET4 ? 600 : 512;
+    // nodes, or 512 hexes within 768 nodes, per block
+    int be = elem == EFEM_TET4 ? 1536 : 512;
+    int bn = elem == EFEM_TET4 ? 600 : 768;
     int scatter = EFEM_SCATTER_HALO;
     int threads = 256;
     if (opts) {
@@ -444,8 +444,10 @@ int efem_create(efem_ctx **out, int32_t elem, int64_t n_nodes, int64_t n_elems,
         }
         if (opts->threads > 0) threads = opts->threads;
     }
-    if (bn < nen || bn > 600 || be < 1 || threads < 64 || threads > 256 || threads % 64) {
-        set_error("efem_create: block_nodes must be in [n_en, 600], threads a multiple of 64 in [64, 256]");
+    // 768 nodes x (80-byte record + 24-byte FP64 sums) = 78 KB of LDS, so two
+    // blocks share a CU's 160 KB
+    if (bn < nen || bn > 768 || be < 1 || threads < 64 || threads > 256 || threads % 64) {
+        set_error("efem_create: block_nodes must be in [n_en, 768], threads a multiple of 64 in [64, 256]");
         return EFEM_ERR_INVALID;
     }
 
@@ -557,6 +559,20 @@ int efem_set_stream(efem_ctx *ctx, void *stream)
 {
     if (!ctx) return EFEM_ERR_INVALID;
     ctx->stream = (hipStream_t)stream;
+    return EFEM_OK;
+}
+
+int efem_set_model(efem_ctx *ctx, int32_t model)
+{
+    if (!ctx) {
+        set_error("efem_set_model: null context");
+        return EFEM_ERR_INVALID;
+    }
+    if (model != EFEM_MODEL_NEO_HOOKE && model != EFEM_MODEL_LINEAR) {
+        set_error("efem_set_model: unknown material model");
+        return EFEM_ERR_INVALID;
+    }
+    ctx->model = model;
     return EFEM_OK;
 }
 

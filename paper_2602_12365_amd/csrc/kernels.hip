@@ -555,6 +555,62 @@ __device__ __forceinline__ bool qp_residual(T w, const T Jx[9], const T Jd[9], T
     return Dd > T(0);
 }
 
+// ---- small-strain linear elasticity (the second material model)
+//   psi = mu eps:eps + lam/2 (tr eps)^2,  sigma = mu (H + H^T) + lam tr(H) I,
+// with H = Hxi Jx^-1 = Hxi Ae / De the gradient of a nodal field.
+
+// H of a nodal field; returns det Jx, and Ae (Jx^-1 = Ae / De).
+template <class T>
+__device__ __forceinline__ T lin_grad(const T Jx[9], const T Hxi[9], T Ae[9], T H[9])
+{
+    const T De = adj_det(Jx, Ae);
+    const T r = rcp(De);
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int L = 0; L < 3; ++L)
+            H[i * 3 + L] = (Hxi[i * 3 + 0] * Ae[0 * 3 + L] + Hxi[i * 3 + 1] * Ae[1 * 3 + L]
+                            + Hxi[i * 3 + 2] * Ae[2 * 3 + L]) * r;
+    return De;
+}
+
+template <class T>
+__device__ __forceinline__ void lin_stress(const T H[9], T mu, T lam, T S[9])
+{
+    const T t = lam * (H[0] + H[4] + H[8]);
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int L = 0; L < 3; ++L) S[i * 3 + L] = mu * (H[i * 3 + L] + H[L * 3 + i]) + (i == L ? t : T(0));
+}
+
+// eps:eps and tr eps of H
+template <class T>
+__device__ __forceinline__ void lin_invariants(const T H[9], T &ee, T &tr)
+{
+    tr = H[0] + H[4] + H[8];
+    ee = H[0] * H[0] + H[4] * H[4] + H[8] * H[8];
+    const T a = T(0.5) * (H[1] + H[3]), b = T(0.5) * (H[2] + H[6]), c = T(0.5) * (H[5] + H[7]);
+    ee += T(2) * (a * a + b * b + c * c);
+}
+
+// Nodal forces of the linear model at one point: Q = w det Jx sigma Jx^-T =
+// w sigma Ae^T.  Linear in Hxi, so the residual (Hxi of u) and the tangent
+// action (Hxi of v) are the same map.
+template <class T>
+__device__ __forceinline__ void qp_linear(T w, const T Jx[9], const T Hxi[9], T mu, T lam, T Q[9])
+{
+    T Ae[9], H[9], S[9];
+    lin_grad(Jx, Hxi, Ae, H);
+    lin_stress(H, mu, lam, S);
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int J = 0; J < 3; ++J)
+            Q[i * 3 + J] = w * (S[i * 3 + 0] * Ae[J * 3 + 0] + S[i * 3 + 1] * Ae[J * 3 + 1]
+                                + S[i * 3 + 2] * Ae[J * 3 + 2]);
+}
+
 // Kinematics of the displacement gradient H = Hxi Jx^-1 without cancellation:
 // I1 - 3 = 2 tr H + H:H, J - 1 = tr H + ((tr H)^2 - tr H^2)/2 + det H.
 struct Kin {
@@ -944,6 +1000,159 @@ struct GradCoordsOp : XUStage {
     }
 };
 
+// ---- operations of the linear model
+
+// X and a direction v: the linear model's tangent does not depend on u.
+template <class T> struct alignas(16) NodeXV {
+    T X[3], v[3];
+};
+
+template <class T> struct LinHvpOp {
+    using Node = NodeXV<T>;
+    const T *X, *v;
+    __device__ void stage(const BlockMesh &m, Node &n, int64_t g) const
+    {
+        load3(X, g, n.X);
+        load3(v, g, n.v);
+        if (m.nmask) {
+            const uint8_t b = m.nmask[g];
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+                if ((b >> c) & 1) n.v[c] = T(0);
+        }
+    }
+    template <class E>
+    __device__ __forceinline__ bool element(const Node *sn, const uint16_t *lc, const T *mu, const T *lam,
+                                            bool pair, T f[E::NEN][3]) const
+    {
+        T Xe[E::NEN][3], ve[E::NEN][3];
+#pragma unroll
+        for (int a = 0; a < E::NEN; ++a)
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                Xe[a][i] = sn[lc[a]].X[i];
+                ve[a][i] = sn[lc[a]].v[i];
+            }
+        typename E::template Field<T> FX, Fv;
+        E::prep(Xe, FX);
+        E::prep(ve, Fv);
+        typename E::template Acc<T> A;
+#pragma unroll
+        for (int q = 0; q < E::NQ; ++q) {
+            if (E::skip(q, pair)) continue;
+            T Jx[9], dJ[9], Q[9];
+            E::grad(FX, q, Jx);
+            E::grad(Fv, q, dJ);
+            qp_linear(E::template weight<T>(), Jx, dJ, mu[E::sub(q)], lam[E::sub(q)], Q);
+            E::template add_forces<true>(Q, q, A);
+        }
+        E::finish(A, f);
+        return true;
+    }
+};
+
+struct LinResidualOp : XUStage {
+    using Node = NodeXU;
+    template <class E>
+    __device__ __forceinline__ bool element(const Node *sn, const uint16_t *lc, const double *mu,
+                                            const double *lam, bool pair, double f[E::NEN][3]) const
+    {
+        typename E::template Field<double> FX, Fu;
+        gather_xu<E>(sn, lc, FX, Fu);
+        typename E::template Acc<double> A;
+#pragma unroll
+        for (int q = 0; q < E::NQ; ++q) {
+            if (E::skip(q, pair)) continue;
+            double Jx[9], Hxi[9], Q[9];
+            E::grad(FX, q, Jx);
+            E::grad(Fu, q, Hxi);
+            qp_linear(E::template weight<double>(), Jx, Hxi, mu[E::sub(q)], lam[E::sub(q)], Q);
+            E::template add_forces<true>(Q, q, A);
+        }
+        E::finish(A, f);
+        return true;
+    }
+};
+
+// diag K of the linear model: w det Jx [mu |grad N_a|^2 + (mu + lam) (grad N_a)_i^2]
+// = w / De [mu |Ae^T n|^2 + (mu + lam) ((Ae^T n)_i)^2],  n = dN_a/dxi
+struct LinDiagOp : XUStage {
+    using Node = NodeXU;
+    template <class E>
+    __device__ __forceinline__ bool element(const Node *sn, const uint16_t *lc, const double *mu,
+                                            const double *lam, bool pair, double f[E::NEN][3]) const
+    {
+        typename E::template Field<double> FX, Fu;
+        gather_xu<E>(sn, lc, FX, Fu);
+#pragma unroll
+        for (int a = 0; a < E::NEN; ++a) f[a][0] = f[a][1] = f[a][2] = 0.0;
+#pragma unroll
+        for (int q = 0; q < E::NQ; ++q) {
+            if (E::skip(q, pair)) continue;
+            const double mq = mu[E::sub(q)], lq = lam[E::sub(q)];
+            double Jx[9], Ae[9];
+            E::grad(FX, q, Jx);
+            const double De = adj_det(Jx, Ae);
+            const double c = E::template weight<double>() / De;
+#pragma unroll
+            for (int n = 0; n < E::NEN; ++n) {
+                const double g0 = E::template dN<double>(q, n, 0);
+                const double g1 = E::template dN<double>(q, n, 1);
+                const double g2 = E::template dN<double>(q, n, 2);
+                const double t[3] = {Ae[0] * g0 + Ae[3] * g1 + Ae[6] * g2,
+                                     Ae[1] * g0 + Ae[4] * g1 + Ae[7] * g2,
+                                     Ae[2] * g0 + Ae[5] * g1 + Ae[8] * g2};
+                const double tt = t[0] * t[0] + t[1] * t[1] + t[2] * t[2];
+#pragma unroll
+                for (int i = 0; i < 3; ++i) f[n][i] += c * (mq * tt + (mq + lq) * t[i] * t[i]);
+            }
+        }
+        return true;
+    }
+};
+
+// dPsi/dX of the linear model at fixed nodal u: Q = w det Jx (psi I - H^T sigma) Jx^-T
+struct LinGradCoordsOp : XUStage {
+    using Node = NodeXU;
+    template <class E>
+    __device__ __forceinline__ bool element(const Node *sn, const uint16_t *lc, const double *mu,
+                                            const double *lam, bool pair, double f[E::NEN][3]) const
+    {
+        typename E::template Field<double> FX, Fu;
+        gather_xu<E>(sn, lc, FX, Fu);
+        typename E::template Acc<double> A;
+#pragma unroll
+        for (int q = 0; q < E::NQ; ++q) {
+            if (E::skip(q, pair)) continue;
+            const double mq = mu[E::sub(q)], lq = lam[E::sub(q)];
+            double Jx[9], Hxi[9], Ae[9], H[9], S[9], Sg[9], Q[9];
+            E::grad(FX, q, Jx);
+            E::grad(Fu, q, Hxi);
+            lin_grad(Jx, Hxi, Ae, H);
+            lin_stress(H, mq, lq, S);
+            double ee, tr;
+            lin_invariants(H, ee, tr);
+            const double psi = mq * ee + 0.5 * lq * tr * tr;
+#pragma unroll
+            for (int mm = 0; mm < 3; ++mm)
+#pragma unroll
+                for (int L = 0; L < 3; ++L)
+                    Sg[mm * 3 + L] = (mm == L ? psi : 0.0) - (H[0 * 3 + mm] * S[0 * 3 + L]
+                                     + H[1 * 3 + mm] * S[1 * 3 + L] + H[2 * 3 + mm] * S[2 * 3 + L]);
+            const double w = E::template weight<double>();
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+#pragma unroll
+                for (int J = 0; J < 3; ++J)
+                    Q[i * 3 + J] = w * (Sg[i * 3 + 0] * Ae[J * 3 + 0] + Sg[i * 3 + 1] * Ae[J * 3 + 1]
+                                        + Sg[i * 3 + 2] * Ae[J * 3 + 2]);
+            E::template add_forces<true>(Q, q, A);
+        }
+        E::finish(A, f);
+        return true;
+    }
+};
+
 // ------------------------------------------------------------ per-item inputs
 
 // Work items of one block.  Pairs come first; item k covers the internal
@@ -1141,7 +1350,7 @@ __global__ void __launch_bounds__(256) k_fill_nodal(int64_t n_nodes, T *__restri
 
 // ------------------------------------------------------------------- energy
 
-template <class E>
+template <class E, bool LIN>
 __global__ void __launch_bounds__(256) k_energy(BlockMesh m, const double *__restrict__ X,
                                                 const double *__restrict__ u,
                                                 double *__restrict__ partials)
@@ -1178,6 +1387,13 @@ __global__ void __launch_bounds__(256) k_energy(BlockMesh m, const double *__res
             double Jx[9], Hxi[9];
             E::grad(FX, q, Jx);
             E::grad(Fu, q, Hxi);
+            if (LIN) {
+                double Ae[9], H[9], ee, tr;
+                const double De = lin_grad(Jx, Hxi, Ae, H);
+                lin_invariants(H, ee, tr);
+                pe += E::template weight<double>() * De * (mu * ee + 0.5 * lam * tr * tr);
+                continue;
+            }
             Kin kk;
             kinematics(E::template weight<double>(), Jx, Hxi, kk);
             if (!(1.0 + kk.Jm1 > 0.0)) {
@@ -1229,7 +1445,7 @@ __global__ void __launch_bounds__(256) k_sum_partials(const double *__restrict__
 // ---------------------------------------------------- per-element adjoint kernels
 
 // dPsi/dmu_e, dPsi/dlam_e at fixed u.
-template <class E>
+template <class E, bool LIN>
 __global__ void __launch_bounds__(256) k_grad_material(BlockMesh m, const double *__restrict__ X,
                                                        const double *__restrict__ u,
                                                        double *__restrict__ dmu,
@@ -1258,6 +1474,14 @@ __global__ void __launch_bounds__(256) k_grad_material(BlockMesh m, const double
             double Jx[9], Hxi[9];
             E::grad(FX, q, Jx);
             E::grad(Fu, q, Hxi);
+            if (LIN) {
+                double Ae[9], H[9], ee, tr;
+                const double wDe = E::template weight<double>() * lin_grad(Jx, Hxi, Ae, H);
+                lin_invariants(H, ee, tr);
+                gm[E::sub(q)] += wDe * ee;
+                gl[E::sub(q)] += wDe * 0.5 * tr * tr;
+                continue;
+            }
             Kin kk;
             kinematics(E::template weight<double>(), Jx, Hxi, kk);
             if (!(1.0 + kk.Jm1 > 0.0)) {
@@ -1280,7 +1504,8 @@ __global__ void __launch_bounds__(256) k_grad_material(BlockMesh m, const double
 }
 
 // w . dr/dmu_e = sum_q w detJ (F - F^-T) : grad w,  w . dr/dlam_e = sum_q w detJ lnJ F^-T : grad w
-template <class E>
+// linear model: w . dr/dmu_e = sum_q w detJ 2 eps(u) : grad w,  w . dr/dlam_e = sum_q w detJ tr eps(u) div w
+template <class E, bool LIN>
 __global__ void __launch_bounds__(256) k_vjp_material(BlockMesh m, const double *__restrict__ X,
                                                       const double *__restrict__ u,
                                                       const double *__restrict__ wv,
@@ -1328,6 +1553,19 @@ __global__ void __launch_bounds__(256) k_vjp_material(BlockMesh m, const double 
             E::grad(FX, q, Jx);
             E::grad(Fu, q, Hxi);
             E::grad(Fw, q, Wxi);
+            if (LIN) {
+                double H[9], Gw[9];
+                const double wDe = E::template weight<double>() * lin_grad(Jx, Hxi, Ae, H);
+                lin_grad(Jx, Wxi, Ae, Gw);
+                double sm = 0.0;
+#pragma unroll
+                for (int i = 0; i < 3; ++i)
+#pragma unroll
+                    for (int J = 0; J < 3; ++J) sm += (H[i * 3 + J] + H[J * 3 + i]) * Gw[i * 3 + J];
+                gm[E::sub(q)] += wDe * sm;
+                gl[E::sub(q)] += wDe * (H[0] + H[4] + H[8]) * (Gw[0] + Gw[4] + Gw[8]);
+                continue;
+            }
             Kin kk;
             kinematics(E::template weight<double>(), Jx, Hxi, kk);
             if (!(1.0 + kk.Jm1 > 0.0)) {
@@ -1422,6 +1660,12 @@ static hipError_t dispatch(const Ctx &c, const Op &op, T *y, bool use_mask, T fi
 
 hipError_t launch_residual(const Ctx &c, const double *u, double *r)
 {
+    if (c.model == EFEM_MODEL_LINEAR) {
+        LinResidualOp op;
+        op.X = c.m.X;
+        op.u = u;
+        return dispatch(c, op, r, true, 0.0);
+    }
     ResidualOp op;
     op.X = c.m.X;
     op.u = u;
@@ -1430,6 +1674,12 @@ hipError_t launch_residual(const Ctx &c, const double *u, double *r)
 
 hipError_t launch_diag(const Ctx &c, const double *u, double *d)
 {
+    if (c.model == EFEM_MODEL_LINEAR) {
+        LinDiagOp op;
+        op.X = c.m.X;
+        op.u = u;
+        return dispatch(c, op, d, true, 1.0);
+    }
     DiagOp op;
     op.X = c.m.X;
     op.u = u;
@@ -1438,6 +1688,12 @@ hipError_t launch_diag(const Ctx &c, const double *u, double *d)
 
 hipError_t launch_grad_coords(const Ctx &c, const double *u, double *g)
 {
+    if (c.model == EFEM_MODEL_LINEAR) {
+        LinGradCoordsOp op;
+        op.X = c.m.X;
+        op.u = u;
+        return dispatch(c, op, g, false, 0.0);
+    }
     GradCoordsOp op;
     op.X = c.m.X;
     op.u = u;
@@ -1447,6 +1703,10 @@ hipError_t launch_grad_coords(const Ctx &c, const double *u, double *g)
 hipError_t launch_hvp_f64(const Ctx &c, const double *xlin, const double *v, double *y,
                           const int32_t *skip, WriteMode mode)
 {
+    if (c.model == EFEM_MODEL_LINEAR) {
+        LinHvpOp<double> op{c.m.X, v};
+        return dispatch(c, op, y, true, 0.0, skip, mode);
+    }
     HvpOp<double> op{c.m.X, xlin, v, y};
     return dispatch(c, op, y, true, 0.0, skip, mode);
 }
@@ -1454,45 +1714,70 @@ hipError_t launch_hvp_f64(const Ctx &c, const double *xlin, const double *v, dou
 hipError_t launch_hvp_f32(const Ctx &c, const float *ulin, const float *v, float *y,
                           const int32_t *skip, WriteMode mode)
 {
+    if (c.model == EFEM_MODEL_LINEAR) {
+        LinHvpOp<float> op{c.m.Xf, v};
+        return dispatch(c, op, y, true, 0.0f, skip, mode);
+    }
     HvpOp<float> op{c.m.Xf, ulin, v, y};
     return dispatch(c, op, y, true, 0.0f, skip, mode);
+}
+
+template <class E, bool LIN>
+static void energy_pass(const Ctx &c, const double *u, size_t lds)
+{
+    hipLaunchKernelGGL((k_energy<E, LIN>), dim3(c.m.n_blocks), dim3(256), lds, c.stream, c.m, c.m.X, u,
+                       c.partials);
 }
 
 hipError_t launch_energy(const Ctx &c, const double *u, double *psi)
 {
     const size_t lds = sizeof(NodeXU) * (size_t)c.max_block_nodes;
-    if (c.elem == EFEM_TET4)
-        hipLaunchKernelGGL(k_energy<Tet4Pair>, dim3(c.m.n_blocks), dim3(256), lds, c.stream, c.m, c.m.X,
-                           u, c.partials);
-    else
-        hipLaunchKernelGGL(k_energy<Hex8>, dim3(c.m.n_blocks), dim3(256), lds, c.stream, c.m, c.m.X,
-                           u, c.partials);
+    const bool lin = c.model == EFEM_MODEL_LINEAR;
+    if (c.elem == EFEM_TET4) lin ? energy_pass<Tet4Pair, true>(c, u, lds) : energy_pass<Tet4Pair, false>(c, u, lds);
+    else lin ? energy_pass<Hex8, true>(c, u, lds) : energy_pass<Hex8, false>(c, u, lds);
     hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, c.stream, c.partials, c.m.n_blocks, psi);
     return hipGetLastError();
+}
+
+template <class E, bool LIN>
+static void grad_material_pass(const Ctx &c, const double *u, double *dmu, double *dlam, size_t lds)
+{
+    hipLaunchKernelGGL((k_grad_material<E, LIN>), dim3(c.m.n_blocks), dim3(c.threads), lds, c.stream, c.m,
+                       c.m.X, u, dmu, dlam);
 }
 
 hipError_t launch_grad_material(const Ctx &c, const double *u, double *dmu, double *dlam)
 {
     const size_t lds = sizeof(NodeXU) * (size_t)c.max_block_nodes;
+    const bool lin = c.model == EFEM_MODEL_LINEAR;
     if (c.elem == EFEM_TET4)
-        hipLaunchKernelGGL(k_grad_material<Tet4Pair>, dim3(c.m.n_blocks), dim3(c.threads), lds,
-                           c.stream, c.m, c.m.X, u, dmu, dlam);
+        lin ? grad_material_pass<Tet4Pair, true>(c, u, dmu, dlam, lds)
+            : grad_material_pass<Tet4Pair, false>(c, u, dmu, dlam, lds);
     else
-        hipLaunchKernelGGL(k_grad_material<Hex8>, dim3(c.m.n_blocks), dim3(c.threads), lds,
-                           c.stream, c.m, c.m.X, u, dmu, dlam);
+        lin ? grad_material_pass<Hex8, true>(c, u, dmu, dlam, lds)
+            : grad_material_pass<Hex8, false>(c, u, dmu, dlam, lds);
     return hipGetLastError();
+}
+
+template <class E, bool LIN>
+static void vjp_material_pass(const Ctx &c, const double *u, const double *w, double *dmu, double *dlam,
+                              size_t lds)
+{
+    hipLaunchKernelGGL((k_vjp_material<E, LIN>), dim3(c.m.n_blocks), dim3(c.threads), lds, c.stream, c.m,
+                       c.m.X, u, w, dmu, dlam);
 }
 
 hipError_t launch_vjp_material(const Ctx &c, const double *u, const double *w, double *dmu,
                                double *dlam)
 {
     const size_t lds = sizeof(NodeXUW) * (size_t)c.max_block_nodes;
+    const bool lin = c.model == EFEM_MODEL_LINEAR;
     if (c.elem == EFEM_TET4)
-        hipLaunchKernelGGL(k_vjp_material<Tet4Pair>, dim3(c.m.n_blocks), dim3(c.threads), lds,
-                           c.stream, c.m, c.m.X, u, w, dmu, dlam);
+        lin ? vjp_material_pass<Tet4Pair, true>(c, u, w, dmu, dlam, lds)
+            : vjp_material_pass<Tet4Pair, false>(c, u, w, dmu, dlam, lds);
     else
-        hipLaunchKernelGGL(k_vjp_material<Hex8>, dim3(c.m.n_blocks), dim3(c.threads), lds,
-                           c.stream, c.m, c.m.X, u, w, dmu, dlam);
+        lin ? vjp_material_pass<Hex8, true>(c, u, w, dmu, dlam, lds)
+            : vjp_material_pass<Hex8, false>(c, u, w, dmu, dlam, lds);
     return hipGetLastError();
 }
 

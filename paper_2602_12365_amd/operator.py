@@ -17,6 +17,7 @@ from . import _lib as L
 
 _ELEM = {"tet4": L.EFEM_TET4, "hex8": L.EFEM_HEX8, L.EFEM_TET4: L.EFEM_TET4, L.EFEM_HEX8: L.EFEM_HEX8}
 _PREC = {"f64": L.EFEM_F64, "f32": L.EFEM_F32, torch.float64: L.EFEM_F64, torch.float32: L.EFEM_F32}
+_MODEL = {"neo_hookean": L.EFEM_MODEL_NEO_HOOKE, "linear": L.EFEM_MODEL_LINEAR}
 _SCATTER = {"halo": L.EFEM_SCATTER_HALO, "color": L.EFEM_SCATTER_COLOR, "atomic": L.EFEM_SCATTER_ATOMIC}
 
 
@@ -34,7 +35,7 @@ class Operator:
     """
 
     def __init__(self, elem, X, conn, *, block_elems=0, block_nodes=0, scatter="halo",
-                 threads=0, pairs=True, device=None):
+                 threads=0, pairs=True, model="neo_hookean", device=None):
         self._lib = L.load()
         X = np.ascontiguousarray(np.asarray(X, dtype=np.float64))
         conn = np.ascontiguousarray(np.asarray(conn, dtype=np.int32))
@@ -62,6 +63,9 @@ class Operator:
         self._h = h
         self._lin = None
         self.X = torch.from_numpy(X).to(self.device)
+        self.model = "neo_hookean"
+        if model != "neo_hookean":
+            self.set_model(model)
 
     # ------------------------------------------------------------- plumbing
     def close(self):
@@ -103,6 +107,14 @@ class Operator:
         self._sync_stream()
         L.check(self._lib.efem_set_material(self._h, _ptr(self._elemwise(mu, "mu")),
                                             _ptr(self._elemwise(lam, "lam"))), "efem_set_material")
+
+    def set_model(self, model):
+        """Strain energy density: "neo_hookean" (default) or "linear" (small strain)."""
+        if model not in _MODEL:
+            raise ValueError(f"unknown material model {model!r}")
+        L.check(self._lib.efem_set_model(self._h, _MODEL[model]), "efem_set_model")
+        self.model = model
+        self._lin = None
 
     def set_coords(self, X):
         """Replace the reference coordinates (float64 [n_nodes, 3] device tensor),

@@ -14,16 +14,16 @@ def dev(a, dtype=torch.float64):
     return torch.as_tensor(np.ascontiguousarray(a)).to("cuda", dtype=dtype)
 
 
-def setup(elem, n, dz, mu_sigma=0.0, n_steps=5):
+def setup(elem, n, dz, mu_sigma=0.0, n_steps=5, model="neo_hookean"):
     from paper_2602_12365_amd import Operator
     m = I.make_mesh(elem, n)
     mu = np.ones(m.n_elems) if mu_sigma == 0 else I.lognormal_field(m.n_elems, mu_sigma, 3)
     lam = 1.5 * mu
     mask, ubc = I.clamp_top_bottom(m.X, dz)
-    op = Operator(elem, m.X, m.conn)
+    op = Operator(elem, m.X, m.conn, model=model)
     op.set_material(dev(mu), dev(lam))
     op.set_dirichlet(dev(mask, torch.uint8))
-    orc = F.FEM(elem, m.X, m.conn, mu, lam)
+    orc = F.FEM(elem, m.X, m.conn, mu, lam, model)
     return m, op, orc, mask, ubc
 
 
@@ -69,6 +69,26 @@ def test_hex_compression_newton(prec):
     ug = u.cpu().numpy()
     assert free_residual_norm(orc, ug, mask) <= 2e-8 * st_ref.residual_history[-1][0]
     assert np.linalg.norm(ug - u_ref) <= 1e-6 * np.linalg.norm(u_ref)
+
+
+@pytest.mark.parametrize("elem", [I.TET4, I.HEX8])
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_linear_model_solve_matches_oracle(elem, prec):
+    """Small-strain linear elasticity (the paper's first example's density):
+    the same load case in one step is a single linear system; the GPU solve
+    and the oracle's agree, and the oracle's residual of the GPU solution
+    meets the tolerance."""
+    print(f"\n[newton] linear model elem={elem} prec={prec}", flush=True)
+    m, op, orc, mask, ubc = setup(elem, 6, 0.1, mu_sigma=0.4, model="linear")
+    u = torch.zeros((m.n_nodes, 3), dtype=torch.float64, device="cuda")
+    rc, st = op.newton_solve(u, dev(ubc), n_steps=1, hvp_prec=prec)
+    assert rc == 0 and st["converged"] == 1, st
+    u_ref, st_ref = F.newton_solve(orc, mask, ubc, F.SolveOptions(n_steps=1))
+    ug = u.cpu().numpy()
+    assert free_residual_norm(orc, ug, mask) <= 2e-8 * st_ref.residual_history[-1][0]
+    assert np.linalg.norm(ug - u_ref) <= 1e-6 * np.linalg.norm(u_ref)
+    # energy of the linear model is quadratic: Psi(u) = u.r(u)/2 at any u
+    assert abs(st["final_energy"] - 0.5 * np.sum(ug * orc.residual(ug))) <= 1e-12 * abs(st["final_energy"])
 
 
 def test_newton_needs_mask():

@@ -39,6 +39,11 @@ CASES = [
     ("hex_6_atomic", I.HEX8, 6, dict(scatter="atomic")),
     ("hex_7_ragged", I.HEX8, 7, dict(block_elems=45, block_nodes=100, threads=64)),
     ("hex_5_scrambled", I.HEX8, 5, dict(scramble=13)),
+    ("tet_6_linear", I.TET4, 6, dict(model="linear")),
+    ("tet_5_linear_small_blocks", I.TET4, 5, dict(model="linear", block_elems=37, block_nodes=40)),
+    ("tet_5_linear_color", I.TET4, 5, dict(model="linear", scatter="color")),
+    ("hex_5_linear", I.HEX8, 5, dict(model="linear")),
+    ("hex_4_linear_atomic", I.HEX8, 4, dict(model="linear", scatter="atomic", block_elems=9)),
 ]
 
 
@@ -61,6 +66,7 @@ class Case:
         from paper_2602_12365_amd import Operator
         opts = dict(opts)
         scramble = opts.pop("scramble", None)
+        model = opts.get("model", "neo_hookean")
         self.mesh = I.make_mesh(elem, n)
         if scramble is not None:
             self.mesh = I.scrambled_mesh(self.mesh, scramble)
@@ -70,7 +76,7 @@ class Case:
         self.u = I.gaussian_field(m.n_nodes, min(I.cube_amplitude(n), 0.05), 0)
         self.v = I.unit_direction(m.n_nodes, 1)
         self.w = I.unit_direction(m.n_nodes, 2)
-        self.orc = F.FEM(elem, m.X, m.conn, self.mu, self.lam)
+        self.orc = F.FEM(elem, m.X, m.conn, self.mu, self.lam, model)
         self.op = Operator(elem, m.X, m.conn, **opts)
         self.op.set_material(dev(self.mu), dev(self.lam))
 
@@ -266,6 +272,46 @@ def test_full_size_64cube_tets():
         op.linearize(dev(u), "f32")
         assert rel(host(op.hvp(dev(v, torch.float32))), ref) <= TOL32
         op.close()
+
+
+def test_full_size_64cube_tets_linear_model():
+    """The same 64^3 mesh under the small-strain linear model: every output
+    entry of energy, residual and both tangent actions against the oracle."""
+    from paper_2602_12365_amd import Operator
+    n = 64
+    m = I.tet_mesh(n)
+    print(f"\n[parity case] full-size tet n={n} linear model", flush=True)
+    u = I.gaussian_field(m.n_nodes, I.cube_amplitude(n), 0)
+    v = I.unit_direction(m.n_nodes, 100)
+    mu, lam = np.ones(m.n_elems), 1.5 * np.ones(m.n_elems)
+    orc = F.FEM(I.TET4, m.X, m.conn, mu, lam, "linear")
+    op = Operator(I.TET4, m.X, m.conn, model="linear")
+    assert abs(host(op.energy(dev(u))) - orc.energy(u)) <= TOL_E * orc.energy(u)
+    assert rel(host(op.residual(dev(u))), orc.residual(u)) <= TOL64
+    ref = orc.hvp(u, v)
+    op.linearize(dev(u), "f64")
+    assert rel(host(op.hvp(dev(v))), ref) <= TOL64
+    op.linearize(dev(u), "f32")
+    assert rel(host(op.hvp(dev(v, torch.float32))), ref) <= TOL32
+    op.close()
+
+
+def test_model_switch_and_bad_model():
+    """efem_set_model switches every operator; an unknown model is rejected."""
+    from paper_2602_12365_amd import Operator
+    m = I.tet_mesh(3)
+    u = I.gaussian_field(m.n_nodes, 0.02, 0)
+    mu, lam = np.ones(m.n_elems), 1.5 * np.ones(m.n_elems)
+    op = Operator(I.TET4, m.X, m.conn)
+    for model in ("linear", "neo_hookean", "linear"):
+        op.set_model(model)
+        orc = F.FEM(I.TET4, m.X, m.conn, mu, lam, model)
+        assert abs(host(op.energy(dev(u))) - orc.energy(u)) <= TOL_E * orc.energy(u)
+    with pytest.raises(ValueError):
+        op.set_model("hyperelastic")
+    from paper_2602_12365_amd import _lib as L
+    assert op._lib.efem_set_model(op._h, 7) == L.EFEM_ERR_INVALID
+    op.close()
 
 
 def test_zero_state(case):

@@ -17,15 +17,21 @@ MUTATIONS = {
     "tangent_last_term_transposed": ("+ c * Fi[J][k] * Fi[L][i]", "+ c * Fi[J][i] * Fi[L][k]"),
     "tangent_lambda_term_transposed": ("lam * Fi[J][i] * Fi[L][k]", "lam * Fi[J][k] * Fi[L][i]"),
     "tangent_dropped_identity": ("(i == k && J == L ? mu : 0.0)", "0.0"),
-    "stress_transposed_inverse": ("mu * (s->F[i][J] - s->Finv[J][i])", "mu * (s->F[i][J] - s->Finv[i][J])"),
-    "energy_log_sign": ("- mu * s->lnJ +", "+ mu * s->lnJ +"),
+    "stress_transposed_inverse": ("Pm[i][J] = s->F[i][J] - s->Finv[J][i];",
+                                  "Pm[i][J] = s->F[i][J] - s->Finv[i][J];"),
+    "energy_log_sign": ("*dmu = 0.5 * s->I1m3 - s->lnJ;", "*dmu = 0.5 * s->I1m3 + s->lnJ;"),
     "gradient_uses_J_inverse_not_transpose": ("t += Ji[J][L] * r->dN[q][a][J]", "t += Ji[L][J] * r->dN[q][a][J]"),
     "jacobian_dropped_det_term": ("+ 0.5 * (trH * trH - trH2) + det3(H);", "+ 0.5 * (trH * trH - trH2);"),
     "coords_adjoint_transposed_H": ("t -= s.H[i][m] * P[i][L]", "t -= s.H[m][i] * P[i][L]"),
     "hex_gauss_point": ("const double g = 1.0 / sqrt(3.0);", "const double g = 0.5;"),
     "diag_wrong_index": ("A[i][J][i][L] * s.gN[a][J] * s.gN[a][L]", "A[i][J][i][J] * s.gN[a][J] * s.gN[a][L]"),
-    "vjp_mu_transposed": ("(s.F[i][J] - s.Finv[J][i]) * gw", "(s.F[i][J] - s.Finv[i][J]) * gw"),
-    "grad_mu_log_sign": ("(0.5 * s.I1m3 - s.lnJ)", "(0.5 * s.I1m3 + s.lnJ)"),
+    "vjp_mu_transposed": ("gm += s.wdetJ * Pm[i][J] * gw;", "gm += s.wdetJ * Pm[J][i] * gw;"),
+    "grad_material_swapped_parts": ("gm += s.wdetJ * pm;", "gm += s.wdetJ * pl;"),
+    "linear_tangent_dropped_minor_symmetry": ("+ (i == L && J == k ? 1.0 : 0.0))", "+ 0.0)"),
+    "linear_stress_factor": ("Pm[i][J] = 2.0 * s->eps[i][J];", "Pm[i][J] = s->eps[i][J];"),
+    "linear_energy_lambda_half": ("*dlam = 0.5 * s->treps * s->treps;", "*dlam = s->treps * s->treps;"),
+    "linear_strain_not_symmetrised": ("s->eps[i][j] = 0.5 * (H[i][j] + H[j][i]);", "s->eps[i][j] = H[i][j];"),
+    "linear_lambda_term_off_diagonal": ("Pl[i][J] = i == J ? s->treps : 0.0;", "Pl[i][J] = s->treps;"),
     "tet_weight": ("r->w[0] = 1.0 / 6.0;", "r->w[0] = 1.0 / 3.0;"),
 }
 

@@ -15,11 +15,14 @@ from tests import pins
 ELEMS = [I.TET4, I.HEX8]
 
 
-def make(elem, n, mu_sigma=0.0, seed=3, lam_ratio=None):
+MODELS = ["neo_hookean", "linear"]
+
+
+def make(elem, n, mu_sigma=0.0, seed=3, lam_ratio=None, model="neo_hookean"):
     m = I.make_mesh(elem, n)
     mu = np.ones(m.n_elems) if mu_sigma == 0 else I.lognormal_field(m.n_elems, mu_sigma, seed)
     lam = 1.5 * np.ones(m.n_elems) if lam_ratio is None else lam_ratio * mu
-    return m, F.FEM(elem, m.X, m.conn, mu, lam)
+    return m, F.FEM(elem, m.X, m.conn, mu, lam, model)
 
 
 def affine(X, F0):
@@ -126,8 +129,9 @@ def test_inverted_element_gives_inf():
 # --------------------------------------------------------------- residual
 
 @pytest.mark.parametrize("elem", ELEMS)
-def test_residual_fd_of_energy(elem):
-    m, f = make(elem, 3, mu_sigma=0.3)
+@pytest.mark.parametrize("model", MODELS)
+def test_residual_fd_of_energy(elem, model):
+    m, f = make(elem, 3, mu_sigma=0.3, model=model)
     u = I.gaussian_field(m.n_nodes, 0.02, 0)
     r = f.residual(u)
     for s in range(3):
@@ -170,8 +174,9 @@ def test_residual_objectivity(elem):
 # ----------------------------------------------------------------- tangent
 
 @pytest.mark.parametrize("elem", ELEMS)
-def test_hvp_fd_of_residual(elem):
-    m, f = make(elem, 3, mu_sigma=0.3)
+@pytest.mark.parametrize("model", MODELS)
+def test_hvp_fd_of_residual(elem, model):
+    m, f = make(elem, 3, mu_sigma=0.3, model=model)
     u = I.gaussian_field(m.n_nodes, 0.02, 0)
     v = I.unit_direction(m.n_nodes, 1)
     h = 1e-6
@@ -181,8 +186,9 @@ def test_hvp_fd_of_residual(elem):
 
 
 @pytest.mark.parametrize("elem", ELEMS)
-def test_hvp_symmetry(elem):
-    m, f = make(elem, 3, mu_sigma=0.3)
+@pytest.mark.parametrize("model", MODELS)
+def test_hvp_symmetry(elem, model):
+    m, f = make(elem, 3, mu_sigma=0.3, model=model)
     u = I.gaussian_field(m.n_nodes, 0.03, 0)
     v = I.unit_direction(m.n_nodes, 1)
     w = I.unit_direction(m.n_nodes, 2)
@@ -221,8 +227,9 @@ def test_tangent_under_rigid_rotation(elem):
 
 
 @pytest.mark.parametrize("elem", ELEMS)
-def test_jacobi_diag_equals_diag_of_K(elem):
-    m, f = make(elem, 2, mu_sigma=0.3)
+@pytest.mark.parametrize("model", MODELS)
+def test_jacobi_diag_equals_diag_of_K(elem, model):
+    m, f = make(elem, 2, mu_sigma=0.3, model=model)
     u = I.gaussian_field(m.n_nodes, 0.02, 7)
     d = f.jacobi_diag(u).ravel()
     assert np.abs(d - np.diag(dense_K(f, u))).max() <= 1e-13 * np.abs(d).max()
@@ -231,8 +238,9 @@ def test_jacobi_diag_equals_diag_of_K(elem):
 # ----------------------------------------------------------- adjoints
 
 @pytest.mark.parametrize("elem", ELEMS)
-def test_grad_material_fd_and_homogeneity(elem):
-    m, f = make(elem, 3, mu_sigma=0.3, lam_ratio=1.5)
+@pytest.mark.parametrize("model", MODELS)
+def test_grad_material_fd_and_homogeneity(elem, model):
+    m, f = make(elem, 3, mu_sigma=0.3, lam_ratio=1.5, model=model)
     u = I.gaussian_field(m.n_nodes, 0.03, 0)
     gm, gl = f.grad_material(u)
     psi = f.energy(u)
@@ -262,8 +270,9 @@ def test_grad_material_affine_closed_form():
 
 
 @pytest.mark.parametrize("elem", ELEMS)
-def test_residual_vjp_material(elem):
-    m, f = make(elem, 3, mu_sigma=0.3, lam_ratio=1.5)
+@pytest.mark.parametrize("model", MODELS)
+def test_residual_vjp_material(elem, model):
+    m, f = make(elem, 3, mu_sigma=0.3, lam_ratio=1.5, model=model)
     u = I.gaussian_field(m.n_nodes, 0.03, 0)
     w = I.unit_direction(m.n_nodes, 5)
     gm, gl = f.residual_vjp_material(u, w)
@@ -281,8 +290,9 @@ def test_residual_vjp_material(elem):
 
 
 @pytest.mark.parametrize("elem", ELEMS)
-def test_grad_coords_fd_and_invariants(elem):
-    m, f = make(elem, 3, mu_sigma=0.3, lam_ratio=1.5)
+@pytest.mark.parametrize("model", MODELS)
+def test_grad_coords_fd_and_invariants(elem, model):
+    m, f = make(elem, 3, mu_sigma=0.3, lam_ratio=1.5, model=model)
     u = I.gaussian_field(m.n_nodes, 0.03, 0)
     g = f.grad_coords(u)
     r = f.residual(u)
@@ -299,6 +309,71 @@ def test_grad_coords_fd_and_invariants(elem):
     h = 1e-6
     for s in range(3):
         w = I.unit_direction(m.n_nodes, 40 + s)
-        fp = F.FEM(elem, m.X + h * w, m.conn, f.mu, f.lam).energy(u)
-        fm = F.FEM(elem, m.X - h * w, m.conn, f.mu, f.lam).energy(u)
+        fp = F.FEM(elem, m.X + h * w, m.conn, f.mu, f.lam, model).energy(u)
+        fm = F.FEM(elem, m.X - h * w, m.conn, f.mu, f.lam, model).energy(u)
         assert abs((fp - fm) / (2 * h) - np.sum(g * w)) <= 1e-7 * np.linalg.norm(g)
+
+
+# ------------------------------------------------ small-strain linear model
+
+@pytest.mark.parametrize("elem", ELEMS)
+def test_linear_model_is_the_textbook_stiffness_at_any_state(elem):
+    """Linear model: K is the Hooke-tensor B^T D B stiffness whatever u is,
+    Psi(u) = u.K u / 2 and r(u) = K u exactly (a quadratic energy)."""
+    m, f = make(elem, 2, mu_sigma=0.4, lam_ratio=1.5, model="linear")
+    Klin = pins.linear_stiffness(elem, m.X, m.conn, f.mu, f.lam)
+    u = I.gaussian_field(m.n_nodes, 0.3, 4)   # large: no smallness is assumed
+    K = dense_K(f, u)
+    assert np.abs(K - Klin).max() <= 1e-13 * np.abs(Klin).max()
+    Ku = Klin @ u.ravel()
+    assert np.abs(f.residual(u).ravel() - Ku).max() <= 1e-13 * np.abs(Ku).max()
+    psi = 0.5 * u.ravel() @ Ku
+    assert abs(f.energy(u) - psi) <= 1e-13 * abs(psi)
+
+
+@pytest.mark.parametrize("elem", ELEMS)
+def test_linear_model_equals_neo_hookean_tangent_at_zero(elem):
+    """The small-strain limit: both models share the reference tangent."""
+    _, fl = make(elem, 2, mu_sigma=0.3, lam_ratio=1.5, model="linear")
+    m, fn = make(elem, 2, mu_sigma=0.3, lam_ratio=1.5)
+    u = I.gaussian_field(m.n_nodes, 0.05, 6)
+    K0 = dense_K(fn, np.zeros_like(m.X))
+    assert np.abs(dense_K(fl, u) - K0).max() <= 1e-13 * np.abs(K0).max()
+
+
+@pytest.mark.parametrize("elem", ELEMS)
+@pytest.mark.parametrize("ci", range(len(F0_CASES)))
+def test_linear_model_patch_test(elem, ci):
+    """Affine u = (G - I) X: Psi = V psi_lin(G - I), and the residual vanishes
+    at every node not on the boundary."""
+    G = F0_CASES[ci] - np.eye(3)
+    m, f = make(elem, 3, model="linear")
+    u = affine(m.X, np.eye(3) + G)
+    vol = np.sum(f.volumes()[0])
+    ref = vol * pins.psi_linear(G, 1.0, 1.5)
+    assert abs(f.energy(u) - ref) <= 1e-13 * abs(ref)
+    inner = np.all((m.X > 1e-12) & (m.X < 1 - 1e-12), axis=1)
+    r = f.residual(u)
+    assert np.abs(r[inner]).max() <= 1e-13 * np.abs(r).max()
+
+
+@pytest.mark.parametrize("elem", ELEMS)
+def test_linear_model_infinitesimal_rotation_is_strain_free(elem):
+    """A skew displacement gradient has eps = 0: no energy, no force."""
+    W = np.array([[0.0, 0.3, -0.2], [-0.3, 0.0, 0.1], [0.2, -0.1, 0.0]])
+    m, f = make(elem, 3, mu_sigma=0.3, model="linear")
+    u = m.X @ W.T + np.array([0.1, -0.2, 0.3])
+    assert abs(f.energy(u)) <= 1e-15
+    assert np.abs(f.residual(u)).max() <= 1e-14
+
+
+def test_linear_model_grad_material_closed_form():
+    """Affine strain: dPsi/dmu_e = V_e eps:eps, dPsi/dlam_e = V_e (tr eps)^2 / 2."""
+    G = F0_CASES[0] - np.eye(3)
+    eps = 0.5 * (G + G.T)
+    for elem in ELEMS:
+        m, f = make(elem, 2, model="linear")
+        gm, gl = f.grad_material(affine(m.X, np.eye(3) + G))
+        vol, _ = f.volumes()
+        assert np.abs(gm - vol * np.sum(eps * eps)).max() <= 1e-15
+        assert np.abs(gl - vol * 0.5 * np.trace(eps) ** 2).max() <= 1e-15
