@@ -7,10 +7,13 @@ this package imports nothing from the product path; inputs reach both sides as
 plain numpy arrays.
 
 * ``oracle.fem``    element operators (energy, residual, tangent action,
-                    Jacobi diagonal, material and coordinate adjoints) in plain
-                    C (``efem_oracle.c``), Dirichlet condensation, Newton-CG.
+                    Jacobi diagonal, material and coordinate adjoints) for the
+                    neo-Hookean and linear-elastic densities in plain C
+                    (``efem_oracle.c``), Dirichlet condensation, Newton-CG.
 * ``oracle.mlp``    forward and backward of the per-node MLP in FP64 numpy.
 * ``oracle.precond`` node features of the learned preconditioner.
+* ``oracle.transport`` the non-variational transport operator (virtual work,
+                    Sec. 5.5): residual, element matrices, direct reduced solve.
 
 Every function cites the passage of the paper it follows.  Functions with no
 independent pin say "parity unpinned" in their docstring.

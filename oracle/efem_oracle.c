@@ -63,6 +63,7 @@ typedef struct {
     int nq;             /* quadrature points */
     double w[8];        /* weights */
     double dN[8][8][3]; /* dN[q][a][J]: reference gradients at point q */
+    double N[8][8];     /* N[q][a]: shape function values at point q */
 } rule_t;
 
 static int make_rule(int type, rule_t *r)
@@ -73,8 +74,10 @@ static int make_rule(int type, rule_t *r)
         r->nen = 4;
         r->nq = 1;
         r->w[0] = 1.0 / 6.0;
-        for (int a = 0; a < 4; ++a)
+        for (int a = 0; a < 4; ++a) {
             for (int J = 0; J < 3; ++J) r->dN[0][a][J] = g[a][J];
+            r->N[0][a] = 0.25;   /* the centroid xi = eta = zeta = 1/4 */
+        }
         return 0;
     }
     if (type == ORC_HEX8) {
@@ -95,6 +98,7 @@ static int make_rule(int type, rule_t *r)
                         r->dN[q][a][0] = 0.125 * c[a][0] * f1 * f2;
                         r->dN[q][a][1] = 0.125 * f0 * c[a][1] * f2;
                         r->dN[q][a][2] = 0.125 * f0 * f1 * c[a][2];
+                        r->N[q][a] = 0.125 * f0 * f1 * f2;
                     }
                 }
         return 0;
@@ -594,6 +598,99 @@ int orc_grad_coords(int type, int model, int64_t nn, int64_t ne, const double *X
     scatter_blocks(&r, nn, ne, conn, blk, gX);
     free(blk);
     return bad ? -4 : 0;
+}
+
+/* ------------------------------------------- non-variational transport */
+
+/* The virtual-work form of Sec. 5.5, for the advection-diffusion example's
+ * weak form (steady, or one implicit time step with k = 1/dt), applied to
+ * three species carried in the three nodal components s:
+ *   W(c, v) = sum_s int [ D grad c_s . grad v_s + (b . grad c_s) v_s + k c_s v_s ]
+ *   r = dW/dv:  r_{a,s} = sum_e sum_q w detJ [ D grad c_s . grad N_a
+ *                                              + (b(x_q) . grad c_s + k c_s(x_q)) N_a ]
+ * with b(x) = omega x x (a rigid rotation: divergence-free, as in the
+ * example), D = D_e and k = k_e per element.  r is linear in c, so the tangent
+ * K = dr/dc is constant and K v = r(v); the advection term makes it
+ * non-symmetric.  With `Ke` non-null the element matrices
+ * Ke[e][(a,s)][(b,t)] = dr_{a,s}/dc_{b,t} are written instead of r. */
+static int transport(int type, int64_t nn, int64_t ne, const double *X, const int32_t *conn,
+                     const double *D, const double *k, const double *omega, const double *c,
+                     double *res, double *Ke)
+{
+    rule_t r;
+    if (check_args(type, ORC_NEO_HOOKE, nn, ne, conn, &r)) return -1;
+    const int m = 3 * r.nen;
+    double *blk = NULL;
+    if (!Ke) {
+        blk = (double *)calloc((size_t)(ne * r.nen * 3 + 1), sizeof(double));
+        if (!blk) return -1;
+    }
+    int bad = 0;
+#pragma omp parallel for schedule(static) reduction(|| : bad)
+    for (int64_t e = 0; e < ne; ++e) {
+        double Xe[8][3], ce[8][3] = {{0}}, zero[8][3] = {{0}};
+        gather(&r, X, conn + e * r.nen, Xe);
+        if (c) gather(&r, c, conn + e * r.nen, ce);
+        double *f = Ke ? NULL : blk + e * r.nen * 3;
+        double *K = Ke ? Ke + e * (int64_t)m * m : NULL;
+        if (K) memset(K, 0, sizeof(double) * (size_t)(m * m));
+        for (int q = 0; q < r.nq; ++q) {
+            qp_t s;
+            qp_eval(&r, q, Xe, zero, ORC_LINEAR, &s);   /* geometry only */
+            if (!s.ok) { bad = 1; break; }
+            double xq[3] = {0, 0, 0};
+            for (int a = 0; a < r.nen; ++a)
+                for (int i = 0; i < 3; ++i) xq[i] += r.N[q][a] * Xe[a][i];
+            const double b[3] = {omega[1] * xq[2] - omega[2] * xq[1], omega[2] * xq[0] - omega[0] * xq[2],
+                                 omega[0] * xq[1] - omega[1] * xq[0]};
+            if (K) {
+                /* dr_{a,s}/dc_{b,s} = w detJ [D gN_a.gN_b + (b.gN_b) N_a + k N_b N_a] */
+                for (int a = 0; a < r.nen; ++a)
+                    for (int bb = 0; bb < r.nen; ++bb) {
+                        double dd = 0, adv = 0;
+                        for (int L = 0; L < 3; ++L) {
+                            dd += s.gN[a][L] * s.gN[bb][L];
+                            adv += b[L] * s.gN[bb][L];
+                        }
+                        const double kab = s.wdetJ * (D[e] * dd + adv * r.N[q][a] + k[e] * r.N[q][bb] * r.N[q][a]);
+                        for (int sp = 0; sp < 3; ++sp) K[(3 * a + sp) * m + 3 * bb + sp] += kab;
+                    }
+                continue;
+            }
+            for (int sp = 0; sp < 3; ++sp) {
+                double gc[3] = {0, 0, 0}, cq = 0;
+                for (int a = 0; a < r.nen; ++a) {
+                    cq += r.N[q][a] * ce[a][sp];
+                    for (int L = 0; L < 3; ++L) gc[L] += ce[a][sp] * s.gN[a][L];
+                }
+                const double val = b[0] * gc[0] + b[1] * gc[1] + b[2] * gc[2] + k[e] * cq;
+                for (int a = 0; a < r.nen; ++a) {
+                    const double diff = gc[0] * s.gN[a][0] + gc[1] * s.gN[a][1] + gc[2] * s.gN[a][2];
+                    f[a * 3 + sp] += s.wdetJ * (D[e] * diff + val * r.N[q][a]);
+                }
+            }
+        }
+    }
+    if (!Ke) {
+        scatter_blocks(&r, nn, ne, conn, blk, res);
+        free(blk);
+    }
+    return bad ? -4 : 0;
+}
+
+int orc_transport_residual(int type, int64_t nn, int64_t ne, const double *X, const int32_t *conn,
+                           const double *D, const double *k, const double *omega, const double *c,
+                           double *res)
+{
+    if (!c || !res) return -1;
+    return transport(type, nn, ne, X, conn, D, k, omega, c, res, NULL);
+}
+
+int orc_transport_tangents(int type, int64_t nn, int64_t ne, const double *X, const int32_t *conn,
+                           const double *D, const double *k, const double *omega, double *Ke)
+{
+    if (!Ke) return -1;
+    return transport(type, nn, ne, X, conn, D, k, omega, NULL, NULL, Ke);
 }
 
 /* Element volumes sum_q w detJ, for mesh checks.  Returns -4 if any det J <= 0. */

@@ -33,7 +33,15 @@ MUTATIONS = {
     "linear_strain_not_symmetrised": ("s->eps[i][j] = 0.5 * (H[i][j] + H[j][i]);", "s->eps[i][j] = H[i][j];"),
     "linear_lambda_term_off_diagonal": ("Pl[i][J] = i == J ? s->treps : 0.0;", "Pl[i][J] = s->treps;"),
     "tet_weight": ("r->w[0] = 1.0 / 6.0;", "r->w[0] = 1.0 / 3.0;"),
+    "transport_rotation_orientation": ("const double b[3] = {omega[1] * xq[2] - omega[2] * xq[1],",
+                                       "const double b[3] = {omega[2] * xq[1] - omega[1] * xq[2],"),
+    "transport_matrix_test_trial_swapped": ("adv += b[L] * s.gN[bb][L];", "adv += b[L] * s.gN[a][L];"),
+    "transport_matrix_reaction_dropped_trial": ("k[e] * r.N[q][bb] * r.N[q][a]", "k[e] * r.N[q][a]"),
+    "transport_residual_dropped_diffusion": ("(D[e] * diff + val * r.N[q][a])", "(val * r.N[q][a])"),
+    "transport_residual_value_not_interpolated": ("cq += r.N[q][a] * ce[a][sp];", "cq += ce[a][sp];"),
+    "tet_centroid_value": ("r->N[0][a] = 0.25;", "r->N[0][a] = 1.0 / 3.0;"),
 }
+PIN_FILES = ["test_oracle_pins.py", "test_oracle_transport.py"]
 
 
 @pytest.mark.parametrize("name", sorted(MUTATIONS))
@@ -47,7 +55,7 @@ def test_pins_catch_planted_mistake(name, tmp_path):
     subprocess.run(["gcc", "-O2", "-std=c11", "-fopenmp", "-ffp-contract=off", "-fPIC", "-shared",
                     str(mutated), "-o", str(lib), "-lm"], check=True)
     env = dict(os.environ, EFEM_ORACLE_LIB=str(lib), OMP_NUM_THREADS="2")
-    res = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
-                          os.path.join(ROOT, "tests", "test_oracle_pins.py")],
+    res = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider"]
+                         + [os.path.join(ROOT, "tests", f) for f in PIN_FILES],
                          cwd=ROOT, env=env, capture_output=True, text=True, timeout=300)
     assert res.returncode != 0, f"pins did not catch mutation {name}:\n{res.stdout[-2000:]}"
