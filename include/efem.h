@@ -66,6 +66,7 @@ extern "C" {
 /* material models (efem_set_model) */
 #define EFEM_MODEL_NEO_HOOKE 0
 #define EFEM_MODEL_LINEAR    1
+#define EFEM_MODEL_TRANSPORT 2   /* non-variational: virtual work, no energy */
 
 /* arithmetic of the tangent action */
 #define EFEM_F64 0
@@ -130,9 +131,26 @@ int efem_set_material(efem_ctx *ctx, const double *mu, const double *lam);
  * residual, tangent action, diagonal, adjoints, solves, sparse tangent) uses
  * it.  Under the linear model the tangent does not depend on u, so the state
  * given to efem_linearize is not read by efem_hvp (linearize is still required
- * first), and there is no det F condition.  Returns EFEM_ERR_INVALID for an
- * unknown model. */
+ * first), and there is no det F condition.
+ *
+ * EFEM_MODEL_TRANSPORT is the non-variational case of Sec. 5.5: a virtual-work
+ * functional W(c, v) instead of an energy, here the advection-diffusion
+ * example's weak form (steady, or one implicit time step with k = 1/dt) for
+ * three species carried in the three nodal components:
+ *   r_{a,s}(c) = sum_e sum_q w det J [ D grad c_s . grad N_a
+ *                                      + (b(x_q) . grad c_s + k c_s) N_a ]
+ * with D = mu_e, k = lam_e (efem_set_material) and b(x) = omega x x
+ * (efem_set_velocity).  efem_residual returns r(c), efem_hvp K v (K = dr/dc
+ * is constant and non-symmetric), efem_jacobi_diag diag K, and
+ * efem_gmres_solve solves with it.  There is no energy: efem_energy, the
+ * material and coordinate adjoints, efem_newton_solve and the CG-based
+ * solves return EFEM_ERR_STATE.  Returns EFEM_ERR_INVALID for an unknown
+ * model. */
 int efem_set_model(efem_ctx *ctx, int32_t model);
+
+/* Rotation vector omega (HOST float64 [3]) of the transport model's
+ * velocity b(x) = omega x x (divergence-free).  Default 0. */
+int efem_set_velocity(efem_ctx *ctx, const double *omega);
 
 /* Replace the reference coordinates (DEVICE float64 [3*n_nodes]) keeping the
  * connectivity and the element blocks (e.g. for derivatives with respect to X
@@ -360,6 +378,22 @@ int efem_cg_snapshots(efem_ctx *ctx, const double *u, const double *b, double si
 int efem_linear_solve(efem_ctx *ctx, const double *u, const double *b, double *x, double rtol,
                       int32_t hvp_prec, int32_t precond, int32_t max_iter, int32_t *iters,
                       int32_t *fallback);
+
+/* Solve K(u)_ff x = b by restarted GMRES(restart) with right Jacobi
+ * preconditioning, from x = 0, to ||b - K x|| <= rtol ||b|| on the free DOFs
+ * (all DOFs without a Dirichlet mask).  The Krylov solver of the
+ * non-symmetric transport model (Sec. 5.5), usable with every model.
+ * u, b, x: DEVICE float64 [3*n_nodes] (x distinct from u and b; prescribed
+ * entries of b ignored, of x set to 0).  hvp_prec: EFEM_F64 or EFEM_F32 for
+ * the tangent actions (the basis is float64 either way); restart in
+ * [1, 100]; max_iter caps the total iterations.  Allocates (restart + 5)
+ * float64 vectors for the solve.  Synchronous; *iters receives the
+ * iterations, *relres the relative residual ||b - K x|| / ||b|| of the
+ * returned x, recomputed with one more tangent action.  Returns
+ * EFEM_NOT_CONVERGED when max_iter is reached first. */
+int efem_gmres_solve(efem_ctx *ctx, const double *u, const double *b, double *x, double rtol,
+                     int32_t hvp_prec, int32_t restart, int32_t max_iter, int32_t *iters,
+                     double *relres);
 
 /* ------------------------------------------ sparse tangent by colouring
  * The paper's second technique (Alg. 2): the tangent K(u) as a sparse matrix,

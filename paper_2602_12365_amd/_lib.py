@@ -21,7 +21,7 @@ EFEM_ERR_STATE = -5
 
 EFEM_TET4, EFEM_HEX8 = 0, 1
 EFEM_F64, EFEM_F32 = 0, 1
-EFEM_MODEL_NEO_HOOKE, EFEM_MODEL_LINEAR = 0, 1
+EFEM_MODEL_NEO_HOOKE, EFEM_MODEL_LINEAR, EFEM_MODEL_TRANSPORT = 0, 1, 2
 EFEM_SCATTER_HALO, EFEM_SCATTER_COLOR, EFEM_SCATTER_ATOMIC = 0, 1, 2
 
 EFEM_MLP_IN, EFEM_MLP_HID, EFEM_MLP_OUT = 12, 64, 3
@@ -111,6 +111,10 @@ SIGNATURES = {
     "efem_linear_solve": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_double, c_int32,
                                     c_int32, c_int32, ctypes.POINTER(c_int32),
                                     ctypes.POINTER(c_int32)]),
+    "efem_gmres_solve": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_double, c_int32,
+                                   c_int32, c_int32, ctypes.POINTER(c_int32),
+                                   ctypes.POINTER(c_double)]),
+    "efem_set_velocity": (c_int32, [c_void_p, ctypes.POINTER(c_double)]),
     "efem_last_error": (ctypes.c_char_p, []),
 }
 

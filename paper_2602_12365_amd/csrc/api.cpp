@@ -568,11 +568,26 @@ int efem_set_model(efem_ctx *ctx, int32_t model)
         set_error("efem_set_model: null context");
         return EFEM_ERR_INVALID;
     }
-    if (model != EFEM_MODEL_NEO_HOOKE && model != EFEM_MODEL_LINEAR) {
+    if (model != EFEM_MODEL_NEO_HOOKE && model != EFEM_MODEL_LINEAR && model != EFEM_MODEL_TRANSPORT) {
         set_error("efem_set_model: unknown material model");
         return EFEM_ERR_INVALID;
     }
     ctx->model = model;
+    return EFEM_OK;
+}
+
+int efem_set_velocity(efem_ctx *ctx, const double *omega)
+{
+    if (!ctx || !omega) {
+        set_error("efem_set_velocity: null pointer");
+        return EFEM_ERR_INVALID;
+    }
+    for (int i = 0; i < 3; ++i)
+        if (!std::isfinite(omega[i])) {
+            set_error("efem_set_velocity: omega must be finite");
+            return EFEM_ERR_INVALID;
+        }
+    for (int i = 0; i < 3; ++i) ctx->omega[i] = omega[i];
     return EFEM_OK;
 }
 
@@ -647,9 +662,21 @@ int efem_set_dirichlet(efem_ctx *ctx, const uint8_t *mask)
         }                                              \
     } while (0)
 
+// The transport model is non-variational: it has a residual and a tangent
+// but no energy, so the energy and its parameter / coordinate derivatives
+// are refused.
+#define NEEDS_ENERGY(name)                                                              \
+    do {                                                                                \
+        if (ctx->model == EFEM_MODEL_TRANSPORT) {                                       \
+            set_error(name ": the transport model has no energy (non-variational)");    \
+            return EFEM_ERR_STATE;                                                      \
+        }                                                                               \
+    } while (0)
+
 int efem_energy(efem_ctx *ctx, const double *u, double *psi)
 {
     CHECK_ARGS(u && psi, "efem_energy");
+    NEEDS_ENERGY("efem_energy");
     DeviceGuard dg(ctx->device);
     HIP_TRY(launch_energy(*ctx, u, psi));
     return EFEM_OK;
@@ -732,6 +759,7 @@ int efem_jacobi_diag(efem_ctx *ctx, const double *u, double *d)
 int efem_grad_material(efem_ctx *ctx, const double *u, double *dmu, double *dlam)
 {
     CHECK_ARGS(u && dmu && dlam, "efem_grad_material");
+    NEEDS_ENERGY("efem_grad_material");
     DeviceGuard dg(ctx->device);
     HIP_TRY(launch_grad_material(*ctx, u, dmu, dlam));
     return EFEM_OK;
@@ -741,6 +769,7 @@ int efem_residual_vjp_material(efem_ctx *ctx, const double *u, const double *w, 
                                double *dlam)
 {
     CHECK_ARGS(u && w && dmu && dlam, "efem_residual_vjp_material");
+    NEEDS_ENERGY("efem_residual_vjp_material");
     DeviceGuard dg(ctx->device);
     HIP_TRY(launch_vjp_material(*ctx, u, w, dmu, dlam));
     return EFEM_OK;
@@ -749,6 +778,7 @@ int efem_residual_vjp_material(efem_ctx *ctx, const double *u, const double *w, 
 int efem_grad_coords(efem_ctx *ctx, const double *u, double *dX)
 {
     CHECK_ARGS(u && dX, "efem_grad_coords");
+    NEEDS_ENERGY("efem_grad_coords");
     DeviceGuard dg(ctx->device);
     HIP_TRY(launch_grad_coords(*ctx, u, dX));
     return EFEM_OK;

@@ -93,6 +93,7 @@ hipError_t launch_uniform_check(const double *a, const double *b, int64_t n, int
 struct Ctx {
     int elem = 0, nen = 4, nq = 1;
     int32_t model = EFEM_MODEL_NEO_HOOKE;
+    double omega[3] = {0.0, 0.0, 0.0};   // transport model: velocity b(x) = omega x x
     int64_t n_nodes = 0, n_elems = 0, n_items = 0;
     int device = 0;
     hipStream_t stream = nullptr;

@@ -242,6 +242,11 @@ struct Tet4Pair {
         if (a == 0) return T(-1);
         return node(q, J + 1) == a ? T(1) : T(0);
     }
+    // N_a at point q, the centroid of tet q: 1/4 on its four nodes
+    template <class T> __device__ static __forceinline__ T N(int q, int a)
+    {
+        return (q == 0 ? a != 4 : a != 3) ? T(0.25) : T(0);
+    }
 };
 
 // Hex8 in node form: the same element with gradients and forces as sums over
@@ -261,6 +266,14 @@ struct Hex8Nodes {
         const T f2 = T(1) + T(kHexSgn[a][2]) * p2;
         const T s = T(0.125) * T(kHexSgn[a][J]);
         return J == 0 ? s * f1 * f2 : (J == 1 ? s * f0 * f2 : s * f0 * f1);
+    }
+    // N_a at Gauss point q
+    template <class T> __device__ static __forceinline__ T N(int q, int a)
+    {
+        const T g = T(0.57735026918962576451);
+        const T p0 = (q & 1) ? g : -g, p1 = (q & 2) ? g : -g, p2 = (q & 4) ? g : -g;
+        return T(0.125) * (T(1) + T(kHexSgn[a][0]) * p0) * (T(1) + T(kHexSgn[a][1]) * p1)
+             * (T(1) + T(kHexSgn[a][2]) * p2);
     }
     template <class T> struct Field {
         T f[NEN][3];
@@ -1153,6 +1166,144 @@ struct LinGradCoordsOp : XUStage {
     }
 };
 
+// ---- non-variational transport (virtual work): three species in the three
+// nodal components, per species s and node a
+//   r_{a,s} = sum_q w det J [ D grad c_s . grad N_a + (b(x_q) . grad c_s + k c_s) N_a ]
+// with b(x) = omega x x, D = mu_e, k = lam_e.  Linear in c: the residual of c
+// and the tangent action on v are the same map; the advection term makes the
+// tangent non-symmetric.  Gradients and forces in the node form (E::Lean),
+// which also interpolates values.
+
+template <class T> struct TransportOp {
+    using Node = NodeXV<T>;
+    const T *X, *c;
+    T om0, om1, om2;
+    int mask_input;   // tangent action: prescribed components of v read as 0
+    __device__ void stage(const BlockMesh &m, Node &n, int64_t g) const
+    {
+        load3(X, g, n.X);
+        load3(c, g, n.v);
+        if (mask_input && m.nmask) {
+            const uint8_t b = m.nmask[g];
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+                if ((b >> i) & 1) n.v[i] = T(0);
+        }
+    }
+    template <class E>
+    __device__ __forceinline__ bool element(const Node *sn, const uint16_t *lc, const T *mu, const T *lam,
+                                            bool pair, T f[E::NEN][3]) const
+    {
+        using G = typename E::Lean;
+        T Xe[E::NEN][3], ce[E::NEN][3];
+#pragma unroll
+        for (int a = 0; a < E::NEN; ++a)
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                Xe[a][i] = sn[lc[a]].X[i];
+                ce[a][i] = sn[lc[a]].v[i];
+                f[a][i] = T(0);
+            }
+        typename G::template Field<T> FX, Fc;
+        G::prep(Xe, FX);
+        G::prep(ce, Fc);
+#pragma unroll
+        for (int q = 0; q < E::NQ; ++q) {
+            if (E::skip(q, pair)) continue;
+            T Jx[9], Cxi[9], Ae[9], Gc[9], Q[9];
+            G::grad(FX, q, Jx);
+            G::grad(Fc, q, Cxi);
+            const T De = lin_grad(Jx, Cxi, Ae, Gc);   // Gc[s][L] = d c_s / d x_L
+            T xq[3] = {T(0), T(0), T(0)}, cq[3] = {T(0), T(0), T(0)};
+#pragma unroll
+            for (int a = 0; a < E::NEN; ++a) {
+                const T Na = G::template N<T>(q, a);
+#pragma unroll
+                for (int i = 0; i < 3; ++i) {
+                    xq[i] += Na * Xe[a][i];
+                    cq[i] += Na * ce[a][i];
+                }
+            }
+            const T b0 = om1 * xq[2] - om2 * xq[1], b1 = om2 * xq[0] - om0 * xq[2], b2 = om0 * xq[1] - om1 * xq[0];
+            const T w = E::template weight<T>(), D = mu[E::sub(q)], k = lam[E::sub(q)];
+            // diffusion: w det Jx D grad c Jx^-T = w D Gc Ae^T
+#pragma unroll
+            for (int sp = 0; sp < 3; ++sp)
+#pragma unroll
+                for (int J = 0; J < 3; ++J)
+                    Q[sp * 3 + J] = w * D * (Gc[sp * 3 + 0] * Ae[J * 3 + 0] + Gc[sp * 3 + 1] * Ae[J * 3 + 1]
+                                             + Gc[sp * 3 + 2] * Ae[J * 3 + 2]);
+            G::template add_forces_to<false>(Q, q, f);
+            const T wDe = w * De;
+            T g[3];
+#pragma unroll
+            for (int sp = 0; sp < 3; ++sp)
+                g[sp] = wDe * (b0 * Gc[sp * 3 + 0] + b1 * Gc[sp * 3 + 1] + b2 * Gc[sp * 3 + 2] + k * cq[sp]);
+#pragma unroll
+            for (int a = 0; a < E::NEN; ++a) {
+                const T Na = G::template N<T>(q, a);
+#pragma unroll
+                for (int sp = 0; sp < 3; ++sp) f[a][sp] += Na * g[sp];
+            }
+        }
+        return true;
+    }
+};
+
+// diag K of the transport operator (the same for the three species):
+// w det J [D |grad N_a|^2 + (b . grad N_a) N_a + k N_a^2], grad N_a = Ae^T n / De
+struct TransportDiagOp : XUStage {
+    using Node = NodeXU;
+    double om0, om1, om2;
+    template <class E>
+    __device__ __forceinline__ bool element(const Node *sn, const uint16_t *lc, const double *mu,
+                                            const double *lam, bool pair, double f[E::NEN][3]) const
+    {
+        using G = typename E::Lean;
+        double Xe[E::NEN][3];
+#pragma unroll
+        for (int a = 0; a < E::NEN; ++a)
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                Xe[a][i] = sn[lc[a]].X[i];
+                f[a][i] = 0.0;
+            }
+        typename G::template Field<double> FX;
+        G::prep(Xe, FX);
+#pragma unroll
+        for (int q = 0; q < E::NQ; ++q) {
+            if (E::skip(q, pair)) continue;
+            double Jx[9], Ae[9];
+            G::grad(FX, q, Jx);
+            const double De = adj_det(Jx, Ae);
+            double xq[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+            for (int a = 0; a < E::NEN; ++a)
+#pragma unroll
+                for (int i = 0; i < 3; ++i) xq[i] += G::template N<double>(q, a) * Xe[a][i];
+            const double b0 = om1 * xq[2] - om2 * xq[1], b1 = om2 * xq[0] - om0 * xq[2],
+                         b2 = om0 * xq[1] - om1 * xq[0];
+            const double w = E::template weight<double>(), D = mu[E::sub(q)], k = lam[E::sub(q)];
+#pragma unroll
+            for (int n = 0; n < E::NEN; ++n) {
+                const double g0 = G::template dN<double>(q, n, 0);
+                const double g1 = G::template dN<double>(q, n, 1);
+                const double g2 = G::template dN<double>(q, n, 2);
+                const double t0 = Ae[0] * g0 + Ae[3] * g1 + Ae[6] * g2;
+                const double t1 = Ae[1] * g0 + Ae[4] * g1 + Ae[7] * g2;
+                const double t2 = Ae[2] * g0 + Ae[5] * g1 + Ae[8] * g2;
+                const double Nn = G::template N<double>(q, n);
+                const double d = w * (D * (t0 * t0 + t1 * t1 + t2 * t2) / De + (b0 * t0 + b1 * t1 + b2 * t2) * Nn
+                                      + De * k * Nn * Nn);
+                f[n][0] += d;
+                f[n][1] += d;
+                f[n][2] += d;
+            }
+        }
+        return true;
+    }
+};
+
 // ------------------------------------------------------------ per-item inputs
 
 // Work items of one block.  Pairs come first; item k covers the internal
@@ -1660,6 +1811,10 @@ static hipError_t dispatch(const Ctx &c, const Op &op, T *y, bool use_mask, T fi
 
 hipError_t launch_residual(const Ctx &c, const double *u, double *r)
 {
+    if (c.model == EFEM_MODEL_TRANSPORT) {
+        TransportOp<double> op{c.m.X, u, c.omega[0], c.omega[1], c.omega[2], 0};
+        return dispatch(c, op, r, true, 0.0);
+    }
     if (c.model == EFEM_MODEL_LINEAR) {
         LinResidualOp op;
         op.X = c.m.X;
@@ -1674,6 +1829,15 @@ hipError_t launch_residual(const Ctx &c, const double *u, double *r)
 
 hipError_t launch_diag(const Ctx &c, const double *u, double *d)
 {
+    if (c.model == EFEM_MODEL_TRANSPORT) {
+        TransportDiagOp op;
+        op.X = c.m.X;
+        op.u = u;
+        op.om0 = c.omega[0];
+        op.om1 = c.omega[1];
+        op.om2 = c.omega[2];
+        return dispatch(c, op, d, true, 1.0);
+    }
     if (c.model == EFEM_MODEL_LINEAR) {
         LinDiagOp op;
         op.X = c.m.X;
@@ -1703,6 +1867,10 @@ hipError_t launch_grad_coords(const Ctx &c, const double *u, double *g)
 hipError_t launch_hvp_f64(const Ctx &c, const double *xlin, const double *v, double *y,
                           const int32_t *skip, WriteMode mode)
 {
+    if (c.model == EFEM_MODEL_TRANSPORT) {
+        TransportOp<double> op{c.m.X, v, c.omega[0], c.omega[1], c.omega[2], 1};
+        return dispatch(c, op, y, true, 0.0, skip, mode);
+    }
     if (c.model == EFEM_MODEL_LINEAR) {
         LinHvpOp<double> op{c.m.X, v};
         return dispatch(c, op, y, true, 0.0, skip, mode);
@@ -1714,6 +1882,10 @@ hipError_t launch_hvp_f64(const Ctx &c, const double *xlin, const double *v, dou
 hipError_t launch_hvp_f32(const Ctx &c, const float *ulin, const float *v, float *y,
                           const int32_t *skip, WriteMode mode)
 {
+    if (c.model == EFEM_MODEL_TRANSPORT) {
+        TransportOp<float> op{c.m.Xf, v, float(c.omega[0]), float(c.omega[1]), float(c.omega[2]), 1};
+        return dispatch(c, op, y, true, 0.0f, skip, mode);
+    }
     if (c.model == EFEM_MODEL_LINEAR) {
         LinHvpOp<float> op{c.m.Xf, v};
         return dispatch(c, op, y, true, 0.0f, skip, mode);

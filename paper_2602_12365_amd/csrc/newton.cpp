@@ -415,6 +415,10 @@ int efem_newton_solve(efem_ctx *ctx, double *u_inout, const double *u_bc, const 
         set_error("efem_newton_solve: set a Dirichlet mask first (efem_set_dirichlet)");
         return EFEM_ERR_STATE;
     }
+    if (ctx->model == EFEM_MODEL_TRANSPORT) {
+        set_error("efem_newton_solve: the transport model has no energy; use efem_gmres_solve");
+        return EFEM_ERR_STATE;
+    }
     if (opts->n_steps < 1 || opts->max_cg < 1 || opts->max_newton < 0 || opts->rtol <= 0
         || (opts->hvp_prec != EFEM_F64 && opts->hvp_prec != EFEM_F32)) {
         set_error("efem_newton_solve: bad options");
@@ -454,6 +458,10 @@ extern "C" int efem_linear_solve(efem_ctx *ctx, const double *u, const double *b
     }
     if (!ctx->m.nmask) {
         set_error("efem_linear_solve: set a Dirichlet mask first (efem_set_dirichlet)");
+        return EFEM_ERR_STATE;
+    }
+    if (ctx->model == EFEM_MODEL_TRANSPORT) {
+        set_error("efem_linear_solve: CG needs a symmetric tangent; use efem_gmres_solve");
         return EFEM_ERR_STATE;
     }
     if (precond == 1) {
@@ -496,6 +504,10 @@ extern "C" int efem_cg_snapshots(efem_ctx *ctx, const double *u, const double *b
         }
     if (!ctx->m.nmask) {
         set_error("efem_cg_snapshots: set a Dirichlet mask first (efem_set_dirichlet)");
+        return EFEM_ERR_STATE;
+    }
+    if (ctx->model == EFEM_MODEL_TRANSPORT) {
+        set_error("efem_cg_snapshots: CG needs a symmetric tangent");
         return EFEM_ERR_STATE;
     }
     efem_solve_opts o;

@@ -17,7 +17,8 @@ from . import _lib as L
 
 _ELEM = {"tet4": L.EFEM_TET4, "hex8": L.EFEM_HEX8, L.EFEM_TET4: L.EFEM_TET4, L.EFEM_HEX8: L.EFEM_HEX8}
 _PREC = {"f64": L.EFEM_F64, "f32": L.EFEM_F32, torch.float64: L.EFEM_F64, torch.float32: L.EFEM_F32}
-_MODEL = {"neo_hookean": L.EFEM_MODEL_NEO_HOOKE, "linear": L.EFEM_MODEL_LINEAR}
+_MODEL = {"neo_hookean": L.EFEM_MODEL_NEO_HOOKE, "linear": L.EFEM_MODEL_LINEAR,
+          "transport": L.EFEM_MODEL_TRANSPORT}
 _SCATTER = {"halo": L.EFEM_SCATTER_HALO, "color": L.EFEM_SCATTER_COLOR, "atomic": L.EFEM_SCATTER_ATOMIC}
 
 
@@ -109,12 +110,20 @@ class Operator:
                                             _ptr(self._elemwise(lam, "lam"))), "efem_set_material")
 
     def set_model(self, model):
-        """Strain energy density: "neo_hookean" (default) or "linear" (small strain)."""
+        """Strain energy density: "neo_hookean" (default) or "linear" (small
+        strain); or "transport", the non-variational advection-diffusion
+        operator of three species (mu = diffusivity, lam = reaction rate,
+        velocity omega x x from set_velocity), which has no energy."""
         if model not in _MODEL:
             raise ValueError(f"unknown material model {model!r}")
         L.check(self._lib.efem_set_model(self._h, _MODEL[model]), "efem_set_model")
         self.model = model
         self._lin = None
+
+    def set_velocity(self, omega):
+        """Rotation vector of the transport model's velocity b(x) = omega x x."""
+        om = (ctypes.c_double * 3)(*[float(v) for v in omega])
+        L.check(self._lib.efem_set_velocity(self._h, om), "efem_set_velocity")
 
     def set_coords(self, X):
         """Replace the reference coordinates (float64 [n_nodes, 3] device tensor),
@@ -303,6 +312,18 @@ class Operator:
                                             _PREC[hvp_prec], int(precond), int(max_iter),
                                             ctypes.byref(it), ctypes.byref(fb)), "efem_linear_solve")
         return x, it.value, bool(fb.value)
+
+    def gmres_solve(self, u, b, rtol=1e-8, hvp_prec="f64", restart=30, max_iter=100000):
+        """Solve K(u)_ff x = b by restarted GMRES with right Jacobi
+        preconditioning; returns (x, iterations, relative residual, converged)."""
+        self._sync_stream()
+        x = self._new_nodal()
+        it, rr = ctypes.c_int32(), ctypes.c_double()
+        rc = L.check(self._lib.efem_gmres_solve(self._h, _ptr(self._nodal(u, name="u")),
+                                                _ptr(self._nodal(b, name="b")), _ptr(x), float(rtol),
+                                                _PREC[hvp_prec], int(restart), int(max_iter),
+                                                ctypes.byref(it), ctypes.byref(rr)), "efem_gmres_solve")
+        return x, it.value, rr.value, rc == L.EFEM_OK
 
     # ------------------------------------------------- learned preconditioner
     def set_mlp(self, params):

@@ -1,0 +1,207 @@
+"""The non-variational transport operator (virtual work, Sec. 5.5) and the
+GMRES solve on the GPU, against the oracle: residual, tangent action in FP64
+and FP32, Jacobi diagonal, the non-symmetry, the sparse tangent by colouring,
+and Dirichlet solves against the oracle's direct solve."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import transport as OT
+from paper_2602_12365_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+TOL64, TOL32 = 1e-10, 5e-5
+OMEGA = np.array([0.3, -0.5, 1.1])
+
+CASES = [
+    ("tet_6", I.TET4, 6, {}),
+    ("tet_5_small_blocks", I.TET4, 5, dict(block_elems=37, block_nodes=40)),
+    ("tet_5_color", I.TET4, 5, dict(scatter="color")),
+    ("tet_4_no_pairs_atomic", I.TET4, 4, dict(pairs=False, scatter="atomic")),
+    ("hex_5", I.HEX8, 5, {}),
+    ("hex_4_small_blocks", I.HEX8, 4, dict(block_elems=7, block_nodes=30)),
+]
+
+
+def dev(a, dtype=torch.float64):
+    return torch.as_tensor(np.ascontiguousarray(a)).to("cuda", dtype=dtype)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+def rel(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+class Case:
+    def __init__(self, elem, n, opts):
+        from paper_2602_12365_amd import Operator
+        self.m = m = I.make_mesh(elem, n)
+        self.D = I.lognormal_field(m.n_elems, 0.4, 21)
+        self.k = 0.5 * I.lognormal_field(m.n_elems, 0.3, 22)
+        self.orc = OT.Transport(elem, m.X, m.conn, self.D, self.k, OMEGA)
+        self.op = Operator(elem, m.X, m.conn, model="transport", **opts)
+        self.op.set_material(dev(self.D), dev(self.k))
+        self.op.set_velocity(OMEGA)
+        self.c = I.gaussian_field(m.n_nodes, 1.0, 23)
+        self.v = I.unit_direction(m.n_nodes, 24)
+        self.w = I.unit_direction(m.n_nodes, 25)
+
+
+@pytest.fixture(scope="module", params=CASES, ids=[c[0] for c in CASES])
+def case(request):
+    _, elem, n, opts = request.param
+    print(f"\n[transport case] {request.param[0]}", flush=True)
+    return Case(elem, n, opts)
+
+
+def test_residual(case):
+    assert rel(host(case.op.residual(dev(case.c))), case.orc.residual(case.c)) <= TOL64
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_tangent_action(case, prec):
+    dt = torch.float64 if prec == "f64" else torch.float32
+    case.op.linearize(dev(case.c), prec)
+    y = host(case.op.hvp(dev(case.v, dt)))
+    assert rel(y, case.orc.hvp(case.v)) <= (TOL64 if prec == "f64" else TOL32)
+
+
+def test_non_symmetric(case):
+    """w.Kv and v.Kw differ, each as the oracle's."""
+    case.op.linearize(dev(case.c), "f64")
+    a = float(np.sum(case.w * host(case.op.hvp(dev(case.v)))))
+    b = float(np.sum(case.v * host(case.op.hvp(dev(case.w)))))
+    ra = float(np.sum(case.w * case.orc.hvp(case.v)))
+    rb = float(np.sum(case.v * case.orc.hvp(case.w)))
+    scale = np.abs(case.orc.hvp(case.v)).max()
+    assert abs(a - ra) <= 1e-12 * scale and abs(b - rb) <= 1e-12 * scale
+    assert abs(ra - rb) > 1e-6 * scale
+
+
+def test_jacobi_diag(case):
+    d = host(case.op.jacobi_diag(dev(case.c)))
+    assert rel(d, case.orc.diag()) <= TOL64
+
+
+def test_dirichlet_mask(case):
+    """Prescribed components: residual and action 0 there, v read as 0."""
+    m = case.m
+    mask = np.zeros((m.n_nodes, 3), dtype=np.uint8)
+    mask[m.X[:, 2] < 1e-12] = 1
+    mask[m.X[:, 0] > 1 - 1e-12, 1] = 1
+    case.op.set_dirichlet(dev(mask, torch.uint8))
+    try:
+        r = host(case.op.residual(dev(case.c)))
+        ref = case.orc.residual(case.c)
+        ref[mask == 1] = 0
+        assert rel(r, ref) <= TOL64
+        case.op.linearize(dev(case.c), "f64")
+        y = host(case.op.hvp(dev(case.v)))
+        vm = case.v.copy()
+        vm[mask == 1] = 0
+        ref = case.orc.hvp(vm)
+        ref[mask == 1] = 0
+        assert rel(y, ref) <= TOL64
+    finally:
+        case.op.set_dirichlet(None)
+
+
+def test_energy_and_cg_solves_refused(case):
+    from paper_2602_12365_amd import _lib as L
+    with pytest.raises(L.EfemError):
+        case.op.energy(dev(case.c))
+    with pytest.raises(L.EfemError):
+        case.op.grad_material(dev(case.c))
+
+
+def test_sparse_tangent_is_the_non_symmetric_matrix(case):
+    """Alg. 2 on the non-symmetric operator: every stored entry equals the
+    oracle's assembled matrix (the pattern is still the symmetric 1-ring)."""
+    import scipy.sparse as sp
+    info = case.op.sparse_setup()
+    rp, col, _ = case.op.sparse_pattern()
+    vals = host(case.op.sparse_assemble(dev(case.c)))
+    n = 3 * case.m.n_nodes
+    K = sp.csr_matrix((vals, col.cpu().numpy(), rp.cpu().numpy()), shape=(n, n)).toarray()
+    Kref = case.orc.tangent_matrix().toarray()
+    assert np.abs(K - Kref).max() <= 1e-12 * np.abs(Kref).max()
+    assert info["nnz"] >= np.count_nonzero(Kref)
+
+
+@pytest.mark.parametrize("elem", [I.TET4, I.HEX8])
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_gmres_solve_matches_direct_solve(elem, prec):
+    """One implicit step (k = 1/dt = 10) of the three-species transport on a
+    cube with the x = 0 face held: GMRES(30) to 1e-10 (FP64 actions) or 1e-6
+    (FP32 actions), across restarts, against the oracle's sparse LU solution
+    of the same reduced system.  The cell Peclet number is about 1: the
+    unstabilised Galerkin form of a much more advective step has negative
+    diagonal entries, and restarted GMRES stagnates on it (scipy's as well)."""
+    from paper_2602_12365_amd import Operator
+    print(f"\n[transport] gmres elem={elem} prec={prec}", flush=True)
+    m = I.make_mesh(elem, 6)
+    D = 0.1 * I.lognormal_field(m.n_elems, 0.4, 31)
+    k = 10.0 * np.ones(m.n_elems)
+    orc = OT.Transport(elem, m.X, m.conn, D, k, 2.0 * OMEGA)
+    mask = np.zeros((m.n_nodes, 3), dtype=np.uint8)
+    mask[m.X[:, 0] < 1e-12] = 1
+    b = I.gaussian_field(m.n_nodes, 1.0, 32)
+    x_ref = orc.solve_reduced(mask, b)
+    op = Operator(elem, m.X, m.conn, model="transport")
+    op.set_material(dev(D), dev(k))
+    op.set_velocity(2.0 * OMEGA)
+    op.set_dirichlet(dev(mask, torch.uint8))
+    rtol = 1e-10 if prec == "f64" else 1e-6
+    x, it, rr, ok = op.gmres_solve(dev(np.zeros_like(b)), dev(b), rtol=rtol, hvp_prec=prec, restart=30,
+                                   max_iter=2000)
+    print(f"[transport] gmres {prec}: {it} iterations, relres {rr:.2e}", flush=True)
+    assert ok and rr <= rtol * 1.01
+    xg = host(x)
+    assert np.all(xg[mask == 1] == 0)
+    tol = 1e-8 if prec == "f64" else 1e-4
+    assert np.linalg.norm(xg - x_ref) <= tol * np.linalg.norm(x_ref)
+    # the oracle's FP64 residual of the GPU solution (with FP32 actions it
+    # also carries the FP32 rounding of K)
+    r = orc.residual(xg)
+    free = mask == 0
+    slack = 1.01 if prec == "f64" else 10.0
+    assert np.linalg.norm(r[free] - b[free]) <= slack * rtol * np.linalg.norm(b[free]) + 1e-12
+
+
+def test_gmres_on_a_symmetric_model_agrees_with_cg():
+    """GMRES works for every model: on the neo-Hookean tangent it reaches the
+    CG solution of the same system."""
+    from paper_2602_12365_amd import Operator
+    m = I.tet_mesh(6)
+    mask, _ = I.clamp_top_bottom(m.X, 0.1)
+    op = Operator(I.TET4, m.X, m.conn)
+    op.set_dirichlet(dev(mask, torch.uint8))
+    u = dev(I.gaussian_field(m.n_nodes, 0.01, 0))
+    b = dev(I.unit_direction(m.n_nodes, 33))
+    x_cg, _, _ = op.linear_solve(u, b, rtol=1e-11)
+    x_gm, it, rr, ok = op.gmres_solve(u, b, rtol=1e-11, restart=40)
+    assert ok and rr <= 1.01e-11
+    assert rel(host(x_gm), host(x_cg)) <= 1e-8
+
+
+def test_gmres_restart_and_iteration_cap():
+    """A small restart still converges (more iterations); a tiny cap returns
+    NOT_CONVERGED with the residual of what it has."""
+    from paper_2602_12365_amd import Operator
+    m = I.tet_mesh(5)
+    op = Operator(I.TET4, m.X, m.conn, model="transport")
+    n = m.n_elems
+    op.set_material(dev(0.1 * np.ones(n)), dev(np.ones(n)))
+    op.set_velocity(OMEGA)
+    b = dev(I.unit_direction(m.n_nodes, 34))
+    z = torch.zeros_like(b)
+    _, it30, rr30, ok30 = op.gmres_solve(z, b, rtol=1e-9, restart=30)
+    _, it5, rr5, ok5 = op.gmres_solve(z, b, rtol=1e-9, restart=5)
+    assert ok30 and ok5 and rr5 <= 1.01e-9 and it5 >= it30
+    _, it2, rr2, ok2 = op.gmres_solve(z, b, rtol=1e-12, restart=30, max_iter=3)
+    assert not ok2 and it2 == 3 and 0 < rr2 < 1
