@@ -8,7 +8,8 @@ linearization plus 100 FP64 tangent actions y = K(u) v (efem_hvp).  `value` is
 DOF/s of the tangent action over the timed steps.
 
 Beside it: the FP32 tangent action, the colour and atomic scatters, energy
-and residual times, the same operators under the small-strain linear model, a roofline object for the dominant kernel (the FP64
+and residual times, the same operators under the small-strain linear model,
+the non-variational transport operator with a GMRES solve, a roofline object for the dominant kernel (the FP64
 tangent action's block pass with its halo gather, timed with HIP events on
 its stream), the Newton
 solves of the metric's second half (plain FP64 Jacobi-CG vs FP32 tangent
@@ -352,6 +353,37 @@ def main():
     log(f"linear model: hvp f64 {t_l64*1e6:.2f} us ({linear['hvp_f64_pct_hbm']}% HBM), "
         f"f32 {t_l32*1e6:.2f} us, residual {t_lres*1e6:.2f} us, energy {t_len*1e6:.2f} us")
 
+    # the non-variational transport operator (virtual work): three species,
+    # D = 0.1, k = 1/dt = 10, b = omega x x; its tangent action, and one
+    # implicit step with the x = 0 face held solved by GMRES(30)
+    opt = Operator(I.TET4, mesh.X, mesh.conn, model="transport", device=dev)
+    ne_ = mesh.n_elems
+    opt.set_material(torch.full((ne_,), 0.1, dtype=torch.float64, device=dev),
+                     torch.full((ne_,), 10.0, dtype=torch.float64, device=dev))
+    opt.set_velocity([0.6, -1.0, 2.2])
+    opt.linearize(u, "f64")
+    opt.hvp(V[0], out=Y)
+    t_t64 = event_time(lambda: opt.hvp(V[0], out=Y), 200, stream)
+    tmask = torch.zeros((mesh.n_nodes, 3), dtype=torch.uint8, device=dev)
+    tmask[torch.as_tensor(mesh.X[:, 0] < 1e-12, device=dev)] = 1
+    opt.set_dirichlet(tmask)
+    zero = torch.zeros_like(u)
+    opt.gmres_solve(zero, V[1], rtol=1e-8, restart=30)   # warm-up
+    torch.cuda.synchronize()
+    t0 = time.time()
+    _, gm_it, gm_rr, gm_ok = opt.gmres_solve(zero, V[1], rtol=1e-8, restart=30)
+    torch.cuda.synchronize()
+    t_gm = time.time() - t0
+    opt.close()
+    transport = {
+        "hvp_f64_us": round(t_t64 * 1e6, 3), "hvp_f64_gdofs": round(ndof / t_t64 / 1e9, 3),
+        "hvp_f64_pct_hbm": round(100 * b_l64 / t_t64 / 1e9 / HBM_PEAK_GBS, 2),
+        "gmres": {"restart": 30, "rtol": 1e-8, "iterations": gm_it, "relres": gm_rr, "converged": gm_ok,
+                  "wall_ms": round(t_gm * 1e3, 3), "ms_per_iteration": round(t_gm * 1e3 / max(gm_it, 1), 4)},
+        "case": "D=0.1, k=1/dt=10, omega=(0.6,-1,2.2), x=0 face held, rhs = unit direction seed 101",
+    }
+    log(f"transport: hvp {t_t64*1e6:.2f} us, gmres {gm_it} its to {gm_rr:.2e} in {t_gm*1e3:.1f} ms")
+
     # sparse tangent by colouring (Alg. 2): K(u) from n_colours tangent
     # actions, then CSR products against the matrix-free one
     sp_info = op.sparse_setup()
@@ -421,6 +453,7 @@ def main():
         "setup_s": round(setup_s, 3),
         "sparse_tangent": sparse,
         "linear_model": linear,
+        "transport": transport,
         "paper_context": "matrix-free JVP ~13 MDoF/s, 3D linear tets, NVIDIA A100 (JAX), precision unstated",
     }
 
