@@ -37,7 +37,10 @@
  *
  * Elements: Tet4 with the one-point centroid rule (w = 1/6) and trilinear
  * Hex8 on [-1,1]^3 with the 2x2x2 Gauss rule (points +-1/sqrt 3, w = 1); the
- * paper leaves the rules unspecified (Eq. 2).
+ * paper leaves the rules unspecified (Eq. 2).  Tri3 (the 2D setup of Sec. 5):
+ * linear triangles in the x-y plane with the centroid rule (w = 1/2) and unit
+ * thickness, carried in the same three nodal components; with the
+ * out-of-plane component held at zero this is plane strain.
  *
  * Assembly: every element writes its own contribution block in parallel
  * (OpenMP); the blocks are then summed serially in element order, so results
@@ -54,6 +57,7 @@
 
 #define ORC_TET4 0
 #define ORC_HEX8 1
+#define ORC_TRI3 2
 
 #define ORC_NEO_HOOKE 0
 #define ORC_LINEAR 1
@@ -64,10 +68,29 @@ typedef struct {
     double w[8];        /* weights */
     double dN[8][8][3]; /* dN[q][a][J]: reference gradients at point q */
     double N[8][8];     /* N[q][a]: shape function values at point q */
+    int planar;         /* 2D element in the x-y plane: unit thickness along z */
 } rule_t;
 
 static int make_rule(int type, rule_t *r)
 {
+    r->planar = 0;
+    if (type == ORC_TRI3) {
+        /* linear triangle N0 = 1 - xi - eta, N1 = xi, N2 = eta, one centroid
+         * point of weight 1/2 (the reference area).  The third reference
+         * direction is the thickness: no shape function varies along it and
+         * qp_eval adds a unit z column to J, so J = [J_2D 0; 0 1], grad N has
+         * no z part, and with u_z held at zero F = [F_2D 0; 0 1] (plane strain) */
+        static const double g[3][3] = {{-1, -1, 0}, {1, 0, 0}, {0, 1, 0}};
+        r->nen = 3;
+        r->nq = 1;
+        r->w[0] = 0.5;
+        r->planar = 1;
+        for (int a = 0; a < 3; ++a) {
+            for (int J = 0; J < 3; ++J) r->dN[0][a][J] = g[a][J];
+            r->N[0][a] = 1.0 / 3.0;
+        }
+        return 0;
+    }
     if (type == ORC_TET4) {
         /* N0 = 1 - xi - eta - zeta, N1 = xi, N2 = eta, N3 = zeta */
         static const double g[4][3] = {{-1, -1, -1}, {1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
@@ -150,6 +173,7 @@ static void qp_eval(const rule_t *r, int q, const double Xe[8][3], const double 
     for (int a = 0; a < r->nen; ++a)
         for (int i = 0; i < 3; ++i)
             for (int J = 0; J < 3; ++J) Jm[i][J] += Xe[a][i] * r->dN[q][a][J];
+    if (r->planar) Jm[2][2] += 1.0;   /* unit thickness */
     double detJ = inv3(Jm, Ji);
     s->ok = detJ > 0.0;
     s->wdetJ = r->w[q] * detJ;

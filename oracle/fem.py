@@ -16,7 +16,7 @@ import numpy as np
 
 from . import build as _build
 
-TET4, HEX8 = 0, 1
+TET4, HEX8, TRI3 = 0, 1, 2
 # material models: compressible neo-Hookean (Sec. 6.1) and small-strain
 # linear elasticity (the density of the paper's first example)
 NEO_HOOKE, LINEAR = 0, 1

@@ -24,7 +24,8 @@ import numpy as np
 
 TET4 = 0
 HEX8 = 1
-N_EN = {TET4: 4, HEX8: 8}
+TRI3 = 2
+N_EN = {TET4: 4, HEX8: 8, TRI3: 3}
 
 
 @dataclass
@@ -44,7 +45,8 @@ class Mesh:
 
     @property
     def n_dofs(self) -> int:
-        return 3 * self.X.shape[0]
+        """Unknowns: 3 per node, 2 (in-plane) for the planar Tri3 mesh."""
+        return (2 if self.elem == TRI3 else 3) * self.X.shape[0]
 
 
 def grid_nodes(n: int) -> np.ndarray:
@@ -100,7 +102,36 @@ def tet_mesh(n: int) -> Mesh:
     return Mesh(TET4, n, grid_nodes(n), conn)
 
 
+def tri_mesh(n: int) -> Mesh:
+    """Unit square in the z = 0 plane, n x n cells, each cut into two
+    counter-clockwise triangles along alternating diagonals (a criss-cross
+    free of a preferred direction); node id = i + (n+1) j."""
+    t = np.linspace(0.0, 1.0, n + 1)
+    x, y = np.meshgrid(t, t, indexing="xy")
+    X = np.stack([x.ravel(), y.ravel(), np.zeros((n + 1) ** 2)], axis=1)
+    tris = []
+    for j in range(n):
+        for i in range(n):
+            a = i + (n + 1) * j
+            b, c, d = a + 1, a + 1 + (n + 1), a + (n + 1)
+            if (i + j) % 2 == 0:
+                tris += [(a, b, c), (a, c, d)]
+            else:
+                tris += [(a, b, d), (b, c, d)]
+    return Mesh(TRI3, n, X, np.asarray(tris, dtype=np.int32))
+
+
+def planar_mask(X: np.ndarray) -> np.ndarray:
+    """uint8 [n_nodes, 3] holding the out-of-plane component of every node
+    (plane strain on a Tri3 mesh)."""
+    m = np.zeros((X.shape[0], 3), dtype=np.uint8)
+    m[:, 2] = 1
+    return m
+
+
 def make_mesh(elem: int, n: int) -> Mesh:
+    if elem == TRI3:
+        return tri_mesh(n)
     return tet_mesh(n) if elem == TET4 else hex_mesh(n)
 
 

@@ -41,6 +41,11 @@ MUTATIONS = {
     "transport_residual_value_not_interpolated": ("cq += r.N[q][a] * ce[a][sp];", "cq += ce[a][sp];"),
     "tet_centroid_value": ("r->N[0][a] = 0.25;", "r->N[0][a] = 1.0 / 3.0;"),
 }
+MUTATIONS.update({
+    "tri_weight": ("r->w[0] = 0.5;", "r->w[0] = 1.0;"),
+    "tri_thickness": ("Jm[2][2] += 1.0;", "Jm[2][2] += 2.0;"),
+    "tri_shape_gradient": ("{{-1, -1, 0}, {1, 0, 0}, {0, 1, 0}}", "{{-1, -1, 0}, {1, 0, 0}, {0, 1, 1}}"),
+})
 PIN_FILES = ["test_oracle_pins.py", "test_oracle_transport.py"]
 
 

@@ -13,6 +13,7 @@ from paper_2602_12365_amd import inputs as I
 from tests import pins
 
 ELEMS = [I.TET4, I.HEX8]
+ALL_ELEMS = [I.TET4, I.HEX8, I.TRI3]   # for pins that hold in any kinematics
 
 
 MODELS = ["neo_hookean", "linear"]
@@ -128,7 +129,7 @@ def test_inverted_element_gives_inf():
 
 # --------------------------------------------------------------- residual
 
-@pytest.mark.parametrize("elem", ELEMS)
+@pytest.mark.parametrize("elem", ALL_ELEMS)
 @pytest.mark.parametrize("model", MODELS)
 def test_residual_fd_of_energy(elem, model):
     m, f = make(elem, 3, mu_sigma=0.3, model=model)
@@ -173,7 +174,7 @@ def test_residual_objectivity(elem):
 
 # ----------------------------------------------------------------- tangent
 
-@pytest.mark.parametrize("elem", ELEMS)
+@pytest.mark.parametrize("elem", ALL_ELEMS)
 @pytest.mark.parametrize("model", MODELS)
 def test_hvp_fd_of_residual(elem, model):
     m, f = make(elem, 3, mu_sigma=0.3, model=model)
@@ -185,7 +186,7 @@ def test_hvp_fd_of_residual(elem, model):
     assert np.linalg.norm(Kv - fd) <= 1e-8 * np.linalg.norm(Kv)
 
 
-@pytest.mark.parametrize("elem", ELEMS)
+@pytest.mark.parametrize("elem", ALL_ELEMS)
 @pytest.mark.parametrize("model", MODELS)
 def test_hvp_symmetry(elem, model):
     m, f = make(elem, 3, mu_sigma=0.3, model=model)
@@ -226,7 +227,7 @@ def test_tangent_under_rigid_rotation(elem):
     assert np.abs(lhs - rhs).max() <= 1e-13 * np.abs(rhs).max()
 
 
-@pytest.mark.parametrize("elem", ELEMS)
+@pytest.mark.parametrize("elem", ALL_ELEMS)
 @pytest.mark.parametrize("model", MODELS)
 def test_jacobi_diag_equals_diag_of_K(elem, model):
     m, f = make(elem, 2, mu_sigma=0.3, model=model)
@@ -237,7 +238,7 @@ def test_jacobi_diag_equals_diag_of_K(elem, model):
 
 # ----------------------------------------------------------- adjoints
 
-@pytest.mark.parametrize("elem", ELEMS)
+@pytest.mark.parametrize("elem", ALL_ELEMS)
 @pytest.mark.parametrize("model", MODELS)
 def test_grad_material_fd_and_homogeneity(elem, model):
     m, f = make(elem, 3, mu_sigma=0.3, lam_ratio=1.5, model=model)
@@ -269,7 +270,7 @@ def test_grad_material_affine_closed_form():
         assert np.abs(gl - vol * pins.psi_principal(F0, 0.0, 1.0)).max() <= 1e-14
 
 
-@pytest.mark.parametrize("elem", ELEMS)
+@pytest.mark.parametrize("elem", ALL_ELEMS)
 @pytest.mark.parametrize("model", MODELS)
 def test_residual_vjp_material(elem, model):
     m, f = make(elem, 3, mu_sigma=0.3, lam_ratio=1.5, model=model)
@@ -377,3 +378,69 @@ def test_linear_model_grad_material_closed_form():
         vol, _ = f.volumes()
         assert np.abs(gm - vol * np.sum(eps * eps)).max() <= 1e-15
         assert np.abs(gl - vol * 0.5 * np.trace(eps) ** 2).max() <= 1e-15
+
+
+# ------------------------------------------------- Tri3 (plane strain)
+
+def plane(F2):
+    F = np.eye(3)
+    F[:2, :2] = F2
+    return F
+
+
+def planar_affine(X, F2):
+    u = X @ (plane(F2) - np.eye(3)).T
+    u[:, 2] = 0.0
+    return u
+
+
+@pytest.mark.parametrize("model", MODELS)
+@pytest.mark.parametrize("ci", range(2))
+def test_tri3_plane_strain_patch_test(model, ci):
+    """In-plane affine u with u_z = 0: Psi = area psi(F) with F = diag(F_2D, 1)
+    (numpy SVD principal stretches, or the linear density), no force on
+    interior nodes, and no out-of-plane force anywhere."""
+    F2 = [np.array([[1.10, 0.05], [0.03, 0.95]]), np.array([[0.80, 0.30], [0.10, 1.20]])][ci]
+    m, f = make(I.TRI3, 4, model=model)
+    u = planar_affine(m.X, F2)
+    F = plane(F2)
+    ref = pins.psi_principal(F, 1.0, 1.5) if model == "neo_hookean" else pins.psi_linear(F - np.eye(3), 1.0, 1.5)
+    assert abs(f.energy(u) - ref) <= 1e-13 * abs(ref)
+    r = f.residual(u)
+    inner = np.all((m.X[:, :2] > 1e-12) & (m.X[:, :2] < 1 - 1e-12), axis=1)
+    assert np.abs(r[inner]).max() <= 1e-13 * np.abs(r).max()
+    assert np.abs(r[:, 2]).max() <= 1e-15
+
+
+def test_tri3_reference_stiffness_is_textbook_plane_strain():
+    """K(0) on in-plane DOFs = sum B^T D B area with the plane-strain Hooke
+    matrix; in-plane and out-of-plane DOFs do not couple."""
+    m, f = make(I.TRI3, 3, mu_sigma=0.4, lam_ratio=1.5)
+    K = dense_K(f, np.zeros_like(m.X))
+    n = m.n_nodes
+    Kt = np.zeros((2 * n, 2 * n))
+    for e, ce in enumerate(m.conn):
+        Xe = m.X[ce][:, :2]
+        M = np.hstack([np.ones((3, 1)), Xe])
+        G = np.linalg.inv(M)[1:, :].T            # [3, 2] gradients
+        area = 0.5 * np.linalg.det(M)
+        B = np.zeros((3, 6))
+        for a in range(3):
+            B[0, 2 * a], B[1, 2 * a + 1] = G[a]
+            B[2, 2 * a], B[2, 2 * a + 1] = G[a, 1], G[a, 0]
+        mu, lam = f.mu[e], f.lam[e]
+        D = np.array([[lam + 2 * mu, lam, 0], [lam, lam + 2 * mu, 0], [0, 0, mu]])
+        dofs = (2 * ce[:, None] + np.arange(2)[None, :]).ravel()
+        Kt[np.ix_(dofs, dofs)] += area * B.T @ D @ B
+    ip = (3 * np.arange(n)[:, None] + np.arange(2)[None, :]).ravel()
+    assert np.abs(K[np.ix_(ip, ip)] - Kt).max() <= 1e-13 * np.abs(Kt).max()
+    assert np.abs(K[np.ix_(ip, 3 * np.arange(n) + 2)]).max() == 0.0
+
+
+def test_tri3_in_plane_rotation_is_stress_free():
+    th = 0.7
+    R2 = np.array([[np.cos(th), -np.sin(th)], [np.sin(th), np.cos(th)]])
+    m, f = make(I.TRI3, 4, mu_sigma=0.3)
+    u = planar_affine(m.X, R2)
+    assert abs(f.energy(u)) < 1e-14
+    assert np.abs(f.residual(u)).max() < 1e-14
