@@ -17,7 +17,12 @@
  *   - the sparse tangent recovered from tangent actions by colouring, Alg. 2.
  *
  * Element types: 4-node tetrahedra with the one-point centroid rule, 8-node
- * trilinear hexahedra with the 2x2x2 Gauss rule.  Material (per-element mu,
+ * trilinear hexahedra with the 2x2x2 Gauss rule, and linear triangles with
+ * the centroid rule for the 2D setup (Sec. 5).  Triangles lie in the x-y
+ * plane (counter-clockwise seen from +z) with unit thickness along z and use
+ * the same three nodal components: the reference Jacobian is [J_2D 0; 0 1],
+ * and with the z components held by the Dirichlet mask the model is plane
+ * strain.  Material (per-element mu,
  * lam): compressible neo-Hookean, psi = mu/2 (tr F^T F - 3) - mu ln J +
  * lam/2 (ln J)^2 (Sec. 6.1), or small-strain linear elasticity, psi = mu
  * eps:eps + lam/2 (tr eps)^2 with eps = sym grad u (the density of the
@@ -62,6 +67,7 @@ extern "C" {
 /* element types */
 #define EFEM_TET4 0
 #define EFEM_HEX8 1
+#define EFEM_TRI3 2   /* planar: triangles in the x-y plane, unit thickness */
 
 /* material models (efem_set_model) */
 #define EFEM_MODEL_NEO_HOOKE 0
@@ -99,10 +105,11 @@ typedef struct {
 } efem_options;
 
 /* Build an operator for a mesh (Sec. 4, Operator(mesh, element, batchsize)).
- *   elem      EFEM_TET4 or EFEM_HEX8
+ *   elem      EFEM_TET4, EFEM_HEX8 or EFEM_TRI3
  *   coords    HOST float64 [n_nodes*3] reference coordinates X
- *   conn      HOST int32 [n_elems*n_en] connectivity (4 or 8 nodes, element-major;
- *             hexahedra in the order (0,0,0),(1,0,0),(1,1,0),(0,1,0), then z=1)
+ *   conn      HOST int32 [n_elems*n_en] connectivity (4, 8 or 3 nodes, element-major;
+ *             hexahedra in the order (0,0,0),(1,0,0),(1,1,0),(0,1,0), then z=1;
+ *             triangles counter-clockwise seen from +z)
  *   opts      may be NULL (defaults)
  *   stream    hipStream_t to run on, NULL = the null stream
  * Elements are reordered internally along a Morton curve and cut into blocks

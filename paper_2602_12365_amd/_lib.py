@@ -19,7 +19,7 @@ EFEM_ERR_OOM = -3
 EFEM_ERR_INVERTED = -4
 EFEM_ERR_STATE = -5
 
-EFEM_TET4, EFEM_HEX8 = 0, 1
+EFEM_TET4, EFEM_HEX8, EFEM_TRI3 = 0, 1, 2
 EFEM_F64, EFEM_F32 = 0, 1
 EFEM_MODEL_NEO_HOOKE, EFEM_MODEL_LINEAR, EFEM_MODEL_TRANSPORT = 0, 1, 2
 EFEM_SCATTER_HALO, EFEM_SCATTER_COLOR, EFEM_SCATTER_ATOMIC = 0, 1, 2

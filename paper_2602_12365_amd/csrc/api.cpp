@@ -72,6 +72,8 @@ static double det3(const double m[9])
 }
 
 // det J of the reference map at every quadrature point must be positive.
+static int nodes_per_elem(int elem) { return elem == EFEM_TET4 ? 4 : (elem == EFEM_TRI3 ? 3 : 8); }
+
 static bool reference_jacobians_positive(int elem, int nen, int64_t ne, const double *X,
                                          const int32_t *conn)
 {
@@ -80,7 +82,12 @@ static bool reference_jacobians_positive(int elem, int nen, int64_t ne, const do
     const double g = 1.0 / std::sqrt(3.0);
     for (int64_t e = 0; e < ne; ++e) {
         const int32_t *ce = conn + e * nen;
-        if (elem == EFEM_TET4) {
+        if (elem == EFEM_TRI3) {
+            // det [e1 e2 z] = (e1 x e2)_z: counter-clockwise seen from +z
+            const double *a = X + 3 * (int64_t)ce[0], *b = X + 3 * (int64_t)ce[1], *c = X + 3 * (int64_t)ce[2];
+            const double cz = (b[0] - a[0]) * (c[1] - a[1]) - (b[1] - a[1]) * (c[0] - a[0]);
+            if (!(cz > 0.0)) return false;
+        } else if (elem == EFEM_TET4) {
             double E[9];
             for (int i = 0; i < 3; ++i)
                 for (int c = 0; c < 3; ++c) E[i * 3 + c] = X[3 * ce[c + 1] + i] - X[3 * ce[0] + i];
@@ -226,7 +233,7 @@ static int pair_tets(const double *X, const int32_t *conn, std::vector<int32_t> 
 static void build_blocks(int elem, int64_t nn, int64_t ne, const double *X, const int32_t *conn,
                          int be, int bn, bool colour, bool pairs, HostBlocks &hb)
 {
-    const int nen = elem == EFEM_TET4 ? 4 : 8;
+    const int nen = nodes_per_elem(elem);
     // Morton order of element centroids
     double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
     for (int64_t i = 0; i < nn; ++i)
@@ -320,6 +327,14 @@ static void build_blocks(int elem, int64_t nn, int64_t ne, const double *X, cons
                 hb.items.push_back((uint32_t)local[ce[3]] | (uint32_t)local[ce[3]] << 10);
             }
             hb.istart.push_back(hb.istart.back() + (int32_t)el.size() - np);
+        } else if (elem == EFEM_TRI3) {
+            // item word: a | b << 10 | c << 20 (local ids < 1024)
+            for (int32_t e : el) {
+                const int32_t *ce = conn + 3 * (int64_t)e;
+                hb.items.push_back((uint32_t)local[ce[0]] | (uint32_t)local[ce[1]] << 10
+                                   | (uint32_t)local[ce[2]] << 20);
+            }
+            hb.istart.push_back(hb.istart.back() + (int32_t)el.size());
         } else {
             for (int32_t e : el) {
                 const int32_t *ce = conn + 8 * (int64_t)e;
@@ -410,7 +425,7 @@ int efem_create(efem_ctx **out, int32_t elem, int64_t n_nodes, int64_t n_elems,
         return EFEM_ERR_INVALID;
     }
     *out = nullptr;
-    if (elem != EFEM_TET4 && elem != EFEM_HEX8) {
+    if (elem != EFEM_TET4 && elem != EFEM_HEX8 && elem != EFEM_TRI3) {
         set_error("efem_create: unknown element type");
         return EFEM_ERR_INVALID;
     }
@@ -418,7 +433,7 @@ int efem_create(efem_ctx **out, int32_t elem, int64_t n_nodes, int64_t n_elems,
         set_error("efem_create: bad mesh sizes");
         return EFEM_ERR_INVALID;
     }
-    const int nen = elem == EFEM_TET4 ? 4 : 8;
+    const int nen = nodes_per_elem(elem);
     for (int64_t k = 0; k < n_elems * nen; ++k)
         if (conn[k] < 0 || conn[k] >= n_nodes) {
             set_error("efem_create: connectivity entry out of range");
@@ -429,8 +444,9 @@ int efem_create(efem_ctx **out, int32_t elem, int64_t n_nodes, int64_t n_elems,
         return EFEM_ERR_INVERTED;
     }
     // defaults measured on the 64^3 workloads: 1536 tets (768 pairs) within 600
-    // nodes, or 512 hexes within 768 nodes, per block
-    int be = elem == EFEM_TET4 ? 1536 : 512;
+    // nodes, or 512 hexes within 768 nodes, per block; triangles: 1024 within
+    // 768 nodes
+    int be = elem == EFEM_TET4 ? 1536 : (elem == EFEM_TRI3 ? 1024 : 512);
     int bn = elem == EFEM_TET4 ? 600 : 768;
     int scatter = EFEM_SCATTER_HALO;
     int threads = 256;
@@ -455,7 +471,7 @@ int efem_create(efem_ctx **out, int32_t elem, int64_t n_nodes, int64_t n_elems,
     if (!ctx) return EFEM_ERR_OOM;
     ctx->elem = elem;
     ctx->nen = nen;
-    ctx->nq = elem == EFEM_TET4 ? 1 : 8;
+    ctx->nq = elem == EFEM_HEX8 ? 8 : 1;
     ctx->n_nodes = n_nodes;
     ctx->n_elems = n_elems;
     ctx->stream = (hipStream_t)stream;

@@ -164,6 +164,8 @@ __device__ __forceinline__ void flag_inverted(int32_t *flags) { atomicOr(flags, 
 struct Tet4Pair {
     static constexpr int NEN = 5, NQ = 2, NSUB = 2;
     using Lean = Tet4Pair;   // the form with the fewest live registers
+    // completes the gradient of a coordinate field (planar elements only)
+    template <class T> __device__ static __forceinline__ void geom(T *) {}
     template <class T> __device__ static constexpr T weight() { return T(1.0 / 6.0); }
     __device__ static constexpr int sub(int q) { return q; }
     // the second point of an unpaired tetrahedron is skipped
@@ -249,6 +251,86 @@ struct Tet4Pair {
     }
 };
 
+// Tri3: linear triangle in the x-y plane, one centroid point, weight 1/2 (the
+// reference area), unit thickness.  The third reference direction is the
+// thickness: no field varies along it, so grad() leaves column 2 zero and
+// geom() puts the unit z column into the gradient of a coordinate field, which
+// makes Jx = [Jx_2D 0; 0 1] and, with u_z held, F = [F_2D 0; 0 1] (plane strain).
+struct Tri3 {
+    static constexpr int NEN = 3, NQ = 1, NSUB = 1;
+    using Lean = Tri3;
+    template <class T> __device__ static constexpr T weight() { return T(0.5); }
+    __device__ static constexpr int sub(int) { return 0; }
+    __device__ static constexpr bool skip(int, bool) { return false; }
+    template <class T> __device__ static __forceinline__ void geom(T *G) { G[8] += T(1); }
+    template <class T> struct Field {
+        T f[NEN][3];
+    };
+    template <class T>
+    __device__ static __forceinline__ void prep(const T f[NEN][3], Field<T> &F)
+    {
+#pragma unroll
+        for (int a = 0; a < NEN; ++a)
+#pragma unroll
+            for (int i = 0; i < 3; ++i) F.f[a][i] = f[a][i];
+    }
+    template <class T>
+    __device__ static __forceinline__ void grad(const Field<T> &F, int, T G[9])
+    {
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            G[i * 3 + 0] = F.f[1][i] - F.f[0][i];
+            G[i * 3 + 1] = F.f[2][i] - F.f[0][i];
+            G[i * 3 + 2] = T(0);
+        }
+    }
+    template <class T> struct Acc {
+        T f[NEN][3];
+    };
+    template <class T> __device__ static __forceinline__ void zero(Acc<T> &A)
+    {
+#pragma unroll
+        for (int a = 0; a < NEN; ++a) A.f[a][0] = A.f[a][1] = A.f[a][2] = T(0);
+    }
+    template <bool INIT, class T>
+    __device__ static __forceinline__ void add_forces_to(const T Q[9], int, T out[NEN][3])
+    {
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            const T s = -(Q[i * 3 + 0] + Q[i * 3 + 1]);
+            if (INIT) {
+                out[1][i] = Q[i * 3 + 0];
+                out[2][i] = Q[i * 3 + 1];
+                out[0][i] = s;
+            } else {
+                out[1][i] += Q[i * 3 + 0];
+                out[2][i] += Q[i * 3 + 1];
+                out[0][i] += s;
+            }
+        }
+    }
+    template <bool INIT, class T>
+    __device__ static __forceinline__ void add_forces(const T Q[9], int q, Acc<T> &A)
+    {
+        add_forces_to<INIT>(Q, q, A.f);
+    }
+    template <class T>
+    __device__ static __forceinline__ void finish(const Acc<T> &A, T out[NEN][3])
+    {
+#pragma unroll
+        for (int a = 0; a < NEN; ++a)
+#pragma unroll
+            for (int i = 0; i < 3; ++i) out[a][i] = A.f[a][i];
+    }
+    template <class T> __device__ static __forceinline__ T dN(int, int a, int J)
+    {
+        if (J == 2) return T(0);
+        if (a == 0) return T(-1);
+        return a == J + 1 ? T(1) : T(0);
+    }
+    template <class T> __device__ static __forceinline__ T N(int, int) { return T(1.0 / 3.0); }
+};
+
 // Hex8 in node form: the same element with gradients and forces as sums over
 // the 8 nodes (8 terms per entry).  It keeps 24 values per field live instead
 // of 36, which is what the three-field FP64 tangent action needs to stay out
@@ -257,6 +339,7 @@ __device__ constexpr int kHexSgn[8][3] = {{-1, -1, -1}, {1, -1, -1}, {1, 1, -1},
                                           {-1, -1, 1},  {1, -1, 1},  {1, 1, 1},  {-1, 1, 1}};
 struct Hex8Nodes {
     static constexpr int NEN = 8;
+    template <class T> __device__ static __forceinline__ void geom(T *) {}
     template <class T> __device__ static __forceinline__ T dN(int q, int a, int J)
     {
         const T g = T(0.57735026918962576451);
@@ -357,6 +440,7 @@ __device__ constexpr int kHexEdge[3][4][2] = {{{0, 1}, {3, 2}, {4, 5}, {7, 6}},
 struct Hex8 {
     static constexpr int NEN = 8, NQ = 8, NSUB = 1;
     using Lean = Hex8Nodes;   // the form with the fewest live registers
+    template <class T> __device__ static __forceinline__ void geom(T *) {}
     template <class T> __device__ static constexpr T weight() { return T(1); }
     __device__ static constexpr int sub(int) { return 0; }
     __device__ static constexpr bool skip(int, bool) { return false; }
@@ -783,7 +867,9 @@ template <> struct HvpOp<double> {
             if (E::skip(q, pair)) continue;
             double Jx[9], Jd[9], dJ[9], Q[9];
             G::grad(FX, q, Jx);
+            G::geom(Jx);
             G::grad(Fx, q, Jd);
+            G::geom(Jd);
             G::grad(Fv, q, dJ);
             ok &= qp_hvp(E::template weight<double>(), Jx, Jd, dJ, mu[E::sub(q)], lam[E::sub(q)], Q);
             G::template add_forces_to<true>(Q, q, f);
@@ -834,6 +920,7 @@ template <> struct HvpOp<float> {
             if (E::skip(q, pair)) continue;
             float Jx[9], Jd[9], dJ[9], Q[9];
             E::grad(FX, q, Jx);
+            E::geom(Jx);
             E::grad(Fu, q, Jd);
 #pragma unroll
             for (int k = 0; k < 9; ++k) Jd[k] += Jx[k];
@@ -890,6 +977,7 @@ struct ResidualOp : XUStage {
             if (E::skip(q, pair)) continue;
             double Jx[9], Jd[9], Q[9];
             E::grad(FX, q, Jx);
+            E::geom(Jx);
             E::grad(Fu, q, Jd);
 #pragma unroll
             for (int k = 0; k < 9; ++k) Jd[k] += Jx[k];
@@ -919,6 +1007,7 @@ struct DiagOp : XUStage {
             const double mq = mu[E::sub(q)], lq = lam[E::sub(q)];
             double Jx[9], Jd[9], Ae[9], Ad[9];
             E::grad(FX, q, Jx);
+            E::geom(Jx);
             E::grad(Fu, q, Jd);
 #pragma unroll
             for (int k = 0; k < 9; ++k) Jd[k] += Jx[k];
@@ -968,6 +1057,7 @@ struct GradCoordsOp : XUStage {
             const double mu_ = mu[E::sub(q)], lam_ = lam[E::sub(q)];
             double Jx[9], Hxi[9], Ae[9];
             E::grad(FX, q, Jx);
+            E::geom(Jx);
             E::grad(Fu, q, Hxi);
             Kin k;
             kinematics(E::template weight<double>(), Jx, Hxi, k);
@@ -1055,6 +1145,7 @@ template <class T> struct LinHvpOp {
             if (E::skip(q, pair)) continue;
             T Jx[9], dJ[9], Q[9];
             E::grad(FX, q, Jx);
+            E::geom(Jx);
             E::grad(Fv, q, dJ);
             qp_linear(E::template weight<T>(), Jx, dJ, mu[E::sub(q)], lam[E::sub(q)], Q);
             E::template add_forces<true>(Q, q, A);
@@ -1078,6 +1169,7 @@ struct LinResidualOp : XUStage {
             if (E::skip(q, pair)) continue;
             double Jx[9], Hxi[9], Q[9];
             E::grad(FX, q, Jx);
+            E::geom(Jx);
             E::grad(Fu, q, Hxi);
             qp_linear(E::template weight<double>(), Jx, Hxi, mu[E::sub(q)], lam[E::sub(q)], Q);
             E::template add_forces<true>(Q, q, A);
@@ -1105,6 +1197,7 @@ struct LinDiagOp : XUStage {
             const double mq = mu[E::sub(q)], lq = lam[E::sub(q)];
             double Jx[9], Ae[9];
             E::grad(FX, q, Jx);
+            E::geom(Jx);
             const double De = adj_det(Jx, Ae);
             const double c = E::template weight<double>() / De;
 #pragma unroll
@@ -1140,6 +1233,7 @@ struct LinGradCoordsOp : XUStage {
             const double mq = mu[E::sub(q)], lq = lam[E::sub(q)];
             double Jx[9], Hxi[9], Ae[9], H[9], S[9], Sg[9], Q[9];
             E::grad(FX, q, Jx);
+            E::geom(Jx);
             E::grad(Fu, q, Hxi);
             lin_grad(Jx, Hxi, Ae, H);
             lin_stress(H, mq, lq, S);
@@ -1212,6 +1306,7 @@ template <class T> struct TransportOp {
             if (E::skip(q, pair)) continue;
             T Jx[9], Cxi[9], Ae[9], Gc[9], Q[9];
             G::grad(FX, q, Jx);
+            G::geom(Jx);
             G::grad(Fc, q, Cxi);
             const T De = lin_grad(Jx, Cxi, Ae, Gc);   // Gc[s][L] = d c_s / d x_L
             T xq[3] = {T(0), T(0), T(0)}, cq[3] = {T(0), T(0), T(0)};
@@ -1275,6 +1370,7 @@ struct TransportDiagOp : XUStage {
             if (E::skip(q, pair)) continue;
             double Jx[9], Ae[9];
             G::grad(FX, q, Jx);
+            G::geom(Jx);
             const double De = adj_det(Jx, Ae);
             double xq[3] = {0.0, 0.0, 0.0};
 #pragma unroll
@@ -1329,6 +1425,7 @@ __device__ __forceinline__ ItemRange item_range(const BlockMesh &m, int b)
 template <class E> struct ItemWord;
 template <> struct ItemWord<Tet4Pair> { uint2 w; };
 template <> struct ItemWord<Hex8> { uint4 w; };
+template <> struct ItemWord<Tri3> { uint32_t w; };
 
 template <class E> struct IData {
     ItemWord<E> lc;
@@ -1341,6 +1438,7 @@ __device__ __forceinline__ IData<E> fetch_item(const BlockMesh &m, const ItemRan
     IData<E> d;
     const int64_t i = r.i0 + k;
     if constexpr (E::NEN == 5) d.lc.w = *reinterpret_cast<const uint2 *>(m.items + 2 * i);
+    else if constexpr (E::NEN == 3) d.lc.w = m.items[i];
     else d.lc.w = *reinterpret_cast<const uint4 *>(m.items + 4 * i);
 #pragma unroll
     for (int s = 0; s < E::NSUB; ++s) {
@@ -1363,6 +1461,8 @@ __device__ __forceinline__ void unpack_lc(const ItemWord<E> &l, uint16_t lc[E::N
     if constexpr (E::NEN == 5) {
         lc[0] = l.w.x & 1023u, lc[1] = (l.w.x >> 10) & 1023u, lc[2] = (l.w.x >> 20) & 1023u;
         lc[3] = l.w.y & 1023u, lc[4] = (l.w.y >> 10) & 1023u;
+    } else if constexpr (E::NEN == 3) {
+        lc[0] = l.w & 1023u, lc[1] = (l.w >> 10) & 1023u, lc[2] = (l.w >> 20) & 1023u;
     } else {
         lc[0] = l.w.x & 0xffff, lc[1] = l.w.x >> 16, lc[2] = l.w.y & 0xffff, lc[3] = l.w.y >> 16;
         lc[4] = l.w.z & 0xffff, lc[5] = l.w.z >> 16, lc[6] = l.w.w & 0xffff, lc[7] = l.w.w >> 16;
@@ -1537,6 +1637,7 @@ __global__ void __launch_bounds__(256) k_energy(BlockMesh m, const double *__res
             const double mu = cur.mu[E::sub(q)], lam = cur.lam[E::sub(q)];
             double Jx[9], Hxi[9];
             E::grad(FX, q, Jx);
+            E::geom(Jx);
             E::grad(Fu, q, Hxi);
             if (LIN) {
                 double Ae[9], H[9], ee, tr;
@@ -1624,6 +1725,7 @@ __global__ void __launch_bounds__(256) k_grad_material(BlockMesh m, const double
             if (E::skip(q, pair)) continue;
             double Jx[9], Hxi[9];
             E::grad(FX, q, Jx);
+            E::geom(Jx);
             E::grad(Fu, q, Hxi);
             if (LIN) {
                 double Ae[9], H[9], ee, tr;
@@ -1702,6 +1804,7 @@ __global__ void __launch_bounds__(256) k_vjp_material(BlockMesh m, const double 
             if (E::skip(q, pair)) continue;
             double Jx[9], Hxi[9], Wxi[9], Ae[9];
             E::grad(FX, q, Jx);
+            E::geom(Jx);
             E::grad(Fu, q, Hxi);
             E::grad(Fw, q, Wxi);
             if (LIN) {
@@ -1805,6 +1908,7 @@ template <class Op, class T>
 static hipError_t dispatch(const Ctx &c, const Op &op, T *y, bool use_mask, T fixed_val,
                            const int32_t *skip = nullptr, WriteMode mode = WriteMode::Overwrite)
 {
+    if (c.elem == EFEM_TRI3) return run_accumulate<Tri3>(c, op, y, use_mask, fixed_val, skip, mode);
     return c.elem == EFEM_TET4 ? run_accumulate<Tet4Pair>(c, op, y, use_mask, fixed_val, skip, mode)
                                : run_accumulate<Hex8>(c, op, y, use_mask, fixed_val, skip, mode);
 }
@@ -1906,6 +2010,7 @@ hipError_t launch_energy(const Ctx &c, const double *u, double *psi)
     const size_t lds = sizeof(NodeXU) * (size_t)c.max_block_nodes;
     const bool lin = c.model == EFEM_MODEL_LINEAR;
     if (c.elem == EFEM_TET4) lin ? energy_pass<Tet4Pair, true>(c, u, lds) : energy_pass<Tet4Pair, false>(c, u, lds);
+    else if (c.elem == EFEM_TRI3) lin ? energy_pass<Tri3, true>(c, u, lds) : energy_pass<Tri3, false>(c, u, lds);
     else lin ? energy_pass<Hex8, true>(c, u, lds) : energy_pass<Hex8, false>(c, u, lds);
     hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, c.stream, c.partials, c.m.n_blocks, psi);
     return hipGetLastError();
@@ -1925,6 +2030,8 @@ hipError_t launch_grad_material(const Ctx &c, const double *u, double *dmu, doub
     if (c.elem == EFEM_TET4)
         lin ? grad_material_pass<Tet4Pair, true>(c, u, dmu, dlam, lds)
             : grad_material_pass<Tet4Pair, false>(c, u, dmu, dlam, lds);
+    else if (c.elem == EFEM_TRI3)
+        lin ? grad_material_pass<Tri3, true>(c, u, dmu, dlam, lds) : grad_material_pass<Tri3, false>(c, u, dmu, dlam, lds);
     else
         lin ? grad_material_pass<Hex8, true>(c, u, dmu, dlam, lds)
             : grad_material_pass<Hex8, false>(c, u, dmu, dlam, lds);
@@ -1947,6 +2054,9 @@ hipError_t launch_vjp_material(const Ctx &c, const double *u, const double *w, d
     if (c.elem == EFEM_TET4)
         lin ? vjp_material_pass<Tet4Pair, true>(c, u, w, dmu, dlam, lds)
             : vjp_material_pass<Tet4Pair, false>(c, u, w, dmu, dlam, lds);
+    else if (c.elem == EFEM_TRI3)
+        lin ? vjp_material_pass<Tri3, true>(c, u, w, dmu, dlam, lds)
+            : vjp_material_pass<Tri3, false>(c, u, w, dmu, dlam, lds);
     else
         lin ? vjp_material_pass<Hex8, true>(c, u, w, dmu, dlam, lds)
             : vjp_material_pass<Hex8, false>(c, u, w, dmu, dlam, lds);

@@ -129,6 +129,20 @@ def planar_mask(X: np.ndarray) -> np.ndarray:
     return m
 
 
+def clamp_planar(X: np.ndarray, top_dy: float):
+    """Plane-strain load case on the unit square: every out-of-plane
+    component held at 0, the bottom edge y = 0 clamped, the top edge y = 1
+    gripped and moved by top_dy in y.  Returns (mask uint8 [3 n], u_bc [n, 3])."""
+    mask = planar_mask(X)
+    ubc = np.zeros_like(X)
+    bottom = np.abs(X[:, 1]) < 1e-12
+    top = np.abs(X[:, 1] - 1.0) < 1e-12
+    mask[bottom] = 1
+    mask[top] = 1
+    ubc[top, 1] = top_dy
+    return mask.reshape(-1), ubc
+
+
 def make_mesh(elem: int, n: int) -> Mesh:
     if elem == TRI3:
         return tri_mesh(n)

@@ -15,7 +15,9 @@ import torch
 
 from . import _lib as L
 
-_ELEM = {"tet4": L.EFEM_TET4, "hex8": L.EFEM_HEX8, L.EFEM_TET4: L.EFEM_TET4, L.EFEM_HEX8: L.EFEM_HEX8}
+_ELEM = {"tet4": L.EFEM_TET4, "hex8": L.EFEM_HEX8, "tri3": L.EFEM_TRI3,
+         L.EFEM_TET4: L.EFEM_TET4, L.EFEM_HEX8: L.EFEM_HEX8, L.EFEM_TRI3: L.EFEM_TRI3}
+_NEN = {L.EFEM_TET4: 4, L.EFEM_HEX8: 8, L.EFEM_TRI3: 3}
 _PREC = {"f64": L.EFEM_F64, "f32": L.EFEM_F32, torch.float64: L.EFEM_F64, torch.float32: L.EFEM_F32}
 _MODEL = {"neo_hookean": L.EFEM_MODEL_NEO_HOOKE, "linear": L.EFEM_MODEL_LINEAR,
           "transport": L.EFEM_MODEL_TRANSPORT}
@@ -43,7 +45,7 @@ class Operator:
         if X.ndim != 2 or X.shape[1] != 3:
             raise ValueError("X must be [n_nodes, 3]")
         self.elem = _ELEM[elem]
-        self.nen = 4 if self.elem == L.EFEM_TET4 else 8
+        self.nen = _NEN[self.elem]
         if conn.ndim != 2 or conn.shape[1] != self.nen:
             raise ValueError(f"conn must be [n_elems, {self.nen}]")
         self.n_nodes, self.n_elems = X.shape[0], conn.shape[0]

@@ -44,6 +44,10 @@ CASES = [
     ("tet_5_linear_color", I.TET4, 5, dict(model="linear", scatter="color")),
     ("hex_5_linear", I.HEX8, 5, dict(model="linear")),
     ("hex_4_linear_atomic", I.HEX8, 4, dict(model="linear", scatter="atomic", block_elems=9)),
+    ("tri_12", I.TRI3, 12, {}),
+    ("tri_9_small_blocks", I.TRI3, 9, dict(block_elems=50, block_nodes=40, threads=64)),
+    ("tri_10_color", I.TRI3, 10, dict(scatter="color")),
+    ("tri_10_linear_atomic", I.TRI3, 10, dict(model="linear", scatter="atomic")),
 ]
 
 
@@ -164,7 +168,10 @@ def test_grad_coords(case):
 
 def test_dirichlet_reduced_functional(case):
     m = case.mesh
-    mask, _ = I.clamp_top_bottom(m.X, 0.1)
+    if m.elem == I.TRI3:
+        mask, _ = I.clamp_planar(m.X, 0.1)
+    else:
+        mask, _ = I.clamp_top_bottom(m.X, 0.1)
     op = case.op
     op.set_dirichlet(dev(mask, torch.uint8))
     try:
@@ -218,7 +225,7 @@ def test_work_items(case):
     info = case.op.info()
     ne = case.mesh.n_elems
     assert info["n_items"] <= ne
-    if case.mesh.elem == I.HEX8 or not case.op.pairs:
+    if case.mesh.elem in (I.HEX8, I.TRI3) or not case.op.pairs:
         assert info["n_items"] == ne
     else:
         # every element is in exactly one item and most are paired

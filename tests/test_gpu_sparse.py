@@ -13,7 +13,8 @@ from paper_2602_12365_amd import inputs as I
 pytestmark = pytest.mark.gpu
 
 CASES = [("tet_4", I.TET4, 4, None), ("hex_3", I.HEX8, 3, None),
-         ("tet_4_scrambled", I.TET4, 4, 21), ("hex_4_scrambled", I.HEX8, 4, 22)]
+         ("tet_4_scrambled", I.TET4, 4, 21), ("hex_4_scrambled", I.HEX8, 4, 22),
+         ("tri_8", I.TRI3, 8, None)]
 
 
 def dev(a, dtype=torch.float64):
@@ -62,7 +63,7 @@ def test_assembled_values_match_oracle(case):
 
 def test_assembled_values_reduced_by_dirichlet_mask(case):
     m, op, orc, u = case
-    mask, _ = I.clamp_top_bottom(m.X, 0.1)
+    mask, _ = I.clamp_planar(m.X, 0.1) if m.elem == I.TRI3 else I.clamp_top_bottom(m.X, 0.1)
     op.set_dirichlet(dev(mask, torch.uint8))
     try:
         vals = op.sparse_assemble(dev(u)).cpu().numpy()

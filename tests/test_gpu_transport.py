@@ -21,6 +21,7 @@ CASES = [
     ("tet_4_no_pairs_atomic", I.TET4, 4, dict(pairs=False, scatter="atomic")),
     ("hex_5", I.HEX8, 5, {}),
     ("hex_4_small_blocks", I.HEX8, 4, dict(block_elems=7, block_nodes=30)),
+    ("tri_10", I.TRI3, 10, {}),
 ]
 
 
