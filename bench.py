@@ -9,7 +9,8 @@ DOF/s of the tangent action over the timed steps.
 
 Beside it: the FP32 tangent action, the colour and atomic scatters, energy
 and residual times, the same operators under the small-strain linear model,
-the non-variational transport operator with a GMRES solve, a roofline object for the dominant kernel (the FP64
+the non-variational transport operator with a GMRES solve, the 2D Tri3
+plane-strain tangent action (1024^2 cells), a roofline object for the dominant kernel (the FP64
 tangent action's block pass with its halo gather, timed with HIP events on
 its stream), the Newton
 solves of the metric's second half (plain FP64 Jacobi-CG vs FP32 tangent
@@ -227,6 +228,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=64, help="hexes per cube edge")
+    ap.add_argument("--n2d", type=int, default=1024, help="cells per edge of the 2D Tri3 mesh")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-solve", action="store_true")
@@ -384,6 +386,31 @@ def main():
     }
     log(f"transport: hvp {t_t64*1e6:.2f} us, gmres {gm_it} its to {gm_rr:.2e} in {t_gm*1e3:.1f} ms")
 
+    # the 2D setup (Tri3, plane strain: out-of-plane components held), the
+    # paper's 2D JVP throughput configuration; DOFs counted in plane
+    n2 = args.n2d
+    m2 = I.tri_mesh(n2)
+    dof2 = m2.n_dofs
+    op2 = Operator(I.TRI3, m2.X, m2.conn, device=dev)
+    op2.set_dirichlet(torch.as_tensor(I.planar_mask(m2.X)).to(dev))
+    u2 = torch.as_tensor(I.gaussian_field(m2.n_nodes, 0.01 * 8 / n2, 0)).to(dev)
+    u2[:, 2] = 0
+    v2 = torch.as_tensor(I.unit_direction(m2.n_nodes, 100)).to(dev)
+    y2 = torch.empty_like(v2)
+    planar = {"mesh": f"unit square {n2}^2 cells x 2 triangles: {m2.n_elems} Tri3, {m2.n_nodes} nodes, "
+                      f"{dof2} in-plane DOF", "paper_context": "matrix-free JVP ~47 MDoF/s in 2D, A100 (JAX)"}
+    for model in ("neo_hookean", "linear"):
+        op2.set_model(model)
+        op2.linearize(u2, "f64")
+        op2.hvp(v2, out=y2)
+        t2 = event_time(lambda: op2.hvp(v2, out=y2), 200, stream)
+        b2 = m2.n_elems * 12 + (4 if model == "neo_hookean" else 3) * m2.n_nodes * 16
+        planar[model] = {"hvp_f64_us": round(t2 * 1e6, 3), "hvp_f64_gdofs": round(dof2 / t2 / 1e9, 3),
+                         "hvp_f64_pct_hbm_2d_bytes": round(100 * b2 / t2 / 1e9 / HBM_PEAK_GBS, 2)}
+        log(f"2D {model}: hvp {t2*1e6:.2f} us -> {dof2 / t2 / 1e9:.2f} GDoF/s")
+    op2.close()
+    del m2, u2, v2, y2
+
     # sparse tangent by colouring (Alg. 2): K(u) from n_colours tangent
     # actions, then CSR products against the matrix-free one
     sp_info = op.sparse_setup()
@@ -454,6 +481,7 @@ def main():
         "sparse_tangent": sparse,
         "linear_model": linear,
         "transport": transport,
+        "planar_2d": planar,
         "paper_context": "matrix-free JVP ~13 MDoF/s, 3D linear tets, NVIDIA A100 (JAX), precision unstated",
     }
 

@@ -444,10 +444,10 @@ int efem_create(efem_ctx **out, int32_t elem, int64_t n_nodes, int64_t n_elems,
         return EFEM_ERR_INVERTED;
     }
     // defaults measured on the 64^3 workloads: 1536 tets (768 pairs) within 600
-    // nodes, or 512 hexes within 768 nodes, per block; triangles: 1024 within
-    // 768 nodes
-    int be = elem == EFEM_TET4 ? 1536 : (elem == EFEM_TRI3 ? 1024 : 512);
-    int bn = elem == EFEM_TET4 ? 600 : 768;
+    // nodes, or 512 hexes within 768 nodes, per block; triangles (1024^2 cells):
+    // 768 within 600 nodes
+    int be = elem == EFEM_TET4 ? 1536 : (elem == EFEM_TRI3 ? 768 : 512);
+    int bn = elem == EFEM_HEX8 ? 768 : 600;
     int scatter = EFEM_SCATTER_HALO;
     int threads = 256;
     if (opts) {

@@ -109,16 +109,14 @@ def tri_mesh(n: int) -> Mesh:
     t = np.linspace(0.0, 1.0, n + 1)
     x, y = np.meshgrid(t, t, indexing="xy")
     X = np.stack([x.ravel(), y.ravel(), np.zeros((n + 1) ** 2)], axis=1)
-    tris = []
-    for j in range(n):
-        for i in range(n):
-            a = i + (n + 1) * j
-            b, c, d = a + 1, a + 1 + (n + 1), a + (n + 1)
-            if (i + j) % 2 == 0:
-                tris += [(a, b, c), (a, c, d)]
-            else:
-                tris += [(a, b, d), (b, c, d)]
-    return Mesh(TRI3, n, X, np.asarray(tris, dtype=np.int32))
+    j, i = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    a = (i + (n + 1) * j).ravel()
+    b, c, d = a + 1, a + 1 + (n + 1), a + (n + 1)
+    even = ((i + j) % 2 == 0).ravel()
+    t1 = np.where(even[:, None], np.stack([a, b, c], 1), np.stack([a, b, d], 1))
+    t2 = np.where(even[:, None], np.stack([a, c, d], 1), np.stack([b, c, d], 1))
+    tris = np.stack([t1, t2], axis=1).reshape(-1, 3)   # cell by cell, two triangles each
+    return Mesh(TRI3, n, X, tris.astype(np.int32))
 
 
 def planar_mask(X: np.ndarray) -> np.ndarray:
