@@ -23,10 +23,13 @@ static_assert(kP == EFEM_MLP_PARAMS, "parameter count");
 struct MlpState {
     int64_t *ptr = nullptr;      // [n_nodes+1] node 1-ring CSR
     int32_t *idx = nullptr;
+    int32_t *ell = nullptr;      // [max_deg][n_nodes] the same 1-ring, column-major,
+    int32_t max_deg = 0;         //   padded with n_nodes (a zero record of g4)
     uint16_t *W = nullptr;       // bf16 parameters [kP]
     bool have_weights = false;
     uint16_t *X = nullptr;       // [n_nodes][16] bf16 features
     float *scale = nullptr;      // [n_nodes]
+    float4 *g4 = nullptr;        // [n_nodes + 1] (D^-1 r, |D^-1 r|^2) of the features; last = 0
     float *dinv = nullptr;       // [3 n_nodes]
     float *z = nullptr;          // [3 n_nodes] scratch of the apply
     float *zold = nullptr;       // [3 n_nodes] flexible CG
@@ -43,7 +46,7 @@ constexpr int kEnergyBlocks = 512;
 hipError_t mlp_features_static(hipStream_t s, const MlpState &M, int64_t n, const double *diag,
                                const uint8_t *nmask, uint16_t *X);
 hipError_t mlp_features_dyn(hipStream_t s, const MlpState &M, int64_t n, const float *r,
-                            const float *dinv, uint16_t *X, float *scale);
+                            const float *dinv, uint16_t *X, float *scale, float4 *g4);
 hipError_t mlp_forward(hipStream_t s, const uint16_t *W, int64_t n, const uint16_t *X, float *out);
 int mlp_apply_grid(int64_t n);
 hipError_t mlp_apply(hipStream_t s, const uint16_t *W, int64_t n, const uint16_t *X, const float *r,

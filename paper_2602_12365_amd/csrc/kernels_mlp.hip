@@ -15,16 +15,21 @@ namespace efem {
 typedef short s4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 
-__device__ __forceinline__ uint16_t f2bf(float f)
-{
-    uint32_t u = __float_as_uint(f);
-    u += 0x7fffu + ((u >> 16) & 1u);   // round to nearest, ties to even
-    return (uint16_t)(u >> 16);
-}
+// float -> bfloat16 bits, round to nearest even (one hardware conversion on gfx950)
+__device__ __forceinline__ uint16_t f2bf(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 __device__ __forceinline__ float bfr(float f) { return bf2f(f2bf(f)); }
 
-__device__ __forceinline__ float softplus(float x) { return fmaxf(x, 0.f) + log1pf(__expf(-fabsf(x))); }
+// softplus(x) = max(x, 0) + ln(1 + e^-|x|) with the hardware base-2
+// exponential and logarithm: the exponent is <= 0 and the logarithm's argument
+// lies in [1, 2], so neither needs range reduction; where 1 + e^-|x| rounds to
+// 1 the term is below 2^-24, far under the bfloat16 rounding every activation
+// then takes.
+__device__ __forceinline__ float softplus(float x)
+{
+    const float t = __builtin_amdgcn_exp2f(-fabsf(x) * 1.4426950408889634f);
+    return fmaxf(x, 0.f) + 0.6931471805599453f * __builtin_amdgcn_logf(1.f + t);
+}
 __device__ __forceinline__ float sigmoidf_(float x) { return 1.f / (1.f + __expf(-x)); }
 
 // ------------------------------------------------------------------ features
@@ -57,26 +62,45 @@ __global__ void k_feat_static(int64_t n, const int64_t *__restrict__ ptr, const 
     x[12] = x[13] = x[14] = x[15] = 0;
 }
 
-// Dynamic features (slots 0..5) and the scale s from r and dinv (dinv = 0 on prescribed DOFs).
-__global__ void k_feat_dyn(int64_t n, const int64_t *__restrict__ ptr, const int32_t *__restrict__ idx,
-                           const float *__restrict__ r, const float *__restrict__ dinv,
-                           uint16_t *__restrict__ X, float *__restrict__ s_out)
+// g = D^-1 r per node with |g|^2, one 16-byte record each, so that the
+// 1-ring gather of the features reads one vector per neighbour.
+__global__ void k_g4(int64_t n, const float *__restrict__ r, const float *__restrict__ dinv,
+                     float4 *__restrict__ g4)
 {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const int64_t p0 = ptr[i], p1 = ptr[i + 1];
-    const int deg = (int)(p1 - p0);
-    const float g0 = r[3 * i] * dinv[3 * i], g1 = r[3 * i + 1] * dinv[3 * i + 1],
-                g2 = r[3 * i + 2] * dinv[3 * i + 2];
-    float s0 = 0.f, s1 = 0.f, s2 = 0.f, q = g0 * g0 + g1 * g1 + g2 * g2;
-    for (int64_t p = p0; p < p1; ++p) {
-        const int64_t j = idx[p];
-        const float a = r[3 * j] * dinv[3 * j], b = r[3 * j + 1] * dinv[3 * j + 1],
-                    c = r[3 * j + 2] * dinv[3 * j + 2];
-        s0 += a;
-        s1 += b;
-        s2 += c;
-        q += a * a + b * b + c * c;
+    const float a = r[3 * i] * dinv[3 * i], b = r[3 * i + 1] * dinv[3 * i + 1], c = r[3 * i + 2] * dinv[3 * i + 2];
+    g4[i] = make_float4(a, b, c, a * a + b * b + c * c);
+}
+
+// Dynamic features (slots 0..5) and the scale s from g4 = (D^-1 r, |D^-1 r|^2)
+// (dinv = 0 on prescribed DOFs).  The 1-ring comes column-major (ell[k][i],
+// padded with the zero record g4[n]), so every neighbour slot is one
+// coalesced index load; slots are taken two at a time.
+__global__ void k_feat_dyn(int64_t n, const int64_t *__restrict__ ptr, const int32_t *__restrict__ ell,
+                           int max_deg, const float4 *__restrict__ g4, uint16_t *__restrict__ X,
+                           float *__restrict__ s_out)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int deg = (int)(ptr[i + 1] - ptr[i]);
+    const float4 gi = g4[i];
+    const float g0 = gi.x, g1 = gi.y, g2 = gi.z;
+    float s0 = 0.f, s1 = 0.f, s2 = 0.f, q = gi.w;
+    int k = 0;
+    for (; k + 2 <= max_deg; k += 2) {
+        const float4 a = g4[ell[(int64_t)k * n + i]], b = g4[ell[(int64_t)(k + 1) * n + i]];
+        s0 += a.x + b.x;
+        s1 += a.y + b.y;
+        s2 += a.z + b.z;
+        q += a.w + b.w;
+    }
+    if (k < max_deg) {
+        const float4 a = g4[ell[(int64_t)k * n + i]];
+        s0 += a.x;
+        s1 += a.y;
+        s2 += a.z;
+        q += a.w;
     }
     const float s = sqrtf(q / (3.f * (float)(deg + 1)));
     uint16_t *x = X + i * kInPad;
@@ -171,9 +195,13 @@ __global__ void __launch_bounds__(256) k_mlp_forward(int64_t n, const uint16_t *
     const int lane = threadIdx.x & 63;
     const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
     const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    // the next group's features are loaded while this group is evaluated
+    s4 xn = load_x(X, wave * 16 + (lane & 15), n);
     for (int64_t g0 = wave * 16; g0 < n; g0 += nw * 16) {
         const int64_t node = g0 + (lane & 15);
-        const f4 o = mlp16(R, load_x(X, node, n));
+        const s4 xb = xn;
+        xn = load_x(X, node + nw * 16, n);
+        const f4 o = mlp16(R, xb);
         if (lane < 16 && node < n) {
             out[3 * node] = o[0];
             out[3 * node + 1] = o[1];
@@ -198,9 +226,13 @@ __global__ void __launch_bounds__(256) k_mlp_apply(int64_t n, const uint16_t *__
     const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
     const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
     double rz = 0.0;
+    // the next group's features are loaded while this group is evaluated
+    s4 xn = load_x(X, wave * 16 + (lane & 15), n);
     for (int64_t g0 = wave * 16; g0 < n; g0 += nw * 16) {
         const int64_t node = g0 + (lane & 15);
-        const f4 o = mlp16(R, load_x(X, node, n));
+        const s4 xb = xn;
+        xn = load_x(X, node + nw * 16, n);
+        const f4 o = mlp16(R, xb);
         if (lane < 16 && node < n) {
             // z = g + gamma c with g = D^-1 r, c = s MLP; gamma < 1 only where
             // r_i.z_i would fall below half of r_i.g_i, so r.z >= r.D^-1 r / 2
@@ -533,7 +565,9 @@ __global__ void k_dinv_f32(int64_t n, const double *__restrict__ diag, const uin
 // ---------------------------------------------------------------- launchers
 
 static unsigned g256(int64_t n) { return (unsigned)((n + 255) / 256); }
-static unsigned mlp_grid(int64_t n) { return (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 63) / 64, 2048)); }
+// The MLP kernels load the weights once per wave; a grid of about the
+// resident wave count (3 waves per SIMD) spreads that over many node groups.
+static unsigned mlp_grid(int64_t n) { return (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 63) / 64, 768)); }
 
 hipError_t mlp_features_static(hipStream_t s, const MlpState &M, int64_t n, const double *diag,
                                const uint8_t *nmask, uint16_t *X)
@@ -543,9 +577,10 @@ hipError_t mlp_features_static(hipStream_t s, const MlpState &M, int64_t n, cons
 }
 
 hipError_t mlp_features_dyn(hipStream_t s, const MlpState &M, int64_t n, const float *r,
-                            const float *dinv, uint16_t *X, float *scale)
+                            const float *dinv, uint16_t *X, float *scale, float4 *g4)
 {
-    hipLaunchKernelGGL(k_feat_dyn, dim3(g256(n)), dim3(256), 0, s, n, M.ptr, M.idx, r, dinv, X, scale);
+    hipLaunchKernelGGL(k_g4, dim3(g256(n)), dim3(256), 0, s, n, r, dinv, g4);
+    hipLaunchKernelGGL(k_feat_dyn, dim3(g256(n)), dim3(256), 0, s, n, M.ptr, M.ell, M.max_deg, g4, X, scale);
     return hipGetLastError();
 }
 

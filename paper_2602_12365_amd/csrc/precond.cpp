@@ -82,7 +82,8 @@ MlpState *mlp_state(Ctx &c, int *rc)
     int r;
     if ((r = malloc_into(*M, &M->ptr, ptr.size())) || (r = malloc_into(*M, &M->idx, idx.size()))
         || (r = malloc_into(*M, &M->W, kP)) || (r = malloc_into(*M, &M->X, (size_t)nn * kInPad))
-        || (r = malloc_into(*M, &M->scale, (size_t)nn)) || (r = malloc_into(*M, &M->dinv, 3 * (size_t)nn))
+        || (r = malloc_into(*M, &M->scale, (size_t)nn)) || (r = malloc_into(*M, &M->g4, (size_t)nn + 1))
+        || (r = malloc_into(*M, &M->dinv, 3 * (size_t)nn))
         || (r = malloc_into(*M, &M->z, 3 * (size_t)nn)) || (r = malloc_into(*M, &M->zold, 3 * (size_t)nn))
         || (r = malloc_into(*M, &M->prz, 2048)) || (r = malloc_into(*M, &M->gpart, (size_t)kGradBlocks * kP))
         || (r = malloc_into(*M, &M->lpart, kGradBlocks)) || (r = malloc_into(*M, &M->tt, 1))
@@ -90,6 +91,23 @@ MlpState *mlp_state(Ctx &c, int *rc)
         for (void *p : M->owned) (void)hipFree(p);
         delete M;
         *rc = r;
+        return nullptr;
+    }
+    // the 1-ring again, column-major and padded to the largest degree, so that
+    // the per-iteration feature gather reads its indices coalesced
+    int32_t max_deg = 0;
+    for (int64_t i = 0; i < nn; ++i) max_deg = std::max<int32_t>(max_deg, (int32_t)(ptr[(size_t)i + 1] - ptr[(size_t)i]));
+    std::vector<int32_t> ell((size_t)max_deg * (size_t)nn, (int32_t)nn);
+    for (int64_t i = 0; i < nn; ++i)
+        for (int64_t p = ptr[(size_t)i]; p < ptr[(size_t)i + 1]; ++p)
+            ell[(size_t)(p - ptr[(size_t)i]) * (size_t)nn + (size_t)i] = idx[(size_t)p];
+    M->max_deg = max_deg;
+    if ((r = malloc_into(*M, &M->ell, ell.size()))
+        || hipMemcpy(M->ell, ell.data(), ell.size() * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess
+        || hipMemset(M->g4 + nn, 0, sizeof(float4)) != hipSuccess) {
+        for (void *p : M->owned) (void)hipFree(p);
+        delete M;
+        *rc = r ? r : hip_fail(hipGetLastError(), "hipMemcpy");
         return nullptr;
     }
     if (hipMemcpy(M->ptr, ptr.data(), ptr.size() * sizeof(int64_t), hipMemcpyHostToDevice) != hipSuccess
@@ -107,7 +125,7 @@ MlpState *mlp_state(Ctx &c, int *rc)
 // Features of r (static part from diag) and z = M(r); partials of r.z in M.prz.
 hipError_t mlp_precondition(Ctx &c, MlpState &M, const float *r, float *z)
 {
-    hipError_t e = mlp_features_dyn(c.stream, M, c.n_nodes, r, M.dinv, M.X, M.scale);
+    hipError_t e = mlp_features_dyn(c.stream, M, c.n_nodes, r, M.dinv, M.X, M.scale, M.g4);
     if (e != hipSuccess) return e;
     return mlp_apply(c.stream, M.W, c.n_nodes, M.X, r, M.dinv, M.scale, z, M.prz);
 }
@@ -173,7 +191,7 @@ int efem_precond_rows(efem_ctx *ctx, const float *b, const double *diag, const f
     }
     TRY(mlp_dinv_f32(ctx->stream, 3 * ctx->n_nodes, diag, ctx->m.nmask, M->dinv));
     TRY(mlp_features_static(ctx->stream, *M, ctx->n_nodes, diag, ctx->m.nmask, X));
-    TRY(mlp_features_dyn(ctx->stream, *M, ctx->n_nodes, b, M->dinv, X, M->scale));
+    TRY(mlp_features_dyn(ctx->stream, *M, ctx->n_nodes, b, M->dinv, X, M->scale, M->g4));
     TRY(mlp_rows_aux(ctx->stream, ctx->n_nodes, b, M->dinv, t, M->scale, M->tt, n_total, aux));
     return EFEM_OK;
 }
