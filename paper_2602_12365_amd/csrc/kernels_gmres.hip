@@ -23,23 +23,42 @@ __device__ __forceinline__ bool fixed_dof(const uint8_t *nmask, int64_t i)
     return nmask && ((nmask[i / 3] >> (i % 3)) & 1);
 }
 
-// Each workgroup covers a grid-stride share of the entries and reduces the
-// k products with V_j in turn; partial j of workgroup g goes to part[j * G + g].
+// Each workgroup covers a grid-stride share of the entries.  A thread keeps
+// the products with up to kChunk basis vectors in registers, so w is read
+// once per chunk, then every sum is reduced across the wave with shuffles and
+// across the four waves in LDS; partial j of workgroup g goes to part[j * G + g].
+constexpr int kChunk = 16;
+
 __global__ void __launch_bounds__(kT) k_mdot(int64_t n, const double *__restrict__ V, int k,
                                              const double *__restrict__ w, double *__restrict__ part)
 {
-    __shared__ double red[kT];
-    for (int j = 0; j < k; ++j) {
-        const double *v = V + (int64_t)j * n;
-        double s = 0.0;
-        GSTRIDE(i, n) s += v[i] * w[i];
-        red[threadIdx.x] = s;
-        __syncthreads();
-        for (int h = kT / 2; h > 0; h >>= 1) {
-            if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
-            __syncthreads();
+    __shared__ double red[kT / 64][kChunk];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int j0 = 0; j0 < k; j0 += kChunk) {
+        const int kc = min(kChunk, k - j0);
+        double acc[kChunk];
+#pragma unroll
+        for (int j = 0; j < kChunk; ++j) acc[j] = 0.0;
+        GSTRIDE(i, n) {
+            const double wi = w[i];
+#pragma unroll
+            for (int j = 0; j < kChunk; ++j)
+                if (j < kc) acc[j] += V[(int64_t)(j0 + j) * n + i] * wi;
         }
-        if (threadIdx.x == 0) part[(int64_t)j * gridDim.x + blockIdx.x] = red[0];
+#pragma unroll
+        for (int j = 0; j < kChunk; ++j) {
+            double v = acc[j];
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+            if (lane == 0) red[wave][j] = v;
+        }
+        __syncthreads();
+        if ((int)threadIdx.x < kc) {
+            double t = 0.0;
+#pragma unroll
+            for (int q = 0; q < kT / 64; ++q) t += red[q][threadIdx.x];
+            part[(int64_t)(j0 + threadIdx.x) * gridDim.x + blockIdx.x] = t;
+        }
         __syncthreads();
     }
 }
@@ -63,9 +82,16 @@ __global__ void __launch_bounds__(kT) k_mdot_fin(const double *__restrict__ part
 __global__ void __launch_bounds__(kT) k_subtract(int64_t n, const double *__restrict__ V, int k,
                                                  const double *__restrict__ h, double *__restrict__ w)
 {
+    __shared__ double hs[kGmresMaxRestart + 1];
+    for (int j = threadIdx.x; j < k; j += kT) hs[j] = h[j];
+    __syncthreads();
     GSTRIDE(i, n) {
         double t = w[i];
-        for (int j = 0; j < k; ++j) t -= h[j] * V[(int64_t)j * n + i];
+        int j = 0;
+        for (; j + 4 <= k; j += 4)
+            t -= (hs[j] * V[(int64_t)j * n + i] + hs[j + 1] * V[(int64_t)(j + 1) * n + i])
+               + (hs[j + 2] * V[(int64_t)(j + 2) * n + i] + hs[j + 3] * V[(int64_t)(j + 3) * n + i]);
+        for (; j < k; ++j) t -= hs[j] * V[(int64_t)j * n + i];
         w[i] = t;
     }
 }
