@@ -1455,6 +1455,37 @@ __device__ __forceinline__ IData<E> fetch_item(const BlockMesh &m, const ItemRan
     return d;
 }
 
+// the packed local connectivity of item k alone (one vector load)
+template <class E>
+__device__ __forceinline__ ItemWord<E> fetch_lc(const BlockMesh &m, const ItemRange &r, int k)
+{
+    ItemWord<E> w;
+    const int64_t i = r.i0 + k;
+    if constexpr (E::NEN == 5) w.w = *reinterpret_cast<const uint2 *>(m.items + 2 * i);
+    else if constexpr (E::NEN == 3) w.w = m.items[i];
+    else w.w = *reinterpret_cast<const uint4 *>(m.items + 4 * i);
+    return w;
+}
+
+// materials of item k: the two kernel-argument scalars when uniform, else
+// per element (an unpaired tetrahedron repeats its first element)
+template <class E, class T>
+__device__ __forceinline__ void item_materials(const BlockMesh &m, const ItemRange &r, int k, T mu[E::NSUB],
+                                               T lam[E::NSUB])
+{
+#pragma unroll
+    for (int s = 0; s < E::NSUB; ++s) {
+        if (m.mu) {
+            const int e = r.elem(k, (s > 0 && k >= r.np) ? 0 : s);
+            mu[s] = T(m.mu[e]);
+            lam[s] = T(m.lam[e]);
+        } else {
+            mu[s] = T(m.mu0);
+            lam[s] = T(m.lam0);
+        }
+    }
+}
+
 template <class E>
 __device__ __forceinline__ void unpack_lc(const ItemWord<E> &l, uint16_t lc[E::NEN])
 {
@@ -1482,20 +1513,21 @@ __device__ __forceinline__ void materials(const IData<E> &d, T mu[E::NSUB], T la
 // ---------------------------------------------------------- block pass kernel
 
 // Waves per SIMD the register allocator must leave room for.  The FP64 Tet4
-// pair pass needs about 186 VGPRs unconstrained (2 waves); the other item
+// pair pass needs 170 VGPRs unconstrained (2 waves per SIMD); held to 168 for
+// 3 waves it spills one register and runs about 3% faster.  The other item
 // kernels keep the compiler's choice.
 #ifndef EFEM_TET64_MIN_WAVES
-#define EFEM_TET64_MIN_WAVES 1
+#define EFEM_TET64_MIN_WAVES 3
 #endif
-template <class E, class T> struct MinWaves {
+template <class E, class Op> struct MinWaves {
     static constexpr int value = 1;
 };
-template <> struct MinWaves<Tet4Pair, double> {
+template <> struct MinWaves<Tet4Pair, HvpOp<double>> {
     static constexpr int value = EFEM_TET64_MIN_WAVES;
 };
 
 template <class E, class Op, class T, bool ACC>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MinWaves<E, T>::value, 8)))
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MinWaves<E, Op>::value, 8)))
 k_accumulate(BlockMesh m, Op op, T *__restrict__ y,
                                                     const int32_t *__restrict__ list, int count,
                                                     Scatter mode, int use_mask, T fixed_val,
@@ -1520,8 +1552,11 @@ k_accumulate(BlockMesh m, Op op, T *__restrict__ y,
     const int S = (r.ni + 63) >> 6;
     int j = threadIdx.x >> 6;
     auto item_of = [&](int jj) { return lane * S + jj; };
-    IData<E> nxt{};
-    if (j < S && item_of(j) < r.ni) nxt = fetch_item<E>(m, r, item_of(j));   // in flight during staging
+    // the next item's connectivity is in flight while this one computes; its
+    // materials are read at use (two scalars when uniform), which keeps four
+    // doubles per item out of the registers
+    ItemWord<E> nxt{};
+    if (j < S && item_of(j) < r.ni) nxt = fetch_lc<E>(m, r, item_of(j));   // in flight during staging
     for (int l = threadIdx.x; l < nn; l += nt) {
         op.stage(m, sn[l], bnode[l] & kGidMask);
         acc[3 * l + 0] = 0.0;
@@ -1533,12 +1568,12 @@ k_accumulate(BlockMesh m, Op op, T *__restrict__ y,
     for (; j < S; j += W) {
         const int k = item_of(j);
         if (k >= r.ni) break;
-        const IData<E> cur = nxt;
-        if (j + W < S && item_of(j + W) < r.ni) nxt = fetch_item<E>(m, r, item_of(j + W));
+        const ItemWord<E> cur = nxt;
+        if (j + W < S && item_of(j + W) < r.ni) nxt = fetch_lc<E>(m, r, item_of(j + W));
         uint16_t lc[E::NEN];
-        unpack_lc<E>(cur.lc, lc);
+        unpack_lc<E>(cur, lc);
         T mu[E::NSUB], lam[E::NSUB];
-        materials<E>(cur, mu, lam);
+        item_materials<E>(m, r, k, mu, lam);
         T f[E::NEN][3];   // written in full by element()
         bad |= !op.template element<E>(sn, lc, mu, lam, k < r.np, f);
 #pragma unroll
