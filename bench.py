@@ -299,6 +299,15 @@ def main():
     achieved_tf = alg_flops / t_acc / 1e12
     log(f"hvp block pass + gather {t_acc*1e6:.2f} us -> {achieved:.0f} GB/s, {achieved_tf:.2f} TFLOP/s")
 
+    # achievable HBM bandwidth: a plain 1 GiB device copy (read + write)
+    ca = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
+    cb = torch.empty_like(ca)
+    cb.copy_(ca)
+    t_copy = event_time(lambda: cb.copy_(ca), 20, stream)
+    copy_gbs = 2 * ca.numel() / t_copy / 1e9
+    del ca, cb
+    log(f"1 GiB device copy: {copy_gbs:.0f} GB/s")
+
     # FP32 tangent action
     op.linearize(u, "f32")
 
@@ -466,6 +475,8 @@ def main():
             "alg_bytes": alg_hvp,
             "hbm_achieved_gbs": round(achieved, 1),
             "hbm_frac": round(achieved / HBM_PEAK_GBS, 4),
+            "hbm_copy_gbs": round(copy_gbs, 1),   # achievable: 1 GiB device copy
+            "hbm_frac_of_copy": round(achieved / copy_gbs, 4),
         },
         "hvp_f64_us": round(t_hvp * 1e6, 3),
         "hvp_f64_pct_hbm": round(100 * alg_hvp / t_hvp / 1e9 / HBM_PEAK_GBS, 2),
