@@ -48,6 +48,10 @@ CASES = [
     ("tri_9_small_blocks", I.TRI3, 9, dict(block_elems=50, block_nodes=40, threads=64)),
     ("tri_10_color", I.TRI3, 10, dict(scatter="color")),
     ("tri_10_linear_atomic", I.TRI3, 10, dict(model="linear", scatter="atomic")),
+    # the largest blocks: 768 distinct nodes (78 KB of LDS per workgroup)
+    ("tet_10_max_blocks", I.TET4, 10, dict(block_elems=100000, block_nodes=768)),
+    ("hex_10_max_blocks", I.HEX8, 10, dict(block_elems=100000, block_nodes=768, scatter="color")),
+    ("tri_40_max_blocks", I.TRI3, 40, dict(block_elems=100000, block_nodes=768)),
 ]
 
 
@@ -256,6 +260,21 @@ def test_error_codes():
         op.hvp(dev(np.zeros_like(m.X)))       # not linearized
     lib = L.load()
     assert lib.efem_hvp(op._h, None, None) == L.EFEM_ERR_INVALID
+    # sizes and options the library refuses before touching the GPU
+    with pytest.raises(L.EfemError):
+        Operator(I.TET4, m.X, m.conn[:0])                       # no elements
+    with pytest.raises(L.EfemError):
+        Operator(I.TET4, m.X, m.conn, block_nodes=769)          # beyond the LDS cap
+    with pytest.raises(L.EfemError):
+        Operator(I.TET4, m.X, m.conn, threads=96)               # not a multiple of 64
+    bad = m.conn.copy()
+    bad[0, 0] = m.n_nodes                                       # node id out of range
+    with pytest.raises(L.EfemError):
+        Operator(I.TET4, m.X, bad)
+    flipped = m.conn.copy()
+    flipped[0, [1, 2]] = flipped[0, [2, 1]]                     # inverted reference element
+    with pytest.raises(L.EfemError):
+        Operator(I.TET4, m.X, flipped)
 
 
 def test_full_size_64cube_tets():
