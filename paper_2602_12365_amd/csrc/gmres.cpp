@@ -4,8 +4,8 @@
 //     K(u)_ff x_f = b_f,   x = 0 on prescribed DOFs,
 // from x = 0.  The Arnoldi basis is float64 on the device; orthogonalisation
 // is classical Gram-Schmidt applied twice (one multi-dot and one multi-axpy
-// kernel per pass), so each iteration needs three small host reads (the two
-// projections and the new norm).  The Hessenberg matrix, its Givens rotations
+// kernel per pass, the projections kept on the device), so each iteration
+// needs one small host read (both projections and w.w).  The Hessenberg matrix, its Givens rotations
 // and the small triangular solve live on the host.
 #include <algorithm>
 #include <cmath>
@@ -61,8 +61,8 @@ struct Gmres {
         const size_t nb = (size_t)n * sizeof(double);
         if ((rc = dev_alloc(V, nb * (size_t)(m + 1))) || (rc = dev_alloc(w, nb)) || (rc = dev_alloc(z, nb))
             || (rc = dev_alloc(dinv, nb)) || (rc = dev_alloc(diag, nb))
-            || (rc = dev_alloc(part, sizeof(double) * kGmresRedBlocks * (size_t)(m + 1)))
-            || (rc = dev_alloc(hdev, sizeof(double) * (size_t)(m + 1))))
+            || (rc = dev_alloc(part, sizeof(double) * kGmresRedBlocks * (size_t)(m + 2)))
+            || (rc = dev_alloc(hdev, sizeof(double) * (size_t)(2 * m + 3))))
             return rc;
         if (prec == EFEM_F32 && ((rc = dev_alloc(z32, (size_t)n * sizeof(float))) || (rc = dev_alloc(w32, (size_t)n * sizeof(float)))))
             return rc;
@@ -82,14 +82,6 @@ struct Gmres {
         }
         return EFEM_OK;
     }
-    // projections h[0..k) = V_j . vec, read back to the host
-    int project(int k, const double *vec, double *h_host)
-    {
-        GTRY(gm_mdot(s, n, V.as<double>(), k, vec, part.as<double>(), hdev.as<double>()));
-        GTRY(hipMemcpyAsync(h_host, hdev.p, sizeof(double) * (size_t)k, hipMemcpyDeviceToHost, s));
-        GTRY(hipStreamSynchronize(s));
-        return EFEM_OK;
-    }
     int norm(const double *vec, double &out)
     {
         double h = 0.0;
@@ -107,7 +99,7 @@ struct Gmres {
         GTRY(launch_diag(c, x, diag.as<double>()));   // x holds u here: the diagonal at u
         GTRY(gm_dinv(s, n, diag.as<double>(), mask, dinv.as<double>()));
         GTRY(hipMemsetAsync(x, 0, (size_t)n * sizeof(double), s));
-        std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), h(m + 1), h2(m + 1), y(m);
+        std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), h(m + 1), h2(m + 2), y(m);
         auto Hx = [&](int i, int j) -> double & { return H[(size_t)i * m + j]; };
         double bnorm = -1.0, tol = 0.0;
         int total = 0;
@@ -136,17 +128,34 @@ struct Gmres {
             g[0] = beta;
             int jend = 0;
             for (int j = 0; j < m; ++j) {
+                // the new vector is built in place, in basis slot j + 1
+                double *wj = Vj(j + 1);
+                double *h1d = hdev.as<double>(), *h2d = hdev.as<double>() + (m + 1);
                 GTRY(gm_mul(s, n, dinv.as<double>(), Vj(j), z.as<double>()));
-                if ((rc = apply(z.as<double>(), w.as<double>()))) return rc;
-                // classical Gram-Schmidt, twice
-                if ((rc = project(j + 1, w.as<double>(), h.data()))) return rc;
-                GTRY(hipMemcpyAsync(hdev.p, h.data(), sizeof(double) * (size_t)(j + 1), hipMemcpyHostToDevice, s));
-                GTRY(gm_subtract(s, n, V.as<double>(), j + 1, hdev.as<double>(), w.as<double>()));
-                if ((rc = project(j + 1, w.as<double>(), h2.data()))) return rc;
-                GTRY(hipMemcpyAsync(hdev.p, h2.data(), sizeof(double) * (size_t)(j + 1), hipMemcpyHostToDevice, s));
-                GTRY(gm_subtract(s, n, V.as<double>(), j + 1, hdev.as<double>(), w.as<double>()));
+                if ((rc = apply(z.as<double>(), wj))) return rc;
+                // classical Gram-Schmidt twice; the projections stay on the
+                // device for the subtractions, and the second multi-dot also
+                // takes w.w (slot j + 1 is w itself), so one read-back per
+                // iteration serves the Hessenberg column and the new norm
+                GTRY(gm_mdot(s, n, V.as<double>(), j + 1, wj, part.as<double>(), h1d));
+                GTRY(gm_subtract(s, n, V.as<double>(), j + 1, h1d, wj));
+                GTRY(gm_mdot(s, n, V.as<double>(), j + 2, wj, part.as<double>(), h2d));
+                GTRY(gm_subtract(s, n, V.as<double>(), j + 1, h2d, wj));
+                GTRY(hipMemcpyAsync(h.data(), h1d, sizeof(double) * (size_t)(j + 1), hipMemcpyDeviceToHost, s));
+                GTRY(hipMemcpyAsync(h2.data(), h2d, sizeof(double) * (size_t)(j + 2), hipMemcpyDeviceToHost, s));
+                GTRY(hipStreamSynchronize(s));
+                // |w - V h2|^2 = w.w - |h2|^2 for orthonormal V; after the first
+                // pass h2 is small against w, and where it is not (near a
+                // breakdown) the norm is taken directly
+                double hh = 0.0;
+                for (int i = 0; i <= j; ++i) hh += h2[i] * h2[i];
+                const double ww = h2[j + 1];
                 double hn;
-                if ((rc = norm(w.as<double>(), hn))) return rc;
+                if (ww - hh > 1e-8 * ww) {
+                    hn = std::sqrt(ww - hh);
+                } else if ((rc = norm(wj, hn))) {
+                    return rc;
+                }
                 for (int i = 0; i <= j; ++i) Hx(i, j) = h[i] + h2[i];
                 Hx(j + 1, j) = hn;
                 // previous rotations, then a new one that zeroes H(j+1, j)
@@ -166,7 +175,7 @@ struct Gmres {
                 jend = j + 1;
                 const double res = std::fabs(g[j + 1]);
                 const bool breakdown = !(hn > 1e-300 * beta);
-                if (!breakdown) GTRY(gm_scale(s, n, 1.0 / hn, w.as<double>(), Vj(j + 1)));
+                if (!breakdown) GTRY(gm_scale(s, n, 1.0 / hn, wj, wj));
                 if (res <= tol || breakdown || total >= max_iter) break;
             }
             // y = H^-1 g (upper triangular), x += dinv V y
