@@ -41,6 +41,8 @@ struct CgLaunch {
     hipError_t dinv_from_diag(const double *diag, const uint8_t *nmask, T *dinv) const;
     hipError_t axpy_state(const double *u, double alpha, const T *d, double *out) const;
     hipError_t scaled(const T *dinv, const double *b, double sign, T *x) const;
+    hipError_t widen(const T *a, double *out) const;   // out = (double) a
+    hipError_t add_to(T *x, const T *d) const;          // x += d
     hipError_t dot_state(const double *a, const T *b, double *out) const;
     hipError_t apply_predictor(const double *u_old, const double *dc, const T *df,
                                const uint8_t *nmask, bool use_df, double *u) const;

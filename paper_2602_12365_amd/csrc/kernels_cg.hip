@@ -224,6 +224,20 @@ __global__ void k_axpy_state(int64_t n, const double *__restrict__ u, double alp
     GRID_STRIDE(i, n) out[i] = u[i] + alpha * (double)d[i];
 }
 
+// out = (double) a
+template <class T>
+__global__ void k_widen(int64_t n, const T *__restrict__ a, double *__restrict__ out)
+{
+    GRID_STRIDE(i, n) out[i] = (double)a[i];
+}
+
+// x += d
+template <class T>
+__global__ void k_add_to(int64_t n, T *__restrict__ x, const T *__restrict__ d)
+{
+    GRID_STRIDE(i, n) x[i] += d[i];
+}
+
 // x = dinv * sign * b (steepest-descent fallback step)
 template <class T>
 __global__ void k_scaled(int64_t n, const T *__restrict__ dinv, const double *__restrict__ b,
@@ -317,6 +331,20 @@ template <class T>
 hipError_t CgLaunch<T>::axpy_state(const double *u, double alpha, const T *d, double *out) const
 {
     hipLaunchKernelGGL(k_axpy_state<T>, dim3(red_grid(n)), dim3(kThreads), 0, s, n, u, alpha, d, out);
+    return hipGetLastError();
+}
+
+template <class T>
+hipError_t CgLaunch<T>::widen(const T *a, double *out) const
+{
+    hipLaunchKernelGGL(k_widen<T>, dim3(red_grid(n)), dim3(kThreads), 0, s, n, a, out);
+    return hipGetLastError();
+}
+
+template <class T>
+hipError_t CgLaunch<T>::add_to(T *x, const T *d) const
+{
+    hipLaunchKernelGGL(k_add_to<T>, dim3(red_grid(n)), dim3(kThreads), 0, s, n, x, d);
     return hipGetLastError();
 }
 

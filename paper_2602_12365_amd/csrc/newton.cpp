@@ -161,7 +161,10 @@ struct Solver {
     }
 
     // Flexible CG with the learned preconditioner for K_ff x = sign * b from
-    // x = 0; on breakdown, non-positive r.z or stagnation, Jacobi PCG from x = 0.
+    // x = 0.  On breakdown, non-positive r.z or stagnation it falls back to
+    // Jacobi PCG, which continues from the flexible-CG iterate when that is
+    // finite (K d = r for its residual r, to the original tolerance, then
+    // x += d), else starts again from x = 0.
     int fcg(const double *b, double sign, double eta, int max_it, int &iters, int &fallbacks)
     {
         MlpState &M = *static_cast<MlpState *>(c.mlp);
@@ -186,11 +189,24 @@ struct Solver {
         }
         iters = h_sc->iter;
         if (h_sc->fallback) {
-            int it2 = 0;
-            int rc = pcg(b, sign, eta, max_it, it2);
-            iters += it2;
             fallbacks += 1;
-            return rc;
+            int it2 = 0, rc;
+            // the flexible-CG residual as the new right-hand side (diag is
+            // free here: the features are built and dinv is set)
+            const double bnorm = std::sqrt(h_sc->bb);
+            double rnorm = 0.0;
+            TRY(L.widen(rv, diag));
+            if ((rc = norm(diag, rnorm))) return rc;
+            if (std::isfinite(rnorm) && rnorm > 0.0 && bnorm > 0.0 && iters > 0) {
+                TRY(hipMemcpyAsync(M.zold, x, n * sizeof(T), hipMemcpyDeviceToDevice, c.stream));
+                rc = pcg(diag, 1.0, eta * bnorm / rnorm, std::max(1, max_it - iters), it2);
+                if (rc) return rc;
+                TRY(L.add_to(x, reinterpret_cast<const T *>(M.zold)));
+            } else {
+                rc = pcg(b, sign, eta, max_it, it2);
+                if (rc) return rc;
+            }
+            iters += it2;
         }
         return EFEM_OK;
     }
