@@ -174,6 +174,16 @@ int efem_set_coords(efem_ctx *ctx, const double *coords);
  * are part of u).  Copied into the context. */
 int efem_set_dirichlet(efem_ctx *ctx, const uint8_t *mask);
 
+/* External nodal forces f (DEVICE float64 [3*n_nodes]) of the final load step,
+ * or NULL to remove them.  The total potential energy of Sec. 6.1 subtracts
+ * the work of a boundary traction t; for the linear boundary interpolation
+ * that work is exactly f.u with f_a the integral of t N_a over the loaded
+ * boundary, which the caller computes.  Only efem_newton_solve uses f: at
+ * load step k of n it minimizes Psi_h(u) - (k/n) f.u.  efem_energy,
+ * efem_residual and the tangent action stay those of Psi_h.  Entries of f on
+ * prescribed DOFs have no effect on the solution.  Copied; asynchronous. */
+int efem_set_load(efem_ctx *ctx, const double *f);
+
 /* Psi_h(u), Eq. (2): u DEVICE float64 [3*n_nodes]; psi DEVICE float64 [1].
  * A block-wise then compensated FP64 sum, bitwise deterministic.  If an element
  * has det F <= 0 the result is +inf and the context's inverted flag is set
@@ -281,9 +291,11 @@ void efem_solve_opts_default(efem_solve_opts *opts);
  *   u_inout   DEVICE float64 [3*n_nodes]: initial free values in, solution out
  *   u_bc      DEVICE float64 [3*n_nodes]: prescribed values of the final load
  *             step (entries on free DOFs are ignored)
- * Per load step: prescribed DOFs set to k/n of u_bc, a tangent predictor, then
- * Newton iterations with PCG (Jacobi or learned), Eisenstat-Walker forcing and
- * Armijo backtracking on the FP64 energy.  Synchronous.
+ * Per load step: prescribed DOFs set to k/n of u_bc and the load of
+ * efem_set_load to k/n of f, a tangent predictor, then Newton iterations with
+ * PCG (Jacobi or learned), Eisenstat-Walker forcing and Armijo backtracking on
+ * the FP64 total energy Psi_h(u) - (k/n) f.u.  final_energy reports that
+ * total and final_residual the norm of its free gradient.  Synchronous.
  * Returns EFEM_OK, EFEM_NOT_CONVERGED (stats say where) or an error. */
 int efem_newton_solve(efem_ctx *ctx, double *u_inout, const double *u_bc,
                       const efem_solve_opts *opts, efem_solve_stats *stats);

@@ -267,7 +267,7 @@ def pcg(apply_K, b, dinv, rtol, max_iter):
     return x, max_iter
 
 
-def newton_solve(fem: FEM, mask, u_bc_final, opts: SolveOptions, u0=None):
+def newton_solve(fem: FEM, mask, u_bc_final, opts: SolveOptions, u0=None, f_ext=None):
     """Matrix-free Newton-Krylov on the reduced functional (Sec. 6.1, Sec. 6.3.1).
 
     The paper names the method but gives none of its parts; the reading used:
@@ -280,6 +280,11 @@ def newton_solve(fem: FEM, mask, u_bc_final, opts: SolveOptions, u0=None):
         sufficient-decrease test allows 64 eps |Psi| for the energy's rounding,
         below which a decrease cannot be resolved);
       * stop when ||r_f|| <= rtol ||r_f(step start)||.
+
+    With external nodal forces f_ext (the work of a boundary traction,
+    Sec. 6.1) the functional is the total potential energy Psi_h(u) - s f.u,
+    s = k/n at step k: the residual gains -s f, the predictor's right-hand side
+    +(s_k - s_(k-1)) f, and the line search compares total energies.
     """
     mask = np.asarray(mask).reshape(-1)
     free = (mask == 0).astype(np.float64)
@@ -287,23 +292,29 @@ def newton_solve(fem: FEM, mask, u_bc_final, opts: SolveOptions, u0=None):
     u = np.zeros(3 * fem.n_nodes) if u0 is None else np.array(u0, dtype=np.float64).reshape(-1)
     ubc = np.asarray(u_bc_final, dtype=np.float64).reshape(-1)
     st = SolveStats()
+    f = np.zeros_like(u) if f_ext is None else np.asarray(f_ext, dtype=np.float64).reshape(-1)
+    s = 0.0
 
     def K_ff(uu, p):
         return free * fem.hvp(uu, free * p).reshape(-1)
 
     def res_f(uu):
-        return free * fem.residual(uu).reshape(-1)
+        return free * (fem.residual(uu).reshape(-1) - s * f)
+
+    def total_energy(uu, allow_inverted=False):
+        return fem.energy(uu, allow_inverted=allow_inverted) - s * (f @ uu)
 
     for k in range(1, opts.n_steps + 1):
+        s_prev, s = s, k / opts.n_steps
         target = (k / opts.n_steps) * ubc
         # tangent predictor: prescribed increment dc, free part from K_ff d_f = -(K dc)_f
         dc = cons * (target - u)
         d_inv = 1.0 / np.where(cons > 0, 1.0, fem.jacobi_diag(u).reshape(-1))
-        rhs = -(free * fem.hvp(u, dc).reshape(-1))
+        rhs = free * ((s - s_prev) * f - fem.hvp(u, dc).reshape(-1))
         df, it_pred = pcg(lambda p: K_ff(u, p), rhs, d_inv * free + cons, opts.predictor_rtol,
                           opts.max_cg)
         u_try = u + dc + free * df
-        if not np.isfinite(fem.energy(u_try, allow_inverted=True)):
+        if not np.isfinite(total_energy(u_try, allow_inverted=True)):
             u_try = u + dc          # predictor inverted an element: plain lift
         u = u_try
         cg_total = it_pred
@@ -311,7 +322,7 @@ def newton_solve(fem: FEM, mask, u_bc_final, opts: SolveOptions, u0=None):
         rho0 = np.linalg.norm(r)
         tol = max(opts.rtol * rho0, opts.atol_floor * max(1.0, rho0))
         hist = [rho0]
-        ehist = [fem.energy(u)]
+        ehist = [total_energy(u)]
         eta_prev, rn_prev = opts.eta_max, None
         nit = 0
         while np.linalg.norm(r) > tol:
@@ -342,7 +353,7 @@ def newton_solve(fem: FEM, mask, u_bc_final, opts: SolveOptions, u0=None):
             slope = r @ d
             alpha = 1.0
             for _ in range(opts.max_halvings + 1):
-                e1 = fem.energy(u + alpha * d, allow_inverted=True)
+                e1 = total_energy(u + alpha * d, allow_inverted=True)
                 # sufficient decrease up to the rounding of the energy sum (64 eps |Psi|)
                 noise = 64.0 * np.finfo(np.float64).eps * abs(e0)
                 if np.isfinite(e1) and e1 <= e0 + opts.armijo_c * alpha * slope + noise:

@@ -75,6 +75,7 @@ SIGNATURES = {
     "efem_set_material": (c_int32, [c_void_p, c_void_p, c_void_p]),
     "efem_set_model": (c_int32, [c_void_p, c_int32]),
     "efem_set_dirichlet": (c_int32, [c_void_p, c_void_p]),
+    "efem_set_load": (c_int32, [c_void_p, c_void_p]),
     "efem_set_coords": (c_int32, [c_void_p, c_void_p]),
     "efem_energy": (c_int32, [c_void_p, c_void_p, c_void_p]),
     "efem_residual": (c_int32, [c_void_p, c_void_p, c_void_p]),

@@ -670,6 +670,24 @@ int efem_set_dirichlet(efem_ctx *ctx, const uint8_t *mask)
     return EFEM_OK;
 }
 
+int efem_set_load(efem_ctx *ctx, const double *f)
+{
+    if (!ctx) return EFEM_ERR_INVALID;
+    DeviceGuard dg(ctx->device);
+    if (!f) {
+        ctx->have_load = false;
+        return EFEM_OK;
+    }
+    if (!ctx->fext) {
+        int rc = dalloc(*ctx, &ctx->fext, (size_t)(3 * ctx->n_nodes));
+        if (rc) return rc;
+    }
+    HIP_TRY(hipMemcpyAsync(ctx->fext, f, 3 * ctx->n_nodes * sizeof(double),
+                           hipMemcpyDeviceToDevice, ctx->stream));
+    ctx->have_load = true;
+    return EFEM_OK;
+}
+
 #define CHECK_ARGS(cond, name)                         \
     do {                                               \
         if (!ctx || !(cond)) {                         \

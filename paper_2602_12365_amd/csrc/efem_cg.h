@@ -69,5 +69,8 @@ hipError_t launch_bc_increment(hipStream_t s, int64_t n, const double *u, const 
                                double frac, const uint8_t *nmask, double *dc, double *u_old);
 hipError_t launch_dot64(hipStream_t s, const CgWorkspace &ws, int64_t n, const double *a,
                         const double *b, double *out);
+// y -= scale f on the DOFs the node mask leaves free (all of them for a null mask)
+hipError_t launch_sub_load(hipStream_t s, int64_t n, double *y, const double *f, double scale,
+                           const uint8_t *nmask);
 
 }  // namespace efem

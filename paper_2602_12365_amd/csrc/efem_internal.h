@@ -115,6 +115,9 @@ struct Ctx {
     double *mu = nullptr, *lam = nullptr;
     uint8_t *nmask = nullptr;
     int32_t *flags = nullptr;
+    // external nodal forces of the final load step (efem_set_load)
+    double *fext = nullptr;
+    bool have_load = false;
 
     // linearization point
     int lin_prec = -1;

@@ -383,6 +383,23 @@ hipError_t launch_bc_increment(hipStream_t s, int64_t n, const double *u, const 
     return hipGetLastError();
 }
 
+// y -= s f on the free DOFs (prescribed entries of y are left as they are)
+__global__ void k_sub_load(int64_t n, double *__restrict__ y, const double *__restrict__ f,
+                           double s, const uint8_t *__restrict__ nmask)
+{
+    GRID_STRIDE(i, n)
+    {
+        if (!dof_fixed(nmask, i)) y[i] -= s * f[i];
+    }
+}
+
+hipError_t launch_sub_load(hipStream_t s, int64_t n, double *y, const double *f, double scale,
+                           const uint8_t *nmask)
+{
+    hipLaunchKernelGGL(k_sub_load, dim3(red_grid(n)), dim3(kThreads), 0, s, n, y, f, scale, nmask);
+    return hipGetLastError();
+}
+
 hipError_t launch_dot64(hipStream_t s, const CgWorkspace &ws, int64_t n, const double *a,
                         const double *b, double *out)
 {

@@ -46,6 +46,7 @@ struct Solver {
     double *r = nullptr, *dc = nullptr, *u_old = nullptr, *u_trial = nullptr, *diag = nullptr,
            *kdc = nullptr, *dscal = nullptr;
     T *x = nullptr, *rv = nullptr, *p = nullptr, *q = nullptr, *dinv = nullptr;
+    double load_s = 0.0;   // load factor of the current step
     CgScalars *sc = nullptr;
     CgWorkspace ws;
     CgScalars *h_sc = nullptr;
@@ -107,10 +108,24 @@ struct Solver {
         return EFEM_OK;
     }
 
+    // total potential energy Psi_h(u) - s f.u at load factor s (f = 0 without a load)
     int energy(const double *u, double &e)
     {
         TRY(launch_energy(c, u, dscal));
-        return read_scalar(dscal, e);
+        if (!c.have_load) return read_scalar(dscal, e);
+        TRY(launch_dot64(c.stream, ws, n, c.fext, u, dscal + 3));
+        TRY(hipMemcpyAsync(h_scal, dscal, 4 * sizeof(double), hipMemcpyDeviceToHost, c.stream));
+        TRY(hipStreamSynchronize(c.stream));
+        e = h_scal[0] - load_s * h_scal[3];
+        return EFEM_OK;
+    }
+
+    // its gradient over the free DOFs: r = (grad Psi_h(u) - s f)_free
+    hipError_t residual(const double *u)
+    {
+        hipError_t e = launch_residual(c, u, r);
+        if (e != hipSuccess || !c.have_load) return e;
+        return launch_sub_load(c.stream, n, r, c.fext, load_s, c.m.nmask);
     }
 
     int norm(const double *v, double &out)
@@ -291,9 +306,11 @@ struct Solver {
         const double eta_min = f32 ? std::max(o.eta_min, 1e-5) : o.eta_min;
         st->converged = 1;
         for (int k = 1; k <= o.n_steps; ++k) {
-            const double frac = (double)k / o.n_steps;
+            const double frac = (double)k / o.n_steps, dload = frac - load_s;
+            load_s = frac;
             int cg_step = 0, nit = 0, fb = 0;
-            // tangent predictor: K_ff d_f = -(K dc)_f, with K dc taken on the unmasked input
+            // tangent predictor: K_ff d_f = (dload f - K dc)_f, with K dc taken on the
+            // unmasked input
             TRY(launch_bc_increment(c.stream, n, u, u_bc, frac, c.m.nmask, dc, u_old));
             TRY(launch_add_x_u(c, u, c.xlin));
             const uint8_t *mask = c.m.nmask;
@@ -301,6 +318,7 @@ struct Solver {
             hipError_t he = launch_hvp_f64(c, c.xlin, dc, kdc, nullptr, WriteMode::Overwrite);
             c.m.nmask = mask;
             TRY(he);
+            if (c.have_load) TRY(launch_sub_load(c.stream, n, kdc, c.fext, dload, nullptr));
             int it = 0;
             if ((rc = linear_solve(u, kdc, o.predictor_rtol, o.max_cg, it, fb))) return rc;
             cg_step += it;
@@ -316,7 +334,7 @@ struct Solver {
                 }
             }
             double rho;
-            TRY(launch_residual(c, u, r));
+            TRY(residual(u));
             if ((rc = norm(r, rho))) return rc;
             const double rho0 = rho;
             const double tol = std::max(o.rtol * rho0, o.atol_floor * std::max(1.0, rho0));
@@ -362,7 +380,7 @@ struct Solver {
                 e0 = e1;
                 rho_prev = rho;
                 eta_prev = eta;
-                TRY(launch_residual(c, u, r));
+                TRY(residual(u));
                 if ((rc = norm(r, rho))) return rc;
                 ++nit;
                 if (o.verbose)

@@ -119,6 +119,61 @@ def tri_mesh(n: int) -> Mesh:
     return Mesh(TRI3, n, X, tris.astype(np.int32))
 
 
+def plate_with_hole_mesh(n_r: int, n_t: int, radius: float = 0.05,
+                         half_width: float = 0.5) -> Mesh:
+    """Quarter of a square plate (side 2 half_width) with a centred circular
+    hole of ``radius``, in the z = 0 plane: the first-quadrant region between
+    the circle and the square max(x, y) = half_width, for the plate-with-hole
+    example of Sec. 6.1 (hole radius 0.05 there; the plate size is not
+    stated, a unit plate is taken).
+
+    Node (i, j), id = i + (n_r + 1) j, lies on the straight ray from the hole
+    point at angle (pi/2) j / (2 n_t) to the point at arc length fraction
+    j / (2 n_t) of the outer path (W, 0) -> (W, W) -> (0, W), W = half_width;
+    both meet the diagonal at j = n_t.  Along a ray, i = 0..n_r is spaced
+    geometrically with cell ratio (W / radius)^(1/n_r), which makes the x and
+    y axis rays exactly logarithmic in r.  Every quad is cut into two
+    counter-clockwise triangles along alternating diagonals.  Boundaries: j = 0
+    is the x axis, j = 2 n_t the y axis, i = 0 the hole, i = n_r the outer
+    edges x = W (j <= n_t) and y = W (j >= n_t)."""
+    m_t = 2 * n_t
+    g = (half_width / radius) ** (1.0 / n_r)
+    xi = (g ** np.arange(n_r + 1) - 1.0) / (g ** n_r - 1.0)
+    j = np.arange(m_t + 1)
+    th = 0.5 * np.pi * j / m_t
+    inner = radius * np.stack([np.cos(th), np.sin(th)], axis=1)
+    s = 2.0 * half_width * j / m_t
+    outer = np.where((s <= half_width)[:, None],
+                     np.stack([np.full_like(s, half_width), s], axis=1),
+                     np.stack([2.0 * half_width - s, np.full_like(s, half_width)], axis=1))
+    outer[-1, 0] = 0.0
+    outer[0, 1] = 0.0
+    P = (1.0 - xi[None, :, None]) * inner[:, None, :] + xi[None, :, None] * outer[:, None, :]
+    X = np.concatenate([P.reshape(-1, 2), np.zeros(((n_r + 1) * (m_t + 1), 1))], axis=1)
+    jj, ii = np.meshgrid(np.arange(m_t), np.arange(n_r), indexing="ij")
+    a = (ii + (n_r + 1) * jj).ravel()
+    b, c, d = a + 1, a + 1 + (n_r + 1), a + (n_r + 1)
+    even = ((ii + jj) % 2 == 0).ravel()
+    t1 = np.where(even[:, None], np.stack([a, b, c], 1), np.stack([a, b, d], 1))
+    t2 = np.where(even[:, None], np.stack([a, c, d], 1), np.stack([b, c, d], 1))
+    tris = np.stack([t1, t2], axis=1).reshape(-1, 3)
+    return Mesh(TRI3, n_t, X, tris.astype(np.int32))
+
+
+def symmetry_mask(X: np.ndarray, planar: bool) -> np.ndarray:
+    """Symmetry conditions on the coordinate planes: u_x = 0 where x = 0,
+    u_y = 0 where y = 0, and u_z = 0 where z = 0 (3D) or everywhere (plane
+    strain, ``planar``).  uint8 [3 n_nodes]; every prescribed value is 0."""
+    mask = np.zeros((X.shape[0], 3), dtype=np.uint8)
+    mask[np.abs(X[:, 0]) < 1e-12, 0] = 1
+    mask[np.abs(X[:, 1]) < 1e-12, 1] = 1
+    if planar:
+        mask[:, 2] = 1
+    else:
+        mask[np.abs(X[:, 2]) < 1e-12, 2] = 1
+    return mask.reshape(-1)
+
+
 def planar_mask(X: np.ndarray) -> np.ndarray:
     """uint8 [n_nodes, 3] holding the out-of-plane component of every node
     (plane strain on a Tri3 mesh)."""

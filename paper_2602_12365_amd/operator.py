@@ -145,6 +145,16 @@ class Operator:
         self._mask = self._nodal(mask, torch.uint8, "mask")
         L.check(self._lib.efem_set_dirichlet(self._h, _ptr(self._mask)), "efem_set_dirichlet")
 
+    def set_load(self, f):
+        """External nodal forces of the final load step (float64 [n_nodes, 3] or
+        [3*n_nodes]) for ``newton_solve``, or None to remove them."""
+        self._sync_stream()
+        if f is None:
+            L.check(self._lib.efem_set_load(self._h, None), "efem_set_load")
+            return
+        self._load = self._nodal(f, torch.float64, "load")
+        L.check(self._lib.efem_set_load(self._h, _ptr(self._load)), "efem_set_load")
+
     def info(self):
         i = L.Info()
         L.check(self._lib.efem_get_info(self._h, ctypes.byref(i)), "efem_get_info")

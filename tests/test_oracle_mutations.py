@@ -64,3 +64,38 @@ def test_pins_catch_planted_mistake(name, tmp_path):
                          + [os.path.join(ROOT, "tests", f) for f in PIN_FILES],
                          cwd=ROOT, env=env, capture_output=True, text=True, timeout=300)
     assert res.returncode != 0, f"pins did not catch mutation {name}:\n{res.stdout[-2000:]}"
+
+
+# Mistakes in the oracle's Python layer (the loaded Newton solve): planted in a
+# copy of the oracle package placed in a scratch tree with the tests and the
+# input generators, and run there against the real C oracle.
+PY_MUTATIONS = {
+    "load_residual_not_scaled_by_step": ("reshape(-1) - s * f)", "reshape(-1) - f)"),
+    "load_residual_sign": ("reshape(-1) - s * f)", "reshape(-1) + s * f)"),
+    "load_energy_not_scaled_by_step": ("- s * (f @ uu)", "- (f @ uu)"),
+    "load_energy_sign": ("- s * (f @ uu)", "+ s * (f @ uu)"),
+}
+PY_PIN_FILES = ["test_oracle_load.py"]
+
+
+@pytest.mark.parametrize("name", sorted(PY_MUTATIONS))
+def test_pins_catch_planted_mistake_in_solve(name, tmp_path):
+    import shutil
+
+    from oracle import build as _build
+    old, new = PY_MUTATIONS[name]
+    for d in ("oracle", "tests", "paper_2602_12365_amd"):
+        (tmp_path / d).mkdir()
+        for f in os.listdir(os.path.join(ROOT, d)):
+            if f.endswith(".py"):
+                shutil.copy(os.path.join(ROOT, d, f), tmp_path / d / f)
+    fem_py = tmp_path / "oracle" / "fem.py"
+    src = fem_py.read_text()
+    assert src.count(old) == 1, f"mutation anchor not found once: {old!r}"
+    fem_py.write_text(src.replace(old, new))
+    env = dict(os.environ, EFEM_ORACLE_LIB=_build.build(), OMP_NUM_THREADS="2")
+    res = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider"]
+                         + [str(tmp_path / "tests" / f) for f in PY_PIN_FILES],
+                         cwd=str(tmp_path), env=env, capture_output=True, text=True, timeout=300)
+    assert "passed" in res.stdout or "failed" in res.stdout, res.stdout[-2000:] + res.stderr[-2000:]
+    assert res.returncode != 0, f"pins did not catch mutation {name}:\n{res.stdout[-2000:]}"
