@@ -460,8 +460,8 @@ int efem_create(efem_ctx **out, int32_t elem, int64_t n_nodes, int64_t n_elems,
         }
         if (opts->threads > 0) threads = opts->threads;
     }
-    // 768 nodes x (80-byte record + 24-byte FP64 sums) = 78 KB of LDS, so two
-    // blocks share a CU's 160 KB
+    // 768 nodes x (80-byte record + 24-byte FP64 sums + 4-byte node word) =
+    // 81 KB of LDS, within a workgroup's 160 KB
     if (bn < nen || bn > 768 || be < 1 || threads < 64 || threads > 256 || threads % 64) {
         set_error("efem_create: block_nodes must be in [n_en, 768], threads a multiple of 64 in [64, 256]");
         return EFEM_ERR_INVALID;

@@ -1557,11 +1557,31 @@ k_accumulate(BlockMesh m, Op op, T *__restrict__ y,
     // doubles per item out of the registers
     ItemWord<E> nxt{};
     if (j < S && item_of(j) < r.ni) nxt = fetch_lc<E>(m, r, item_of(j));   // in flight during staging
-    for (int l = threadIdx.x; l < nn; l += nt) {
-        op.stage(m, sn[l], bnode[l] & kGidMask);
-        acc[3 * l + 0] = 0.0;
-        acc[3 * l + 1] = 0.0;
-        acc[3 * l + 2] = 0.0;
+    // Staging: a thread issues all its global loads (block-node words, then
+    // node data) before its LDS stores, so the phase costs two memory
+    // latencies rather than two per staged node.  The block-node words stay in
+    // LDS for write_out.
+    uint32_t *sbn = reinterpret_cast<uint32_t *>(acc + 3 * nn);
+    constexpr int kU = 3;
+    for (int l0 = threadIdx.x; l0 < nn; l0 += kU * nt) {
+        uint32_t ent[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) ent[u] = l0 + u * nt < nn ? bnode[l0 + u * nt] : 0u;
+        Node tmp[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u)
+            if (l0 + u * nt < nn) op.stage(m, tmp[u], ent[u] & kGidMask);
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const int l = l0 + u * nt;
+            if (l < nn) {
+                sn[l] = tmp[u];
+                sbn[l] = ent[u];
+                acc[3 * l + 0] = 0.0;
+                acc[3 * l + 1] = 0.0;
+                acc[3 * l + 2] = 0.0;
+            }
+        }
     }
     __syncthreads();
     bool bad = false;
@@ -1583,7 +1603,7 @@ k_accumulate(BlockMesh m, Op op, T *__restrict__ y,
     }
     if (bad) flag_inverted(m.flags);
     __syncthreads();
-    write_out<ACC>(m, bnode, nn, acc, y, mode, use_mask != 0, fixed_val,
+    write_out<ACC>(m, sbn, nn, acc, y, mode, use_mask != 0, fixed_val,
                    reinterpret_cast<T *>(m.halo), m.hslot ? m.hslot + n0 : nullptr);
 }
 
@@ -1897,7 +1917,8 @@ __global__ void __launch_bounds__(256) k_vjp_material(BlockMesh m, const double 
 template <class Op>
 static size_t lds_bytes(const Ctx &c, size_t acc_elem)
 {
-    return (sizeof(typename Op::Node) + 3 * acc_elem) * (size_t)c.max_block_nodes;
+    // node records, FP64 accumulators and the block-node words
+    return (sizeof(typename Op::Node) + 3 * acc_elem + sizeof(uint32_t)) * (size_t)c.max_block_nodes;
 }
 
 template <class E, class Op, class T>

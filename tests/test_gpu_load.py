@@ -108,6 +108,9 @@ def test_kirsch_plate_converges_on_the_gpu():
         k = np.argmax(sxx)
         kxx = LD.kirsch_stress(cen[k, 0], cen[k, 1], R, SIGMA)[0]
         peaks.append((sxx[k], kxx, cen[k]))
+        print(f"[load] kirsch n_t={n_t}: {m.n_nodes} nodes, {st['cg_iters']} CG, {st['seconds']:.3f} s, "
+              f"stress L2 error {err:.3e}, peak sxx/sigma {sxx[k] / SIGMA:.4f} "
+              f"(Kirsch at the centroid {kxx / SIGMA:.4f})", flush=True)
     assert errs[0] / errs[1] > 1.7 and errs[1] / errs[2] > 1.7, errs
     assert errs[2] < 1e-3, errs
     s_fe, s_k, c = peaks[-1]
