@@ -961,6 +961,16 @@ struct XUStage {
         load3(u, g, n.u);
     }
 };
+// stages X, u and w (residual VJP)
+struct XUWStage {
+    const double *X, *u, *w;
+    __device__ __forceinline__ void stage(const BlockMesh &, NodeXUW &n, int64_t g) const
+    {
+        load3(X, g, n.X);
+        load3(u, g, n.u);
+        load3(w, g, n.w);
+    }
+};
 
 struct ResidualOp : XUStage {
     using Node = NodeXU;
@@ -1510,6 +1520,35 @@ __device__ __forceinline__ void materials(const IData<E> &d, T mu[E::NSUB], T la
     }
 }
 
+// Stage a block's node records into LDS.  A thread issues all its global
+// loads (block-node words, then node data) before its LDS stores, so the phase
+// costs two memory latencies however many nodes the thread stages; extra(l,
+// word) runs beside each record's store.
+template <class Node, class St, class Extra>
+__device__ __forceinline__ void stage_nodes(const BlockMesh &m, const St &st, Node *sn,
+                                            const uint32_t *bnode, int nn, Extra extra)
+{
+    constexpr int kU = 3;
+    const int nt = blockDim.x;
+    for (int l0 = threadIdx.x; l0 < nn; l0 += kU * nt) {
+        uint32_t ent[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) ent[u] = l0 + u * nt < nn ? bnode[l0 + u * nt] : 0u;
+        Node tmp[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u)
+            if (l0 + u * nt < nn) st.stage(m, tmp[u], ent[u] & kGidMask);
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const int l = l0 + u * nt;
+            if (l < nn) {
+                sn[l] = tmp[u];
+                extra(l, ent[u]);
+            }
+        }
+    }
+}
+
 // ---------------------------------------------------------- block pass kernel
 
 // Waves per SIMD the register allocator must leave room for.  The FP64 Tet4
@@ -1557,32 +1596,14 @@ k_accumulate(BlockMesh m, Op op, T *__restrict__ y,
     // doubles per item out of the registers
     ItemWord<E> nxt{};
     if (j < S && item_of(j) < r.ni) nxt = fetch_lc<E>(m, r, item_of(j));   // in flight during staging
-    // Staging: a thread issues all its global loads (block-node words, then
-    // node data) before its LDS stores, so the phase costs two memory
-    // latencies rather than two per staged node.  The block-node words stay in
-    // LDS for write_out.
+    // the block-node words stay in LDS for write_out
     uint32_t *sbn = reinterpret_cast<uint32_t *>(acc + 3 * nn);
-    constexpr int kU = 3;
-    for (int l0 = threadIdx.x; l0 < nn; l0 += kU * nt) {
-        uint32_t ent[kU];
-#pragma unroll
-        for (int u = 0; u < kU; ++u) ent[u] = l0 + u * nt < nn ? bnode[l0 + u * nt] : 0u;
-        Node tmp[kU];
-#pragma unroll
-        for (int u = 0; u < kU; ++u)
-            if (l0 + u * nt < nn) op.stage(m, tmp[u], ent[u] & kGidMask);
-#pragma unroll
-        for (int u = 0; u < kU; ++u) {
-            const int l = l0 + u * nt;
-            if (l < nn) {
-                sn[l] = tmp[u];
-                sbn[l] = ent[u];
-                acc[3 * l + 0] = 0.0;
-                acc[3 * l + 1] = 0.0;
-                acc[3 * l + 2] = 0.0;
-            }
-        }
-    }
+    stage_nodes(m, op, sn, bnode, nn, [&](int l, uint32_t ent) {
+        sbn[l] = ent;
+        acc[3 * l + 0] = 0.0;
+        acc[3 * l + 1] = 0.0;
+        acc[3 * l + 2] = 0.0;
+    });
     __syncthreads();
     bool bad = false;
     for (; j < S; j += W) {
@@ -1673,7 +1694,7 @@ __global__ void __launch_bounds__(256) k_energy(BlockMesh m, const double *__res
     int k = threadIdx.x;
     IData<E> nxt{};
     if (k < r.ni) nxt = fetch_item<E>(m, r, k);
-    for (int l = threadIdx.x; l < nn; l += nt) st.stage(m, sn[l], m.bnode[n0 + l] & kGidMask);
+    stage_nodes(m, st, sn, m.bnode + n0, nn, [](int, uint32_t) {});
     __syncthreads();
     double acc = 0.0;
     bool bad = false;
@@ -1764,7 +1785,7 @@ __global__ void __launch_bounds__(256) k_grad_material(BlockMesh m, const double
     const ItemRange r = item_range(m, b);
     NodeXU *sn = reinterpret_cast<NodeXU *>(smem);
     XUStage st{X, u};
-    for (int l = threadIdx.x; l < nn; l += blockDim.x) st.stage(m, sn[l], m.bnode[n0 + l] & kGidMask);
+    stage_nodes(m, st, sn, m.bnode + n0, nn, [](int, uint32_t) {});
     __syncthreads();
     bool bad = false;
     for (int k = threadIdx.x; k < r.ni; k += blockDim.x) {
@@ -1825,12 +1846,8 @@ __global__ void __launch_bounds__(256) k_vjp_material(BlockMesh m, const double 
     const int n0 = m.nstart[b], nn = m.nstart[b + 1] - n0;
     const ItemRange r = item_range(m, b);
     NodeXUW *sn = reinterpret_cast<NodeXUW *>(smem);
-    for (int l = threadIdx.x; l < nn; l += blockDim.x) {
-        const int64_t g = m.bnode[n0 + l] & kGidMask;
-        load3(X, g, sn[l].X);
-        load3(u, g, sn[l].u);
-        load3(wv, g, sn[l].w);
-    }
+    XUWStage st{X, u, wv};
+    stage_nodes(m, st, sn, m.bnode + n0, nn, [](int, uint32_t) {});
     __syncthreads();
     bool bad = false;
     for (int k = threadIdx.x; k < r.ni; k += blockDim.x) {
