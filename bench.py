@@ -104,7 +104,9 @@ def solve_section(args, dev):
     hexes, 2x2x2 Gauss, mu ~ lognormal(0, 0.5), lam = 1.5 mu) on the 128^3
     mesh (mu seed 3) and on the unseen 96^3 test mesh of the preconditioner
     (mu seed 2000): plain FP64 Newton-CG (Jacobi), mixed FP32-HVP (Jacobi), and
-    mixed FP32-HVP with the learned preconditioner trained on 32^3 samples.
+    mixed FP32-HVP with the learned preconditioner trained on 32^3 samples,
+    for the first 8 flexible-CG iterations of each Krylov solve (then Jacobi
+    PCG from that iterate) and, beside it, for whole solves.
     Wall time from the first load step to the last step's convergence."""
     import torch
     from paper_2602_12365_amd import Operator, inputs as I, precond as PC
@@ -146,7 +148,8 @@ def solve_section(args, dev):
 
 def compression_solves(dev, n, seed, theta):
     """Compression case on n^3 Q1 hexes (mu seed `seed`): plain FP64 Jacobi,
-    mixed FP32 Jacobi and mixed FP32 with the learned preconditioner."""
+    mixed FP32 Jacobi and mixed FP32 with the learned preconditioner (8
+    flexible-CG iterations per Krylov solve, and whole solves)."""
     import torch
     from paper_2602_12365_amd import Operator, inputs as I, precond as PC
     mesh, mu, lam, mask, ubc = PC.compression_case(I.HEX8, n, seed)
@@ -161,7 +164,8 @@ def compression_solves(dev, n, seed, theta):
     u_ref = None
     for name, kw in [("plain_f64_jacobi", dict(hvp_prec="f64", precond=0)),
                      ("mixed_f32_jacobi", dict(hvp_prec="f32", precond=0)),
-                     ("mixed_f32_learned", dict(hvp_prec="f32", precond=1))]:
+                     ("mixed_f32_learned", dict(hvp_prec="f32", precond=1, learned_iters=8)),
+                     ("mixed_f32_learned_whole_solve", dict(hvp_prec="f32", precond=1, learned_iters=0))]:
         u = torch.zeros((mesh.n_nodes, 3), dtype=torch.float64, device=dev)
         log(f"solve {name}")
         torch.cuda.synchronize()
@@ -175,6 +179,9 @@ def compression_solves(dev, n, seed, theta):
                  "fallbacks": st["precond_fallbacks"], "final_residual_fp64": st["final_residual"],
                  "newton_per_step": st["newton_per_step"], "cg_per_step": st["cg_per_step"],
                  "energy": st["final_energy"]}
+        if kw["precond"] == 1:
+            # flexible-CG iterations with the network before Jacobi PCG takes over (0: all)
+            entry["learned_iters"] = kw["learned_iters"]
         if u_ref is None:
             u_ref = u.clone()
         else:

@@ -267,6 +267,11 @@ typedef struct {
     double armijo_c;          /* sufficient-decrease constant of the line search */
     int32_t max_halvings;
     int32_t verbose;          /* 0 silent, 1 one line per Newton iteration on stderr */
+    int32_t learned_iters;    /* precond = 1: flexible-CG iterations with the learned
+                                 preconditioner, after which a Krylov solve continues
+                                 with Jacobi PCG from the flexible-CG iterate (default
+                                 8; 0: no limit; rounded up to a multiple of
+                                 check_every) */
 } efem_solve_opts;
 
 typedef struct {
@@ -283,7 +288,8 @@ typedef struct {
     int32_t cg_per_step[64];
 } efem_solve_stats;
 
-/* Fill opts with the defaults (n_steps 5, FP64, Jacobi, rtol 1e-8, ...). */
+/* Fill opts with the defaults (n_steps 5, FP64, Jacobi, rtol 1e-8,
+ * learned_iters 8, ...). */
 void efem_solve_opts_default(efem_solve_opts *opts);
 
 /* Matrix-free Newton-Krylov solve of the reduced functional (Sec. 6.1,
@@ -391,7 +397,8 @@ int efem_cg_snapshots(efem_ctx *ctx, const double *u, const double *b, double si
 /* Solve K(u)_ff x = b (b, x DEVICE float64 [3*n_nodes]; prescribed entries of b
  * ignored and of x set to 0) by preconditioned CG from x = 0 to
  * ||b - K x|| <= rtol ||b||, with the tangent action in hvp_prec and precond 0
- * (Jacobi) or 1 (learned, flexible CG, Jacobi fallback; needs EFEM_F32).
+ * (Jacobi) or 1 (learned, flexible CG for the whole solve, Jacobi fallback;
+ * needs EFEM_F32).
  * Requires a Dirichlet mask.  Synchronous; *iters receives the CG iterations,
  * *fallback 1 if the learned solve fell back to Jacobi. */
 int efem_linear_solve(efem_ctx *ctx, const double *u, const double *b, double *x, double rtol,

@@ -55,7 +55,7 @@ class SolveOpts(ctypes.Structure):
                 ("rtol", c_double), ("atol_floor", c_double), ("eta_max", c_double),
                 ("eta_min", c_double), ("ew_gamma", c_double), ("ew_alpha", c_double),
                 ("eta_fixed", c_double), ("predictor_rtol", c_double), ("armijo_c", c_double),
-                ("max_halvings", c_int32), ("verbose", c_int32)]
+                ("max_halvings", c_int32), ("verbose", c_int32), ("learned_iters", c_int32)]
 
 
 class SolveStats(ctypes.Structure):

@@ -177,7 +177,8 @@ struct Solver {
 
     // Flexible CG with the learned preconditioner for K_ff x = sign * b from
     // x = 0.  On breakdown, non-positive r.z or stagnation it falls back to
-    // Jacobi PCG, which continues from the flexible-CG iterate when that is
+    // Jacobi PCG, and after learned_iters iterations (if set) it hands over to
+    // it.  Jacobi PCG continues from the flexible-CG iterate when that is
     // finite (K d = r for its residual r, to the original tolerance, then
     // x += d), else starts again from x = 0.
     int fcg(const double *b, double sign, double eta, int max_it, int &iters, int &fallbacks)
@@ -201,10 +202,12 @@ struct Solver {
             TRY(hipMemcpyAsync(h_sc, sc, sizeof(CgScalars), hipMemcpyDeviceToHost, c.stream));
             TRY(hipStreamSynchronize(c.stream));
             if (h_sc->done || h_sc->iter >= max_it) break;
+            if (o.learned_iters > 0 && h_sc->iter >= o.learned_iters) break;
         }
         iters = h_sc->iter;
-        if (h_sc->fallback) {
-            fallbacks += 1;
+        const bool capped = !h_sc->done && iters < max_it;
+        if (h_sc->fallback || capped) {
+            if (h_sc->fallback) fallbacks += 1;
             int it2 = 0, rc;
             // the flexible-CG residual as the new right-hand side (diag is
             // free here: the features are built and dinv is set)
@@ -436,6 +439,7 @@ void efem_solve_opts_default(efem_solve_opts *o)
     o->armijo_c = 1e-4;
     o->max_halvings = 30;
     o->verbose = 0;
+    o->learned_iters = 8;
 }
 
 int efem_newton_solve(efem_ctx *ctx, double *u_inout, const double *u_bc, const efem_solve_opts *opts,
@@ -509,6 +513,7 @@ extern "C" int efem_linear_solve(efem_ctx *ctx, const double *u, const double *b
     efem_solve_opts_default(&o);
     o.precond = precond;
     o.hvp_prec = hvp_prec;
+    o.learned_iters = 0;   // the learned preconditioner alone, no hand-over
     int dev_prev = -1;
     (void)hipGetDevice(&dev_prev);
     if (dev_prev != ctx->device) (void)hipSetDevice(ctx->device);

@@ -171,14 +171,20 @@ def test_broken_network_falls_back_to_jacobi():
     assert not fb2                             # the zero network is Jacobi and works
 
 
-def test_newton_with_learned_preconditioner():
+@pytest.mark.parametrize("learned_iters", [8, 0])
+def test_newton_with_learned_preconditioner(learned_iters):
+    """The learned preconditioner for the first learned_iters flexible-CG
+    iterations of each Krylov solve, then Jacobi PCG from that iterate (0: for
+    whole solves): the solution against the oracle's Newton solve."""
     from paper_2602_12365_amd import precond as PC
+    print(f"\n[precond] newton learned_iters={learned_iters}", flush=True)
     X, aux, op = PC.generate_rows(n=6, seeds=range(1000, 1002), n_steps=3)
     theta, _ = PC.train(op, X, aux, epochs=60)
     m, op2, mu, mask, ubc = make_op(I.HEX8, 6)
     op2.set_mlp(theta)
     u = torch.zeros((m.n_nodes, 3), dtype=torch.float64, device="cuda")
-    rc, st = op2.newton_solve(u, dev(ubc), n_steps=10, hvp_prec="f32", precond=1)
+    rc, st = op2.newton_solve(u, dev(ubc), n_steps=10, hvp_prec="f32", precond=1,
+                              learned_iters=learned_iters)
     assert rc == 0, st
     orc = F.FEM(I.HEX8, m.X, m.conn, mu, 1.5 * mu)
     u_ref, st_ref = F.newton_solve(orc, mask, ubc, F.SolveOptions(n_steps=10))
