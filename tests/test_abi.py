@@ -57,3 +57,25 @@ def test_oracle_does_not_import_product():
                 text = open(os.path.join(dirpath, f)).read()
                 assert not re.search(r"(import|from)\s+paper_2602_12365_amd", text), f
                 assert "libefem" not in text, f
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libefem.so not built")
+def test_solve_options_layout_matches_the_header():
+    """efem_solve_opts_default (host only) fills the ctypes mirror of
+    efem_solve_opts: every field lands where the binding expects it."""
+    from paper_2602_12365_amd import _lib
+    lib = _lib.load()
+    o = _lib.SolveOpts()
+    lib.efem_solve_opts_default(ctypes.byref(o))
+    assert (o.n_steps, o.hvp_prec, o.precond, o.max_newton, o.max_cg, o.check_every) == (5, 0, 0, 50, 20000, 8)
+    assert (o.rtol, o.atol_floor, o.eta_max, o.eta_min) == (1e-8, 1e-14, 0.5, 1e-10)
+    assert (o.ew_gamma, o.ew_alpha, o.eta_fixed, o.predictor_rtol, o.armijo_c) == (0.9, 2.0, 0.0, 1e-4, 1e-4)
+    assert (o.max_halvings, o.verbose, o.learned_iters) == (30, 0, 8)
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libefem.so not built")
+def test_null_context_is_rejected_without_a_device():
+    from paper_2602_12365_amd import _lib
+    lib = _lib.load()
+    assert lib.efem_set_load(None, None) == _lib.EFEM_ERR_INVALID
+    assert lib.efem_set_dirichlet(None, None) == _lib.EFEM_ERR_INVALID
