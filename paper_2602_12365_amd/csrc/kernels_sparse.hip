@@ -22,10 +22,15 @@ __global__ void __launch_bounds__(256) k_extract(int64_t count, const int64_t *_
     if (t < count) values[ent[t]] = y[ent_row[t]];
 }
 
-// y = K x, 16 lanes per row (4 rows per wave): the lanes stride over the
-// row's entries (coalesced), then a butterfly sum over the 16 lanes.
-constexpr int kLanesPerRow = 16;
-
+// y = K x.  The pattern is built per node: a row's nonzeros come in triples,
+// the three components of one neighbour node in consecutive columns.  So a
+// lane takes whole triples (one column index, three contiguous values and
+// three contiguous x entries), kLanesPerRow lanes stride over the row's
+// triples (coalesced), and a butterfly sums over them.
+#ifndef EFEM_SPMV_LANES
+#define EFEM_SPMV_LANES 16
+#endif
+constexpr int kLanesPerRow = EFEM_SPMV_LANES;
 __global__ void __launch_bounds__(256) k_spmv(int64_t n_rows, const int64_t *__restrict__ row_ptr,
                                               const int32_t *__restrict__ col,
                                               const double *__restrict__ val,
@@ -37,7 +42,10 @@ __global__ void __launch_bounds__(256) k_spmv(int64_t n_rows, const int64_t *__r
     double s = 0.0;
     if (row < n_rows) {
         const int64_t b = row_ptr[row], e = row_ptr[row + 1];
-        for (int64_t k = b + sub; k < e; k += kLanesPerRow) s += val[k] * x[col[k]];
+        for (int64_t k = b + 3 * sub; k < e; k += 3 * kLanesPerRow) {
+            const int64_t c = col[k];
+            s += val[k] * x[c] + val[k + 1] * x[c + 1] + val[k + 2] * x[c + 2];
+        }
     }
 #pragma unroll
     for (int off = kLanesPerRow / 2; off > 0; off >>= 1) s += __shfl_xor(s, off, kLanesPerRow);
