@@ -79,3 +79,12 @@ def test_null_context_is_rejected_without_a_device():
     lib = _lib.load()
     assert lib.efem_set_load(None, None) == _lib.EFEM_ERR_INVALID
     assert lib.efem_set_dirichlet(None, None) == _lib.EFEM_ERR_INVALID
+
+
+def test_missing_library_fails_loudly(tmp_path, monkeypatch):
+    """No CPU fallback: without libefem.so the binding raises ImportError."""
+    from paper_2602_12365_amd import _lib
+    monkeypatch.setattr(_lib, "LIB_PATH", str(tmp_path / "libefem.so"))
+    monkeypatch.setattr(_lib, "_lib", None)
+    with pytest.raises(ImportError):
+        _lib.load()
