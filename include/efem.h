@@ -140,9 +140,9 @@ int efem_set_material(efem_ctx *ctx, const double *mu, const double *lam);
  * given to efem_linearize is not read by efem_hvp (linearize is still required
  * first), and there is no det F condition.
  *
- * EFEM_MODEL_TRANSPORT is the non-variational case of Sec. 5.5: a virtual-work
+ * EFEM_MODEL_TRANSPORT is the non-variational case of Sec. 3.1 (Eqs. 4-6): a virtual-work
  * functional W(c, v) instead of an energy, here the advection-diffusion
- * example's weak form (steady, or one implicit time step with k = 1/dt) for
+ * example's weak form (Sec. 6.5) (steady, or one implicit time step with k = 1/dt) for
  * three species carried in the three nodal components:
  *   r_{a,s}(c) = sum_e sum_q w det J [ D grad c_s . grad N_a
  *                                      + (b(x_q) . grad c_s + k c_s) N_a ]
@@ -405,10 +405,21 @@ int efem_linear_solve(efem_ctx *ctx, const double *u, const double *b, double *x
                       int32_t hvp_prec, int32_t precond, int32_t max_iter, int32_t *iters,
                       int32_t *fallback);
 
+/* Derivative through the equilibrium solve (the derivative of a quantity of
+ * interest through a Newton solve, Sec. 6.2) is a caller-side composition of
+ * the calls above, with no entry point of its own.  For the total reaction
+ * J = sum_{i in T} r_i(u*) on a set T of prescribed DOFs at an equilibrium
+ * u* of the masked problem:
+ *   1. efem_hvp without the mask on 1_T (the indicator of T): k = K 1_T;
+ *   2. efem_linear_solve with the mask on b = k: lambda (lambda_T = 0);
+ *   3. efem_residual_vjp_material with w = 1_T - lambda:
+ *      dJ/dmu_e = w . dr/dmu_e, dJ/dlam_e = w . dr/dlam_e.
+ * The caller forms 1_T and 1_T - lambda and sums the selected entries of r. */
+
 /* Solve K(u)_ff x = b by restarted GMRES(restart) with right Jacobi
  * preconditioning, from x = 0, to ||b - K x|| <= rtol ||b|| on the free DOFs
  * (all DOFs without a Dirichlet mask).  The Krylov solver of the
- * non-symmetric transport model (Sec. 5.5), usable with every model.
+ * non-symmetric transport model (Sec. 3.1), usable with every model.
  * u, b, x: DEVICE float64 [3*n_nodes] (x distinct from u and b; prescribed
  * entries of b ignored, of x set to 0).  hvp_prec: EFEM_F64 or EFEM_F32 for
  * the tangent actions (the basis is float64 either way); restart in

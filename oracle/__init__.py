@@ -13,7 +13,7 @@ plain numpy arrays.
 * ``oracle.mlp``    forward and backward of the per-node MLP in FP64 numpy.
 * ``oracle.precond`` node features of the learned preconditioner.
 * ``oracle.transport`` the non-variational transport operator (virtual work,
-                    Sec. 5.5): residual, element matrices, direct reduced solve.
+                    Sec. 3.1, Eqs. 4-6; example of Sec. 6.5): residual, element matrices, direct reduced solve.
 
 Every function cites the passage of the paper it follows.  Functions with no
 independent pin say "parity unpinned" in their docstring.

@@ -626,7 +626,7 @@ int orc_grad_coords(int type, int model, int64_t nn, int64_t ne, const double *X
 
 /* ------------------------------------------- non-variational transport */
 
-/* The virtual-work form of Sec. 5.5, for the advection-diffusion example's
+/* The virtual-work form of Sec. 3.1 (Eqs. 4-6), for the advection-diffusion example's
  * weak form (steady, or one implicit time step with k = 1/dt), applied to
  * three species carried in the three nodal components s:
  *   W(c, v) = sum_s int [ D grad c_s . grad v_s + (b . grad c_s) v_s + k c_s v_s ]

@@ -1,4 +1,5 @@
-"""FP64 oracle of the non-variational transport problem (virtual work, Sec. 5.5).
+"""FP64 oracle of the non-variational transport problem (virtual work, Sec. 3.1,
+Eqs. 4-6; the example of Sec. 6.5).
 
 TEST INFRASTRUCTURE ONLY (see ``oracle/__init__.py``).
 

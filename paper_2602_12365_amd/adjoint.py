@@ -15,27 +15,22 @@ constraint, K_FF du_F = -(dr_F/dm) dm with du_T = 0, so
 K 1_T is one tangent action without the Dirichlet mask, lambda one masked
 Krylov solve (efem_linear_solve), and the product with dr/dm one residual
 vector-Jacobian product (efem_residual_vjp_material, which ignores the mask).
-Torch only allocates and combines the two nodal vectors.
+This is a caller-side composition of three library calls: torch allocates the
+nodal vectors, forms 1_T and the difference 1_T - lambda, and sums the
+selected reaction entries; every element loop and Krylov iteration runs in
+the library.
 """
 from __future__ import annotations
-
-import contextlib
 
 import torch
 
 from .operator import Operator
 
 
-@contextlib.contextmanager
 def unmasked(op: Operator):
-    """Temporarily remove the operator's Dirichlet mask."""
-    mask = getattr(op, "_mask", None)
-    op.set_dirichlet(None)
-    try:
-        yield op
-    finally:
-        if mask is not None:
-            op.set_dirichlet(mask)
+    """Temporarily remove the operator's Dirichlet mask (the mask in force on
+    entry, if any, is restored on exit)."""
+    return op.unmasked()
 
 
 def reaction(op: Operator, u: torch.Tensor, sel: torch.Tensor) -> float:

@@ -1,5 +1,5 @@
 // Restarted GMRES with right Jacobi preconditioning, the Krylov solver for a
-// non-symmetric tangent (the non-variational transport model of Sec. 5.5,
+// non-symmetric tangent (the non-variational transport model: the virtual-work form of Sec. 3.1,
 // where CG does not apply), usable with every model.  Solves
 //     K(u)_ff x_f = b_f,   x = 0 on prescribed DOFs,
 // from x = 0.  The Arnoldi basis is float64 on the device; orthogonalisation

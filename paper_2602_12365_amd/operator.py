@@ -8,6 +8,7 @@ and passes raw pointers.
 """
 from __future__ import annotations
 
+import contextlib
 import ctypes
 
 import numpy as np
@@ -141,9 +142,29 @@ class Operator:
         self._sync_stream()
         if mask is None:
             L.check(self._lib.efem_set_dirichlet(self._h, None), "efem_set_dirichlet")
+            self._mask = None
             return
         self._mask = self._nodal(mask, torch.uint8, "mask")
         L.check(self._lib.efem_set_dirichlet(self._h, _ptr(self._mask)), "efem_set_dirichlet")
+
+    @property
+    def mask(self):
+        """The Dirichlet mask in force (uint8 [3*n_nodes]), or None."""
+        return getattr(self, "_mask", None)
+
+    @contextlib.contextmanager
+    def unmasked(self):
+        """Temporarily remove the Dirichlet mask; the mask in force on entry
+        (if any) is put back on exit."""
+        mask = self.mask
+        if mask is None:
+            yield self
+            return
+        self.set_dirichlet(None)
+        try:
+            yield self
+        finally:
+            self.set_dirichlet(mask)
 
     def set_load(self, f):
         """External nodal forces of the final load step (float64 [n_nodes, 3] or
@@ -421,58 +442,84 @@ class Operator:
 
 class EnergyFn(torch.autograd.Function):
     """Psi(u; mu, lam, X) with the hand-written adjoints as its backward:
-    dPsi/du = r (residual kernel), dPsi/dmu, dPsi/dlam (material kernel),
-    dPsi/dX at fixed nodal u (coordinate kernel).  ``X`` must hold the
-    coordinates the operator was built with; it is an input only so that its
-    gradient can be requested."""
+    dPsi/du = r (residual kernel, without the Dirichlet mask: Psi depends on
+    every DOF), dPsi/dmu, dPsi/dlam (material kernel), dPsi/dX at fixed nodal u
+    (coordinate kernel).  When ``X`` is not the operator's current coordinate
+    tensor, the operator is moved to ``X`` (set_coords) first."""
 
     @staticmethod
     def forward(ctx, u, mu, lam, X, op: Operator):
+        _use_coords(op, X)
         op.set_material(mu.contiguous(), lam.contiguous())
         ctx.op = op
-        ctx.save_for_backward(u, mu, lam)
+        ctx.save_for_backward(u, mu, lam, X)
         return op.energy(u.contiguous()).clone()
 
     @staticmethod
     def backward(ctx, g):
-        u, mu, lam = ctx.saved_tensors
+        u, mu, lam, X = ctx.saved_tensors
         op = ctx.op
+        _use_coords(op, X)
         op.set_material(mu.contiguous(), lam.contiguous())
         uc = u.contiguous()
         du = dmu = dlam = dX = None
         if ctx.needs_input_grad[0]:
-            du = (g * op.residual(uc)).reshape(u.shape)
+            with op.unmasked():
+                du = (g * op.residual(uc)).reshape(u.shape)
         if ctx.needs_input_grad[1] or ctx.needs_input_grad[2]:
             gm, gl = op.grad_material(uc)
             dmu, dlam = g * gm, g * gl
         if ctx.needs_input_grad[3]:
-            dX = g * op.grad_coords(uc)
+            dX = (g * op.grad_coords(uc)).reshape(X.shape)
         return du, dmu, dlam, dX, None
+
+
+def _use_coords(op: Operator, X):
+    """Point the operator at the coordinates X (float64 [n_nodes, 3] device
+    tensor) unless it already uses them."""
+    if X is op.X:
+        return
+    Xc = X.detach().reshape(op.n_nodes, 3).contiguous()
+    if not torch.equal(Xc, op.X):
+        op.set_coords(Xc)
 
 
 class ResidualFn(torch.autograd.Function):
     """r(u; mu, lam) with backward(w) = (K(u) w, w.dr/dmu, w.dr/dlam): the
-    forward-over-adjoint tangent kernel and the residual's material VJP."""
+    forward-over-adjoint tangent kernel and the residual's material VJP.
+
+    With a Dirichlet mask the forward is the reduced residual P r(u) (rows of
+    prescribed DOFs zero, Sec. 6.1's condensation), so its exact VJP is
+    K(u) P w and (P w).dr/dm: the cotangent's prescribed components are
+    dropped, and the tangent action runs without the mask so that the rows of
+    prescribed DOFs keep their coupling to the free ones."""
 
     @staticmethod
     def forward(ctx, u, mu, lam, op: Operator):
         op.set_material(mu.contiguous(), lam.contiguous())
         ctx.op = op
-        ctx.save_for_backward(u, mu, lam)
+        mask = op.mask
+        ctx.save_for_backward(u, mu, lam, mask if mask is not None else torch.empty(0))
+        ctx.masked = mask is not None
         return op.residual(u.contiguous()).reshape(u.shape)
 
     @staticmethod
     def backward(ctx, w):
-        u, mu, lam = ctx.saved_tensors
+        u, mu, lam, mask = ctx.saved_tensors
         op = ctx.op
         op.set_material(mu.contiguous(), lam.contiguous())
-        uc, wc = u.contiguous(), w.contiguous()
+        uc = u.contiguous()
+        wc = w.reshape(-1, 3).contiguous()
+        if ctx.masked:
+            # P w: the reduced residual does not depend on its prescribed rows
+            wc = wc.masked_fill(mask.reshape(-1, 3).bool(), 0.0)
         du = dmu = dlam = None
-        if ctx.needs_input_grad[0]:
-            op.linearize(uc, "f64")
-            du = op.hvp(wc.reshape(-1, 3)).reshape(u.shape)
-        if ctx.needs_input_grad[1] or ctx.needs_input_grad[2]:
-            dmu, dlam = op.residual_vjp_material(uc, wc.reshape(-1, 3))
+        with op.unmasked():
+            if ctx.needs_input_grad[0]:
+                op.linearize(uc, "f64")
+                du = op.hvp(wc).reshape(u.shape)
+            if ctx.needs_input_grad[1] or ctx.needs_input_grad[2]:
+                dmu, dlam = op.residual_vjp_material(uc, wc)
         return du, dmu, dlam, None
 
 

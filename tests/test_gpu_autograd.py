@@ -79,6 +79,93 @@ def test_gradcheck_material_small():
                                     eps=1e-6, atol=1e-9, rtol=1e-6)
 
 
+def test_gradcheck_with_dirichlet_mask():
+    """gradcheck of EnergyFn and ResidualFn with a Dirichlet mask in force: the
+    energy depends on every DOF (its u-gradient is the full residual), the
+    masked residual's VJP is K P w and (P w).dr/dm."""
+    from paper_2602_12365_amd import Operator, EnergyFn, ResidualFn
+    m = I.tet_mesh(2)
+    op = Operator(I.TET4, m.X, m.conn)
+    mask, _ = I.clamp_top_bottom(m.X, 0.05)
+    op.set_dirichlet(dev(mask, torch.uint8))
+    u = dev(I.gaussian_field(m.n_nodes, 0.02, 0)).requires_grad_()
+    mu = dev(I.lognormal_field(m.n_elems, 0.3, 4)).requires_grad_()
+    lam = dev(1.5 * np.ones(m.n_elems)).requires_grad_()
+    X = op.X.clone().requires_grad_()
+    assert torch.autograd.gradcheck(lambda a, b, c: EnergyFn.apply(a, b, c, X, op), (u, mu, lam),
+                                    eps=1e-6, atol=1e-9, rtol=1e-6)
+    assert torch.autograd.gradcheck(lambda a, b, c: ResidualFn.apply(a, b, c, op), (u, mu, lam),
+                                    eps=1e-6, atol=1e-9, rtol=1e-6)
+    assert op.mask is not None   # the backward passes put the mask back
+
+
+def test_residual_fn_masked_backward_matches_oracle():
+    """With a mask, r.backward(w) gives K(u) P w and (P w).dr/dm (P zeroes the
+    prescribed components), against the oracle's unmasked tangent action and
+    material VJP on P w."""
+    from paper_2602_12365_amd import Operator, residual
+    m = I.hex_mesh(3)
+    mu_h = I.lognormal_field(m.n_elems, 0.3, 4)
+    lam_h = 1.5 * mu_h
+    u_h = I.gaussian_field(m.n_nodes, 0.015, 0)
+    w_h = I.unit_direction(m.n_nodes, 9)
+    mask, _ = I.clamp_top_bottom(m.X, 0.05)
+    op = Operator(I.HEX8, m.X, m.conn)
+    op.set_dirichlet(dev(mask, torch.uint8))
+    u = dev(u_h).requires_grad_()
+    mu = dev(mu_h).requires_grad_()
+    lam = dev(lam_h).requires_grad_()
+    r = residual(op, u, mu, lam)
+    r.backward(dev(w_h))
+    pw = np.where(mask.reshape(-1, 3) != 0, 0.0, w_h.reshape(-1, 3))
+    orc = F.FEM(I.HEX8, m.X, m.conn, mu_h, lam_h)
+    r_ref = np.where(mask.reshape(-1, 3) != 0, 0.0, orc.residual(u_h).reshape(-1, 3))
+    vm, vl = orc.residual_vjp_material(u_h, pw)
+    assert rel(r.detach().cpu().numpy().reshape(-1, 3), r_ref) <= 1e-10
+    assert rel(u.grad.cpu().numpy(), orc.hvp(u_h, pw)) <= 1e-10
+    assert rel(mu.grad.cpu().numpy(), vm) <= 1e-10
+    assert rel(lam.grad.cpu().numpy(), vl) <= 1e-10
+
+
+def test_energy_fn_uses_given_coordinates():
+    """EnergyFn evaluated at coordinates other than the operator's: the value
+    and every gradient are those of the given X (the operator is moved there)."""
+    from paper_2602_12365_amd import Operator, energy
+    m = I.tet_mesh(3)
+    mu_h = I.lognormal_field(m.n_elems, 0.3, 4)
+    lam_h = 1.5 * np.ones(m.n_elems)
+    u_h = I.gaussian_field(m.n_nodes, 0.015, 0)
+    X2_h = m.X + I.gaussian_field(m.n_nodes, 0.01, 11)
+    op = Operator(I.TET4, m.X, m.conn)
+    u = dev(u_h).requires_grad_()
+    X2 = dev(X2_h).requires_grad_()
+    psi = energy(op, u, dev(mu_h), dev(lam_h), X2)
+    psi.backward()
+    orc = F.FEM(I.TET4, X2_h, m.conn, mu_h, lam_h)
+    assert abs(psi.item() - orc.energy(u_h)) <= 1e-12 * abs(orc.energy(u_h))
+    assert rel(u.grad.cpu().numpy(), orc.residual(u_h)) <= 1e-10
+    assert rel(X2.grad.cpu().numpy(), orc.grad_coords(u_h)) <= 1e-10
+
+
+def test_unmasked_restores_only_the_mask_in_force():
+    """A mask removed with set_dirichlet(None) stays removed after an unmasked
+    section (the reaction helpers use one)."""
+    from paper_2602_12365_amd import Operator
+    from paper_2602_12365_amd.adjoint import reaction
+    m = I.tet_mesh(2)
+    op = Operator(I.TET4, m.X, m.conn)
+    mask, _ = I.clamp_top_bottom(m.X, 0.05)
+    op.set_dirichlet(dev(mask, torch.uint8))
+    op.set_dirichlet(None)
+    u = dev(I.gaussian_field(m.n_nodes, 0.02, 0))
+    sel = dev(mask, torch.uint8)
+    reaction(op, u, sel)
+    assert op.mask is None
+    r = op.residual(u).cpu().numpy().reshape(-1)
+    orc = F.FEM(I.TET4, m.X, m.conn, np.ones(m.n_elems), 1.5 * np.ones(m.n_elems))
+    assert rel(r, orc.residual(u.cpu().numpy()).reshape(-1)) <= 1e-10   # no mask applied
+
+
 def solve_equilibrium(op, m, mu, dz, n_steps, u0=None, **kw):
     mask, ubc = I.clamp_top_bottom(m.X, dz)
     op.set_material(dev(mu), dev(1.5 * np.ones(m.n_elems)))

@@ -1,4 +1,4 @@
-"""The non-variational transport operator (virtual work, Sec. 5.5) and the
+"""The non-variational transport operator (virtual work, Sec. 3.1, Eqs. 4-6; example of Sec. 6.5) and the
 GMRES solve on the GPU, against the oracle: residual, tangent action in FP64
 and FP32, Jacobi diagonal, the non-symmetry, the sparse tangent by colouring,
 and Dirichlet solves against the oracle's direct solve."""

@@ -1,5 +1,5 @@
 """Pins of the oracle's non-variational transport operator (virtual work,
-Sec. 5.5; the advection-diffusion example's weak form for three species).
+Sec. 3.1, Eqs. 4-6; the weak form of the advection-diffusion example of Sec. 6.5 for three species).
 
 Every closed form is checked through both oracle paths, the residual r(c) and
 the assembled element matrices K c, so that a mistake in either is caught:
