@@ -102,6 +102,13 @@ typedef struct {
                               default two tetrahedra that share a face form one item
                               (5 nodes instead of 8), which results do not depend on
                               beyond rounding */
+    int32_t no_chunks;     /* EFEM_TET4, halo scatter: nonzero = the FP64 tangent
+                              action runs block by block.  By default runs of
+                              consecutive blocks form chunks whose nodes stay
+                              resident in one workgroup's LDS (the whole 160 KB of
+                              a CU) while the blocks stream through, the next
+                              block's nodes loading during the current block's
+                              arithmetic; a chunk's nodal sums leave LDS once */
 } efem_options;
 
 /* Build an operator for a mesh (Sec. 4, Operator(mesh, element, batchsize)).
@@ -241,6 +248,10 @@ typedef struct {
     int64_t n_shared_nodes;   /* nodes touched by more than one block */
     int64_t n_block_nodes;    /* sum over blocks of distinct nodes (>= n_nodes) */
     int64_t n_items;          /* work items: face-sharing tetrahedron pairs count once */
+    int32_t n_chunks;         /* chunks of the FP64 Tet4 tangent action, 0 = block pass */
+    int32_t max_chunk_slots;  /* largest per-chunk distinct node count (<= 1472) */
+    int64_t n_chunk_slots;    /* sum over chunks of distinct nodes */
+    int64_t n_chunk_shared_nodes; /* nodes touched by more than one chunk */
 } efem_info;
 
 int efem_get_info(efem_ctx *ctx, efem_info *info);

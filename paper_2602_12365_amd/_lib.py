@@ -35,13 +35,15 @@ c_double = ctypes.c_double
 
 class Options(ctypes.Structure):
     _fields_ = [("block_elems", c_int32), ("block_nodes", c_int32), ("scatter", c_int32),
-                ("threads", c_int32), ("no_pairs", c_int32)]
+                ("threads", c_int32), ("no_pairs", c_int32), ("no_chunks", c_int32)]
 
 
 class Info(ctypes.Structure):
     _fields_ = [("n_blocks", c_int32), ("n_colours", c_int32), ("max_block_nodes", c_int32),
                 ("max_block_elems", c_int32), ("n_shared_nodes", c_int64),
-                ("n_block_nodes", c_int64), ("n_items", c_int64)]
+                ("n_block_nodes", c_int64), ("n_items", c_int64), ("n_chunks", c_int32),
+                ("max_chunk_slots", c_int32), ("n_chunk_slots", c_int64),
+                ("n_chunk_shared_nodes", c_int64)]
 
 
 class SparseInfo(ctypes.Structure):

@@ -393,6 +393,111 @@ static void build_blocks(int elem, int64_t nn, int64_t ne, const double *X, cons
         }
 }
 
+// Chunks of consecutive blocks for the LDS-resident pass of the FP64 Tet4
+// tangent action.
+struct HostChunks {
+    std::vector<int32_t> bstart, sstart;
+    std::vector<uint32_t> bnew, cnode, items;
+    std::vector<int32_t> shared_nodes;   // nodes in more than one chunk, increasing id
+    int max_slots = 0;
+};
+
+// n chunks of consecutive blocks (block counts differing by at most one); each
+// chunk numbers its nodes in order of first use.  False if a chunk needs more
+// than kChunkCap slots.
+static bool try_chunks(const HostBlocks &hb, int64_t nn, int n, HostChunks &hc)
+{
+    const int nb = (int)hb.estart.size() - 1;
+    hc = HostChunks{};
+    hc.bstart.resize((size_t)n + 1);
+    for (int i = 0; i <= n; ++i) hc.bstart[(size_t)i] = (int32_t)((int64_t)nb * i / n);
+    hc.sstart.assign(1, 0);
+    hc.bnew.assign((size_t)nb, 0u);
+    for (int c = 0; c < n; ++c)
+        if (hc.bstart[(size_t)c + 1] - hc.bstart[(size_t)c] > kChunkSteps) return false;
+    std::vector<int32_t> slot_of((size_t)nn, -1), nchunks((size_t)nn, 0);
+    std::vector<int32_t> touched;
+    for (int c = 0; c < n; ++c) {
+        touched.clear();
+        int ns = 0;
+        bool fits = true;
+        for (int b = hc.bstart[(size_t)c]; b < hc.bstart[(size_t)c + 1] && fits; ++b) {
+            const int lo = ns;
+            for (int i = hb.nstart[(size_t)b]; i < hb.nstart[(size_t)b + 1]; ++i) {
+                const uint32_t g = hb.bnode[(size_t)i] & kGidMask;
+                if (slot_of[g] < 0) {
+                    slot_of[g] = ns++;
+                    touched.push_back((int32_t)g);
+                    hc.cnode.push_back(g);
+                }
+            }
+            // a block's new slots must span at most one 64-slot group per wave
+            const int groups = ns > lo ? ((ns - 1) >> 6) - (lo >> 6) + 1 : 0;
+            if (ns > kChunkCap || groups > kChunkThreads / 64) {
+                fits = false;
+                break;
+            }
+            hc.bnew[(size_t)b] = (uint32_t)lo | (uint32_t)ns << 16;
+            const uint32_t *bn = hb.bnode.data() + hb.nstart[(size_t)b];
+            auto sl = [&](uint32_t local) { return (uint32_t)slot_of[bn[local] & kGidMask]; };
+            for (int it = hb.istart[(size_t)b]; it < hb.istart[(size_t)b + 1]; ++it) {
+                const uint32_t w0 = hb.items[2 * (size_t)it], w1 = hb.items[2 * (size_t)it + 1];
+                const uint32_t a = sl(w0 & 1023u), bb = sl((w0 >> 10) & 1023u), cc = sl((w0 >> 20) & 1023u);
+                const uint32_t d1 = sl(w1 & 1023u), d2 = sl((w1 >> 10) & 1023u);
+                hc.items.push_back(a | bb << 11 | (d1 & 1023u) << 22);
+                hc.items.push_back(cc | d2 << 11 | (d1 >> 10) << 22);
+            }
+        }
+        for (int32_t g : touched) {
+            nchunks[(size_t)g] += 1;
+            slot_of[(size_t)g] = -1;
+        }
+        if (!fits) return false;
+        hc.sstart.push_back((int32_t)hc.cnode.size());
+        hc.max_slots = std::max(hc.max_slots, ns);
+    }
+    for (uint32_t &e : hc.cnode)
+        if (nchunks[e & kGidMask] > 1) e |= kShared;
+    for (int64_t g = 0; g < nn; ++g)
+        if (nchunks[(size_t)g] > 1) hc.shared_nodes.push_back((int32_t)g);
+    return true;
+}
+
+// Chunk count: a multiple of the CU count (one resident chunk per CU, all of
+// them in one round when it fits), the smallest whose chunks fit the LDS; one
+// block per chunk always fits.  False if the pass does not apply: blocks with
+// more items than the workgroup's threads.
+static bool build_chunks(const HostBlocks &hb, int64_t nn, int n_cu, HostChunks &hc)
+{
+    const int nb = (int)hb.estart.size() - 1;
+    for (int b = 0; b < nb; ++b)
+        if (hb.istart[(size_t)b + 1] - hb.istart[(size_t)b] > kChunkThreads) return false;
+    for (int k = 1;; ++k) {
+        const int n = (int)std::min<int64_t>(nb, (int64_t)k * std::max(n_cu, 1));
+        if (try_chunks(hb, nn, n, hc)) return true;
+        if (n == nb) return false;
+    }
+}
+
+// Halo entries of the shared nodes: entry i (in block or chunk order) of a
+// shared node gets the next slot of that node, so a node's slots are
+// consecutive and in order.
+static void halo_layout(const std::vector<uint32_t> &entries, const std::vector<int32_t> &shared, int64_t nn,
+                        std::vector<int32_t> &hptr, std::vector<int32_t> &hslot)
+{
+    const int32_t ns = (int32_t)shared.size();
+    std::vector<int32_t> slot((size_t)nn, -1);
+    for (int32_t s = 0; s < ns; ++s) slot[(size_t)shared[(size_t)s]] = s;
+    hptr.assign((size_t)ns + 1, 0);
+    for (uint32_t ent : entries)
+        if (ent & kShared) hptr[(size_t)slot[ent & kGidMask] + 1] += 1;
+    for (int32_t s = 0; s < ns; ++s) hptr[(size_t)s + 1] += hptr[(size_t)s];
+    hslot.assign(entries.size(), -1);
+    std::vector<int32_t> fill(hptr.begin(), hptr.end() - 1);
+    for (size_t i = 0; i < entries.size(); ++i)
+        if (entries[i] & kShared) hslot[i] = fill[(size_t)slot[entries[i] & kGidMask]]++;
+}
+
 }  // namespace efem
 
 using namespace efem;
@@ -520,26 +625,57 @@ int efem_create(efem_ctx **out, int32_t elem, int64_t n_nodes, int64_t n_elems,
     m.hslot = nullptr;
     if (ctx->scatter == Scatter::Halo && ctx->n_shared > 0) {
         // each shared node's block-node entries, in block order
-        const int32_t ns = (int32_t)ctx->n_shared;
-        std::vector<int32_t> slot((size_t)n_nodes, -1);
-        for (int32_t s = 0; s < ns; ++s) slot[(size_t)hb.shared_nodes[(size_t)s]] = s;
-        std::vector<int32_t> hptr((size_t)ns + 1, 0);
-        for (uint32_t ent : hb.bnode)
-            if (ent & kShared) hptr[(size_t)slot[ent & kGidMask] + 1] += 1;
-        for (int32_t s = 0; s < ns; ++s) hptr[(size_t)s + 1] += hptr[(size_t)s];
-        // entry i of a shared node gets the next halo slot of that node, so a
-        // node's slots are consecutive and in block order
-        std::vector<int32_t> hslot(hb.bnode.size(), -1), fill(hptr.begin(), hptr.end() - 1);
-        for (size_t i = 0; i < hb.bnode.size(); ++i)
-            if (hb.bnode[i] & kShared) hslot[i] = fill[(size_t)slot[hb.bnode[i] & kGidMask]]++;
+        std::vector<int32_t> hptr, hslot;
+        halo_layout(hb.bnode, hb.shared_nodes, n_nodes, hptr, hslot);
         double *p_h;
         int32_t *p_hs;
         if ((rc = upload(*ctx, &ctx->halo_ptr, hptr)) || (rc = upload(*ctx, &p_hs, hslot))
             || (rc = upload(*ctx, &ctx->halo_node, hb.shared_nodes))
-            || (rc = dalloc(*ctx, &p_h, 3 * (size_t)hptr[(size_t)ns])))
+            || (rc = dalloc(*ctx, &p_h, 3 * (size_t)hptr.back())))
             return fail(rc);
         m.halo = p_h;
         m.hslot = p_hs;
+    }
+
+    // chunks for the LDS-resident FP64 tangent action (Tet4 pairs, halo scatter)
+    int lds_max = 0, n_cu = 0;
+    (void)hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, ctx->device);
+    (void)hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, ctx->device);
+    HostChunks hc;
+    if (elem == EFEM_TET4 && ctx->scatter == Scatter::Halo && !(opts && opts->no_chunks)
+        && n_nodes <= (int64_t)kStageGid && lds_max >= kChunkLds && build_chunks(hb, n_nodes, n_cu, hc)) {
+        ChunkMesh &ch = ctx->ch;
+        ch.n_chunks = (int32_t)hc.bstart.size() - 1;
+        ctx->max_chunk_slots = hc.max_slots;
+        ctx->n_chunk_slots = (int64_t)hc.cnode.size();
+        ctx->n_ch_shared = (int64_t)hc.shared_nodes.size();
+        int32_t *p_bs, *p_ss, *p_hs = nullptr;
+        uint32_t *p_bw, *p_cn, *p_it;
+        if ((rc = upload(*ctx, &p_bs, hc.bstart)) || (rc = upload(*ctx, &p_ss, hc.sstart))
+            || (rc = upload(*ctx, &p_bw, hc.bnew)) || (rc = upload(*ctx, &p_cn, hc.cnode))
+            || (rc = upload(*ctx, &p_it, hc.items)))
+            return fail(rc);
+        ch.bstart = p_bs;
+        ch.sstart = p_ss;
+        ch.bnew = p_bw;
+        ch.cnode = p_cn;
+        ch.items = p_it;
+        ch.halo = nullptr;
+        if (ctx->n_ch_shared > 0) {
+            std::vector<int32_t> hptr, hslot;
+            halo_layout(hc.cnode, hc.shared_nodes, n_nodes, hptr, hslot);
+            double *p_h;
+            if ((rc = upload(*ctx, &ctx->ch_halo_ptr, hptr)) || (rc = upload(*ctx, &p_hs, hslot))
+                || (rc = upload(*ctx, &ctx->ch_halo_node, hc.shared_nodes))
+                || (rc = dalloc(*ctx, &p_h, 3 * (size_t)hptr.back())))
+                return fail(rc);
+            ch.halo = p_h;
+        } else {
+            std::vector<int32_t> none(hc.cnode.size(), -1);
+            if ((rc = upload(*ctx, &p_hs, none))) return fail(rc);
+        }
+        ch.hslot = p_hs;
+        if ((rc = dalloc(*ctx, &ch.cword, hc.cnode.size()))) return fail(rc);
     }
 
     // default material mu = 1, lam = 1.5
@@ -557,6 +693,10 @@ int efem_create(efem_ctx **out, int32_t elem, int64_t n_nodes, int64_t n_elems,
         return fail(hip_fail(hipGetLastError(), "hipMemset"));
     m.flags = ctx->flags;
     m.nmask = nullptr;
+    if (ctx->ch.n_chunks > 0) {
+        const hipError_t e = launch_chunk_words(*ctx);
+        if (e != hipSuccess) return fail(hip_fail(e, "chunk staging words"));
+    }
 
     if (scatter == EFEM_SCATTER_COLOR) {
         for (auto &lst : hb.colours) {
@@ -659,14 +799,16 @@ int efem_set_dirichlet(efem_ctx *ctx, const uint8_t *mask)
     DeviceGuard dg(ctx->device);
     if (!mask) {
         ctx->m.nmask = nullptr;
-        return EFEM_OK;
+    } else {
+        if (!ctx->nmask) {
+            int rc = dalloc(*ctx, &ctx->nmask, (size_t)ctx->n_nodes);
+            if (rc) return rc;
+        }
+        HIP_TRY(launch_build_nmask(*ctx, mask, ctx->nmask));
+        ctx->m.nmask = ctx->nmask;
     }
-    if (!ctx->nmask) {
-        int rc = dalloc(*ctx, &ctx->nmask, (size_t)ctx->n_nodes);
-        if (rc) return rc;
-    }
-    HIP_TRY(launch_build_nmask(*ctx, mask, ctx->nmask));
-    ctx->m.nmask = ctx->nmask;
+    // the chunk pass reads each slot's Dirichlet bits with its node id
+    if (ctx->ch.n_chunks > 0) HIP_TRY(launch_chunk_words(*ctx));
     return EFEM_OK;
 }
 
@@ -735,8 +877,8 @@ int efem_linearize(efem_ctx *ctx, const double *u, int32_t prec)
     const size_t n = 3 * (size_t)ctx->n_nodes;
     int rc;
     if (prec == EFEM_F64) {
-        if (!ctx->xlin && (rc = dalloc(*ctx, &ctx->xlin, n))) return rc;
-        HIP_TRY(launch_add_x_u(*ctx, u, ctx->xlin));
+        if (!ctx->xlin && (rc = dalloc(*ctx, &ctx->xlin, 2 * n))) return rc;
+        HIP_TRY(launch_lin_record(*ctx, u, ctx->xlin));
     } else {
         if (!ctx->ulin && (rc = dalloc(*ctx, &ctx->ulin, n))) return rc;
         HIP_TRY(launch_cast_f32(u, ctx->ulin, (int64_t)n, ctx->stream));
@@ -842,6 +984,10 @@ int efem_get_info(efem_ctx *ctx, efem_info *info)
     int32_t tot = 0;
     HIP_TRY(hipMemcpy(&tot, ctx->m.nstart + ctx->m.n_blocks, sizeof(int32_t), hipMemcpyDeviceToHost));
     info->n_block_nodes = tot;
+    info->n_chunks = ctx->ch.n_chunks;
+    info->max_chunk_slots = ctx->max_chunk_slots;
+    info->n_chunk_slots = ctx->n_chunk_slots;
+    info->n_chunk_shared_nodes = ctx->n_ch_shared;
     return EFEM_OK;
 }
 

@@ -43,6 +43,35 @@ struct BlockMesh {
     const int32_t *hslot;     // [n_block_nodes]
 };
 
+// Chunks: runs of consecutive blocks whose distinct nodes all stay resident in
+// one workgroup's LDS while the blocks stream through it (the FP64 Tet4
+// tangent action).  Node slots are numbered in order of first use; block b of
+// a chunk brings the new slots [lo, hi) with bnew[b] = lo | hi << 16.  A node
+// touched by more than one chunk is shared: its chunk sum goes to a halo entry
+// (hslot), and the nodes' entries are consecutive and in chunk order.
+constexpr int kChunkCap = 1472;      // node slots per chunk (23 groups of 64)
+constexpr int kChunkThreads = 768;   // 12 waves per workgroup: 3 per SIMD
+// LDS of a chunk: five 16-byte record pieces and three FP64 sums per slot, and
+// one 64-slot group of staging words per wave, and the chunk's block table
+constexpr int kPieceBytes = kChunkCap * 16;
+constexpr int kChunkSteps = 32;      // blocks per chunk at most
+constexpr int kChunkLds = 5 * kPieceBytes + kChunkCap * 24 + kChunkThreads * 4 + (3 * kChunkSteps + 2) * 4;
+// staging word of a chunk slot: global id | Dirichlet bits << 28
+constexpr uint32_t kStageGid = 0x0fffffffu;
+struct ChunkMesh {
+    int32_t n_chunks;
+    int32_t pad;
+    const int32_t *bstart;    // [n_chunks+1] block ranges
+    const int32_t *sstart;    // [n_chunks+1] slot ranges into cnode / hslot
+    const uint32_t *bnew;     // [n_blocks] chunk-relative new-slot range of each block
+    const uint32_t *cnode;    // slot -> global id | kShared
+    uint32_t *cword;          // slot -> staging word (global id | Dirichlet bits << 28)
+    const uint32_t *items;    // chunk-slot connectivity, 2 words per item, 11-bit ids:
+                              // a | b<<11 | (d1 & 1023)<<22,  c | d2<<11 | (d1 >> 10)<<22
+    const int32_t *hslot;     // [slots] halo entry of a shared slot, else -1
+    double *halo;             // [3 * entries]
+};
+
 // How block sums reach nodes shared between blocks:
 //   Halo:   plain stores into a per-entry buffer, then a gather kernel sums each
 //           shared node's entries in block order (no device atomics);
@@ -83,8 +112,11 @@ hipError_t launch_grad_coords(const Ctx &c, const double *u, double *g);
 // small utility kernels (kernels_util.hip)
 hipError_t launch_permute_elems(const Ctx &c, const double *src, double *dst);
 hipError_t launch_build_nmask(const Ctx &c, const uint8_t *dofmask, uint8_t *nmask);
-hipError_t launch_add_x_u(const Ctx &c, const double *u, double *x);
+// xrec[6 i + c] = X[3 i + c], xrec[6 i + 3 + c] = X[3 i + c] + u[3 i + c]
+hipError_t launch_lin_record(const Ctx &c, const double *u, double *xrec);
 hipError_t launch_cast_f32(const double *src, float *dst, int64_t n, hipStream_t s);
+// staging words of the chunk slots from cnode and the node mask (null = none)
+hipError_t launch_chunk_words(const Ctx &c);
 // flag = 1 if a[i] == a[0] and b[i] == b[0] for all i (flag must hold 1 on entry)
 hipError_t launch_uniform_check(const double *a, const double *b, int64_t n, int32_t *flag,
                                 hipStream_t s);
@@ -101,6 +133,12 @@ struct Ctx {
     int threads = 256;
     int max_block_nodes = 0;        // max nodes over blocks (LDS sizing)
     int max_block_elems = 0;
+    // chunk pass of the FP64 Tet4 tangent action (n_chunks = 0: block pass only)
+    ChunkMesh ch{};
+    int64_t n_ch_shared = 0;          // nodes in more than one chunk
+    int64_t n_chunk_slots = 0;        // sum over chunks of distinct nodes
+    int max_chunk_slots = 0;
+    int32_t *ch_halo_ptr = nullptr, *ch_halo_node = nullptr;
 
     // device buffers owned by the context
     BlockMesh m{};
@@ -121,7 +159,7 @@ struct Ctx {
 
     // linearization point
     int lin_prec = -1;
-    double *xlin = nullptr;   // X + u  (FP64 tangent)
+    double *xlin = nullptr;   // [n_nodes][6] = (X, X + u) per node (FP64 tangent)
     float *ulin = nullptr;    // u in FP32 (FP32 tangent)
 
     // learned preconditioner state (precond.cpp) and the host connectivity it

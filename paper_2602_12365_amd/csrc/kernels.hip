@@ -75,18 +75,17 @@ __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x);
 // the quotient gets one residual correction, so the result is within a few
 // ulp.  Arguments must be positive and finite (the callers flag det F <= 0
 // before the value is used).
+// The series coefficients 1/19, 1/17, ..., 1/3 live in constant memory: read
+// with scalar loads they sit in scalar registers, where the compiler would
+// otherwise keep 16 vector registers of constants across the element loops.
+__constant__ double kAtanhCoef[9] = {1.0 / 19.0, 1.0 / 17.0, 1.0 / 15.0, 1.0 / 13.0, 1.0 / 11.0,
+                                     1.0 / 9.0,  1.0 / 7.0,  1.0 / 5.0,  1.0 / 3.0};
 __device__ __forceinline__ double two_atanh(double s)
 {
     const double z = s * s;
-    double p = 1.0 / 19.0;
-    p = fma(p, z, 1.0 / 17.0);
-    p = fma(p, z, 1.0 / 15.0);
-    p = fma(p, z, 1.0 / 13.0);
-    p = fma(p, z, 1.0 / 11.0);
-    p = fma(p, z, 1.0 / 9.0);
-    p = fma(p, z, 1.0 / 7.0);
-    p = fma(p, z, 1.0 / 5.0);
-    p = fma(p, z, 1.0 / 3.0);
+    double p = kAtanhCoef[0];
+#pragma unroll
+    for (int i = 1; i < 9; ++i) p = fma(p, z, kAtanhCoef[i]);
     const double s2 = s + s;
     return fma(s2 * z, p, s2);
 }
@@ -826,12 +825,14 @@ template <class T> struct HvpOp;
 
 template <> struct HvpOp<double> {
     using Node = NodeH64;
-    const double *X, *xlin, *v;
+    const double *xrec;   // [n_nodes][6]: X, x = X + u
+    const double *v;
     double *y;
     __device__ void stage(const BlockMesh &m, Node &n, int64_t g) const
     {
-        load3(X, g, n.X);
-        load3(xlin, g, n.x);
+        const double *p = xrec + 6 * g;
+        n.X[0] = p[0], n.X[1] = p[1], n.X[2] = p[2];
+        n.x[0] = p[3], n.x[1] = p[4], n.x[2] = p[5];
         load3(v, g, n.v);
         if (m.nmask) {
             const uint8_t b = m.nmask[g];
@@ -855,6 +856,14 @@ template <> struct HvpOp<double> {
                 ve[a][i] = n.v[i];
             }
         }
+        return compute<E>(Xe, xe, ve, mu, lam, pair, f);
+    }
+    // the element's forces from its nodal X, x and v
+    template <class E>
+    __device__ static __forceinline__ bool compute(const double Xe[E::NEN][3], const double xe[E::NEN][3],
+                                                   const double ve[E::NEN][3], const double *mu,
+                                                   const double *lam, bool pair, double f[E::NEN][3])
+    {
         // three fields: the register-lean form (node sums for Hex8)
         using G = typename E::Lean;
         typename G::template Field<double> FX, Fx, Fv;
@@ -1675,6 +1684,203 @@ __global__ void __launch_bounds__(256) k_fill_nodal(int64_t n_nodes, T *__restri
     for (int c = 0; c < 3; ++c) y[3 * i + c] = ((b >> c) & 1) ? fixed_val : T(0);
 }
 
+// ----------------------------------------------------------- chunk pass
+
+// The FP64 Tet4 tangent action over chunks (one workgroup per chunk, the
+// whole LDS of a CU).  Every node record of a chunk stays resident while its
+// blocks stream through as steps: while the items of step t compute, the
+// records that step t+1 brings are already on their way from HBM with
+// global-to-LDS loads, which take no registers, so the 3 waves per SIMD of the
+// item arithmetic keep their occupancy.  One barrier per step makes the
+// records of step t+1 visible.  The chunk's nodal sums stay in LDS until the
+// last step; shared nodes then go to their halo entries as in the block pass.
+//
+// LDS: five 16-byte record pieces per node slot, each piece in an array of its
+// own, so that one wave's 64-lane load fills 64 consecutive slots:
+//   P0 = (X0, X1), P1 = (X2, x0), P2 = (x1, x2)  from the 48-byte record (X, x)
+//   P3 = (v0, v1), P4 = (v1, v2)                 two overlapping reads of v
+// then the FP64 sums, 3 per slot (kChunkLds bytes in all).
+// Global-to-LDS loads, written as instructions: lane i's 16 (or 4) bytes land
+// at LDS byte address lds + 16 i (4 i); lds must be the same in every lane.
+// The compiler does not see these loads, so it neither waits for them before
+// unrelated LDS reads (it would otherwise assume they may alias) nor counts
+// them; every use of their data follows an explicit wait_vm_loads() and a
+// barrier.  They write no registers.  m0 is set inside the statement (one
+// wait state before the load uses it).
+__device__ __forceinline__ uint32_t lds_addr(const void *p) { return (uint32_t)(uintptr_t)p; }
+__device__ __forceinline__ void load_to_lds16(const void *src, uint32_t lds)
+{
+    asm volatile("s_mov_b32 m0, %1\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %0, off" ::"v"(src), "s"(lds) : "m0");
+}
+__device__ __forceinline__ void load_to_lds4(const void *src, uint32_t lds)
+{
+    asm volatile("s_mov_b32 m0, %1\n\ts_nop 0\n\tglobal_load_lds_dword %0, off" ::"v"(src), "s"(lds) : "m0");
+}
+
+// The slot a lane stages for a block's new-slot range lo | hi << 16: wave w
+// takes slot group (lo >> 6) + w (the host keeps a block's new slots within
+// one group per wave); -1 if the lane has none.
+__device__ __forceinline__ int chunk_stage_slot(uint32_t lohi, int wave, int lane)
+{
+    const int lo = (int)(lohi & 0xffffu), hi = (int)(lohi >> 16);
+    const int l = ((lo >> 6) + wave) * 64 + lane;
+    return (l >= lo && l < hi) ? l : -1;
+}
+
+// Record-piece loads of slot l from its staging word (node id and Dirichlet
+// bits); the wave's 64 slots form one group of the piece arrays.
+__device__ __forceinline__ void chunk_stage_records(unsigned char *smem, const double *__restrict__ xrec,
+                                                    const double *__restrict__ v, int l, uint32_t word)
+{
+    if (l < 0) return;
+    const int64_t g = word & kStageGid;
+    const double *pr = xrec + 6 * g;
+    const double *pv = v + 3 * g;
+    const uint32_t dst = __builtin_amdgcn_readfirstlane(lds_addr(smem) + (uint32_t)(l >> 6) * 1024u);
+    load_to_lds16(pr, dst);
+    load_to_lds16(pr + 2, dst + kPieceBytes);
+    load_to_lds16(pr + 4, dst + 2 * kPieceBytes);
+    load_to_lds16(pv, dst + 3 * kPieceBytes);
+    load_to_lds16(pv + 1, dst + 4 * kPieceBytes);
+}
+
+// After slot l's loads have landed: prescribed direction components read as 0
+// (only while a mask is in force: a caller may clear m.nmask for one launch to
+// take the action on the unmasked input, the staging words keep their bits).
+__device__ __forceinline__ void chunk_stage_mask(const BlockMesh &m, unsigned char *smem, int l, uint32_t word)
+{
+    const uint32_t bits = word >> 28;
+    if (!m.nmask || l < 0 || !bits) return;
+    double *p3 = reinterpret_cast<double *>(smem + 3 * kPieceBytes + 16 * l);
+    double *p4 = reinterpret_cast<double *>(smem + 4 * kPieceBytes + 16 * l);
+    if (bits & 1u) p3[0] = 0.0;
+    if (bits & 2u) p3[1] = 0.0, p4[0] = 0.0;
+    if (bits & 4u) p4[1] = 0.0;
+}
+
+// s_waitcnt vmcnt(0) (expcnt and lgkmcnt left at their maxima).  The builtin,
+// not inline asm, so that the compiler's own wait insertion knows every
+// vector-memory load has completed here.
+__device__ __forceinline__ void wait_vm_loads() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+
+// UNI: a uniform material (the two kernel-argument scalars); otherwise per element.
+template <bool ACC, bool UNI>
+__global__ void __launch_bounds__(kChunkThreads)
+k_chunk_hvp64(BlockMesh m, ChunkMesh ch, const double *__restrict__ xrec, const double *__restrict__ v,
+              double *__restrict__ y, int use_mask, double fixed_val, const int32_t *__restrict__ skip)
+{
+    __shared__ __align__(16) unsigned char smem[kChunkLds];
+    if (skip && *skip) return;
+    constexpr int W = kChunkThreads / 64;
+    const int c = xcd_remap(blockIdx.x, ch.n_chunks);
+    const int b0 = ch.bstart[c], nsteps = ch.bstart[c + 1] - b0;
+    const int s0 = ch.sstart[c], ns = ch.sstart[c + 1] - s0;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    double *acc = reinterpret_cast<double *>(smem + 5 * kPieceBytes);
+    // this wave's staging words: those of the step after next arrive with
+    // global-to-LDS loads, so issuing a step's record loads waits for LDS only
+    uint32_t *words = reinterpret_cast<uint32_t *>(smem + 5 * kPieceBytes + kChunkCap * 24) + 64 * wave;
+    const uint32_t wdst = __builtin_amdgcn_readfirstlane(lds_addr(words));
+    // the chunk's block table in LDS: no global load is waited for inside a
+    // step, where the wait would also wait for the records in flight
+    int32_t *t_istart = reinterpret_cast<int32_t *>(smem + 5 * kPieceBytes + kChunkCap * 24 + kChunkThreads * 4);
+    int32_t *t_estart = t_istart + kChunkSteps + 1;
+    uint32_t *t_bnew = reinterpret_cast<uint32_t *>(t_estart + kChunkSteps + 1);
+    const uint32_t *cword = ch.cword + s0;
+    for (int i = threadIdx.x; i < 3 * ns; i += kChunkThreads) acc[i] = 0.0;
+    if (threadIdx.x <= nsteps) {
+        t_istart[threadIdx.x] = m.istart[b0 + threadIdx.x];
+        t_estart[threadIdx.x] = m.estart[b0 + threadIdx.x];
+        if (threadIdx.x < nsteps) t_bnew[threadIdx.x] = ch.bnew[b0 + threadIdx.x];
+    }
+
+    // the items of a step: lane L of wave w takes item L * W + w, so the
+    // lanes of one LDS atomic are W items apart in Morton order
+    const int k = lane * W + wave;
+
+    // step 0: records staged before the loop from directly read words; the
+    // words of step 1 follow into LDS
+    const int l0 = chunk_stage_slot(ch.bnew[b0], wave, lane);
+    const uint32_t word0 = l0 >= 0 ? cword[l0] : 0u;
+    chunk_stage_records(smem, xrec, v, l0, word0);
+    if (nsteps > 1) {
+        const int l1 = chunk_stage_slot(ch.bnew[b0 + 1], wave, lane);
+        if (l1 >= 0) load_to_lds4(cword + l1, wdst);
+    }
+    uint2 itw = make_uint2(0u, 0u);
+    {
+        const int i0 = m.istart[b0];
+        if (k < m.istart[b0 + 1] - i0) itw = *reinterpret_cast<const uint2 *>(ch.items + 2 * (int64_t)(i0 + k));
+    }
+    wait_vm_loads();
+    chunk_stage_mask(m, smem, l0, word0);
+    __syncthreads();
+
+    bool bad = false;
+    for (int t = 0; t < nsteps; ++t) {
+        // records of step t+1 on their way, then the words of step t+2
+        uint32_t word1 = 0u;
+        if (t + 1 < nsteps) {
+            const int l1 = chunk_stage_slot(t_bnew[t + 1], wave, lane);
+            if (l1 >= 0) word1 = words[lane];
+            chunk_stage_records(smem, xrec, v, l1, word1);
+            if (t + 2 < nsteps) {
+                const int l2 = chunk_stage_slot(t_bnew[t + 2], wave, lane);
+                if (l2 >= 0) load_to_lds4(cword + l2, wdst);
+            }
+        }
+        const uint2 cur = itw;
+        const int i0 = t_istart[t], ni = t_istart[t + 1] - i0;
+        if (t + 1 < nsteps && k < t_istart[t + 2] - t_istart[t + 1])
+            itw = *reinterpret_cast<const uint2 *>(ch.items + 2 * (int64_t)(t_istart[t + 1] + k));
+
+        if (k < ni) {
+            ItemRange r;
+            r.i0 = i0;
+            r.ni = ni;
+            r.e0 = t_estart[t];
+            r.np = (t_estart[t + 1] - r.e0) - ni;
+            int lc[5];
+            lc[0] = (int)(cur.x & 2047u);
+            lc[1] = (int)((cur.x >> 11) & 2047u);
+            lc[2] = (int)(cur.y & 2047u);
+            lc[3] = (int)((cur.x >> 22) | ((cur.y >> 22) << 10));
+            lc[4] = (int)((cur.y >> 11) & 2047u);
+            double Xe[5][3], xe[5][3], ve[5][3];
+            const double2 *P = reinterpret_cast<const double2 *>(smem);
+#pragma unroll
+            for (int a = 0; a < 5; ++a) {
+                const int s = lc[a];
+                const double2 p0 = P[s], p1 = P[kChunkCap + s], p2 = P[2 * kChunkCap + s];
+                const double2 p3 = P[3 * kChunkCap + s];
+                const double v2 = reinterpret_cast<const double *>(P + 4 * kChunkCap + s)[1];
+                Xe[a][0] = p0.x, Xe[a][1] = p0.y, Xe[a][2] = p1.x;
+                xe[a][0] = p1.y, xe[a][1] = p2.x, xe[a][2] = p2.y;
+                ve[a][0] = p3.x, ve[a][1] = p3.y, ve[a][2] = v2;
+            }
+            double mu[2], lam[2];
+            if (UNI) {
+                mu[0] = mu[1] = m.mu0;
+                lam[0] = lam[1] = m.lam0;
+            } else {
+                item_materials<Tet4Pair>(m, r, k, mu, lam);
+            }
+            double f[5][3];
+            bad |= !HvpOp<double>::compute<Tet4Pair>(Xe, xe, ve, mu, lam, k < r.np, f);
+#pragma unroll
+            for (int a = 0; a < 5; ++a)
+#pragma unroll
+                for (int i = 0; i < 3; ++i) atomicAdd(&acc[3 * lc[a] + i], f[a][i]);
+        }
+        wait_vm_loads();
+        if (t + 1 < nsteps) chunk_stage_mask(m, smem, chunk_stage_slot(t_bnew[t + 1], wave, lane), word1);
+        __syncthreads();
+    }
+    if (bad) flag_inverted(m.flags);
+    write_out<ACC>(m, ch.cnode + s0, ns, acc, y, Scatter::Halo, use_mask != 0, fixed_val, ch.halo,
+                   ch.hslot + s0);
+}
+
 // ------------------------------------------------------------------- energy
 
 template <class E, bool LIN>
@@ -1938,10 +2144,37 @@ static size_t lds_bytes(const Ctx &c, size_t acc_elem)
     return (sizeof(typename Op::Node) + 3 * acc_elem + sizeof(uint32_t)) * (size_t)c.max_block_nodes;
 }
 
+// The chunk pass of the FP64 Tet4 tangent action, then the gather of the
+// nodes that several chunks share.
+static hipError_t run_chunks(const Ctx &c, const HvpOp<double> &op, double *y, bool use_mask,
+                             const int32_t *skip, WriteMode mode)
+{
+    const bool acc = mode == WriteMode::Accumulate, uni = c.m.mu == nullptr;
+    const uint8_t *gmask = use_mask ? c.m.nmask : nullptr;
+    auto kern = acc ? (uni ? k_chunk_hvp64<true, true> : k_chunk_hvp64<true, false>)
+                    : (uni ? k_chunk_hvp64<false, true> : k_chunk_hvp64<false, false>);
+    hipLaunchKernelGGL(kern, dim3(c.ch.n_chunks), dim3(kChunkThreads), 0, c.stream, c.m, c.ch, op.xrec, op.v, y,
+                       use_mask ? 1 : 0, 0.0, skip);
+    if (c.n_ch_shared > 0) {
+        const unsigned gb = (unsigned)((c.n_ch_shared + 255) / 256);
+        if (acc)
+            hipLaunchKernelGGL((k_halo_gather<double, true>), dim3(gb), dim3(256), 0, c.stream,
+                               (int32_t)c.n_ch_shared, c.ch_halo_ptr, c.ch_halo_node, c.ch.halo, y, gmask,
+                               0.0, skip);
+        else
+            hipLaunchKernelGGL((k_halo_gather<double, false>), dim3(gb), dim3(256), 0, c.stream,
+                               (int32_t)c.n_ch_shared, c.ch_halo_ptr, c.ch_halo_node, c.ch.halo, y, gmask,
+                               0.0, skip);
+    }
+    return hipGetLastError();
+}
+
 template <class E, class Op, class T>
 static hipError_t run_accumulate(const Ctx &c, const Op &op, T *y, bool use_mask, T fixed_val,
                                  const int32_t *skip, WriteMode mode)
 {
+    if constexpr (std::is_same<E, Tet4Pair>::value && std::is_same<Op, HvpOp<double>>::value)
+        if (c.ch.n_chunks > 0 && c.scatter == Scatter::Halo) return run_chunks(c, op, y, use_mask, skip, mode);
     const size_t lds = lds_bytes<Op>(c, sizeof(double));
     const bool halo = c.scatter == Scatter::Halo && c.n_shared > 0;
     const unsigned gather_blocks = (unsigned)((c.n_shared + 255) / 256);
@@ -2052,7 +2285,7 @@ hipError_t launch_hvp_f64(const Ctx &c, const double *xlin, const double *v, dou
         LinHvpOp<double> op{c.m.X, v};
         return dispatch(c, op, y, true, 0.0, skip, mode);
     }
-    HvpOp<double> op{c.m.X, xlin, v, y};
+    HvpOp<double> op{xlin, v, y};
     return dispatch(c, op, y, true, 0.0, skip, mode);
 }
 

@@ -20,11 +20,17 @@ __global__ void k_build_nmask(const uint8_t *__restrict__ dofmask, int64_t n_nod
                          | ((dofmask[3 * i + 2] != 0) << 2));
 }
 
-__global__ void k_add(const double *__restrict__ a, const double *__restrict__ b, int64_t n,
-                      double *__restrict__ out)
+// the linearization record of each node: (X, X + u), 48 contiguous bytes
+__global__ void k_lin_record(const double *__restrict__ X, const double *__restrict__ u, int64_t n,
+                             double *__restrict__ out)
 {
-    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i < n) out[i] = a[i] + b[i];
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;   // DOF
+    if (i < n) {
+        const int64_t node = i / 3, c = i - 3 * node;
+        const double x = X[i];
+        out[6 * node + c] = x;
+        out[6 * node + 3 + c] = x + u[i];
+    }
 }
 
 __global__ void k_cast_f32(const double *__restrict__ src, int64_t n, float *__restrict__ dst)
@@ -63,10 +69,28 @@ hipError_t launch_build_nmask(const Ctx &c, const uint8_t *dofmask, uint8_t *nma
     return hipGetLastError();
 }
 
-hipError_t launch_add_x_u(const Ctx &c, const double *u, double *x)
+hipError_t launch_lin_record(const Ctx &c, const double *u, double *xrec)
 {
-    hipLaunchKernelGGL(k_add, dim3(grid_for(3 * c.n_nodes)), dim3(256), 0, c.stream, c.m.X, u,
-                       3 * c.n_nodes, x);
+    hipLaunchKernelGGL(k_lin_record, dim3(grid_for(3 * c.n_nodes)), dim3(256), 0, c.stream, c.m.X, u,
+                       3 * c.n_nodes, xrec);
+    return hipGetLastError();
+}
+
+// staging word of each chunk slot: its node id and the node's Dirichlet bits
+__global__ void k_chunk_words(int64_t n, const uint32_t *__restrict__ cnode, const uint8_t *__restrict__ nmask,
+                              uint32_t *__restrict__ cword)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) {
+        const uint32_t g = cnode[i] & kStageGid;
+        cword[i] = g | (nmask ? (uint32_t)(nmask[g] & 7u) << 28 : 0u);
+    }
+}
+
+hipError_t launch_chunk_words(const Ctx &c)
+{
+    hipLaunchKernelGGL(k_chunk_words, dim3(grid_for(c.n_chunk_slots)), dim3(256), 0, c.stream, c.n_chunk_slots,
+                       c.ch.cnode, c.m.nmask, c.ch.cword);
     return hipGetLastError();
 }
 

@@ -84,7 +84,7 @@ struct Solver {
             return rc;
         if (!c.xlin) {
             void *q_ = nullptr;
-            TRY(hipMalloc(&q_, n * sizeof(double)));
+            TRY(hipMalloc(&q_, 2 * n * sizeof(double)));   // (X, X + u) per node
             c.owned.push_back(q_);
             c.xlin = static_cast<double *>(q_);
         }
@@ -138,7 +138,7 @@ struct Solver {
 
     int linearize(const double *u)
     {
-        if (std::is_same<T, double>::value) TRY(launch_add_x_u(c, u, c.xlin));
+        if (std::is_same<T, double>::value) TRY(launch_lin_record(c, u, c.xlin));
         else TRY(launch_cast_f32(u, c.ulin, n, c.stream));
         c.lin_prec = std::is_same<T, double>::value ? EFEM_F64 : EFEM_F32;
         return EFEM_OK;
@@ -315,7 +315,7 @@ struct Solver {
             // tangent predictor: K_ff d_f = (dload f - K dc)_f, with K dc taken on the
             // unmasked input
             TRY(launch_bc_increment(c.stream, n, u, u_bc, frac, c.m.nmask, dc, u_old));
-            TRY(launch_add_x_u(c, u, c.xlin));
+            TRY(launch_lin_record(c, u, c.xlin));
             const uint8_t *mask = c.m.nmask;
             c.m.nmask = nullptr;
             hipError_t he = launch_hvp_f64(c, c.xlin, dc, kdc, nullptr, WriteMode::Overwrite);

@@ -39,7 +39,7 @@ class Operator:
     """
 
     def __init__(self, elem, X, conn, *, block_elems=0, block_nodes=0, scatter="halo",
-                 threads=0, pairs=True, model="neo_hookean", device=None):
+                 threads=0, pairs=True, chunks=True, model="neo_hookean", device=None):
         self._lib = L.load()
         X = np.ascontiguousarray(np.asarray(X, dtype=np.float64))
         conn = np.ascontiguousarray(np.asarray(conn, dtype=np.int32))
@@ -56,7 +56,9 @@ class Operator:
         self.device = torch.device("cuda", dev.index if dev.index is not None else torch.cuda.current_device())
         self.X_host = X
         self.pairs = bool(pairs)
-        opts = L.Options(block_elems, block_nodes, _SCATTER[scatter], threads, 0 if pairs else 1)
+        self.chunks = bool(chunks)
+        opts = L.Options(block_elems, block_nodes, _SCATTER[scatter], threads, 0 if pairs else 1,
+                         0 if chunks else 1)
         h = ctypes.c_void_p()
         with torch.cuda.device(self.device):
             self._stream = torch.cuda.current_stream().cuda_stream

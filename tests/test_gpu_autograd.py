@@ -64,6 +64,12 @@ def test_residual_fn_backward_matches_oracle(elem):
     assert rel(lam.grad.cpu().numpy(), vl) <= 1e-10
 
 
+# Nodal sums meet in LDS through FP64 atomics whose order between waves varies
+# from call to call (the C-ABI documents last-bit variation), so a backward
+# pass repeated on the same input agrees to rounding, not bitwise.
+NONDET = 1e-12
+
+
 def test_gradcheck_material_small():
     """torch.autograd.gradcheck (central differences) of EnergyFn and ResidualFn."""
     from paper_2602_12365_amd import Operator, EnergyFn, ResidualFn
@@ -74,9 +80,9 @@ def test_gradcheck_material_small():
     lam = dev(1.5 * np.ones(m.n_elems)).requires_grad_()
     X = op.X.clone().requires_grad_()
     assert torch.autograd.gradcheck(lambda a, b, c: EnergyFn.apply(a, b, c, X, op), (u, mu, lam),
-                                    eps=1e-6, atol=1e-9, rtol=1e-6)
+                                    eps=1e-6, atol=1e-9, rtol=1e-6, nondet_tol=NONDET)
     assert torch.autograd.gradcheck(lambda a, b, c: ResidualFn.apply(a, b, c, op), (u, mu, lam),
-                                    eps=1e-6, atol=1e-9, rtol=1e-6)
+                                    eps=1e-6, atol=1e-9, rtol=1e-6, nondet_tol=NONDET)
 
 
 def test_gradcheck_with_dirichlet_mask():
@@ -93,9 +99,9 @@ def test_gradcheck_with_dirichlet_mask():
     lam = dev(1.5 * np.ones(m.n_elems)).requires_grad_()
     X = op.X.clone().requires_grad_()
     assert torch.autograd.gradcheck(lambda a, b, c: EnergyFn.apply(a, b, c, X, op), (u, mu, lam),
-                                    eps=1e-6, atol=1e-9, rtol=1e-6)
+                                    eps=1e-6, atol=1e-9, rtol=1e-6, nondet_tol=NONDET)
     assert torch.autograd.gradcheck(lambda a, b, c: ResidualFn.apply(a, b, c, op), (u, mu, lam),
-                                    eps=1e-6, atol=1e-9, rtol=1e-6)
+                                    eps=1e-6, atol=1e-9, rtol=1e-6, nondet_tol=NONDET)
     assert op.mask is not None   # the backward passes put the mask back
 
 
