@@ -197,6 +197,18 @@ int efem_set_load(efem_ctx *ctx, const double *f);
  * (see efem_status). */
 int efem_energy(efem_ctx *ctx, const double *u, double *psi);
 
+/* efem_energy for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same kernels and the same result, bitwise, with the per-block partials in a
+ * static device array of 65536 doubles (512 KiB) that each GPU the library
+ * runs on holds until the process ends.  Allocates nothing and calls no
+ * allocating routine.  Returns EFEM_ERR_INVALID if the mesh has more than
+ * 65536 element blocks (efem_get_info n_blocks).  All calls on one GPU share
+ * its array: calls that overlap in time on one GPU (other streams, other
+ * threads or contexts) race and must be ordered by the caller.  Asynchronous
+ * on the context's stream, like efem_energy. */
+int efem_energy_noalloc(efem_ctx *ctx, const double *u, double *psi);
+
 /* r = grad Psi_h(u), Eq. (1): u, r DEVICE float64 [3*n_nodes]. */
 int efem_residual(efem_ctx *ctx, const double *u, double *r);
 

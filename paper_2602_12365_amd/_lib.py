@@ -80,6 +80,7 @@ SIGNATURES = {
     "efem_set_load": (c_int32, [c_void_p, c_void_p]),
     "efem_set_coords": (c_int32, [c_void_p, c_void_p]),
     "efem_energy": (c_int32, [c_void_p, c_void_p, c_void_p]),
+    "efem_energy_noalloc": (c_int32, [c_void_p, c_void_p, c_void_p]),
     "efem_residual": (c_int32, [c_void_p, c_void_p, c_void_p]),
     "efem_linearize": (c_int32, [c_void_p, c_void_p, c_int32]),
     "efem_hvp": (c_int32, [c_void_p, c_void_p, c_void_p]),

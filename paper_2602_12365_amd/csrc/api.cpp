@@ -585,6 +585,15 @@ int efem_create(efem_ctx **out, int32_t elem, int64_t n_nodes, int64_t n_elems,
                                                     : Scatter::Halo;
     ctx->threads = threads;
     (void)hipGetDevice(&ctx->device);
+    {
+        // the no-allocation energy's device array, addressed once per device
+        const hipError_t e = noalloc_setup(ctx->device);
+        if (e != hipSuccess) {
+            const int rc0 = hip_fail(e, "efem_create: hipGetSymbolAddress of the static partials");
+            delete ctx;
+            return rc0;
+        }
+    }
 
     ctx->conn_host.assign(conn, conn + n_elems * nen);
     HostBlocks hb;
@@ -855,6 +864,20 @@ int efem_energy(efem_ctx *ctx, const double *u, double *psi)
     NEEDS_ENERGY("efem_energy");
     DeviceGuard dg(ctx->device);
     HIP_TRY(launch_energy(*ctx, u, psi));
+    return EFEM_OK;
+}
+
+int efem_energy_noalloc(efem_ctx *ctx, const double *u, double *psi)
+{
+    CHECK_ARGS(u && psi, "efem_energy_noalloc");
+    NEEDS_ENERGY("efem_energy_noalloc");
+    if (ctx->m.n_blocks > kNoAllocBlocks) {
+        set_error("efem_energy_noalloc: " + std::to_string(ctx->m.n_blocks) + " element blocks exceed the " +
+                  std::to_string(kNoAllocBlocks) + " partials of the static array");
+        return EFEM_ERR_INVALID;
+    }
+    DeviceGuard dg(ctx->device);
+    HIP_TRY(launch_energy_noalloc(*ctx, u, psi));
     return EFEM_OK;
 }
 

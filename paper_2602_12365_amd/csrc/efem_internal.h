@@ -90,6 +90,13 @@ struct Ctx;
 // ---- kernel launchers (kernels_*.hip) -------------------------------------
 // All return hipError_t of the launch.  T = double or float.
 hipError_t launch_energy(const Ctx &c, const double *u, double *psi);
+// The energy with its per-block partials in a file-scope device array of
+// kNoAllocBlocks doubles (no allocation).  noalloc_setup(device) takes the
+// array's device address once per device, with that device current; the
+// launch returns hipErrorNotInitialized if it has not run for c.device.
+constexpr int kNoAllocBlocks = 1 << 16;
+hipError_t noalloc_setup(int device);
+hipError_t launch_energy_noalloc(const Ctx &c, const double *u, double *psi);
 hipError_t launch_residual(const Ctx &c, const double *u, double *r);
 // How a nodal output is written:
 //   Overwrite:  y = K v (halo scatter: block pass, then the gather of shared

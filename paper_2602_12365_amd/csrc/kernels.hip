@@ -21,6 +21,8 @@
 //   Q = w [ mu/De dJ S + lam De tr(Ad dJ)/Dd^2 Ad^T + c1 De/Dd^2 (Ad dJ Ad)^T ],
 // which is w det Jx dP Jx^-T with dP = mu dF + lam tr(F^-1 dF) F^-T
 // + c1 F^-T dF^T F^-T, F = Jd Jx^-1, dF = dJ Jx^-1.
+#include <mutex>
+
 #include "efem_internal.h"
 
 namespace efem {
@@ -2305,21 +2307,69 @@ hipError_t launch_hvp_f32(const Ctx &c, const float *ulin, const float *v, float
 }
 
 template <class E, bool LIN>
-static void energy_pass(const Ctx &c, const double *u, size_t lds)
+static void energy_pass(const Ctx &c, const double *u, size_t lds, double *partials)
 {
     hipLaunchKernelGGL((k_energy<E, LIN>), dim3(c.m.n_blocks), dim3(256), lds, c.stream, c.m, c.m.X, u,
-                       c.partials);
+                       partials);
+}
+
+// The energy's two launches with the per-block partials in `partials`.
+static hipError_t energy_into(const Ctx &c, const double *u, double *psi, double *partials)
+{
+    const size_t lds = sizeof(NodeXU) * (size_t)c.max_block_nodes;
+    const bool lin = c.model == EFEM_MODEL_LINEAR;
+    if (c.elem == EFEM_TET4)
+        lin ? energy_pass<Tet4Pair, true>(c, u, lds, partials) : energy_pass<Tet4Pair, false>(c, u, lds, partials);
+    else if (c.elem == EFEM_TRI3)
+        lin ? energy_pass<Tri3, true>(c, u, lds, partials) : energy_pass<Tri3, false>(c, u, lds, partials);
+    else lin ? energy_pass<Hex8, true>(c, u, lds, partials) : energy_pass<Hex8, false>(c, u, lds, partials);
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, c.stream, partials, c.m.n_blocks, psi);
+    return hipGetLastError();
 }
 
 hipError_t launch_energy(const Ctx &c, const double *u, double *psi)
 {
-    const size_t lds = sizeof(NodeXU) * (size_t)c.max_block_nodes;
-    const bool lin = c.model == EFEM_MODEL_LINEAR;
-    if (c.elem == EFEM_TET4) lin ? energy_pass<Tet4Pair, true>(c, u, lds) : energy_pass<Tet4Pair, false>(c, u, lds);
-    else if (c.elem == EFEM_TRI3) lin ? energy_pass<Tri3, true>(c, u, lds) : energy_pass<Tri3, false>(c, u, lds);
-    else lin ? energy_pass<Hex8, true>(c, u, lds) : energy_pass<Hex8, false>(c, u, lds);
-    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, c.stream, c.partials, c.m.n_blocks, psi);
-    return hipGetLastError();
+    return energy_into(c, u, psi, c.partials);
+}
+
+// ---------------------------------------------- energy without allocation
+
+// The per-block energy partials of efem_energy_noalloc live in this array, one
+// copy per GPU for the life of the process.  In host code `scratch` names a
+// host-side stand-in, never the device memory: the device address comes from
+// hipGetSymbolAddress, taken once per device with that device current, and
+// only that address is ever handed to a kernel.
+static __device__ __align__(256) double scratch[kNoAllocBlocks];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+double *g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t noalloc_setup(int device)
+{
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mutex);
+    if (g_scratch_ptr[device]) return hipSuccess;
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));   // the caller made `device` current
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[device] = static_cast<double *>(p);
+    return hipSuccess;
+}
+
+hipError_t launch_energy_noalloc(const Ctx &c, const double *u, double *psi)
+{
+    double *p = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_scratch_mutex);
+        if (c.device >= 0 && c.device < kMaxDevices) p = g_scratch_ptr[c.device];
+    }
+    if (!p) return hipErrorNotInitialized;
+    // every partial is written by its block before k_sum_partials reads it,
+    // so the array needs no clearing between calls
+    return energy_into(c, u, psi, p);
 }
 
 template <class E, bool LIN>
