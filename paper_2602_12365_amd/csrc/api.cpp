@@ -479,23 +479,50 @@ static bool build_chunks(const HostBlocks &hb, int64_t nn, int n_cu, HostChunks 
     }
 }
 
-// Halo entries of the shared nodes: entry i (in block or chunk order) of a
-// shared node gets the next slot of that node, so a node's slots are
-// consecutive and in order.
+// Halo layout of the shared nodes (HaloSegs): each node's entries take
+// consecutive slots in entry order (block or chunk order), nodes grouped by
+// entry count.  hslot[i] is the slot of entry i (-1 for unshared entries);
+// order lists the shared nodes in gather order; gptr the slot ranges of the
+// nodes with more than kSegMax entries.
 static void halo_layout(const std::vector<uint32_t> &entries, const std::vector<int32_t> &shared, int64_t nn,
-                        std::vector<int32_t> &hptr, std::vector<int32_t> &hslot)
+                        HaloSegs &seg, std::vector<int32_t> &order, std::vector<int32_t> &gptr,
+                        std::vector<int32_t> &hslot)
 {
     const int32_t ns = (int32_t)shared.size();
-    std::vector<int32_t> slot((size_t)nn, -1);
-    for (int32_t s = 0; s < ns; ++s) slot[(size_t)shared[(size_t)s]] = s;
-    hptr.assign((size_t)ns + 1, 0);
+    std::vector<int32_t> cnt((size_t)nn, 0);
     for (uint32_t ent : entries)
-        if (ent & kShared) hptr[(size_t)slot[ent & kGidMask] + 1] += 1;
-    for (int32_t s = 0; s < ns; ++s) hptr[(size_t)s + 1] += hptr[(size_t)s];
+        if (ent & kShared) cnt[ent & kGidMask] += 1;
+    auto group = [](int c) { return c <= kSegMax ? c : kSegMax + 1; };
+    // shared-node order: by group, then by node id
+    order.clear();
+    for (int gidx = 2; gidx <= kSegMax + 1; ++gidx) {
+        seg.start[gidx] = (int32_t)order.size();
+        for (int32_t g : shared)
+            if (group(cnt[(size_t)g]) == gidx) order.push_back(g);
+    }
+    seg.start[0] = seg.start[1] = 0;
+    seg.n = ns;
+    // first slot of each shared node
+    std::vector<int32_t> first((size_t)nn, -1);
+    int32_t slot = 0;
+    for (int c = 2; c <= kSegMax; ++c) {
+        seg.base[c] = slot;
+        for (int32_t i = seg.start[c]; i < (c < kSegMax ? seg.start[c + 1] : seg.start[kSegMax + 1]); ++i) {
+            first[(size_t)order[(size_t)i]] = slot;
+            slot += c;
+        }
+    }
+    seg.base[0] = seg.base[1] = 0;
+    gptr.assign(1, slot);
+    for (int32_t i = seg.start[kSegMax + 1]; i < ns; ++i) {
+        const int32_t g = order[(size_t)i];
+        first[(size_t)g] = slot;
+        slot += cnt[(size_t)g];
+        gptr.push_back(slot);
+    }
     hslot.assign(entries.size(), -1);
-    std::vector<int32_t> fill(hptr.begin(), hptr.end() - 1);
     for (size_t i = 0; i < entries.size(); ++i)
-        if (entries[i] & kShared) hslot[i] = fill[(size_t)slot[entries[i] & kGidMask]]++;
+        if (entries[i] & kShared) hslot[i] = first[entries[i] & kGidMask]++;
 }
 
 }  // namespace efem
@@ -634,13 +661,12 @@ int efem_create(efem_ctx **out, int32_t elem, int64_t n_nodes, int64_t n_elems,
     m.hslot = nullptr;
     if (ctx->scatter == Scatter::Halo && ctx->n_shared > 0) {
         // each shared node's block-node entries, in block order
-        std::vector<int32_t> hptr, hslot;
-        halo_layout(hb.bnode, hb.shared_nodes, n_nodes, hptr, hslot);
+        std::vector<int32_t> order, gptr, hslot;
+        halo_layout(hb.bnode, hb.shared_nodes, n_nodes, ctx->halo.seg, order, gptr, hslot);
         double *p_h;
         int32_t *p_hs;
-        if ((rc = upload(*ctx, &ctx->halo_ptr, hptr)) || (rc = upload(*ctx, &p_hs, hslot))
-            || (rc = upload(*ctx, &ctx->halo_node, hb.shared_nodes))
-            || (rc = dalloc(*ctx, &p_h, 3 * (size_t)hptr.back())))
+        if ((rc = upload(*ctx, &ctx->halo.gptr, gptr)) || (rc = upload(*ctx, &p_hs, hslot))
+            || (rc = upload(*ctx, &ctx->halo.node, order)) || (rc = dalloc(*ctx, &p_h, 3 * (size_t)gptr.back())))
             return fail(rc);
         m.halo = p_h;
         m.hslot = p_hs;
@@ -658,12 +684,25 @@ int efem_create(efem_ctx **out, int32_t elem, int64_t n_nodes, int64_t n_elems,
         ctx->max_chunk_slots = hc.max_slots;
         ctx->n_chunk_slots = (int64_t)hc.cnode.size();
         ctx->n_ch_shared = (int64_t)hc.shared_nodes.size();
-        int32_t *p_bs, *p_ss, *p_hs = nullptr;
+        int32_t *p_bs, *p_ss, *p_hs = nullptr, *p_hd;
         uint32_t *p_bw, *p_cn, *p_it;
+        std::vector<int32_t> hdr((size_t)ch.n_chunks * 8, 0);
+        for (int c = 0; c < ch.n_chunks; ++c) {
+            const int b0 = hc.bstart[(size_t)c], b1 = hc.bstart[(size_t)c + 1];
+            int32_t *h = &hdr[(size_t)c * 8];
+            h[0] = b0;
+            h[1] = b1 - b0;
+            h[2] = hc.sstart[(size_t)c];
+            h[3] = hc.sstart[(size_t)c + 1] - hc.sstart[(size_t)c];
+            h[4] = hb.istart[(size_t)b0];
+            h[5] = hb.istart[(size_t)b0 + 1] - hb.istart[(size_t)b0];
+            h[6] = b1 - b0 > 1 ? (int32_t)hc.bnew[(size_t)b0 + 1] : 0;
+        }
         if ((rc = upload(*ctx, &p_bs, hc.bstart)) || (rc = upload(*ctx, &p_ss, hc.sstart))
             || (rc = upload(*ctx, &p_bw, hc.bnew)) || (rc = upload(*ctx, &p_cn, hc.cnode))
-            || (rc = upload(*ctx, &p_it, hc.items)))
+            || (rc = upload(*ctx, &p_it, hc.items)) || (rc = upload(*ctx, &p_hd, hdr)))
             return fail(rc);
+        ch.hdr = reinterpret_cast<const int4 *>(p_hd);
         ch.bstart = p_bs;
         ch.sstart = p_ss;
         ch.bnew = p_bw;
@@ -671,12 +710,11 @@ int efem_create(efem_ctx **out, int32_t elem, int64_t n_nodes, int64_t n_elems,
         ch.items = p_it;
         ch.halo = nullptr;
         if (ctx->n_ch_shared > 0) {
-            std::vector<int32_t> hptr, hslot;
-            halo_layout(hc.cnode, hc.shared_nodes, n_nodes, hptr, hslot);
+            std::vector<int32_t> order, gptr, hslot;
+            halo_layout(hc.cnode, hc.shared_nodes, n_nodes, ctx->ch_halo.seg, order, gptr, hslot);
             double *p_h;
-            if ((rc = upload(*ctx, &ctx->ch_halo_ptr, hptr)) || (rc = upload(*ctx, &p_hs, hslot))
-                || (rc = upload(*ctx, &ctx->ch_halo_node, hc.shared_nodes))
-                || (rc = dalloc(*ctx, &p_h, 3 * (size_t)hptr.back())))
+            if ((rc = upload(*ctx, &ctx->ch_halo.gptr, gptr)) || (rc = upload(*ctx, &p_hs, hslot))
+                || (rc = upload(*ctx, &ctx->ch_halo.node, order)) || (rc = dalloc(*ctx, &p_h, 3 * (size_t)gptr.back())))
                 return fail(rc);
             ch.halo = p_h;
         } else {
@@ -684,7 +722,9 @@ int efem_create(efem_ctx **out, int32_t elem, int64_t n_nodes, int64_t n_elems,
             if ((rc = upload(*ctx, &p_hs, none))) return fail(rc);
         }
         ch.hslot = p_hs;
-        if ((rc = dalloc(*ctx, &ch.cword, hc.cnode.size()))) return fail(rc);
+        if ((rc = dalloc(*ctx, &ch.cword, hc.cnode.size()))
+            || (rc = dalloc(*ctx, &ch.cword0, (size_t)ch.n_chunks * kChunkThreads)))
+            return fail(rc);
     }
 
     // default material mu = 1, lam = 1.5
@@ -1011,6 +1051,7 @@ int efem_get_info(efem_ctx *ctx, efem_info *info)
     info->max_chunk_slots = ctx->max_chunk_slots;
     info->n_chunk_slots = ctx->n_chunk_slots;
     info->n_chunk_shared_nodes = ctx->n_ch_shared;
+
     return EFEM_OK;
 }
 

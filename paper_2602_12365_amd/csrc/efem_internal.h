@@ -66,10 +66,32 @@ struct ChunkMesh {
     const uint32_t *bnew;     // [n_blocks] chunk-relative new-slot range of each block
     const uint32_t *cnode;    // slot -> global id | kShared
     uint32_t *cword;          // slot -> staging word (global id | Dirichlet bits << 28)
+    uint32_t *cword0;         // [n_chunks * kChunkThreads] the first block's staging words,
+                              // indexed by chunk and thread (no load of sstart in front)
+    const int4 *hdr;          // [2 * n_chunks] per chunk: {b0, nsteps, s0, ns},
+                              // {istart[b0], items of block b0, bnew[b0 + 1] (0 if none), 0}
     const uint32_t *items;    // chunk-slot connectivity, 2 words per item, 11-bit ids:
                               // a | b<<11 | (d1 & 1023)<<22,  c | d2<<11 | (d1 >> 10)<<22
     const int32_t *hslot;     // [slots] halo entry of a shared slot, else -1
     double *halo;             // [3 * entries]
+};
+
+// Halo entries of the shared nodes, grouped by how many blocks (or chunks)
+// share a node: the nodes with c entries, c = 2 .. kSegMax, form segment c, in
+// which node p's entries are the c consecutive slots base[c] + c p + k.  So a
+// gather thread finds its slots from its own index, with no load in front.
+// Nodes with more entries come last and use a slot-range array (gptr).
+constexpr int kSegMax = 16;
+struct HaloSegs {
+    int32_t start[kSegMax + 2];   // start[c]: first shared-node index of segment c
+                                  // (c = 2 .. kSegMax); start[kSegMax + 1] = the others
+    int32_t base[kSegMax + 1];    // base[c]: first slot of segment c
+    int32_t n;                    // shared nodes
+};
+struct HaloMap {
+    HaloSegs seg{};
+    int32_t *gptr = nullptr;      // [others + 1] slot ranges of the nodes past the segments
+    int32_t *node = nullptr;      // [n] global node id of shared node i
 };
 
 // How block sums reach nodes shared between blocks:
@@ -142,18 +164,18 @@ struct Ctx {
     int max_block_elems = 0;
     // chunk pass of the FP64 Tet4 tangent action (n_chunks = 0: block pass only)
     ChunkMesh ch{};
+    HaloMap ch_halo;                  // gather of the chunk pass's shared nodes
     int64_t n_ch_shared = 0;          // nodes in more than one chunk
     int64_t n_chunk_slots = 0;        // sum over chunks of distinct nodes
     int max_chunk_slots = 0;
-    int32_t *ch_halo_ptr = nullptr, *ch_halo_node = nullptr;
 
     // device buffers owned by the context
     BlockMesh m{};
     std::vector<void *> owned;      // every hipMalloc of the context
     int64_t n_shared = 0;               // nodes touched by several blocks
-    // halo scatter: shared node i = halo_node[i] sums the halo entries
-    // halo_ptr[i] .. halo_ptr[i+1]-1 (its blocks in block order)
-    int32_t *halo_ptr = nullptr, *halo_node = nullptr;
+    // halo scatter: shared node i = halo.node[i] sums its halo entries (its
+    // blocks in block order)
+    HaloMap halo;
     std::vector<Pass> passes;           // colour lists (Color) or one pass (Atomic)
     double *partials = nullptr;         // [n_blocks] per-block energy partials
     uint32_t *counter = nullptr;        // last-block-done ticket

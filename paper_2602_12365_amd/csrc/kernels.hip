@@ -1576,6 +1576,7 @@ template <> struct MinWaves<Tet4Pair, HvpOp<double>> {
     static constexpr int value = EFEM_TET64_MIN_WAVES;
 };
 
+
 template <class E, class Op, class T, bool ACC>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MinWaves<E, Op>::value, 8)))
 k_accumulate(BlockMesh m, Op op, T *__restrict__ y,
@@ -1639,13 +1640,83 @@ k_accumulate(BlockMesh m, Op op, T *__restrict__ y,
                    reinterpret_cast<T *>(m.halo), m.hslot ? m.hslot + n0 : nullptr);
 }
 
-// Second half of the halo scatter: shared node i = node[i] sums its slots
-// halo[ptr[i] .. ptr[i+1]-1] (its blocks in block order; in FP64, so the
-// result does not depend on the schedule), then y = sum (ACC: y += sum);
-// prescribed components get fixed_val.  Consecutive nodes own consecutive
-// slots, so the reads stream.
-template <class T, bool ACC>
-__global__ void __launch_bounds__(256) k_halo_gather(int32_t n, const int32_t *__restrict__ ptr,
+// Second half of the halo scatter: shared node i = node[i] sums its halo
+// slots (its blocks or chunks in order; in FP64, so the result does not depend
+// on the schedule), then y = sum (ACC: y += sum); prescribed components get
+// fixed_val.  The slots of a node in segment c of the layout follow from the
+// thread's index, so the slot loads, the node id and the node's Dirichlet bits
+// are all one memory latency away (nodes past the segments read their range
+// first).  MASK: a Dirichlet mask is in force (a template flag, so that the
+// mask's load is not behind a branch whose merge would wait for it).
+// s += the N slots at p, in order (all loads before the first add)
+template <int N, class T>
+__device__ __forceinline__ void halo_sum(const T *__restrict__ p, double s[3])
+{
+    T h[N][3];
+#pragma unroll
+    for (int k = 0; k < N; ++k) h[k][0] = p[3 * k], h[k][1] = p[3 * k + 1], h[k][2] = p[3 * k + 2];
+#pragma unroll
+    for (int k = 0; k < N; ++k)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) s[c] += (double)h[k][c];
+}
+
+// Shared node i of the halo layout: its slots summed in order, written to y.
+template <class T, bool ACC, bool MASK>
+__device__ __forceinline__ void gather_node(const HaloSegs &seg, const int32_t *__restrict__ gptr,
+                                            const int32_t *__restrict__ node, const T *__restrict__ halo,
+                                            T *__restrict__ y, const uint8_t *__restrict__ nmask, T fixed_val,
+                                            int i)
+{
+    int64_t k0, cnt;
+    if (i < seg.start[kSegMax + 1]) {
+        // the segment by selects over constant indices (a dynamic index would
+        // put the kernel-argument arrays behind a memory load)
+        int c = 2, st = seg.start[2], bs = seg.base[2];
+#pragma unroll
+        for (int cc = 3; cc <= kSegMax; ++cc) {
+            int sc = seg.start[cc], bc = seg.base[cc];
+            asm volatile("" : "+s"(sc), "+s"(bc));   // values in scalar registers, not re-read by index
+            const bool in = i >= sc;
+            c = in ? cc : c;
+            st = in ? sc : st;
+            bs = in ? bc : bs;
+        }
+        cnt = c;
+        k0 = bs + (int64_t)c * (i - st);
+    } else {
+        const int j = i - seg.start[kSegMax + 1];
+        k0 = gptr[j];
+        cnt = gptr[j + 1] - k0;
+    }
+    const int64_t g = node[i];
+    const uint8_t b = MASK ? nmask[g] : 0;
+    // exactly cnt slot loads, issued back to back (cnt is the same for the
+    // lanes of a wave but at segment boundaries)
+    double s[3] = {0.0, 0.0, 0.0};
+    switch (cnt) {
+        case 2: halo_sum<2>(halo + 3 * k0, s); break;
+        case 3: halo_sum<3>(halo + 3 * k0, s); break;
+        case 4: halo_sum<4>(halo + 3 * k0, s); break;
+        case 5: halo_sum<5>(halo + 3 * k0, s); break;
+        case 6: halo_sum<6>(halo + 3 * k0, s); break;
+        case 7: halo_sum<7>(halo + 3 * k0, s); break;
+        case 8: halo_sum<8>(halo + 3 * k0, s); break;
+        default:
+            for (int64_t k = 0; k < cnt; ++k)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) s[c] += (double)halo[3 * (k0 + k) + c];
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        T *dst = &y[3 * g + c];
+        if ((b >> c) & 1) *dst = fixed_val;
+        else *dst = ACC ? *dst + T(s[c]) : T(s[c]);
+    }
+}
+
+template <class T, bool ACC, bool MASK>
+__global__ void __launch_bounds__(256) k_halo_gather(HaloSegs seg, const int32_t *__restrict__ gptr,
                                                      const int32_t *__restrict__ node,
                                                      const T *__restrict__ halo, T *__restrict__ y,
                                                      const uint8_t *__restrict__ nmask, T fixed_val,
@@ -1653,22 +1724,7 @@ __global__ void __launch_bounds__(256) k_halo_gather(int32_t n, const int32_t *_
 {
     if (skip && *skip) return;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const int64_t g = node[i];
-    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-    for (int64_t k = ptr[i], ke = ptr[i + 1]; k < ke; ++k) {
-        s0 += (double)halo[3 * k + 0];
-        s1 += (double)halo[3 * k + 1];
-        s2 += (double)halo[3 * k + 2];
-    }
-    const uint8_t b = nmask ? nmask[g] : 0;
-    const double s[3] = {s0, s1, s2};
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        T *dst = &y[3 * g + c];
-        if ((b >> c) & 1) *dst = fixed_val;
-        else *dst = ACC ? *dst + T(s[c]) : T(s[c]);
-    }
+    if (i < seg.n) gather_node<T, ACC, MASK>(seg, gptr, node, halo, y, nmask, fixed_val, i);
 }
 
 // y = 0, prescribed components = fixed_val, before an atomic pass adds into
@@ -1775,8 +1831,17 @@ k_chunk_hvp64(BlockMesh m, ChunkMesh ch, const double *__restrict__ xrec, const 
     if (skip && *skip) return;
     constexpr int W = kChunkThreads / 64;
     const int c = xcd_remap(blockIdx.x, ch.n_chunks);
-    const int b0 = ch.bstart[c], nsteps = ch.bstart[c + 1] - b0;
-    const int s0 = ch.sstart[c], ns = ch.sstart[c + 1] - s0;
+    // Step 0 first: thread t stages slot t from a word indexed by chunk and
+    // thread, read beside the chunk's header (scalar loads), so the record
+    // loads wait for one memory latency only.  Everything else the first step
+    // needs arrives while they are in flight, through LDS or in registers: a
+    // vector load waited for here would also wait for the records.
+    const uint32_t word0 = ch.cword0[(int64_t)c * kChunkThreads + threadIdx.x];
+    const int4 h0 = ch.hdr[2 * c], h1 = ch.hdr[2 * c + 1];
+    const int l0 = word0 != 0xffffffffu ? (int)threadIdx.x : -1;
+    chunk_stage_records(smem, xrec, v, l0, word0);
+
+    const int b0 = h0.x, nsteps = h0.y, s0 = h0.z, ns = h0.w;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     double *acc = reinterpret_cast<double *>(smem + 5 * kPieceBytes);
     // this wave's staging words: those of the step after next arrive with
@@ -1789,31 +1854,22 @@ k_chunk_hvp64(BlockMesh m, ChunkMesh ch, const double *__restrict__ xrec, const 
     int32_t *t_estart = t_istart + kChunkSteps + 1;
     uint32_t *t_bnew = reinterpret_cast<uint32_t *>(t_estart + kChunkSteps + 1);
     const uint32_t *cword = ch.cword + s0;
-    for (int i = threadIdx.x; i < 3 * ns; i += kChunkThreads) acc[i] = 0.0;
-    if (threadIdx.x <= nsteps) {
-        t_istart[threadIdx.x] = m.istart[b0 + threadIdx.x];
-        t_estart[threadIdx.x] = m.estart[b0 + threadIdx.x];
-        if (threadIdx.x < nsteps) t_bnew[threadIdx.x] = ch.bnew[b0 + threadIdx.x];
-    }
-
     // the items of a step: lane L of wave w takes item L * W + w, so the
     // lanes of one LDS atomic are W items apart in Morton order
     const int k = lane * W + wave;
-
-    // step 0: records staged before the loop from directly read words; the
-    // words of step 1 follow into LDS
-    const int l0 = chunk_stage_slot(ch.bnew[b0], wave, lane);
-    const uint32_t word0 = l0 >= 0 ? cword[l0] : 0u;
-    chunk_stage_records(smem, xrec, v, l0, word0);
+    uint2 itw = make_uint2(0u, 0u);
+    if (k < h1.y) itw = *reinterpret_cast<const uint2 *>(ch.items + 2 * (int64_t)(h1.x + k));
     if (nsteps > 1) {
-        const int l1 = chunk_stage_slot(ch.bnew[b0 + 1], wave, lane);
+        const int l1 = chunk_stage_slot((uint32_t)h1.z, wave, lane);
         if (l1 >= 0) load_to_lds4(cword + l1, wdst);
     }
-    uint2 itw = make_uint2(0u, 0u);
-    {
-        const int i0 = m.istart[b0];
-        if (k < m.istart[b0 + 1] - i0) itw = *reinterpret_cast<const uint2 *>(ch.items + 2 * (int64_t)(i0 + k));
+    // the block table (nsteps + 1 <= 64 entries) by wave 0 with LDS loads
+    if (wave == 0 && lane <= nsteps) {
+        load_to_lds4(m.istart + b0 + lane, __builtin_amdgcn_readfirstlane(lds_addr(t_istart)));
+        load_to_lds4(m.estart + b0 + lane, __builtin_amdgcn_readfirstlane(lds_addr(t_estart)));
     }
+    if (wave == 0 && lane < nsteps) load_to_lds4(ch.bnew + b0 + lane, __builtin_amdgcn_readfirstlane(lds_addr(t_bnew)));
+    for (int i = threadIdx.x; i < 3 * ns; i += kChunkThreads) acc[i] = 0.0;
     wait_vm_loads();
     chunk_stage_mask(m, smem, l0, word0);
     __syncthreads();
@@ -2146,6 +2202,17 @@ static size_t lds_bytes(const Ctx &c, size_t acc_elem)
     return (sizeof(typename Op::Node) + 3 * acc_elem + sizeof(uint32_t)) * (size_t)c.max_block_nodes;
 }
 
+template <class T>
+static void launch_gather(const Ctx &c, bool acc, const HaloMap &hm, const T *halo, T *y, const uint8_t *mask,
+                          T fixed_val, const int32_t *skip)
+{
+    const unsigned gb = (unsigned)((hm.seg.n + 255) / 256);
+    auto kern = acc ? (mask ? k_halo_gather<T, true, true> : k_halo_gather<T, true, false>)
+                    : (mask ? k_halo_gather<T, false, true> : k_halo_gather<T, false, false>);
+    hipLaunchKernelGGL(kern, dim3(gb), dim3(256), 0, c.stream, hm.seg, hm.gptr, hm.node, halo, y, mask, fixed_val,
+                       skip);
+}
+
 // The chunk pass of the FP64 Tet4 tangent action, then the gather of the
 // nodes that several chunks share.
 static hipError_t run_chunks(const Ctx &c, const HvpOp<double> &op, double *y, bool use_mask,
@@ -2157,17 +2224,8 @@ static hipError_t run_chunks(const Ctx &c, const HvpOp<double> &op, double *y, b
                     : (uni ? k_chunk_hvp64<false, true> : k_chunk_hvp64<false, false>);
     hipLaunchKernelGGL(kern, dim3(c.ch.n_chunks), dim3(kChunkThreads), 0, c.stream, c.m, c.ch, op.xrec, op.v, y,
                        use_mask ? 1 : 0, 0.0, skip);
-    if (c.n_ch_shared > 0) {
-        const unsigned gb = (unsigned)((c.n_ch_shared + 255) / 256);
-        if (acc)
-            hipLaunchKernelGGL((k_halo_gather<double, true>), dim3(gb), dim3(256), 0, c.stream,
-                               (int32_t)c.n_ch_shared, c.ch_halo_ptr, c.ch_halo_node, c.ch.halo, y, gmask,
-                               0.0, skip);
-        else
-            hipLaunchKernelGGL((k_halo_gather<double, false>), dim3(gb), dim3(256), 0, c.stream,
-                               (int32_t)c.n_ch_shared, c.ch_halo_ptr, c.ch_halo_node, c.ch.halo, y, gmask,
-                               0.0, skip);
-    }
+    if (c.n_ch_shared > 0)
+        launch_gather<double>(c, acc, c.ch_halo, c.ch.halo, y, gmask, 0.0, skip);
     return hipGetLastError();
 }
 
@@ -2179,7 +2237,6 @@ static hipError_t run_accumulate(const Ctx &c, const Op &op, T *y, bool use_mask
         if (c.ch.n_chunks > 0 && c.scatter == Scatter::Halo) return run_chunks(c, op, y, use_mask, skip, mode);
     const size_t lds = lds_bytes<Op>(c, sizeof(double));
     const bool halo = c.scatter == Scatter::Halo && c.n_shared > 0;
-    const unsigned gather_blocks = (unsigned)((c.n_shared + 255) / 256);
     const uint8_t *gmask = use_mask ? c.m.nmask : nullptr;
     if (mode == WriteMode::Accumulate) {
         for (const Pass &p : c.passes) {
@@ -2189,9 +2246,7 @@ static hipError_t run_accumulate(const Ctx &c, const Op &op, T *y, bool use_mask
                                fixed_val, skip);
         }
         if (halo)
-            hipLaunchKernelGGL((k_halo_gather<T, true>), dim3(gather_blocks), dim3(256), 0, c.stream,
-                               (int32_t)c.n_shared, c.halo_ptr, c.halo_node,
-                               reinterpret_cast<const T *>(c.m.halo), y, gmask, fixed_val, skip);
+            launch_gather<T>(c, true, c.halo, reinterpret_cast<const T *>(c.m.halo), y, gmask, fixed_val, skip);
         return hipGetLastError();
     }
     if (mode == WriteMode::Overwrite && c.scatter == Scatter::Atomic && c.n_shared > 0) {
@@ -2206,9 +2261,7 @@ static hipError_t run_accumulate(const Ctx &c, const Op &op, T *y, bool use_mask
                            skip);
     }
     if (halo)
-        hipLaunchKernelGGL((k_halo_gather<T, false>), dim3(gather_blocks), dim3(256), 0, c.stream,
-                           (int32_t)c.n_shared, c.halo_ptr, c.halo_node,
-                           reinterpret_cast<const T *>(c.m.halo), y, gmask, fixed_val, skip);
+        launch_gather<T>(c, false, c.halo, reinterpret_cast<const T *>(c.m.halo), y, gmask, fixed_val, skip);
     return hipGetLastError();
 }
 

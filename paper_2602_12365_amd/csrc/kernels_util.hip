@@ -87,10 +87,29 @@ __global__ void k_chunk_words(int64_t n, const uint32_t *__restrict__ cnode, con
     }
 }
 
+// the same words for the first block of every chunk, by (chunk, thread):
+// thread t of chunk c stages slot t of the chunk if t is below the block's
+// new-slot end, else its word is all ones (node ids stay below 2^28)
+__global__ void k_chunk_words0(ChunkMesh ch, const uint8_t *__restrict__ nmask)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= (int64_t)ch.n_chunks * kChunkThreads) return;
+    const int c = (int)(i / kChunkThreads), t = (int)(i % kChunkThreads);
+    const int hi = (int)(ch.bnew[ch.bstart[c]] >> 16);
+    uint32_t w = 0xffffffffu;   // no slot for this thread
+    if (t < hi) {
+        const uint32_t g = ch.cnode[ch.sstart[c] + t] & kStageGid;
+        w = g | (nmask ? (uint32_t)(nmask[g] & 7u) << 28 : 0u);
+    }
+    ch.cword0[i] = w;
+}
+
 hipError_t launch_chunk_words(const Ctx &c)
 {
     hipLaunchKernelGGL(k_chunk_words, dim3(grid_for(c.n_chunk_slots)), dim3(256), 0, c.stream, c.n_chunk_slots,
                        c.ch.cnode, c.m.nmask, c.ch.cword);
+    hipLaunchKernelGGL(k_chunk_words0, dim3(grid_for((int64_t)c.ch.n_chunks * kChunkThreads)), dim3(256), 0,
+                       c.stream, c.ch, c.m.nmask);
     return hipGetLastError();
 }
 
