@@ -10,9 +10,11 @@ DOF/s of the tangent action over the timed steps.
 Beside it: the FP32 tangent action, the colour and atomic scatters, energy
 and residual times, the same operators under the small-strain linear model,
 the non-variational transport operator with a GMRES solve, the 2D Tri3
-plane-strain tangent action (1024^2 cells), a roofline object for the dominant kernel (the FP64
-tangent action's block pass with its halo gather, timed with HIP events on
-its stream), the Newton
+plane-strain tangent action (1024^2 cells), the Hex8 tangent action of the
+96^3 and 128^3 compression meshes (FP64 and FP32, %VALU and %HBM), a roofline
+object for the dominant kernel (the FP64 tangent action's chunk pass with its
+halo gather, over the step's 100 directions, timed with HIP events on its
+stream), the Newton
 solves of the metric's second half (plain FP64 Jacobi-CG vs FP32 tangent
 actions with and without the learned preconditioner, on the 128^3 Q1-hex
 compression case and on the unseen 96^3 test mesh of the preconditioner,
@@ -44,6 +46,11 @@ N_DIRS = 100
 # reciprocals, ln J), W = Ad dJ 45, trace and coefficients 5, dJ S 45,
 # W Ad 45, Q 45, the fourth node's force 6, the scatter adds 12.
 FLOPS_PER_TET_HVP = 335
+# One Hex8 tangent action (2x2x2 Gauss, node form): per Gauss point the three
+# reference gradients 3 x 9 x 8 FMAs (432), the point's tangent action as
+# for a tetrahedron without its gradients and forces (290) and the forces on
+# the 8 nodes 8 x 3 x 3 FMAs (144): 866 per point, 6,928 per hexahedron.
+FLOPS_PER_HEX_HVP = 8 * 866
 
 
 def log(msg):
@@ -200,9 +207,10 @@ def compression_solves(dev, n, seed, theta):
 
 def kernels_mode(args, dev):
     """Fixed kernel workload for rocprofv3 (no timing logic): the FP64 and FP32
-    tangent actions (block pass + halo gather) on the 64^3 Kuhn mesh, energy,
-    residual, and a
-    plain 256 MiB device copy of known size that calibrates the HBM counters."""
+    tangent actions (chunk pass + halo gather) on the 64^3 Kuhn mesh, energy,
+    residual, and a plain 256 MiB device copy of known size that calibrates
+    the HBM counters.  --flush: a 512 MiB fill before every FP64 tangent
+    action, so that its counters see the 256 MB Infinity Cache cold."""
     import torch
     from paper_2602_12365_amd import Operator, inputs as I
     mesh = I.tet_mesh(args.n)
@@ -211,8 +219,12 @@ def kernels_mode(args, dev):
     y = torch.zeros_like(u)
     op = Operator(I.TET4, mesh.X, mesh.conn, device=dev)
     op.linearize(u, "f64")
+    flush = torch.empty(512 << 20, dtype=torch.uint8, device=dev) if args.flush else None
     for _ in range(args.steps):
+        if flush is not None:
+            flush.fill_(1)
         op.hvp_zeroed(v, y)
+    del flush
     op.linearize(u, "f32")
     v32, y32 = v.float(), torch.zeros_like(v, dtype=torch.float32)
     for _ in range(args.steps):
@@ -227,6 +239,51 @@ def kernels_mode(args, dev):
         b.copy_(a)
     torch.cuda.synchronize()
     log("kernels mode done")
+
+
+def hex8_section(args, dev, stream):
+    """The Hex8 tangent action (Q1, 2x2x2 Gauss) of the compression meshes:
+    96^3 (mu lognormal(0, 0.5) seed 2000, the preconditioner's test mesh) and
+    128^3 (seed 3), lam = 1.5 mu, at u = 0.01 (8/n) N(0,1): FP64 and FP32 per
+    call over 20 distinct directions, with %HBM of the algorithmic bytes
+    (connectivity 32 B/hex, mu and lam 16 B/hex, X, x and v read and y written
+    per node) and %VALU of the counted FP64 operations (FLOPS_PER_HEX_HVP)
+    against the 78.6 TFLOP/s vector peak."""
+    import torch
+    from paper_2602_12365_amd import Operator, inputs as I
+    res = {"flops_per_hex": FLOPS_PER_HEX_HVP,
+           "note": "%VALU = counted FP64 operations / time / 78.6 TFLOP/s (FP32 without packed math has the same issue rate)"}
+    for n, seed in ((96, 2000), (128, 3)):
+        if (n == 96 and args.n_test == 0) or (n == 128 and args.n_cfg3 == 0):
+            continue
+        m = I.hex_mesh(n)
+        mu = torch.as_tensor(I.lognormal_field(m.n_elems, 0.5, seed)).to(dev)
+        op = Operator(I.HEX8, m.X, m.conn, device=dev)
+        op.set_material(mu, 1.5 * mu)
+        u = torch.as_tensor(I.gaussian_field(m.n_nodes, I.cube_amplitude(n), 0)).to(dev)
+        dirs = [torch.as_tensor(I.unit_direction(m.n_nodes, 100 + k)).to(dev) for k in range(20)]
+        row = {"mesh": f"{n}^3 Q1 hexes: {m.n_elems} Hex8, {m.n_nodes} nodes, {m.n_dofs} DOF"}
+        flops = m.n_elems * FLOPS_PER_HEX_HVP
+        for prec, dt, word in (("f64", torch.float64, 8), ("f32", torch.float32, 4)):
+            op.linearize(u, prec)
+            vv = [d.to(dt) for d in dirs]
+            y = torch.empty_like(vv[0])
+            op.hvp(vv[0], out=y)
+
+            def sweep():
+                for d in vv:
+                    op.hvp(d, out=y)
+            t = event_time(sweep, 5, stream) / len(vv)
+            byts = m.n_elems * (32 + 16) + 4 * m.n_nodes * 3 * word
+            row[prec] = {"us": round(t * 1e6, 2), "gdofs": round(m.n_dofs / t / 1e9, 3),
+                         "alg_bytes": byts, "pct_hbm": round(100 * byts / t / 1e9 / HBM_PEAK_GBS, 2),
+                         "tflops": round(flops / t / 1e12, 3),
+                         "pct_valu": round(100 * flops / t / 1e12 / FP64_PEAK_TFLOPS, 2)}
+            log(f"hex8 {n}^3 {prec}: {t*1e6:.1f} us, {row[prec]['pct_valu']}% VALU, {row[prec]['pct_hbm']}% HBM")
+        res[f"n{n}"] = row
+        op.close()
+        del dirs, u, mu
+    return res
 
 
 def main():
@@ -246,6 +303,7 @@ def main():
     ap.add_argument("--epochs", type=int, default=300)
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--mode", choices=["bench", "kernels"], default="bench")
+    ap.add_argument("--flush", action="store_true", help="kernels mode: cold Infinity Cache before each FP64 action")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU "
@@ -291,20 +349,25 @@ def main():
     value = N_DIRS * ndof / t_step / 1e9
     log(f"f64 step {t_step*1e3:.3f} ms -> {value:.2f} GDoF/s")
 
-    # dominant kernel: the block pass and its halo gather (efem_hvp_zeroed, the
-    # form the Krylov loop uses); y is not re-cleared between timing calls,
-    # which changes its values but not the work
+    # dominant kernel: the chunk pass and its halo gather (efem_hvp_zeroed,
+    # the form the Krylov loop uses; under the halo scatter its launches are
+    # those of efem_hvp), over the same 100 distinct directions as the step;
+    # y is not re-cleared between calls, which changes its values but not the
+    # work
     op.linearize(u, "f64")
     Y.zero_()
-    reps = N_DIRS * max(args.steps // 4, 2)
-    t_acc = event_time(lambda: op.hvp_zeroed(V[0], Y), reps, stream)
+
+    def sweep_zeroed():
+        for k in range(N_DIRS):
+            op.hvp_zeroed(V[k], Y)
+    t_acc = event_time(sweep_zeroed, max(args.steps // 4, 2), stream) / N_DIRS
     conn_b = mesh.n_elems * 4 * 4
     node_b = mesh.n_nodes * 3 * 8
     alg_hvp = conn_b + 3 * node_b + node_b          # conn + X, x, v read + y write
     alg_flops = mesh.n_elems * FLOPS_PER_TET_HVP
     achieved = alg_hvp / t_acc / 1e9
     achieved_tf = alg_flops / t_acc / 1e12
-    log(f"hvp block pass + gather {t_acc*1e6:.2f} us -> {achieved:.0f} GB/s, {achieved_tf:.2f} TFLOP/s")
+    log(f"hvp chunk pass + gather {t_acc*1e6:.2f} us -> {achieved:.0f} GB/s, {achieved_tf:.2f} TFLOP/s")
 
     # the same launch pair with the 256 MB Infinity Cache flushed before each
     # call (a 512 MiB fill), timed by events around the action alone: the
@@ -320,7 +383,7 @@ def main():
     torch.cuda.synchronize()
     t_cold = float(np.median([ev0.elapsed_time(ev1) for ev0, ev1 in evs[5:]])) * 1e-3
     del flush
-    log(f"hvp block pass + gather, cache flushed: {t_cold*1e6:.2f} us")
+    log(f"hvp chunk pass + gather, cache flushed: {t_cold*1e6:.2f} us")
 
     # achievable HBM bandwidth: a plain 1 GiB device copy (read + write)
     ca = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
@@ -508,6 +571,8 @@ def main():
     opa.close()
     del mu4, ua
 
+    hex8 = hex8_section(args, dev, stream)
+
     t_hvp = t_step / N_DIRS
     out = {
         "metric": "HVP Gdof/s & %HBM peak; Newton solve s to 1e-8 resid, plain vs mixed+NN",
@@ -539,8 +604,8 @@ def main():
             "unit": "TFLOP/s",
             "frac": round(achieved_tf / FP64_PEAK_TFLOPS, 4),
             "traffic": measured_traffic(),
-            "kernel": "k_accumulate<Tet4Pair, HvpOp<double>, double, false> + "
-                      "k_halo_gather<double, false> (efem_hvp_zeroed)",
+            "kernel": "k_chunk_hvp64<false, true> + k_halo_gather<double, false, false> (efem_hvp_zeroed, "
+                      "100 distinct directions)",
             "kernel_us": round(t_acc * 1e6, 3),
             "alg_flops": alg_flops,
             "alg_bytes": alg_hvp,
@@ -567,6 +632,7 @@ def main():
         "linear_model": linear,
         "transport": transport,
         "planar_2d": planar,
+        "hex8": hex8,
         "paper_context": "matrix-free JVP ~13 MDoF/s, 3D linear tets, NVIDIA A100 (JAX), precision unstated",
     }
 

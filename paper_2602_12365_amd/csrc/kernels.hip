@@ -866,6 +866,29 @@ template <> struct HvpOp<double> {
                                                    const double ve[E::NEN][3], const double *mu,
                                                    const double *lam, bool pair, double f[E::NEN][3])
     {
+        if constexpr (std::is_same<E, Hex8>::value) {
+            // Hex8 in the column form (gradients from edge differences,
+            // forces back through the columns): half the operations of the
+            // node form; at one wave per SIMD the accumulation registers
+            // hold it
+            typename E::template Field<double> FX, Fx, Fv;
+            E::prep(Xe, FX);
+            E::prep(xe, Fx);
+            E::prep(ve, Fv);
+            typename E::template Acc<double> A;
+            bool ok = true;
+#pragma unroll
+            for (int q = 0; q < E::NQ; ++q) {
+                double Jx[9], Jd[9], dJ[9], Q[9];
+                E::grad(FX, q, Jx);
+                E::grad(Fx, q, Jd);
+                E::grad(Fv, q, dJ);
+                ok &= qp_hvp(E::template weight<double>(), Jx, Jd, dJ, mu[0], lam[0], Q);
+                E::template add_forces<true>(Q, q, A);
+            }
+            E::finish(A, f);
+            return ok;
+        }
         // three fields: the register-lean form (node sums for Hex8)
         using G = typename E::Lean;
         typename G::template Field<double> FX, Fx, Fv;
