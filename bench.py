@@ -507,15 +507,15 @@ def main():
     del m2, u2, v2, y2
 
     # sparse tangent by colouring (Alg. 2): K(u) from n_colours tangent
-    # actions, then CSR products against the matrix-free one
+    # actions, then products by 3x3 blocks against the matrix-free one
     sp_info = op.sparse_setup()
     vals = op.sparse_assemble(u)
     t_asm = event_time(lambda: op.sparse_assemble(u, values=vals), 3, stream)
     t_spmv = event_time(lambda: op.sparse_spmv(vals, V[0], out=Y), 50, stream)
-    # what the product must move: every value, one column index per triple of
-    # consecutive columns (the pattern is built per node), the row pointers,
-    # x once and y
-    spmv_bytes = sp_info["nnz"] * 8 + (sp_info["nnz"] // 3) * 4 + (sp_info["n_rows"] + 1) * 8 + 2 * ndof * 8
+    # what the product by 3x3 blocks moves: every value, one column index
+    # per block, the node-row block offsets, x once and y
+    spmv_bytes = (sp_info["nnz"] * 8 + sp_info["n_blocks"] * 4 + (sp_info["n_rows"] // 3 + 1) * 8
+                  + 2 * ndof * 8)
     sparse = {"n_colours": sp_info["n_colours"], "nnz": sp_info["nnz"],
               "setup_s": round(sp_info["setup_seconds"], 3), "assemble_ms": round(t_asm * 1e3, 3),
               "assemble_gdofs": round(ndof / t_asm / 1e9, 4),

@@ -470,6 +470,7 @@ typedef struct {
     int32_t n_colours;
     int32_t max_row;          /* most nonzeros in a row */
     double setup_seconds;     /* host time of the pattern and the colouring */
+    int64_t n_blocks;         /* 3x3 blocks, nnz / 9 (node pairs of the 1-ring) */
 } efem_sparse_info;
 
 /* Build the pattern and the colouring (host work, synchronous; the first call
@@ -485,7 +486,19 @@ int efem_sparse_pattern(efem_ctx *ctx, int64_t *row_ptr, int32_t *col, int32_t *
  * linearization is set to u). */
 int efem_sparse_assemble(efem_ctx *ctx, const double *u, double *values);
 
-/* y = K x with the assembled values (x, y DEVICE float64 [3*n_nodes]). */
+/* The same pattern by 3x3 blocks: block_ptr DEVICE int64 [n_nodes+1],
+ * block_col DEVICE int32 [n_blocks]; node row i holds the blocks (i, j) for
+ * j = block_col[block_ptr[i] .. block_ptr[i+1]) (sorted).  In the values'
+ * pattern order, node row i's entries start at 9 block_ptr[i]: its three
+ * component rows one after the other, 3 len values each (len = its block
+ * count), row a of block t at offset 3 t of component row a.  Enqueued on the
+ * context's stream.  EFEM_ERR_STATE before setup. */
+int efem_sparse_block_pattern(efem_ctx *ctx, int64_t *block_ptr, int32_t *block_col);
+
+/* y = K x with the assembled values (x, y DEVICE float64 [3*n_nodes]), by
+ * 3x3 blocks: one column index per block (the block pattern above), so the
+ * bytes moved are the values, n_blocks column indices, n_nodes+1 block
+ * offsets, x and y.  Enqueued on the context's stream. */
 int efem_sparse_spmv(efem_ctx *ctx, const double *values, const double *x, double *y);
 
 const char *efem_last_error(void);

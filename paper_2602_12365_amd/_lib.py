@@ -48,7 +48,7 @@ class Info(ctypes.Structure):
 
 class SparseInfo(ctypes.Structure):
     _fields_ = [("n_rows", c_int64), ("nnz", c_int64), ("n_colours", c_int32), ("max_row", c_int32),
-                ("setup_seconds", c_double)]
+                ("setup_seconds", c_double), ("n_blocks", c_int64)]
 
 
 class SolveOpts(ctypes.Structure):
@@ -111,6 +111,7 @@ SIGNATURES = {
     "efem_sparse_setup": (c_int32, [c_void_p, c_void_p]),
     "efem_sparse_pattern": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p]),
     "efem_sparse_assemble": (c_int32, [c_void_p, c_void_p, c_void_p]),
+    "efem_sparse_block_pattern": (c_int32, [c_void_p, c_void_p, c_void_p]),
     "efem_sparse_spmv": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p]),
     "efem_linear_solve": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_double, c_int32,
                                     c_int32, c_int32, ctypes.POINTER(c_int32),

@@ -141,8 +141,10 @@ int build(Ctx &c, SparseState &S)
     if ((rc = upload_into(S, &S.row_ptr, row_ptr)) || (rc = upload_into(S, &S.col, col))
         || (rc = upload_into(S, &S.dof_colour, dcol)) || (rc = upload_into(S, &S.ent, ent))
         || (rc = upload_into(S, &S.ent_row, ent_row)) || (rc = alloc_into(S, &S.seed, (size_t)n_rows))
-        || (rc = alloc_into(S, &S.y, (size_t)n_rows)))
+        || (rc = alloc_into(S, &S.y, (size_t)n_rows)) || (rc = upload_into(S, &S.bptr, rp))
+        || (rc = upload_into(S, &S.bcol, ri)))
         return rc;
+    S.n_blocks = (int64_t)ri.size();
     S.n_rows = n_rows;
     S.nnz = nnz;
     S.n_colours = n_colours;
@@ -194,6 +196,7 @@ int efem_sparse_setup(efem_ctx *ctx, efem_sparse_info *info)
     info->n_colours = S.n_colours;
     info->max_row = S.max_row;
     info->setup_seconds = S.setup_seconds;
+    info->n_blocks = S.n_blocks;
     return EFEM_OK;
 }
 
@@ -250,7 +253,25 @@ int efem_sparse_spmv(efem_ctx *ctx, const double *values, const double *x, doubl
         return EFEM_ERR_STATE;
     }
     const SparseState &S = *static_cast<SparseState *>(ctx->sparse);
-    TRY(launch_spmv(ctx->stream, S.n_rows, S.row_ptr, S.col, values, x, y));
+    TRY(launch_block_spmv(ctx->stream, S.n_rows / 3, S.bptr, S.bcol, values, x, y));
+    return EFEM_OK;
+}
+
+int efem_sparse_block_pattern(efem_ctx *ctx, int64_t *block_ptr, int32_t *block_col)
+{
+    if (!ctx || !block_ptr || !block_col) {
+        set_error("efem_sparse_block_pattern: null pointer");
+        return EFEM_ERR_INVALID;
+    }
+    if (!ctx->sparse) {
+        set_error("efem_sparse_block_pattern: call efem_sparse_setup first");
+        return EFEM_ERR_STATE;
+    }
+    const SparseState &S = *static_cast<SparseState *>(ctx->sparse);
+    TRY(hipMemcpyAsync(block_ptr, S.bptr, (S.n_rows / 3 + 1) * sizeof(int64_t), hipMemcpyDeviceToDevice,
+                       ctx->stream));
+    TRY(hipMemcpyAsync(block_col, S.bcol, std::max<int64_t>(S.n_blocks, 0) * sizeof(int32_t),
+                       hipMemcpyDeviceToDevice, ctx->stream));
     return EFEM_OK;
 }
 

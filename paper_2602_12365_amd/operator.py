@@ -319,6 +319,15 @@ class Operator:
         L.check(self._lib.efem_sparse_pattern(self._h, _ptr(rp), _ptr(col), _ptr(dc)), "efem_sparse_pattern")
         return rp, col, dc
 
+    def sparse_block_pattern(self):
+        """(block_ptr int64 [n_nodes+1], block_col int32 [n_blocks]): the
+        pattern by 3x3 blocks, the layout the SpMV reads."""
+        info = self._sparse if getattr(self, "_sparse", None) else self.sparse_setup()
+        bp = torch.empty(info["n_rows"] // 3 + 1, dtype=torch.int64, device=self.device)
+        bc = torch.empty(info["n_blocks"], dtype=torch.int32, device=self.device)
+        L.check(self._lib.efem_sparse_block_pattern(self._h, _ptr(bp), _ptr(bc)), "efem_sparse_block_pattern")
+        return bp, bc
+
     def sparse_assemble(self, u, values=None):
         """K(u) values (float64 [nnz], pattern order) from n_colours tangent actions."""
         info = self._sparse if getattr(self, "_sparse", None) else self.sparse_setup()
@@ -330,6 +339,7 @@ class Operator:
         return values
 
     def sparse_spmv(self, values, x, out=None):
+        """y = K x with assembled values, by 3x3 blocks."""
         self._sync_stream()
         out = self._new_nodal() if out is None else self._nodal(out, name="out")
         L.check(self._lib.efem_sparse_spmv(self._h, _ptr(values), _ptr(self._nodal(x, name="x")), _ptr(out)),

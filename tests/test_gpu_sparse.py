@@ -1,8 +1,8 @@
 """Sparse tangent by colouring (the paper's Alg. 2) against the oracle's
 assembled K: the pattern (node 1-ring in 3x3 blocks), the validity of the
 distance-2 colouring, the values (FP64, 1e-10 of the largest entry), the
-reduced form under a Dirichlet mask, and the SpMV against the matrix-free
-tangent action."""
+reduced form under a Dirichlet mask, the 3x3-block pattern, and the SpMV
+against the oracle's K x and the matrix-free tangent action."""
 import numpy as np
 import pytest
 import torch
@@ -51,6 +51,33 @@ def test_pattern_is_the_oracle_pattern_and_colouring_is_valid(case):
         assert len(np.unique(c)) == len(c)
     assert dc.max() + 1 == info["n_colours"]
     print(f"[sparse] colours {info['n_colours']}, nnz {info['nnz']}, max row {info['max_row']}", flush=True)
+
+
+def test_block_pattern_is_the_csr_pattern_by_node(case):
+    """The 3x3-block pattern the SpMV reads: node row i's blocks are the
+    distinct column nodes of its component rows, the three rows share them,
+    and nnz = 9 n_blocks."""
+    m, op, orc, u = case
+    info = op.sparse_setup()
+    rp, col, _ = (t.cpu().numpy() for t in op.sparse_pattern())
+    bp, bc = (t.cpu().numpy() for t in op.sparse_block_pattern())
+    assert info["n_blocks"] * 9 == info["nnz"] and bp[-1] == info["n_blocks"] and bp[0] == 0
+    for i in range(m.n_nodes):
+        blocks = bc[bp[i]:bp[i + 1]]
+        for a in range(3):
+            r = col[rp[3 * i + a]:rp[3 * i + a + 1]]
+            assert np.array_equal(r, (3 * blocks[:, None] + np.arange(3)[None, :]).ravel())
+        assert rp[3 * i] == 9 * bp[i]
+
+
+def test_spmv_matches_oracle_product(case):
+    """y = K x by 3x3 blocks against the oracle's assembled K times x."""
+    m, op, orc, u = case
+    vals = op.sparse_assemble(dev(u))
+    x = I.unit_direction(m.n_nodes, 9)
+    y = op.sparse_spmv(vals, dev(x)).cpu().numpy().ravel()
+    ref = orc.tangent_matrix(u) @ x.ravel()
+    assert np.abs(y - ref).max() <= 1e-10 * np.abs(ref).max()
 
 
 def test_assembled_values_match_oracle(case):
