@@ -374,6 +374,13 @@ int efem_precond_rows(efem_ctx *ctx, const float *b, const double *diag, const f
 /* out [rows][3] = MLP(X) on the matrix cores with the context's parameters. */
 int efem_mlp_forward(efem_ctx *ctx, int64_t rows, const uint16_t *X, float *out);
 
+/* The same forward pass with both hidden layers' activations as well: h1, h2
+ * DEVICE uint16 (bfloat16 bits) [rows][EFEM_MLP_HID], h_k = bf16(softplus(
+ * W_k h_{k-1} + b_k)) exactly as the next layer reads it; out as above.  For
+ * checking the network layer by layer. */
+int efem_mlp_forward_layers(efem_ctx *ctx, int64_t rows, const uint16_t *X, uint16_t *h1, uint16_t *h2,
+                            float *out);
+
 /* Loss sum_rows w |m (g + s MLP_params(X)) - m t|^2 and its gradient with respect
  * to params (DEVICE float32 [EFEM_MLP_PARAMS]) into grad (DEVICE float32
  * [EFEM_MLP_PARAMS], overwritten) and loss (DEVICE float64 [1]); forward and

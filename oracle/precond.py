@@ -79,6 +79,17 @@ def mlp_forward(theta, X, keep=False, rounding=True):
     return out
 
 
+def mlp_layer(theta, k, inp):
+    """One layer of mlp_forward (rounded form) applied to a given layer
+    input: k = 1, 2 the hidden layers, bf16(softplus(W_k inp + b_k)) with inp
+    [n, 12] or [n, 64]; k = 3 the output W3 inp + b3.  The input is used as
+    given (bf16 values already), so a test can evaluate each layer on another
+    implementation's own rounded activations."""
+    p = {name: bf16_round(v) for name, v in unpack(theta).items()}
+    a = np.asarray(inp, dtype=np.float64) @ p[f"W{k}"].T + p[f"b{k}"]
+    return a if k == 3 else bf16_round(softplus(a))
+
+
 def mlp_backward(theta, X, dout, rounding=True):
     """Gradient of sum(dout * out) with respect to the flat parameters (the
     bf16 roundings are treated as identity, as in a straight-through estimate)."""

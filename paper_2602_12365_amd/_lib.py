@@ -100,6 +100,7 @@ SIGNATURES = {
     "efem_precond_rows": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_double, c_void_p,
                                     c_void_p]),
     "efem_mlp_forward": (c_int32, [c_void_p, c_int64, c_void_p, c_void_p]),
+    "efem_mlp_forward_layers": (c_int32, [c_void_p, c_int64, c_void_p, c_void_p, c_void_p, c_void_p]),
     "efem_mlp_loss_grad": (c_int32, [c_void_p, c_int64, c_void_p, c_void_p, c_void_p, c_void_p,
                                      c_void_p]),
     "efem_mlp_adam": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, ctypes.c_float,

@@ -47,7 +47,9 @@ hipError_t mlp_features_static(hipStream_t s, const MlpState &M, int64_t n, cons
                                const uint8_t *nmask, uint16_t *X);
 hipError_t mlp_features_dyn(hipStream_t s, const MlpState &M, int64_t n, const float *r,
                             const float *dinv, uint16_t *X, float *scale, float4 *g4);
-hipError_t mlp_forward(hipStream_t s, const uint16_t *W, int64_t n, const uint16_t *X, float *out);
+// H1, H2 (both or neither): the hidden layers' bf16 activations [n][64]
+hipError_t mlp_forward(hipStream_t s, const uint16_t *W, int64_t n, const uint16_t *X, float *out,
+                       uint16_t *H1 = nullptr, uint16_t *H2 = nullptr);
 int mlp_apply_grid(int64_t n);
 hipError_t mlp_apply(hipStream_t s, const uint16_t *W, int64_t n, const uint16_t *X, const float *r,
                      const float *dinv, const float *scale, float *z, double *prz);

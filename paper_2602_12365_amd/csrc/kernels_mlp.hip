@@ -20,15 +20,21 @@ __device__ __forceinline__ uint16_t f2bf(float f) { return __builtin_bit_cast(ui
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 __device__ __forceinline__ float bfr(float f) { return bf2f(f2bf(f)); }
 
-// softplus(x) = max(x, 0) + ln(1 + e^-|x|) with the hardware base-2
-// exponential and logarithm: the exponent is <= 0 and the logarithm's argument
-// lies in [1, 2], so neither needs range reduction; where 1 + e^-|x| rounds to
-// 1 the term is below 2^-24, far under the bfloat16 rounding every activation
-// then takes.
+// softplus(x) = max(x, 0) + ln(1 + t), t = e^-|x| in (0, 1], with the
+// hardware base-2 exponential and logarithm (the exponent is <= 0 and the
+// logarithm's argument lies in [1, 2], so neither needs range reduction).
+// For x < 0 softplus is ln(1 + t) alone, so that term needs relative
+// accuracy: below t = 2^-7 it is the series t - t^2/2 + t^3/3 (the first
+// omitted term is below 2^-23 of the sum); above, the logarithm of the
+// rounded 1 + t is within 2^-17 relative.  (The logarithm of the rounded
+// 1 + t alone would be off by up to 2^-24 / t relative: several bfloat16
+// ulps once x < -12.)
 __device__ __forceinline__ float softplus(float x)
 {
     const float t = __builtin_amdgcn_exp2f(-fabsf(x) * 1.4426950408889634f);
-    return fmaxf(x, 0.f) + 0.6931471805599453f * __builtin_amdgcn_logf(1.f + t);
+    const float series = t * fmaf(t, fmaf(t, 0.33333333f, -0.5f), 1.f);
+    const float l = t < 0.0078125f ? series : 0.6931471805599453f * __builtin_amdgcn_logf(1.f + t);
+    return fmaxf(x, 0.f) + l;
 }
 __device__ __forceinline__ float sigmoidf_(float x) { return 1.f / (1.f + __expf(-x)); }
 
@@ -150,8 +156,23 @@ __device__ __forceinline__ void load_weights(const uint16_t *__restrict__ W, Mlp
     for (int v = 0; v < 4; ++v) R.B3[v] = (4 * quad + v < kOut) ? bf2f(W[kOffB3 + 4 * quad + v]) : 0.f;
 }
 
-// out[v] for v < 3 is valid in lanes 0..15 (node = lane).
-__device__ __forceinline__ f4 mlp16(const MlpRegs &R, s4 xb)
+// The bf16 activations of one hidden layer for this lane's node: hidden
+// units 16 t + 4 quad + (0..3) of tile t, one 8-byte store per tile
+// (H [n][64], only where node < n).
+__device__ __forceinline__ void store_layer(uint16_t *__restrict__ H, const s4 h[4], int64_t node, int64_t n)
+{
+    if (node >= n) return;
+    const int quad = (threadIdx.x & 63) >> 4;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) *reinterpret_cast<s4 *>(H + node * kHid + 16 * t + 4 * quad) = h[t];
+}
+
+// out[v] for v < 3 is valid in lanes 0..15 (node = lane).  LAYERS: the two
+// hidden layers' bf16 activations also go to H1 and H2 ([n][64]) for this
+// lane's node.
+template <bool LAYERS = false>
+__device__ __forceinline__ f4 mlp16(const MlpRegs &R, s4 xb, uint16_t *H1 = nullptr, uint16_t *H2 = nullptr,
+                                    int64_t node = 0, int64_t n = 0)
 {
     const f4 zero = {0.f, 0.f, 0.f, 0.f};
     s4 hb[4];
@@ -161,6 +182,7 @@ __device__ __forceinline__ f4 mlp16(const MlpRegs &R, s4 xb)
 #pragma unroll
         for (int v = 0; v < 4; ++v) hb[t][v] = (short)f2bf(softplus(d[v] + R.B1[t][v]));
     }
+    if constexpr (LAYERS) store_layer(H1, hb, node, n);
     s4 h2[4];
 #pragma unroll
     for (int t2 = 0; t2 < 4; ++t2) {
@@ -170,6 +192,7 @@ __device__ __forceinline__ f4 mlp16(const MlpRegs &R, s4 xb)
 #pragma unroll
         for (int v = 0; v < 4; ++v) h2[t2][v] = (short)f2bf(softplus(d[v] + R.B2[t2][v]));
     }
+    if constexpr (LAYERS) store_layer(H2, h2, node, n);
     f4 o = zero;
 #pragma unroll
     for (int t = 0; t < 4; ++t) o = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(R.A3[t], h2[t], o, 0, 0, 0);
@@ -185,10 +208,12 @@ __device__ __forceinline__ s4 load_x(const uint16_t *__restrict__ X, int64_t nod
     return *reinterpret_cast<const s4 *>(X + node * kInPad + 4 * quad);
 }
 
-// out [n, 3] = MLP(X)
+// out [n, 3] = MLP(X); LAYERS: the hidden activations to H1, H2 as well
+template <bool LAYERS>
 __global__ void __launch_bounds__(256) k_mlp_forward(int64_t n, const uint16_t *__restrict__ X,
                                                      const uint16_t *__restrict__ W,
-                                                     float *__restrict__ out)
+                                                     float *__restrict__ out, uint16_t *__restrict__ H1,
+                                                     uint16_t *__restrict__ H2)
 {
     MlpRegs R;
     load_weights(W, R);
@@ -201,7 +226,7 @@ __global__ void __launch_bounds__(256) k_mlp_forward(int64_t n, const uint16_t *
         const int64_t node = g0 + (lane & 15);
         const s4 xb = xn;
         xn = load_x(X, node + nw * 16, n);
-        const f4 o = mlp16(R, xb);
+        const f4 o = mlp16<LAYERS>(R, xb, H1, H2, node, n);
         if (lane < 16 && node < n) {
             out[3 * node] = o[0];
             out[3 * node + 1] = o[1];
@@ -584,9 +609,13 @@ hipError_t mlp_features_dyn(hipStream_t s, const MlpState &M, int64_t n, const f
     return hipGetLastError();
 }
 
-hipError_t mlp_forward(hipStream_t s, const uint16_t *W, int64_t n, const uint16_t *X, float *out)
+hipError_t mlp_forward(hipStream_t s, const uint16_t *W, int64_t n, const uint16_t *X, float *out, uint16_t *H1,
+                       uint16_t *H2)
 {
-    hipLaunchKernelGGL(k_mlp_forward, dim3(mlp_grid(n)), dim3(256), 0, s, n, X, W, out);
+    if (H1 && H2)
+        hipLaunchKernelGGL(k_mlp_forward<true>, dim3(mlp_grid(n)), dim3(256), 0, s, n, X, W, out, H1, H2);
+    else
+        hipLaunchKernelGGL(k_mlp_forward<false>, dim3(mlp_grid(n)), dim3(256), 0, s, n, X, W, out, H1, H2);
     return hipGetLastError();
 }
 

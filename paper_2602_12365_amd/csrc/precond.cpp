@@ -209,6 +209,20 @@ int efem_mlp_forward(efem_ctx *ctx, int64_t rows, const uint16_t *X, float *out)
     return EFEM_OK;
 }
 
+int efem_mlp_forward_layers(efem_ctx *ctx, int64_t rows, const uint16_t *X, uint16_t *h1, uint16_t *h2,
+                            float *out)
+{
+    if (!ctx || !X || !h1 || !h2 || !out || rows < 0) return EFEM_ERR_INVALID;
+    auto *M = static_cast<MlpState *>(ctx->mlp);
+    if (!M || !M->have_weights) {
+        set_error("efem_mlp_forward_layers: call efem_set_mlp first");
+        return EFEM_ERR_STATE;
+    }
+    if (rows == 0) return EFEM_OK;
+    TRY(mlp_forward(ctx->stream, M->W, rows, X, out, h1, h2));
+    return EFEM_OK;
+}
+
 int efem_mlp_loss_grad(efem_ctx *ctx, int64_t rows, const uint16_t *X, const float *aux,
                        const float *params, float *grad, double *loss)
 {

@@ -412,6 +412,18 @@ class Operator:
                 "efem_mlp_forward")
         return out
 
+    def mlp_forward_layers(self, X):
+        """(h1, h2, out): both hidden layers' bf16 activations as int16 bit
+        patterns [rows, 64] and the output [rows, 3]."""
+        self._sync_stream()
+        rows = X.shape[0]
+        h1 = torch.empty((rows, L.EFEM_MLP_HID), dtype=torch.int16, device=self.device)
+        h2 = torch.empty_like(h1)
+        out = torch.empty((rows, 3), dtype=torch.float32, device=self.device)
+        L.check(self._lib.efem_mlp_forward_layers(self._h, rows, _ptr(X.contiguous()), _ptr(h1), _ptr(h2),
+                                                  _ptr(out)), "efem_mlp_forward_layers")
+        return h1, h2, out
+
     def mlp_loss_grad(self, X, aux, params, grad=None, loss=None):
         self._sync_stream()
         grad = torch.empty(L.EFEM_MLP_PARAMS, dtype=torch.float32, device=self.device) if grad is None else grad

@@ -50,6 +50,18 @@ def test_mlp_matches_torch_autograd():
     assert np.allclose(t.grad.numpy(), P.mlp_backward(th, X, dout, rounding=False), rtol=1e-12, atol=1e-12)
 
 
+def test_mlp_layers_compose_to_the_forward_pass():
+    """The per-layer form used for layer-by-layer parity is the rounded
+    forward pass, layer by layer, to the last bit."""
+    th = rand_theta(8)
+    X = P.bf16_round(np.random.default_rng(9).standard_normal((33, P.N_IN)).astype(np.float32))
+    out, (x0, a1, h1, a2, h2, p) = P.mlp_forward(th, X, keep=True)
+    assert np.array_equal(P.mlp_layer(th, 1, x0), h1)
+    assert np.array_equal(P.mlp_layer(th, 2, h1), h2)
+    assert np.array_equal(P.mlp_layer(th, 3, h2), out)
+    assert np.all(P.mlp_layer(th, 1, x0) > 0)
+
+
 def brute_features(r, D, M, conn, n):
     nb = [set() for _ in range(n)]
     for ce in conn:
