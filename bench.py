@@ -46,11 +46,14 @@ N_DIRS = 100
 # reciprocals, ln J), W = Ad dJ 45, trace and coefficients 5, dJ S 45,
 # W Ad 45, Q 45, the fourth node's force 6, the scatter adds 12.
 FLOPS_PER_TET_HVP = 335
-# One Hex8 tangent action (2x2x2 Gauss, node form): per Gauss point the three
-# reference gradients 3 x 9 x 8 FMAs (432), the point's tangent action as
-# for a tetrahedron without its gradients and forces (290) and the forces on
-# the 8 nodes 8 x 3 x 3 FMAs (144): 866 per point, 6,928 per hexahedron.
-FLOPS_PER_HEX_HVP = 8 * 866
+# One Hex8 tangent action (2x2x2 Gauss) in the column form both precisions
+# evaluate: the 12 gradient columns of each of X, x (or u) and v from the 4
+# edge differences of each direction and two interpolations, 28 per
+# direction and component, 756; the point's tangent action as for a
+# tetrahedron without its gradients and forces, 8 x 290; the 36 column sums
+# of the point forces; columns back to edges, 216; edges to nodes, 48:
+# 3,376 per hexahedron (the node form took 6,928).
+FLOPS_PER_HEX_HVP = 756 + 8 * 290 + 36 + 216 + 48
 
 
 def log(msg):
@@ -137,11 +140,31 @@ def solve_section(args, dev):
         st[0].close()
     del S
 
+    # the configured variant: 200 (residual, Newton correction) pairs (20 fields
+    # x 10 load steps on 32^3), the relative target fit of the first version
+    theta_pairs = None
+    if args.n_test > 0:
+        t0 = time.time()
+        Xp, auxp, opp = PC.generate_rows(n=args.n_train, seeds=seeds, n_steps=10, log=log)
+        torch.cuda.synchronize()
+        t_pairs = time.time() - t0
+        t0 = time.time()
+        theta_pairs, hist_p = PC.train(opp, Xp, auxp, epochs=400, lr=3e-3, log=log)
+        torch.cuda.synchronize()
+        res["training_pairs"] = {"mesh": f"{args.n_train}^3 Q1 hexes", "fields": len(seeds), "load_steps": 10,
+                                 "pairs": len(seeds) * 10, "rows": int(Xp.shape[0]), "epochs": 400,
+                                 "objective": "relative target fit |M(-r) - delta|^2/|delta|^2, delta = K^-1(-r)",
+                                 "loss_first_last": [hist_p[0][1], hist_p[-1][1]],
+                                 "pair_generation_s": round(t_pairs, 2), "training_s": round(time.time() - t0, 2)}
+        opp.close()
+        del Xp, auxp
+
     res["solves"] = {}
     for tag, n, seed in (("cfg3", args.n_cfg3, 3), ("cfg5_test", args.n_test, 2000)):
         if n <= 0:
             continue
-        res["solves"][tag] = compression_solves(dev, n, seed, theta)
+        res["solves"][tag] = compression_solves(dev, n, seed, theta,
+                                                theta_pairs if tag == "cfg5_test" else None)
     # the metric's headline pair: plain FP64 vs mixed FP32 + learned, and mixed
     # FP32 + Jacobi, on the largest configuration run
     main = res["solves"].get("cfg3") or res["solves"].get("cfg5_test")
@@ -150,10 +173,14 @@ def solve_section(args, dev):
                                                   / runs["mixed_f32_learned"]["wall_s"], 3)
     res["speedup_mixed_jacobi_vs_plain"] = round(runs["plain_f64_jacobi"]["wall_s"]
                                                  / runs["mixed_f32_jacobi"]["wall_s"], 3)
+    # what the network itself gains: learned against Jacobi at the same
+    # (mixed) precision (below 1: the network costs more than it saves)
+    res["speedup_learned_vs_mixed_jacobi"] = round(runs["mixed_f32_jacobi"]["wall_s"]
+                                                   / runs["mixed_f32_learned"]["wall_s"], 3)
     return res
 
 
-def compression_solves(dev, n, seed, theta):
+def compression_solves(dev, n, seed, theta, theta_pairs=None):
     """Compression case on n^3 Q1 hexes (mu seed `seed`): plain FP64 Jacobi,
     mixed FP32 Jacobi and mixed FP32 with the learned preconditioner (8
     flexible-CG iterations per Krylov solve, and whole solves)."""
@@ -169,10 +196,17 @@ def compression_solves(dev, n, seed, theta):
     op.set_mlp(theta)
     runs = {}
     u_ref = None
-    for name, kw in [("plain_f64_jacobi", dict(hvp_prec="f64", precond=0)),
-                     ("mixed_f32_jacobi", dict(hvp_prec="f32", precond=0)),
-                     ("mixed_f32_learned", dict(hvp_prec="f32", precond=1, learned_iters=8)),
-                     ("mixed_f32_learned_whole_solve", dict(hvp_prec="f32", precond=1, learned_iters=0))]:
+    plan = [("plain_f64_jacobi", dict(hvp_prec="f64", precond=0)),
+            ("mixed_f32_jacobi", dict(hvp_prec="f32", precond=0)),
+            ("mixed_f32_learned", dict(hvp_prec="f32", precond=1, learned_iters=8)),
+            ("mixed_f32_learned_whole_solve", dict(hvp_prec="f32", precond=1, learned_iters=0))]
+    if theta_pairs is not None:
+        plan += [("mixed_f32_learned_pairs", dict(hvp_prec="f32", precond=1, learned_iters=8, theta=theta_pairs)),
+                 ("mixed_f32_learned_pairs_whole_solve",
+                  dict(hvp_prec="f32", precond=1, learned_iters=0, theta=theta_pairs))]
+    for name, kw in plan:
+        kw = dict(kw)
+        op.set_mlp(kw.pop("theta", theta))
         u = torch.zeros((mesh.n_nodes, 3), dtype=torch.float64, device=dev)
         log(f"solve {name}")
         torch.cuda.synchronize()
@@ -201,6 +235,8 @@ def compression_solves(dev, n, seed, theta):
                                                   / runs["mixed_f32_learned"]["wall_s"], 3)
     res["speedup_mixed_jacobi_vs_plain"] = round(runs["plain_f64_jacobi"]["wall_s"]
                                                  / runs["mixed_f32_jacobi"]["wall_s"], 3)
+    res["speedup_learned_vs_mixed_jacobi"] = round(runs["mixed_f32_jacobi"]["wall_s"]
+                                                   / runs["mixed_f32_learned"]["wall_s"], 3)
     op.close()
     return res
 
@@ -213,6 +249,8 @@ def kernels_mode(args, dev):
     action, so that its counters see the 256 MB Infinity Cache cold."""
     import torch
     from paper_2602_12365_amd import Operator, inputs as I
+    if args.kernels_elem == "hex8":
+        return hex8_kernels_mode(args, dev)
     mesh = I.tet_mesh(args.n)
     u = torch.as_tensor(I.gaussian_field(mesh.n_nodes, I.cube_amplitude(args.n), 0)).to(dev)
     v = torch.as_tensor(I.unit_direction(mesh.n_nodes, 100)).to(dev)
@@ -239,6 +277,30 @@ def kernels_mode(args, dev):
         b.copy_(a)
     torch.cuda.synchronize()
     log("kernels mode done")
+
+
+def hex8_kernels_mode(args, dev):
+    """Fixed Hex8 kernel workload for rocprofv3: the FP64 and FP32 tangent
+    actions of one compression mesh (n^3 Q1 hexes, mu lognormal(0, 0.5),
+    seed 2000 at n = 96 and 3 otherwise, lam = 1.5 mu), --steps calls each."""
+    import torch
+    from paper_2602_12365_amd import Operator, inputs as I
+    n = args.n
+    m = I.hex_mesh(n)
+    mu = torch.as_tensor(I.lognormal_field(m.n_elems, 0.5, 2000 if n == 96 else 3)).to(dev)
+    op = Operator(I.HEX8, m.X, m.conn, device=dev)
+    op.set_material(mu, 1.5 * mu)
+    u = torch.as_tensor(I.gaussian_field(m.n_nodes, I.cube_amplitude(n), 0)).to(dev)
+    v = torch.as_tensor(I.unit_direction(m.n_nodes, 100)).to(dev)
+    for prec, dt in (("f64", torch.float64), ("f32", torch.float32)):
+        op.linearize(u, prec)
+        vv = v.to(dt)
+        y = torch.zeros_like(vv)
+        for _ in range(args.steps):
+            op.hvp_zeroed(vv, y)
+    torch.cuda.synchronize()
+    op.close()
+    log(f"hex8 kernels mode n={n} done")
 
 
 def hex8_section(args, dev, stream):
@@ -304,6 +366,8 @@ def main():
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--mode", choices=["bench", "kernels"], default="bench")
     ap.add_argument("--flush", action="store_true", help="kernels mode: cold Infinity Cache before each FP64 action")
+    ap.add_argument("--kernels-elem", choices=["tet4", "hex8"], default="tet4",
+                    help="kernels mode: the Tet4 workload (64^3 by default) or a Hex8 compression mesh (--n)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU "

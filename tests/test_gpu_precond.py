@@ -339,3 +339,44 @@ def test_energy_training_lowers_the_objective_below_jacobi():
     assert hist[0][1] < 0.0                       # the Jacobi step already lowers the energy
     assert hist[-1][1] < 1.2 * hist[0][1], hist   # and the trained network lowers it further
     print(f"\n[precond] energy objective Jacobi {hist[0][1]:.4f} -> trained {hist[-1][1]:.4f}", flush=True)
+
+
+@pytest.mark.xfail(reason="the 1-ring network does not beat Jacobi PCG at equal precision: its apply "
+                          "(1-ring features and the MLP) costs about half a Jacobi iteration and it saves "
+                          "about 1% of the CG iterations; exact 3x3 block Jacobi, the best node-local "
+                          "linear map, saves only 6-7% on these lognormal(0, 0.5) fields", strict=False)
+def test_learned_beats_jacobi_on_unseen_mesh():
+    """What the trained network gains over the method without it: on an unseen
+    mesh and material field, the mixed-precision Newton solve with the network
+    (its first 8 flexible-CG iterations per Krylov solve, then Jacobi PCG)
+    needs fewer CG iterations and less wall time than the same solve with
+    Jacobi PCG alone."""
+    import time
+    from paper_2602_12365_amd import Operator, precond as PC
+    S = PC.generate_samples(n=10, seeds=range(1000, 1004), n_steps=5, snaps=(0, 5, 20))
+    theta, hist = PC.train_energy(S, epochs=150, lr=1e-3)
+    for st in S.states:
+        st[0].close()
+    assert hist[-1][1] < hist[0][1]          # the energy objective falls below Jacobi's
+    mesh, mu, lam, mask, ubc = PC.compression_case(I.HEX8, 16, 2000)
+    op = Operator(I.HEX8, mesh.X, mesh.conn)
+    op.set_material(dev(mu), dev(lam))
+    op.set_dirichlet(dev(mask, torch.uint8))
+    op.set_mlp(theta)
+    res = {}
+    for name, kw in (("jacobi", dict(precond=0)), ("learned", dict(precond=1, learned_iters=8))):
+        best = None
+        for _ in range(2):                    # the first run warms up
+            u = torch.zeros((mesh.n_nodes, 3), dtype=torch.float64, device="cuda")
+            torch.cuda.synchronize()
+            t0 = time.time()
+            rc, st = op.newton_solve(u, dev(ubc), n_steps=5, hvp_prec="f32", **kw)
+            torch.cuda.synchronize()
+            assert rc == 0, st
+            best = min(best or 1e9, time.time() - t0)
+        res[name] = (st["cg_iters"], best)
+    print(f"\n[precond] unseen 16^3: CG iterations / wall s, Jacobi {res['jacobi']}, learned {res['learned']}",
+          flush=True)
+    op.close()
+    assert res["learned"][0] < res["jacobi"][0]
+    assert res["learned"][1] < res["jacobi"][1]
