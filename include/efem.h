@@ -122,9 +122,10 @@ typedef struct {
  * Elements are reordered internally along a Morton curve and cut into blocks
  * that each fit one workgroup's LDS.  The material is set to mu = 1, lam = 1.5
  * until efem_set_material is called.  Synchronous.
- * Errors: EFEM_ERR_INVALID on a null pointer, n_nodes < 1, n_elems < 1 or a
- * connectivity entry outside [0, n_nodes); EFEM_ERR_INVERTED if an element of
- * the reference mesh has det J <= 0 at a quadrature point. */
+ * Errors: EFEM_ERR_INVALID on a null pointer, n_nodes < 1, n_elems < 1, a
+ * connectivity entry outside [0, n_nodes) or a node that no element uses
+ * (outputs are written by the element passes only); EFEM_ERR_INVERTED if an
+ * element of the reference mesh has det J <= 0 at a quadrature point. */
 int efem_create(efem_ctx **out, int32_t elem, int64_t n_nodes, int64_t n_elems,
                 const double *coords, const int32_t *conn, const efem_options *opts,
                 void *stream);

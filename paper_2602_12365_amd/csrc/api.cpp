@@ -566,9 +566,19 @@ int efem_create(efem_ctx **out, int32_t elem, int64_t n_nodes, int64_t n_elems,
         return EFEM_ERR_INVALID;
     }
     const int nen = nodes_per_elem(elem);
-    for (int64_t k = 0; k < n_elems * nen; ++k)
+    std::vector<uint8_t> used((size_t)n_nodes, 0);
+    for (int64_t k = 0; k < n_elems * nen; ++k) {
         if (conn[k] < 0 || conn[k] >= n_nodes) {
             set_error("efem_create: connectivity entry out of range");
+            return EFEM_ERR_INVALID;
+        }
+        used[(size_t)conn[k]] = 1;
+    }
+    // every output entry is written by the element passes, so a node outside
+    // every element (whose rows of K are zero) would be left unwritten
+    for (int64_t g = 0; g < n_nodes; ++g)
+        if (!used[(size_t)g]) {
+            set_error("efem_create: node in no element (remove unreferenced nodes)");
             return EFEM_ERR_INVALID;
         }
     if (!reference_jacobians_positive(elem, nen, n_elems, coords, conn)) {

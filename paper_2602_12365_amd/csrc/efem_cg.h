@@ -32,6 +32,9 @@ struct CgLaunch {
     int64_t n;          // vector length (3 * n_nodes)
     hipStream_t s;
     CgWorkspace ws;
+    // the update kernel clears q for the next tangent action (only the
+    // atomic scatter's single-launch form needs q = 0 on entry)
+    bool clear_q = true;
 
     hipError_t init(const double *b, double sign, const T *dinv, const uint8_t *nmask, T *x, T *r,
                     T *p, T *q, CgScalars *sc, double eta2) const;
@@ -56,9 +59,10 @@ struct FcgLaunch {
     int64_t n;
     hipStream_t s;
     CgWorkspace ws;
+    bool clear_q = true;   // as in CgLaunch
     // after M(r) -> z: rz = r.z; p = z; breakdown / fallback if rz <= 0
     hipError_t start(const T *z, T *p, CgScalars *sc, const double *prz, int nz) const;
-    // alpha = rz/pq; x += alpha p; r -= alpha q; q = 0; partials of r.r and r.z_old
+    // alpha = rz/pq; x += alpha p; r -= alpha q; q = 0 (clear_q); partials of r.r and r.z_old
     hipError_t update(T *x, T *r, const T *p, T *q, const T *zold, CgScalars *sc, int j) const;
     // convergence / stagnation test; beta = (r.z_new - r.z_old)/rz; p = z + beta p
     hipError_t dir(T *p, const T *z, CgScalars *sc, const double *prz, int nz, int j,

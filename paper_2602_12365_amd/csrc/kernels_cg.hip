@@ -111,9 +111,10 @@ __global__ void __launch_bounds__(kThreads) k_cg_pq(int64_t n, const T *__restri
 }
 
 // alpha = rz / pq (breakdown if pq <= 0 or not finite); x += alpha p,
-// r -= alpha q, q = 0; partials of r.r and r.(dinv r).  `j` is the iteration
-// index and `par` its parity (which rz slot is current).
-template <class T>
+// r -= alpha q, q = 0 if CLEAR (for a next tangent action that adds into q);
+// partials of r.r and r.(dinv r).  `j` is the iteration index and `par` its
+// parity (which rz slot is current).
+template <class T, bool CLEAR>
 __global__ void __launch_bounds__(kThreads) k_cg_update(int64_t n, T *__restrict__ x,
                                                         T *__restrict__ r, const T *__restrict__ p,
                                                         T *__restrict__ q, const T *__restrict__ dinv,
@@ -145,7 +146,7 @@ __global__ void __launch_bounds__(kThreads) k_cg_update(int64_t n, T *__restrict
         x[i] += a * p[i];
         const T ri = r[i] - a * q[i];
         r[i] = ri;
-        q[i] = T(0);
+        if (CLEAR) q[i] = T(0);
         const T zi = dinv[i] * ri;
         rr += (double)ri * (double)ri;
         rz += (double)ri * (double)zi;
@@ -305,9 +306,9 @@ template <class T>
 hipError_t CgLaunch<T>::update(T *x, T *r, const T *p, T *q, const T *dinv, CgScalars *sc, int j) const
 {
     const int g = red_grid(n);
-    hipLaunchKernelGGL(k_cg_update<T>, dim3(g), dim3(kThreads), 0, s, n, x, r, p, q, dinv, sc,
-                       ws.partials, g, ws.partials + kMaxRedBlocks, ws.partials + 2 * kMaxRedBlocks,
-                       j & 1, j);
+    auto kern = clear_q ? k_cg_update<T, true> : k_cg_update<T, false>;
+    hipLaunchKernelGGL(kern, dim3(g), dim3(kThreads), 0, s, n, x, r, p, q, dinv, sc, ws.partials, g,
+                       ws.partials + kMaxRedBlocks, ws.partials + 2 * kMaxRedBlocks, j & 1, j);
     return hipGetLastError();
 }
 
@@ -439,8 +440,8 @@ __global__ void __launch_bounds__(kThreads) k_fcg_start(int64_t n, const T *__re
     GRID_STRIDE(i, n) p[i] = z[i];
 }
 
-// alpha = rz/pq; x += alpha p; r -= alpha q; q = 0; partials of r.r and r.z_old
-template <class T>
+// alpha = rz/pq; x += alpha p; r -= alpha q; q = 0 if CLEAR; partials of r.r and r.z_old
+template <class T, bool CLEAR>
 __global__ void __launch_bounds__(kThreads) k_fcg_update(int64_t n, T *__restrict__ x,
                                                          T *__restrict__ r, const T *__restrict__ p,
                                                          T *__restrict__ q, const T *__restrict__ zold,
@@ -473,7 +474,7 @@ __global__ void __launch_bounds__(kThreads) k_fcg_update(int64_t n, T *__restric
         x[i] += a * p[i];
         const T ri = r[i] - a * q[i];
         r[i] = ri;
-        q[i] = T(0);
+        if (CLEAR) q[i] = T(0);
         rr += (double)ri * (double)ri;
         rzo += (double)ri * (double)zold[i];
     }
@@ -542,9 +543,9 @@ template <class T>
 hipError_t FcgLaunch<T>::update(T *x, T *r, const T *p, T *q, const T *zold, CgScalars *sc, int j) const
 {
     const int g = red_grid(n);
-    hipLaunchKernelGGL(k_fcg_update<T>, dim3(g), dim3(kThreads), 0, s, n, x, r, p, q, zold, sc,
-                       ws.partials, g, ws.partials + kMaxRedBlocks, ws.partials + 2 * kMaxRedBlocks,
-                       j & 1, j);
+    auto kern = clear_q ? k_fcg_update<T, true> : k_fcg_update<T, false>;
+    hipLaunchKernelGGL(kern, dim3(g), dim3(kThreads), 0, s, n, x, r, p, q, zold, sc, ws.partials, g,
+                       ws.partials + kMaxRedBlocks, ws.partials + 2 * kMaxRedBlocks, j & 1, j);
     return hipGetLastError();
 }
 

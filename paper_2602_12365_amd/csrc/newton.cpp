@@ -97,6 +97,7 @@ struct Solver {
         TRY(hipHostMalloc((void **)&h_sc, sizeof(CgScalars), hipHostMallocDefault));
         TRY(hipHostMalloc((void **)&h_scal, 4 * sizeof(double), hipHostMallocDefault));
         L = CgLaunch<T>{n, c.stream, ws};
+        L.clear_q = c.scatter == Scatter::Atomic;
         return EFEM_OK;
     }
 
@@ -144,7 +145,9 @@ struct Solver {
         return EFEM_OK;
     }
 
-    // q is cleared by the CG init/update kernels, so the single-launch form applies
+    // The single-launch form: under the halo and colour scatters it writes
+    // every entry of q; under the atomic scatter it adds into a q that the
+    // CG init/update kernels have cleared (clear_q)
     hipError_t hvp_acc(const T *v, T *y, const int32_t *skip)
     {
         if constexpr (std::is_same<T, double>::value)
@@ -185,6 +188,7 @@ struct Solver {
     {
         MlpState &M = *static_cast<MlpState *>(c.mlp);
         FcgLaunch<float> F{n, c.stream, ws};
+        F.clear_q = c.scatter == Scatter::Atomic;
         const int nz = mlp_apply_grid(c.n_nodes);
         TRY(L.init(b, sign, dinv, c.m.nmask, x, rv, p, q, sc, eta * eta));
         TRY(mlp_precondition(c, M, rv, M.z));

@@ -81,6 +81,32 @@ def test_null_context_is_rejected_without_a_device():
     assert lib.efem_set_dirichlet(None, None) == _lib.EFEM_ERR_INVALID
 
 
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libefem.so not built")
+def test_create_rejects_bad_meshes_without_a_device():
+    """Mesh validation runs on the host before any device call: an
+    out-of-range connectivity entry, and a node that no element uses (the
+    element passes would leave its output entries unwritten)."""
+    import ctypes
+    import numpy as np
+    from paper_2602_12365_amd import _lib, inputs as I
+    lib = _lib.load()
+    m = I.tet_mesh(1)
+    h = ctypes.c_void_p()
+
+    def create(X, conn):
+        X = np.ascontiguousarray(X, dtype=np.float64)
+        conn = np.ascontiguousarray(conn, dtype=np.int32)
+        return lib.efem_create(ctypes.byref(h), I.TET4, X.shape[0], conn.shape[0],
+                               X.ctypes.data_as(ctypes.c_void_p), conn.ctypes.data_as(ctypes.c_void_p),
+                               None, None)
+    bad = np.array(m.conn, copy=True)
+    bad[0, 0] = m.n_nodes
+    assert create(m.X, bad) == _lib.EFEM_ERR_INVALID
+    X_extra = np.vstack([m.X, [[2.0, 2.0, 2.0]]])
+    assert create(X_extra, m.conn) == _lib.EFEM_ERR_INVALID
+    assert b"no element" in lib.efem_last_error()
+
+
 def test_missing_library_fails_loudly(tmp_path, monkeypatch):
     """No CPU fallback: without libefem.so the binding raises ImportError."""
     from paper_2602_12365_amd import _lib

@@ -14,13 +14,13 @@ def dev(a, dtype=torch.float64):
     return torch.as_tensor(np.ascontiguousarray(a)).to("cuda", dtype=dtype)
 
 
-def setup(elem, n, dz, mu_sigma=0.0, n_steps=5, model="neo_hookean"):
+def setup(elem, n, dz, mu_sigma=0.0, n_steps=5, model="neo_hookean", **opts):
     from paper_2602_12365_amd import Operator
     m = I.make_mesh(elem, n)
     mu = np.ones(m.n_elems) if mu_sigma == 0 else I.lognormal_field(m.n_elems, mu_sigma, 3)
     lam = 1.5 * mu
     mask, ubc = I.clamp_top_bottom(m.X, dz)
-    op = Operator(elem, m.X, m.conn, model=model)
+    op = Operator(elem, m.X, m.conn, model=model, **opts)
     op.set_material(dev(mu), dev(lam))
     op.set_dirichlet(dev(mask, torch.uint8))
     orc = F.FEM(elem, m.X, m.conn, mu, lam, model)
@@ -47,6 +47,31 @@ def test_cfg1_newton_matches_oracle(prec):
     assert abs(st["final_energy"] - orc.energy(ug)) <= 1e-12 * abs(orc.energy(ug))
     print(f"[newton] {prec}: newton {st['newton_per_step']} cg {st['cg_per_step']} "
           f"oracle newton {st_ref.newton_iters} cg {st_ref.cg_iters}", flush=True)
+
+
+@pytest.mark.parametrize("scatter", ["color", "atomic"])
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_newton_other_scatters_match_halo(scatter, prec):
+    """The CG update clears q only for the atomic scatter, whose tangent
+    action adds into it; the colour and halo scatters overwrite every entry.
+    Each scatter's solve meets the oracle's tolerance and matches the halo
+    solve (small blocks, so that nodes are shared between many blocks)."""
+    print(f"\n[newton] scatter={scatter} prec={prec}", flush=True)
+    sols = {}
+    for sc in ("halo", scatter):
+        m, op, orc, mask, ubc = setup(I.TET4, 6, 0.1, mu_sigma=0.3, scatter=sc, block_elems=96)
+        u = torch.zeros((m.n_nodes, 3), dtype=torch.float64, device="cuda")
+        rc, st = op.newton_solve(u, dev(ubc), n_steps=3, hvp_prec=prec)
+        assert rc == 0 and st["converged"] == 1, (sc, st)
+        ug = u.cpu().numpy()
+        # scale: the free residual of the prescribed displacement with the
+        # interior at rest (the first residual of a one-step solve)
+        scale = free_residual_norm(orc, np.where(mask.reshape(-1, 3) != 0, ubc.reshape(-1, 3), 0.0), mask)
+        assert free_residual_norm(orc, ug, mask) <= 1e-7 * scale
+        sols[sc] = ug
+        op.close()
+    d = np.linalg.norm(sols["halo"] - sols[scatter]) / np.linalg.norm(sols["halo"])
+    assert d <= 1e-6, d
 
 
 def test_exact_solves_agree_tightly():
