@@ -399,6 +399,10 @@ struct HostChunks {
     std::vector<int32_t> bstart, sstart;
     std::vector<uint32_t> bnew, cnode, items;
     std::vector<int32_t> shared_nodes;   // nodes in more than one chunk, increasing id
+    // a chunk's slots in the order their sums become final (by the last of
+    // its blocks that touches them): fin_slot[s0 + j] is a global slot
+    // index, and the slots final after block b are [fin_start[b], fin_start[b + 1])
+    std::vector<int32_t> fin_slot, fin_start;
     int max_slots = 0;
 };
 
@@ -416,9 +420,11 @@ static bool try_chunks(const HostBlocks &hb, int64_t nn, int n, HostChunks &hc)
     for (int c = 0; c < n; ++c)
         if (hc.bstart[(size_t)c + 1] - hc.bstart[(size_t)c] > kChunkSteps) return false;
     std::vector<int32_t> slot_of((size_t)nn, -1), nchunks((size_t)nn, 0);
-    std::vector<int32_t> touched;
+    std::vector<int32_t> touched, last_blk;
+    hc.fin_start.assign((size_t)nb + 1, 0);
     for (int c = 0; c < n; ++c) {
         touched.clear();
+        last_blk.clear();
         int ns = 0;
         bool fits = true;
         for (int b = hc.bstart[(size_t)c]; b < hc.bstart[(size_t)c + 1] && fits; ++b) {
@@ -429,6 +435,9 @@ static bool try_chunks(const HostBlocks &hb, int64_t nn, int n, HostChunks &hc)
                     slot_of[g] = ns++;
                     touched.push_back((int32_t)g);
                     hc.cnode.push_back(g);
+                    last_blk.push_back(b);
+                } else {
+                    last_blk[(size_t)slot_of[g]] = b;
                 }
             }
             // a block's new slots must span at most one 64-slot group per wave
@@ -453,9 +462,20 @@ static bool try_chunks(const HostBlocks &hb, int64_t nn, int n, HostChunks &hc)
             slot_of[(size_t)g] = -1;
         }
         if (!fits) return false;
+        // the chunk's slots by the block after which they are final (a
+        // counting sort, slot order kept within a block)
+        const int s0 = hc.sstart.back(), cb0 = hc.bstart[(size_t)c], cb1 = hc.bstart[(size_t)c + 1];
+        std::vector<int32_t> cnt((size_t)(cb1 - cb0) + 1, 0);
+        for (int l = 0; l < ns; ++l) cnt[(size_t)(last_blk[(size_t)l] - cb0) + 1] += 1;
+        for (int k = 0; k < cb1 - cb0; ++k) cnt[(size_t)k + 1] += cnt[(size_t)k];
+        for (int k = 0; k < cb1 - cb0; ++k) hc.fin_start[(size_t)(cb0 + k)] = s0 + cnt[(size_t)k];
+        hc.fin_slot.resize((size_t)s0 + ns);
+        for (int l = 0; l < ns; ++l)
+            hc.fin_slot[(size_t)(s0 + cnt[(size_t)(last_blk[(size_t)l] - cb0)]++)] = s0 + l;
         hc.sstart.push_back((int32_t)hc.cnode.size());
         hc.max_slots = std::max(hc.max_slots, ns);
     }
+    hc.fin_start[(size_t)nb] = (int32_t)hc.cnode.size();
     for (uint32_t &e : hc.cnode)
         if (nchunks[e & kGidMask] > 1) e |= kShared;
     for (int64_t g = 0; g < nn; ++g)
@@ -732,9 +752,20 @@ int efem_create(efem_ctx **out, int32_t elem, int64_t n_nodes, int64_t n_elems,
             if ((rc = upload(*ctx, &p_hs, none))) return fail(rc);
         }
         ch.hslot = p_hs;
+        std::vector<uint16_t> fin_rel(hc.fin_slot.size());
+        for (int c = 0; c < ch.n_chunks; ++c)
+            for (int32_t j = hc.sstart[(size_t)c]; j < hc.sstart[(size_t)c + 1]; ++j)
+                fin_rel[(size_t)j] = (uint16_t)(hc.fin_slot[(size_t)j] - hc.sstart[(size_t)c]);
+        int32_t *p_fs, *p_fg;
+        uint16_t *p_fr;
         if ((rc = dalloc(*ctx, &ch.cword, hc.cnode.size()))
-            || (rc = dalloc(*ctx, &ch.cword0, (size_t)ch.n_chunks * kChunkThreads)))
+            || (rc = dalloc(*ctx, &ch.cword0, (size_t)ch.n_chunks * kChunkThreads))
+            || (rc = upload(*ctx, &p_fs, hc.fin_start)) || (rc = upload(*ctx, &p_fr, fin_rel))
+            || (rc = upload(*ctx, &p_fg, hc.fin_slot)) || (rc = dalloc(*ctx, &ch.fin_dst, hc.cnode.size())))
             return fail(rc);
+        ch.fin_start = p_fs;
+        ch.fin_slot = p_fr;
+        ch.fin_gslot = p_fg;
     }
 
     // default material mu = 1, lam = 1.5

@@ -55,7 +55,7 @@ constexpr int kChunkThreads = 768;   // 12 waves per workgroup: 3 per SIMD
 // one 64-slot group of staging words per wave, and the chunk's block table
 constexpr int kPieceBytes = kChunkCap * 16;
 constexpr int kChunkSteps = 32;      // blocks per chunk at most
-constexpr int kChunkLds = 5 * kPieceBytes + kChunkCap * 24 + kChunkThreads * 4 + (3 * kChunkSteps + 2) * 4;
+constexpr int kChunkLds = 5 * kPieceBytes + kChunkCap * 24 + kChunkThreads * 4 + (4 * kChunkSteps + 3) * 4;
 // staging word of a chunk slot: global id | Dirichlet bits << 28
 constexpr uint32_t kStageGid = 0x0fffffffu;
 struct ChunkMesh {
@@ -74,6 +74,16 @@ struct ChunkMesh {
                               // a | b<<11 | (d1 & 1023)<<22,  c | d2<<11 | (d1 >> 10)<<22
     const int32_t *hslot;     // [slots] halo entry of a shared slot, else -1
     double *halo;             // [3 * entries]
+    // write-out in the order the slots' sums become final: the slots final
+    // after block b are entries [fin_start[b], fin_start[b + 1]) (a chunk's
+    // entries lie in its slot range); fin_slot is the chunk-relative slot,
+    // fin_dst where its sum goes: kShared | halo entry, or global id |
+    // Dirichlet bits << 28 (rebuilt with the staging words); fin_gslot the
+    // global slot, for that rebuild
+    const int32_t *fin_start;   // [n_blocks + 1]
+    const uint16_t *fin_slot;   // [slots]
+    const int32_t *fin_gslot;   // [slots]
+    uint32_t *fin_dst;          // [slots]
 };
 
 // Halo entries of the shared nodes, grouped by how many blocks (or chunks)

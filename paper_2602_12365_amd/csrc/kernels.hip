@@ -1839,6 +1839,30 @@ __device__ __forceinline__ void chunk_stage_mask(const BlockMesh &m, unsigned ch
     if (bits & 4u) p4[1] = 0.0;
 }
 
+// Write-out of one chunk slot whose sum is final: to its halo entry (dst =
+// kShared | entry) or to y (dst = global id | Dirichlet bits << 28; ACC:
+// y += sum), prescribed components fixed_val while a mask is in force.
+template <bool ACC>
+__device__ __forceinline__ void chunk_fin_store(const double *acc, int slot, uint32_t dst, double *__restrict__ y,
+                                                double *__restrict__ halo, bool masked, double fixed_val)
+{
+    const double s0 = acc[3 * slot], s1 = acc[3 * slot + 1], s2 = acc[3 * slot + 2];
+    if (dst & kShared) {
+        double *h = halo + 3 * (int64_t)(dst & ~kShared);
+        h[0] = s0, h[1] = s1, h[2] = s2;
+        return;
+    }
+    const int64_t g = dst & kStageGid;
+    const uint32_t bits = masked ? (dst >> 28) & 7u : 0u;
+    const double sv[3] = {s0, s1, s2};
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        double *d = &y[3 * g + c];
+        if ((bits >> c) & 1u) *d = fixed_val;
+        else *d = ACC ? *d + sv[c] : sv[c];
+    }
+}
+
 // s_waitcnt vmcnt(0) (expcnt and lgkmcnt left at their maxima).  The builtin,
 // not inline asm, so that the compiler's own wait insertion knows every
 // vector-memory load has completed here.
@@ -1876,6 +1900,7 @@ k_chunk_hvp64(BlockMesh m, ChunkMesh ch, const double *__restrict__ xrec, const 
     int32_t *t_istart = reinterpret_cast<int32_t *>(smem + 5 * kPieceBytes + kChunkCap * 24 + kChunkThreads * 4);
     int32_t *t_estart = t_istart + kChunkSteps + 1;
     uint32_t *t_bnew = reinterpret_cast<uint32_t *>(t_estart + kChunkSteps + 1);
+    int32_t *t_fin = reinterpret_cast<int32_t *>(t_bnew + kChunkSteps);
     const uint32_t *cword = ch.cword + s0;
     // the items of a step: lane L of wave w takes item L * W + w, so the
     // lanes of one LDS atomic are W items apart in Morton order
@@ -1890,6 +1915,7 @@ k_chunk_hvp64(BlockMesh m, ChunkMesh ch, const double *__restrict__ xrec, const 
     if (wave == 0 && lane <= nsteps) {
         load_to_lds4(m.istart + b0 + lane, __builtin_amdgcn_readfirstlane(lds_addr(t_istart)));
         load_to_lds4(m.estart + b0 + lane, __builtin_amdgcn_readfirstlane(lds_addr(t_estart)));
+        load_to_lds4(ch.fin_start + b0 + lane, __builtin_amdgcn_readfirstlane(lds_addr(t_fin)));
     }
     if (wave == 0 && lane < nsteps) load_to_lds4(ch.bnew + b0 + lane, __builtin_amdgcn_readfirstlane(lds_addr(t_bnew)));
     for (int i = threadIdx.x; i < 3 * ns; i += kChunkThreads) acc[i] = 0.0;
@@ -1898,7 +1924,22 @@ k_chunk_hvp64(BlockMesh m, ChunkMesh ch, const double *__restrict__ xrec, const 
     __syncthreads();
 
     bool bad = false;
+    const bool masked = use_mask != 0 && m.nmask;
+    // Progressive write-out: a slot's sum is final at the barrier after the
+    // last block that touches it.  Its store goes out at the start of the
+    // next step, under that step's arithmetic, instead of in one burst after
+    // the last step.  The destinations are loaded a step ahead, and the
+    // stores are issued at a step's start: every store counts in vmcnt, so a
+    // store issued late in a step would hold up the step's closing wait.
+    int fj = -1, fslot = 0;   // this thread's pending slot (final after the previous block)
+    uint32_t fdst = 0u;
     for (int t = 0; t < nsteps; ++t) {
+        if (fj >= 0) {
+            chunk_fin_store<ACC>(acc, fslot, fdst, y, ch.halo, masked, fixed_val);
+            // more final slots than threads (not met at the default sizes)
+            for (int j = fj + kChunkThreads; j < t_fin[t]; j += kChunkThreads)
+                chunk_fin_store<ACC>(acc, ch.fin_slot[j], ch.fin_dst[j], y, ch.halo, masked, fixed_val);
+        }
         // records of step t+1 on their way, then the words of step t+2
         uint32_t word1 = 0u;
         if (t + 1 < nsteps) {
@@ -1908,6 +1949,16 @@ k_chunk_hvp64(BlockMesh m, ChunkMesh ch, const double *__restrict__ xrec, const 
             if (t + 2 < nsteps) {
                 const int l2 = chunk_stage_slot(t_bnew[t + 2], wave, lane);
                 if (l2 >= 0) load_to_lds4(cword + l2, wdst);
+            }
+        }
+        // the slots final after this step, stored at the next step's start
+        fj = -1;
+        if (t + 1 < nsteps) {
+            const int j = t_fin[t] + (int)threadIdx.x;
+            if (j < t_fin[t + 1]) {
+                fj = j;
+                fslot = ch.fin_slot[j];
+                fdst = ch.fin_dst[j];
             }
         }
         const uint2 cur = itw;
@@ -1958,8 +2009,9 @@ k_chunk_hvp64(BlockMesh m, ChunkMesh ch, const double *__restrict__ xrec, const 
         __syncthreads();
     }
     if (bad) flag_inverted(m.flags);
-    write_out<ACC>(m, ch.cnode + s0, ns, acc, y, Scatter::Halo, use_mask != 0, fixed_val, ch.halo,
-                   ch.hslot + s0);
+    // the slots final after the last step
+    for (int j = t_fin[nsteps - 1] + (int)threadIdx.x; j < t_fin[nsteps]; j += kChunkThreads)
+        chunk_fin_store<ACC>(acc, ch.fin_slot[j], ch.fin_dst[j], y, ch.halo, masked, fixed_val);
 }
 
 // ------------------------------------------------------------------- energy

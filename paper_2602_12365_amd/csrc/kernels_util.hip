@@ -104,8 +104,22 @@ __global__ void k_chunk_words0(ChunkMesh ch, const uint8_t *__restrict__ nmask)
     ch.cword0[i] = w;
 }
 
+// where slot sums go in the write-out order: kShared | halo entry for a node
+// other chunks share, else global id | Dirichlet bits << 28
+__global__ void k_chunk_fin_dst(int64_t n, ChunkMesh ch, const uint8_t *__restrict__ nmask)
+{
+    const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    const int32_t gs = ch.fin_gslot[j];
+    const int32_t hs = ch.hslot[gs];
+    const uint32_t g = ch.cnode[gs] & kStageGid;
+    ch.fin_dst[j] = hs >= 0 ? (kShared | (uint32_t)hs) : (g | (nmask ? (uint32_t)(nmask[g] & 7u) << 28 : 0u));
+}
+
 hipError_t launch_chunk_words(const Ctx &c)
 {
+    hipLaunchKernelGGL(k_chunk_fin_dst, dim3(grid_for(c.n_chunk_slots)), dim3(256), 0, c.stream, c.n_chunk_slots,
+                       c.ch, c.m.nmask);
     hipLaunchKernelGGL(k_chunk_words, dim3(grid_for(c.n_chunk_slots)), dim3(256), 0, c.stream, c.n_chunk_slots,
                        c.ch.cnode, c.m.nmask, c.ch.cword);
     hipLaunchKernelGGL(k_chunk_words0, dim3(grid_for((int64_t)c.ch.n_chunks * kChunkThreads)), dim3(256), 0,
