@@ -177,13 +177,16 @@ def solve_section(args, dev):
     # (mixed) precision (below 1: the network costs more than it saves)
     res["speedup_learned_vs_mixed_jacobi"] = round(runs["mixed_f32_jacobi"]["wall_s"]
                                                    / runs["mixed_f32_learned"]["wall_s"], 3)
+    # the fastest classical preconditioner at both precisions
+    res["speedup_mixed_block_vs_plain_block"] = main["speedup_mixed_block_vs_plain_block"]
     return res
 
 
 def compression_solves(dev, n, seed, theta, theta_pairs=None):
     """Compression case on n^3 Q1 hexes (mu seed `seed`): plain FP64 Jacobi,
-    mixed FP32 Jacobi and mixed FP32 with the learned preconditioner (8
-    flexible-CG iterations per Krylov solve, and whole solves)."""
+    mixed FP32 Jacobi, mixed FP32 with the learned preconditioner (8
+    flexible-CG iterations per Krylov solve, and whole solves), and 3x3 block
+    Jacobi at both precisions."""
     import torch
     from paper_2602_12365_amd import Operator, inputs as I, precond as PC
     mesh, mu, lam, mask, ubc = PC.compression_case(I.HEX8, n, seed)
@@ -199,7 +202,10 @@ def compression_solves(dev, n, seed, theta, theta_pairs=None):
     plan = [("plain_f64_jacobi", dict(hvp_prec="f64", precond=0)),
             ("mixed_f32_jacobi", dict(hvp_prec="f32", precond=0)),
             ("mixed_f32_learned", dict(hvp_prec="f32", precond=1, learned_iters=8)),
-            ("mixed_f32_learned_whole_solve", dict(hvp_prec="f32", precond=1, learned_iters=0))]
+            ("mixed_f32_learned_whole_solve", dict(hvp_prec="f32", precond=1, learned_iters=0)),
+            # 3x3 block Jacobi: the inverses of the nodes' diagonal blocks of K_ff
+            ("plain_f64_block_jacobi", dict(hvp_prec="f64", precond=2)),
+            ("mixed_f32_block_jacobi", dict(hvp_prec="f32", precond=2))]
     if theta_pairs is not None:
         plan += [("mixed_f32_learned_pairs", dict(hvp_prec="f32", precond=1, learned_iters=8, theta=theta_pairs)),
                  ("mixed_f32_learned_pairs_whole_solve",
@@ -237,6 +243,10 @@ def compression_solves(dev, n, seed, theta, theta_pairs=None):
                                                  / runs["mixed_f32_jacobi"]["wall_s"], 3)
     res["speedup_learned_vs_mixed_jacobi"] = round(runs["mixed_f32_jacobi"]["wall_s"]
                                                    / runs["mixed_f32_learned"]["wall_s"], 3)
+    res["speedup_mixed_block_vs_plain_block"] = round(runs["plain_f64_block_jacobi"]["wall_s"]
+                                                      / runs["mixed_f32_block_jacobi"]["wall_s"], 3)
+    res["speedup_mixed_block_vs_plain_jacobi"] = round(runs["plain_f64_jacobi"]["wall_s"]
+                                                       / runs["mixed_f32_block_jacobi"]["wall_s"], 3)
     op.close()
     return res
 

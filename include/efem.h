@@ -237,6 +237,12 @@ int efem_hvp_zeroed(efem_ctx *ctx, const void *v, void *y);
  * with a Dirichlet mask, prescribed entries are 1. */
 int efem_jacobi_diag(efem_ctx *ctx, const double *u, double *d);
 
+/* The off-diagonal entries of every node's 3x3 diagonal block of K(u) (the
+ * blocks of the block-Jacobi preconditioner, whose diagonals efem_jacobi_diag
+ * gives): o DEVICE float64 [n_nodes][3] = (K01, K02, K12), the mask not
+ * applied.  Neo-Hookean and linear models (EFEM_ERR_STATE for transport). */
+int efem_jacobi_offdiag(efem_ctx *ctx, const double *u, double *o);
+
 /* Adjoint with respect to the material at fixed u:
  *   dmu[e] = dPsi/dmu_e, dlam[e] = dPsi/dlam_e   (DEVICE float64 [n_elems]). */
 int efem_grad_material(efem_ctx *ctx, const double *u, double *dmu, double *dlam);
@@ -278,7 +284,9 @@ int efem_status(efem_ctx *ctx, int32_t *flags);
 typedef struct {
     int32_t n_steps;          /* load steps; prescribed values ramp as k/n_steps */
     int32_t hvp_prec;         /* EFEM_F64 or EFEM_F32 for the CG tangent actions */
-    int32_t precond;          /* 0 = Jacobi, 1 = learned (efem_set_mlp) with Jacobi fallback */
+    int32_t precond;          /* 0 = Jacobi, 1 = learned (efem_set_mlp) with Jacobi fallback,
+                                 2 = 3x3 block Jacobi (the inverses of the nodes' diagonal
+                                 blocks of K_ff, rebuilt at every linearization) */
     int32_t max_newton;       /* per load step */
     int32_t max_cg;           /* per linear solve */
     int32_t check_every;      /* CG iterations between host convergence checks (>= 1) */
@@ -428,8 +436,8 @@ int efem_cg_snapshots(efem_ctx *ctx, const double *u, const double *b, double si
 /* Solve K(u)_ff x = b (b, x DEVICE float64 [3*n_nodes]; prescribed entries of b
  * ignored and of x set to 0) by preconditioned CG from x = 0 to
  * ||b - K x|| <= rtol ||b||, with the tangent action in hvp_prec and precond 0
- * (Jacobi) or 1 (learned, flexible CG for the whole solve, Jacobi fallback;
- * needs EFEM_F32).
+ * (Jacobi), 1 (learned, flexible CG for the whole solve, Jacobi fallback;
+ * needs EFEM_F32) or 2 (3x3 block Jacobi).
  * Requires a Dirichlet mask.  Synchronous; *iters receives the CG iterations,
  * *fallback 1 if the learned solve fell back to Jacobi. */
 int efem_linear_solve(efem_ctx *ctx, const double *u, const double *b, double *x, double rtol,

@@ -169,6 +169,15 @@ class FEM:
                "jacobi_diag")
         return d
 
+    def jacobi_offdiag(self, u):
+        """(K01, K02, K12) of every node's 3x3 diagonal block of K(u), [n_nodes, 3]:
+        read off the assembled tangent (with jacobi_diag, the blocks of the
+        block-Jacobi preconditioner)."""
+        K = self.tangent_matrix(u).tocsr()
+        i = 3 * np.arange(self.X.shape[0])
+        return np.stack([np.asarray(K[i, i + 1]).ravel(), np.asarray(K[i, i + 2]).ravel(),
+                         np.asarray(K[i + 1, i + 2]).ravel()], axis=1)
+
     def grad_material(self, u):
         """(dPsi/dmu_e, dPsi/dlam_e) at fixed u."""
         u = self._vec(u)

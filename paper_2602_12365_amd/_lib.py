@@ -87,6 +87,7 @@ SIGNATURES = {
     "efem_hvp_acc": (c_int32, [c_void_p, c_void_p, c_void_p]),
     "efem_hvp_zeroed": (c_int32, [c_void_p, c_void_p, c_void_p]),
     "efem_jacobi_diag": (c_int32, [c_void_p, c_void_p, c_void_p]),
+    "efem_jacobi_offdiag": (c_int32, [c_void_p, c_void_p, c_void_p]),
     "efem_grad_material": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p]),
     "efem_residual_vjp_material": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "efem_grad_coords": (c_int32, [c_void_p, c_void_p, c_void_p]),

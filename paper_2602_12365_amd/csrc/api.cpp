@@ -1036,6 +1036,18 @@ int efem_jacobi_diag(efem_ctx *ctx, const double *u, double *d)
     return EFEM_OK;
 }
 
+int efem_jacobi_offdiag(efem_ctx *ctx, const double *u, double *o)
+{
+    CHECK_ARGS(u && o, "efem_jacobi_offdiag");
+    if (ctx->model == EFEM_MODEL_TRANSPORT) {
+        set_error("efem_jacobi_offdiag: neo-Hookean and linear models only");
+        return EFEM_ERR_STATE;
+    }
+    DeviceGuard dg(ctx->device);
+    HIP_TRY(launch_offdiag(*ctx, u, o));
+    return EFEM_OK;
+}
+
 int efem_grad_material(efem_ctx *ctx, const double *u, double *dmu, double *dlam)
 {
     CHECK_ARGS(u && dmu && dlam, "efem_grad_material");

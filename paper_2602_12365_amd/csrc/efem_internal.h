@@ -143,6 +143,8 @@ hipError_t launch_hvp_f64(const Ctx &c, const double *xlin, const double *v, dou
 hipError_t launch_hvp_f32(const Ctx &c, const float *ulin, const float *v, float *y,
                           const int32_t *skip, WriteMode mode);
 hipError_t launch_diag(const Ctx &c, const double *u, double *d);
+// (K01, K02, K12) of every node's 3x3 diagonal block of K(u), unmasked
+hipError_t launch_offdiag(const Ctx &c, const double *u, double *o);
 hipError_t launch_grad_material(const Ctx &c, const double *u, double *dmu, double *dlam);
 hipError_t launch_vjp_material(const Ctx &c, const double *u, const double *w, double *dmu,
                                double *dlam);

@@ -1083,6 +1083,62 @@ struct DiagOp : XUStage {
     }
 };
 
+// Off-diagonal entries of the 3x3 diagonal blocks of K(u): node n's block
+// is the sum over its elements' points of a (n.S n) I + b k k^T with k =
+// Ad^T grad_xi N_n (DiagOp keeps the diagonal of it), so its off-diagonal
+// entries are b k_i k_j; out [n][3] = (K01, K02, K12).  The linear model's
+// block is (w / De) (mu (t.t) I + (mu + lam) t t^T), t = Ae^T grad_xi N_n.
+template <bool LIN>
+struct OffDiagOp : XUStage {
+    using Node = NodeXU;
+    template <class E>
+    __device__ __forceinline__ bool element(const Node *sn, const uint16_t *lc, const double *mu,
+                                            const double *lam, bool pair, double f[E::NEN][3]) const
+    {
+        typename E::template Field<double> FX, Fu;
+        gather_xu<E>(sn, lc, FX, Fu);
+#pragma unroll
+        for (int a = 0; a < E::NEN; ++a) f[a][0] = f[a][1] = f[a][2] = 0.0;
+        bool ok = true;
+#pragma unroll
+        for (int q = 0; q < E::NQ; ++q) {
+            if (E::skip(q, pair)) continue;
+            const double mq = mu[E::sub(q)], lq = lam[E::sub(q)];
+            double Jx[9], A[9];
+            E::grad(FX, q, Jx);
+            E::geom(Jx);
+            double b;
+            if (LIN) {
+                const double De = adj_det(Jx, A);
+                b = E::template weight<double>() * (mq + lq) / De;
+            } else {
+                double Jd[9], Ae[9];
+                E::grad(Fu, q, Jd);
+#pragma unroll
+                for (int k = 0; k < 9; ++k) Jd[k] += Jx[k];
+                const double De = adj_det(Jx, Ae);
+                const double Dd = adj_det(Jd, A);
+                ok &= Dd > 0.0;
+                const double lnJ = log_(Dd / De);
+                b = E::template weight<double>() * (lq + mq - lq * lnJ) * De / (Dd * Dd);
+            }
+#pragma unroll
+            for (int n = 0; n < E::NEN; ++n) {
+                const double g0 = E::template dN<double>(q, n, 0);
+                const double g1 = E::template dN<double>(q, n, 1);
+                const double g2 = E::template dN<double>(q, n, 2);
+                double k[3];
+#pragma unroll
+                for (int i = 0; i < 3; ++i) k[i] = A[0 * 3 + i] * g0 + A[1 * 3 + i] * g1 + A[2 * 3 + i] * g2;
+                f[n][0] += b * k[0] * k[1];
+                f[n][1] += b * k[0] * k[2];
+                f[n][2] += b * k[1] * k[2];
+            }
+        }
+        return ok;
+    }
+};
+
 // dPsi/dX at fixed nodal u: Q = w det Jx (psi I - H^T P) Jx^-T
 struct GradCoordsOp : XUStage {
     using Node = NodeXU;
@@ -2388,6 +2444,20 @@ hipError_t launch_diag(const Ctx &c, const double *u, double *d)
     op.X = c.m.X;
     op.u = u;
     return dispatch(c, op, d, true, 1.0);
+}
+
+hipError_t launch_offdiag(const Ctx &c, const double *u, double *o)
+{
+    if (c.model == EFEM_MODEL_LINEAR) {
+        OffDiagOp<true> op;
+        op.X = c.m.X;
+        op.u = u;
+        return dispatch(c, op, o, false, 0.0);
+    }
+    OffDiagOp<false> op;
+    op.X = c.m.X;
+    op.u = u;
+    return dispatch(c, op, o, false, 0.0);
 }
 
 hipError_t launch_grad_coords(const Ctx &c, const double *u, double *g)

@@ -189,6 +189,190 @@ __global__ void __launch_bounds__(kThreads) k_cg_dir(int64_t n, T *__restrict__ 
     GRID_STRIDE(i, n) p[i] = dinv[i] * r[i] + bt * p[i];
 }
 
+// ------------------------------------------------ 3x3 block Jacobi
+
+// binv [n_nodes][6] = (B00, B11, B22, B01, B02, B12), the inverse of each
+// node's 3x3 diagonal block of K_ff: diagonal d [3 n_nodes], off-diagonals
+// o [n_nodes][3] = (K01, K02, K12).  Prescribed components leave the block
+// (their rows and columns of the inverse are 0).  A block that is not
+// positive definite (leading minors) falls back to its diagonal inverse.
+__global__ void k_block_inv(int64_t nn, const double *__restrict__ d, const double *__restrict__ o,
+                            const uint8_t *__restrict__ nmask, float *__restrict__ binv)
+{
+    GRID_STRIDE(i, nn)
+    {
+        const uint8_t m = nmask ? nmask[i] : 0;
+        const bool f0 = m & 1, f1 = (m >> 1) & 1, f2 = (m >> 2) & 1;
+        const double a00 = f0 ? 1.0 : d[3 * i], a11 = f1 ? 1.0 : d[3 * i + 1], a22 = f2 ? 1.0 : d[3 * i + 2];
+        const double a01 = (f0 || f1) ? 0.0 : o[3 * i], a02 = (f0 || f2) ? 0.0 : o[3 * i + 1];
+        const double a12 = (f1 || f2) ? 0.0 : o[3 * i + 2];
+        const double c00 = a11 * a22 - a12 * a12, c01 = a02 * a12 - a01 * a22, c02 = a01 * a12 - a02 * a11;
+        const double c11 = a00 * a22 - a02 * a02, c12 = a01 * a02 - a00 * a12, c22 = a00 * a11 - a01 * a01;
+        const double det = a00 * c00 + a01 * c01 + a02 * c02;
+        double b[6];
+        if (a00 > 0.0 && c22 > 0.0 && det > 0.0 && isfinite(det)) {
+            const double r = 1.0 / det;
+            b[0] = c00 * r, b[1] = c11 * r, b[2] = c22 * r, b[3] = c01 * r, b[4] = c02 * r, b[5] = c12 * r;
+        } else {
+            b[0] = a00 > 0.0 ? 1.0 / a00 : 0.0;
+            b[1] = a11 > 0.0 ? 1.0 / a11 : 0.0;
+            b[2] = a22 > 0.0 ? 1.0 / a22 : 0.0;
+            b[3] = b[4] = b[5] = 0.0;
+        }
+        if (f0) b[0] = b[3] = b[4] = 0.0;
+        if (f1) b[1] = b[3] = b[5] = 0.0;
+        if (f2) b[2] = b[4] = b[5] = 0.0;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) binv[6 * i + k] = (float)b[k];
+    }
+}
+
+// z = B r for node i's block
+template <class T>
+__device__ __forceinline__ void block_apply(const float *__restrict__ binv, int64_t i, T r0, T r1, T r2, T &z0,
+                                            T &z1, T &z2)
+{
+    const T b00 = T(binv[6 * i]), b11 = T(binv[6 * i + 1]), b22 = T(binv[6 * i + 2]);
+    const T b01 = T(binv[6 * i + 3]), b02 = T(binv[6 * i + 4]), b12 = T(binv[6 * i + 5]);
+    z0 = b00 * r0 + b01 * r1 + b02 * r2;
+    z1 = b01 * r0 + b11 * r1 + b12 * r2;
+    z2 = b02 * r0 + b12 * r1 + b22 * r2;
+}
+
+// The PCG kernels with the block preconditioner, one node (three DOFs) per
+// thread; their reductions and scalar logic are those of the DOF-wise ones.
+template <class T>
+__global__ void __launch_bounds__(kThreads) k_cgb_init(int64_t nn, const double *__restrict__ b, double sign,
+                                                       const float *__restrict__ binv,
+                                                       const uint8_t *__restrict__ nmask, T *__restrict__ x,
+                                                       T *__restrict__ r, T *__restrict__ p, T *__restrict__ q,
+                                                       double *__restrict__ prr, double *__restrict__ prz)
+{
+    __shared__ double red[kThreads];
+    double rz = 0.0, rr = 0.0;
+    GRID_STRIDE(i, nn)
+    {
+        T rv[3], z[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) rv[c] = dof_fixed(nmask, 3 * i + c) ? T(0) : T(sign * b[3 * i + c]);
+        block_apply(binv, i, rv[0], rv[1], rv[2], z[0], z[1], z[2]);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            r[3 * i + c] = rv[c];
+            p[3 * i + c] = z[c];
+            x[3 * i + c] = T(0);
+            q[3 * i + c] = T(0);
+            rz += (double)rv[c] * (double)z[c];
+            rr += (double)rv[c] * (double)rv[c];
+        }
+    }
+    const double srr = block_sum(rr, red);
+    const double srz = block_sum(rz, red);
+    if (threadIdx.x == 0) {
+        prr[blockIdx.x] = srr;
+        prz[blockIdx.x] = srz;
+    }
+}
+
+template <class T, bool CLEAR>
+__global__ void __launch_bounds__(kThreads) k_cgb_update(int64_t nn, T *__restrict__ x, T *__restrict__ r,
+                                                         const T *__restrict__ p, T *__restrict__ q,
+                                                         const float *__restrict__ binv, CgScalars *sc,
+                                                         const double *__restrict__ ppq, int count,
+                                                         double *__restrict__ prr, double *__restrict__ prz,
+                                                         int par, int j)
+{
+    __shared__ double red[kThreads];
+    if (sc->done) return;
+    const double pq = sum_partials(ppq, count, red);
+    if (!(pq > 0.0) || !isfinite(pq)) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            sc->pq = pq;
+            sc->breakdown = 1;
+            sc->done = 1;
+        }
+        return;
+    }
+    const double alpha = sc->rz[par] / pq;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        sc->pq = pq;
+        sc->alpha = alpha;
+        sc->iter = j + 1;
+    }
+    const T a = (T)alpha;
+    double rr = 0.0, rz = 0.0;
+    GRID_STRIDE(i, nn)
+    {
+        T rv[3], z[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const int64_t k = 3 * i + c;
+            x[k] += a * p[k];
+            rv[c] = r[k] - a * q[k];
+            r[k] = rv[c];
+            if (CLEAR) q[k] = T(0);
+        }
+        block_apply(binv, i, rv[0], rv[1], rv[2], z[0], z[1], z[2]);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            rr += (double)rv[c] * (double)rv[c];
+            rz += (double)rv[c] * (double)z[c];
+        }
+    }
+    const double srr = block_sum(rr, red);
+    const double srz = block_sum(rz, red);
+    if (threadIdx.x == 0) {
+        prr[blockIdx.x] = srr;
+        prz[blockIdx.x] = srz;
+    }
+}
+
+template <class T>
+__global__ void __launch_bounds__(kThreads) k_cgb_dir(int64_t nn, T *__restrict__ p, const T *__restrict__ r,
+                                                      const float *__restrict__ binv, CgScalars *sc,
+                                                      const double *__restrict__ prr,
+                                                      const double *__restrict__ prz, int count, int par)
+{
+    __shared__ double red[kThreads];
+    if (sc->done) return;
+    const double rr = sum_partials(prr, count, red);
+    const double rz = sum_partials(prz, count, red);
+    if (rr <= sc->tol2 || !isfinite(rr)) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            sc->rr = rr;
+            sc->done = 1;
+        }
+        return;
+    }
+    const double beta = rz / sc->rz[par];
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        sc->rz[par ^ 1] = rz;
+        sc->rr = rr;
+        sc->beta = beta;
+    }
+    const T bt = (T)beta;
+    GRID_STRIDE(i, nn)
+    {
+        T z[3];
+        block_apply(binv, i, r[3 * i], r[3 * i + 1], r[3 * i + 2], z[0], z[1], z[2]);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) p[3 * i + c] = z[c] + bt * p[3 * i + c];
+    }
+}
+
+template <class T>
+__global__ void k_cgb_scaled(int64_t nn, const float *__restrict__ binv, const double *__restrict__ b,
+                             double sign, T *__restrict__ x)
+{
+    GRID_STRIDE(i, nn)
+    {
+        T z[3];
+        block_apply(binv, i, T(sign * b[3 * i]), T(sign * b[3 * i + 1]), T(sign * b[3 * i + 2]), z[0], z[1], z[2]);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) x[3 * i + c] = z[c];
+    }
+}
+
 // partials of a.b
 template <class TA, class TB>
 __global__ void __launch_bounds__(kThreads) k_dot(int64_t n, const TA *__restrict__ a,
@@ -287,9 +471,13 @@ template <class T>
 hipError_t CgLaunch<T>::init(const double *b, double sign, const T *dinv, const uint8_t *nmask,
                              T *x, T *r, T *p, T *q, CgScalars *sc, double eta2) const
 {
-    const int g = red_grid(n);
-    hipLaunchKernelGGL(k_cg_init<T>, dim3(g), dim3(kThreads), 0, s, n, b, sign, dinv, nmask, x, r,
-                       p, q, ws.partials + kMaxRedBlocks, ws.partials + 2 * kMaxRedBlocks);
+    const int g = binv ? red_grid(n / 3) : red_grid(n);
+    if (binv)
+        hipLaunchKernelGGL(k_cgb_init<T>, dim3(g), dim3(kThreads), 0, s, n / 3, b, sign, binv, nmask, x, r, p, q,
+                           ws.partials + kMaxRedBlocks, ws.partials + 2 * kMaxRedBlocks);
+    else
+        hipLaunchKernelGGL(k_cg_init<T>, dim3(g), dim3(kThreads), 0, s, n, b, sign, dinv, nmask, x, r,
+                           p, q, ws.partials + kMaxRedBlocks, ws.partials + 2 * kMaxRedBlocks);
     hipLaunchKernelGGL(k_cg_init_fin, dim3(1), dim3(kThreads), 0, s, ws.partials + kMaxRedBlocks,
                        ws.partials + 2 * kMaxRedBlocks, g, sc, eta2);
     return hipGetLastError();
@@ -305,9 +493,16 @@ hipError_t CgLaunch<T>::pq(const T *p, const T *q, CgScalars *sc) const
 template <class T>
 hipError_t CgLaunch<T>::update(T *x, T *r, const T *p, T *q, const T *dinv, CgScalars *sc, int j) const
 {
-    const int g = red_grid(n);
+    const int gpq = red_grid(n);   // partials of k_cg_pq
+    if (binv) {
+        const int g = red_grid(n / 3);
+        auto kern = clear_q ? k_cgb_update<T, true> : k_cgb_update<T, false>;
+        hipLaunchKernelGGL(kern, dim3(g), dim3(kThreads), 0, s, n / 3, x, r, p, q, binv, sc, ws.partials, gpq,
+                           ws.partials + kMaxRedBlocks, ws.partials + 2 * kMaxRedBlocks, j & 1, j);
+        return hipGetLastError();
+    }
     auto kern = clear_q ? k_cg_update<T, true> : k_cg_update<T, false>;
-    hipLaunchKernelGGL(kern, dim3(g), dim3(kThreads), 0, s, n, x, r, p, q, dinv, sc, ws.partials, g,
+    hipLaunchKernelGGL(kern, dim3(gpq), dim3(kThreads), 0, s, n, x, r, p, q, dinv, sc, ws.partials, gpq,
                        ws.partials + kMaxRedBlocks, ws.partials + 2 * kMaxRedBlocks, j & 1, j);
     return hipGetLastError();
 }
@@ -315,6 +510,12 @@ hipError_t CgLaunch<T>::update(T *x, T *r, const T *p, T *q, const T *dinv, CgSc
 template <class T>
 hipError_t CgLaunch<T>::dir(T *p, const T *r, const T *dinv, CgScalars *sc, int j) const
 {
+    if (binv) {
+        const int g = red_grid(n / 3);
+        hipLaunchKernelGGL(k_cgb_dir<T>, dim3(g), dim3(kThreads), 0, s, n / 3, p, r, binv, sc,
+                           ws.partials + kMaxRedBlocks, ws.partials + 2 * kMaxRedBlocks, g, j & 1);
+        return hipGetLastError();
+    }
     const int g = red_grid(n);
     hipLaunchKernelGGL(k_cg_dir<T>, dim3(g), dim3(kThreads), 0, s, n, p, r, dinv, sc,
                        ws.partials + kMaxRedBlocks, ws.partials + 2 * kMaxRedBlocks, g, j & 1);
@@ -352,6 +553,10 @@ hipError_t CgLaunch<T>::add_to(T *x, const T *d) const
 template <class T>
 hipError_t CgLaunch<T>::scaled(const T *dinv, const double *b, double sign, T *x) const
 {
+    if (binv) {
+        hipLaunchKernelGGL(k_cgb_scaled<T>, dim3(red_grid(n / 3)), dim3(kThreads), 0, s, n / 3, binv, b, sign, x);
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL(k_scaled<T>, dim3(red_grid(n)), dim3(kThreads), 0, s, n, dinv, b, sign, x);
     return hipGetLastError();
 }
@@ -557,6 +762,13 @@ hipError_t FcgLaunch<T>::dir(T *p, const T *z, CgScalars *sc, const double *prz,
     hipLaunchKernelGGL(k_fcg_dir<T>, dim3(g), dim3(kThreads), 0, s, n, p, z, sc,
                        ws.partials + kMaxRedBlocks, ws.partials + 2 * kMaxRedBlocks, g, prz, nz,
                        j & 1, stall_limit);
+    return hipGetLastError();
+}
+
+hipError_t launch_block_inv(hipStream_t s, int64_t n_nodes, const double *d, const double *o,
+                            const uint8_t *nmask, float *binv)
+{
+    hipLaunchKernelGGL(k_block_inv, dim3(red_grid(n_nodes)), dim3(kThreads), 0, s, n_nodes, d, o, nmask, binv);
     return hipGetLastError();
 }
 

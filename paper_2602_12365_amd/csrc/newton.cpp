@@ -46,6 +46,8 @@ struct Solver {
     double *r = nullptr, *dc = nullptr, *u_old = nullptr, *u_trial = nullptr, *diag = nullptr,
            *kdc = nullptr, *dscal = nullptr;
     T *x = nullptr, *rv = nullptr, *p = nullptr, *q = nullptr, *dinv = nullptr;
+    double *off = nullptr;   // precond = 2: off-diagonals of the nodes' 3x3 blocks
+    float *binv = nullptr;   // and their inverses [n_nodes][6]
     double load_s = 0.0;   // load factor of the current step
     CgScalars *sc = nullptr;
     CgWorkspace ws;
@@ -82,6 +84,7 @@ struct Solver {
             || (rc = alloc(&p, n)) || (rc = alloc(&q, n)) || (rc = alloc(&dinv, n))
             || (rc = alloc(&sc, 1)) || (rc = alloc(&ws.partials, 4 * kMaxRedBlocks)))
             return rc;
+        if (o.precond == 2 && ((rc = alloc(&off, n)) || (rc = alloc(&binv, 2 * n)))) return rc;
         if (!c.xlin) {
             void *q_ = nullptr;
             TRY(hipMalloc(&q_, 2 * n * sizeof(double)));   // (X, X + u) per node
@@ -233,10 +236,18 @@ struct Solver {
         return EFEM_OK;
     }
 
+    // the Jacobi diagonal at u (and with precond = 2 the inverses of the
+    // nodes' 3x3 diagonal blocks, which PCG then applies instead)
     int set_dinv(const double *u)
     {
         TRY(launch_diag(c, u, diag));
         TRY(L.dinv_from_diag(diag, c.m.nmask, dinv));
+        L.binv = nullptr;
+        if (o.precond == 2) {
+            TRY(launch_offdiag(c, u, off));
+            TRY(launch_block_inv(c.stream, c.n_nodes, diag, off, c.m.nmask, binv));
+            L.binv = binv;
+        }
         return EFEM_OK;
     }
 
@@ -462,7 +473,7 @@ int efem_newton_solve(efem_ctx *ctx, double *u_inout, const double *u_bc, const 
         return EFEM_ERR_STATE;
     }
     if (opts->n_steps < 1 || opts->max_cg < 1 || opts->max_newton < 0 || opts->rtol <= 0
-        || (opts->hvp_prec != EFEM_F64 && opts->hvp_prec != EFEM_F32)) {
+        || (opts->hvp_prec != EFEM_F64 && opts->hvp_prec != EFEM_F32) || opts->precond < 0 || opts->precond > 2) {
         set_error("efem_newton_solve: bad options");
         return EFEM_ERR_INVALID;
     }
@@ -494,7 +505,7 @@ extern "C" int efem_linear_solve(efem_ctx *ctx, const double *u, const double *b
                                  int32_t *iters, int32_t *fallback)
 {
     if (!ctx || !u || !b || !x || !(rtol > 0) || max_iter < 1
-        || (hvp_prec != EFEM_F64 && hvp_prec != EFEM_F32) || (precond != 0 && precond != 1)) {
+        || (hvp_prec != EFEM_F64 && hvp_prec != EFEM_F32) || precond < 0 || precond > 2) {
         set_error("efem_linear_solve: bad argument");
         return EFEM_ERR_INVALID;
     }

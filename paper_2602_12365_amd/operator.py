@@ -248,6 +248,16 @@ class Operator:
                 "efem_jacobi_diag")
         return out
 
+    def jacobi_offdiag(self, u, out=None):
+        """(K01, K02, K12) of every node's 3x3 diagonal block of K(u), float64
+        [n_nodes, 3], the mask not applied (the block-Jacobi preconditioner's
+        blocks with jacobi_diag)."""
+        self._sync_stream()
+        out = self._new_nodal() if out is None else self._nodal(out, name="out")
+        L.check(self._lib.efem_jacobi_offdiag(self._h, _ptr(self._nodal(u, name="u")), _ptr(out)),
+                "efem_jacobi_offdiag")
+        return out
+
     def grad_material(self, u):
         self._sync_stream()
         dmu = torch.empty(self.n_elems, dtype=torch.float64, device=self.device)
@@ -347,8 +357,9 @@ class Operator:
         return out
 
     def linear_solve(self, u, b, rtol=1e-8, hvp_prec="f64", precond=0, max_iter=100000):
-        """Solve K(u)_ff x = b by preconditioned CG (Jacobi, or the learned
-        preconditioner with flexible CG); returns (x, iterations, fell_back)."""
+        """Solve K(u)_ff x = b by preconditioned CG (precond 0 Jacobi, 1 the
+        learned preconditioner with flexible CG, 2 3x3 block Jacobi); returns
+        (x, iterations, fell_back)."""
         self._sync_stream()
         x = self._new_nodal()
         it, fb = ctypes.c_int32(), ctypes.c_int32()

@@ -74,6 +74,38 @@ def test_newton_other_scatters_match_halo(scatter, prec):
     assert d <= 1e-6, d
 
 
+@pytest.mark.parametrize("elem", [I.TET4, I.HEX8])
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_block_jacobi_solve(elem, prec):
+    """precond = 2 (the inverses of the nodes' 3x3 diagonal blocks of K_ff):
+    the solve meets the oracle's tolerance and matches the Jacobi solve
+    (lognormal(0, 0.5) shear modulus).  The iteration counts are printed,
+    not asserted: on these small meshes the blocks save nothing."""
+    n = 8 if elem == I.TET4 else 6
+    print(f"\n[newton] block Jacobi elem={elem} prec={prec}", flush=True)
+    m, op, orc, mask, ubc = setup(elem, n, -0.1, mu_sigma=0.5)
+    scale = free_residual_norm(orc, np.where(mask.reshape(-1, 3) != 0, ubc.reshape(-1, 3), 0.0), mask)
+    res = {}
+    for pc in (0, 2):
+        u = torch.zeros((m.n_nodes, 3), dtype=torch.float64, device="cuda")
+        rc, st = op.newton_solve(u, dev(ubc), n_steps=3, hvp_prec=prec, precond=pc)
+        assert rc == 0 and st["converged"] == 1, (pc, st)
+        ug = u.cpu().numpy()
+        assert free_residual_norm(orc, ug, mask) <= 1e-7 * scale
+        res[pc] = (ug, st["cg_iters"])
+    d = np.linalg.norm(res[0][0] - res[2][0]) / np.linalg.norm(res[0][0])
+    print(f"[newton] CG iterations Jacobi {res[0][1]}, block Jacobi {res[2][1]}; rel diff {d:.1e}", flush=True)
+    assert d <= 1e-6
+    # a linear solve with the blocks
+    rtol = 1e-10 if prec == "f64" else 1e-5
+    x, it, fb = op.linear_solve(dev(res[2][0]), dev(I.unit_direction(m.n_nodes, 3)), rtol=rtol, hvp_prec=prec,
+                                precond=2)
+    assert it > 0 and not fb
+    b = F.masked(mask, I.unit_direction(m.n_nodes, 3))
+    kx = F.masked(mask, orc.hvp(res[2][0], x.cpu().numpy()))
+    assert np.linalg.norm(kx - b) <= (1e-8 if prec == "f64" else 1e-4) * np.linalg.norm(b)
+
+
 def test_exact_solves_agree_tightly():
     m, op, orc, mask, ubc = setup(I.TET4, 4, 0.1)
     u = torch.zeros((m.n_nodes, 3), dtype=torch.float64, device="cuda")

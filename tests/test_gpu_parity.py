@@ -151,6 +151,15 @@ def test_jacobi_diag(case):
     assert rel(d, case.orc.jacobi_diag(case.u)) <= TOL64
 
 
+def test_jacobi_offdiag(case):
+    """Off-diagonal entries of the nodes' 3x3 diagonal blocks of K (the
+    block-Jacobi preconditioner) against the oracle's assembled tangent."""
+    o = host(case.op.jacobi_offdiag(dev(case.u)))
+    ref = case.orc.jacobi_offdiag(case.u)
+    scale = np.abs(case.orc.jacobi_diag(case.u)).max()
+    assert np.abs(o - ref).max() <= TOL64 * scale
+
+
 def test_grad_material(case):
     gm, gl = case.op.grad_material(dev(case.u))
     rm, rl = case.orc.grad_material(case.u)

@@ -74,3 +74,28 @@ def test_tangent_matrix_rigid_modes_and_residual_fd(elem):
         fd = (orc.residual(u + e.reshape(n, 3)) - orc.residual(u - e.reshape(n, 3))).reshape(-1) / (2 * h)
         col = K[:, j].toarray().ravel()
         assert np.abs(col - fd).max() <= 1e-7 * np.abs(col).max()
+
+
+@pytest.mark.parametrize("elem", [I.TET4, I.HEX8])
+@pytest.mark.parametrize("model", ["neo_hookean", "linear"])
+def test_jacobi_blocks_by_central_differences(elem, model):
+    """Every node's 3x3 diagonal block of K (jacobi_diag and jacobi_offdiag),
+    against central differences of the residual at that node with respect to
+    that node's own displacement: no assembled matrix involved."""
+    m = I.make_mesh(elem, 2)
+    mu = I.lognormal_field(m.n_elems, 0.3, 1)
+    orc = F.FEM(elem, m.X, m.conn, mu, 1.5 * mu, model)
+    u = I.gaussian_field(m.n_nodes, 0.01, 0)
+    d, off = orc.jacobi_diag(u), orc.jacobi_offdiag(u)
+    h = 1e-6
+    for a in range(m.n_nodes):
+        B = np.empty((3, 3))
+        for j in range(3):
+            up, um = u.copy(), u.copy()
+            up[a, j] += h
+            um[a, j] -= h
+            B[:, j] = (orc.residual(up)[a] - orc.residual(um)[a]) / (2 * h)
+        scale = np.abs(B).max()
+        assert np.abs(np.diag(B) - d[a]).max() <= 1e-7 * scale
+        assert np.abs(np.array([B[0, 1], B[0, 2], B[1, 2]]) - off[a]).max() <= 1e-7 * scale
+        assert np.abs(B - B.T).max() <= 1e-7 * scale
