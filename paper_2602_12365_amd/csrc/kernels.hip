@@ -54,6 +54,24 @@ __device__ __forceinline__ T adj_det(const T m[9], T a[9])
     return m[0] * a[0] + m[1] * a[3] + m[2] * a[6];
 }
 
+// adj_det with the adjugate's last row given: row 2 of adj(m) is the cross
+// product of m's first two columns, which the two tetrahedra of a face pair
+// share up to sign (their first two edges are the shared face's, swapped)
+template <class T>
+__device__ __forceinline__ T adj_det_row2(const T m[9], const T r2[3], T a[9])
+{
+    a[0] = m[4] * m[8] - m[5] * m[7];
+    a[1] = m[2] * m[7] - m[1] * m[8];
+    a[2] = m[1] * m[5] - m[2] * m[4];
+    a[3] = m[5] * m[6] - m[3] * m[8];
+    a[4] = m[0] * m[8] - m[2] * m[6];
+    a[5] = m[2] * m[3] - m[0] * m[5];
+    a[6] = r2[0];
+    a[7] = r2[1];
+    a[8] = r2[2];
+    return m[0] * a[0] + m[1] * a[3] + m[2] * a[6];
+}
+
 // Reciprocal: the hardware estimate refined by two Newton-Raphson steps
 // r <- r + r (1 - x r) (each step squares the relative error), so the FP64
 // result is correct to about an ulp for the normal-range determinants used
@@ -577,13 +595,26 @@ struct Hex8 {
 // ------------------------------------------------------ quadrature-point math
 
 // Tangent action at one point: Q = w det Jx dP Jx^-T.  Returns false if det Jd <= 0.
-template <class T>
+// ROW2 = 1: the adjugates' last rows go to r2x, r2d as well; ROW2 = 2: they are
+// taken as -r2x, -r2d (the second tetrahedron of a face pair).
+template <class T, int ROW2 = 0>
 __device__ __forceinline__ bool qp_hvp(T w, const T Jx[9], const T Jd[9], const T dJ[9], T mu,
-                                       T lam, T Q[9])
+                                       T lam, T Q[9], T *r2x = nullptr, T *r2d = nullptr)
 {
     T Ae[9], Ad[9];
-    const T De = adj_det(Jx, Ae);
-    const T Dd = adj_det(Jd, Ad);
+    T De, Dd;
+    if constexpr (ROW2 == 2) {
+        const T nx[3] = {-r2x[0], -r2x[1], -r2x[2]}, nd[3] = {-r2d[0], -r2d[1], -r2d[2]};
+        De = adj_det_row2(Jx, nx, Ae);
+        Dd = adj_det_row2(Jd, nd, Ad);
+    } else {
+        De = adj_det(Jx, Ae);
+        Dd = adj_det(Jd, Ad);
+        if constexpr (ROW2 == 1) {
+#pragma unroll
+            for (int i = 0; i < 3; ++i) r2x[i] = Ae[6 + i], r2d[i] = Ad[6 + i];
+        }
+    }
     // S = Ae Ae^T (symmetric)
     const T S00 = Ae[0] * Ae[0] + Ae[1] * Ae[1] + Ae[2] * Ae[2];
     const T S01 = Ae[0] * Ae[3] + Ae[1] * Ae[4] + Ae[2] * Ae[5];
@@ -896,6 +927,24 @@ template <> struct HvpOp<double> {
         G::prep(xe, Fx);
         G::prep(ve, Fv);
         bool ok = true;
+        if constexpr (std::is_same<E, Tet4Pair>::value) {
+            // a face pair: the second tetrahedron reuses the shared face's
+            // cross products from the first
+            double Jx[9], Jd[9], dJ[9], Q[9], r2x[3], r2d[3];
+            G::grad(FX, 0, Jx);
+            G::grad(Fx, 0, Jd);
+            G::grad(Fv, 0, dJ);
+            ok &= qp_hvp<double, 1>(E::template weight<double>(), Jx, Jd, dJ, mu[0], lam[0], Q, r2x, r2d);
+            G::template add_forces_to<true>(Q, 0, f);
+            if (pair) {
+                G::grad(FX, 1, Jx);
+                G::grad(Fx, 1, Jd);
+                G::grad(Fv, 1, dJ);
+                ok &= qp_hvp<double, 2>(E::template weight<double>(), Jx, Jd, dJ, mu[1], lam[1], Q, r2x, r2d);
+                G::template add_forces_to<true>(Q, 1, f);
+            }
+            return ok;
+        }
 #pragma unroll
         for (int q = 0; q < E::NQ; ++q) {
             if (E::skip(q, pair)) continue;
