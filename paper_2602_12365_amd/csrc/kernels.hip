@@ -595,8 +595,12 @@ struct Hex8 {
 // ------------------------------------------------------ quadrature-point math
 
 // Tangent action at one point: Q = w det Jx dP Jx^-T.  Returns false if det Jd <= 0.
-// ROW2 = 1: the adjugates' last rows go to r2x, r2d as well; ROW2 = 2: they are
-// taken as -r2x, -r2d (the second tetrahedron of a face pair).
+// The two tetrahedra of a face pair share what depends only on the face: the
+// adjugates' last rows (cross products of the first two Jacobian columns,
+// which the second tetrahedron has swapped), S22 = |last row of Ae|^2, and
+// W20, W21 (the last row of Ad against the face's two edges of v).
+// ROW2 = 1: those go out to r2x = {Ae row 2, S22}, r2d = {Ad row 2, W20,
+// W21}; ROW2 = 2: they are taken from there, signs and columns swapped.
 template <class T, int ROW2 = 0>
 __device__ __forceinline__ bool qp_hvp(T w, const T Jx[9], const T Jd[9], const T dJ[9], T mu,
                                        T lam, T Q[9], T *r2x = nullptr, T *r2d = nullptr)
@@ -621,7 +625,10 @@ __device__ __forceinline__ bool qp_hvp(T w, const T Jx[9], const T Jd[9], const 
     const T S02 = Ae[0] * Ae[6] + Ae[1] * Ae[7] + Ae[2] * Ae[8];
     const T S11 = Ae[3] * Ae[3] + Ae[4] * Ae[4] + Ae[5] * Ae[5];
     const T S12 = Ae[3] * Ae[6] + Ae[4] * Ae[7] + Ae[5] * Ae[8];
-    const T S22 = Ae[6] * Ae[6] + Ae[7] * Ae[7] + Ae[8] * Ae[8];
+    T S22;
+    if constexpr (ROW2 == 2) S22 = r2x[3];
+    else S22 = Ae[6] * Ae[6] + Ae[7] * Ae[7] + Ae[8] * Ae[8];
+    if constexpr (ROW2 == 1) r2x[3] = S22;
     const T rDe = rcp(De), rDd = rcp(Dd);
     const T a = w * mu * rDe;
     const T s2 = w * De * rDd * rDd;
@@ -632,9 +639,19 @@ __device__ __forceinline__ bool qp_hvp(T w, const T Jx[9], const T Jd[9], const 
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
-        for (int j = 0; j < 3; ++j)
+        for (int j = 0; j < 3; ++j) {
+            if (ROW2 == 2 && i == 2 && j < 2) continue;
             W[i * 3 + j] = Ad[i * 3 + 0] * dJ[0 * 3 + j] + Ad[i * 3 + 1] * dJ[1 * 3 + j]
                          + Ad[i * 3 + 2] * dJ[2 * 3 + j];
+        }
+    if constexpr (ROW2 == 2) {
+        W[6] = -r2d[4];
+        W[7] = -r2d[3];
+    }
+    if constexpr (ROW2 == 1) {
+        r2d[3] = W[6];
+        r2d[4] = W[7];
+    }
     const T tr = W[0] + W[4] + W[8];
     const T b = lam * tr * s2;
     const T c = c1 * s2;
@@ -930,7 +947,7 @@ template <> struct HvpOp<double> {
         if constexpr (std::is_same<E, Tet4Pair>::value) {
             // a face pair: the second tetrahedron reuses the shared face's
             // cross products from the first
-            double Jx[9], Jd[9], dJ[9], Q[9], r2x[3], r2d[3];
+            double Jx[9], Jd[9], dJ[9], Q[9], r2x[4], r2d[5];
             G::grad(FX, 0, Jx);
             G::grad(Fx, 0, Jd);
             G::grad(Fv, 0, dJ);
