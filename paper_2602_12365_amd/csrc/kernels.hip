@@ -1015,6 +1015,8 @@ template <> struct HvpOp<float> {
         E::prep(ve, Fv);
         typename E::template Acc<float> A;
         bool ok = true;
+        // face pairs: the second tetrahedron reuses the face's shared terms
+        float r2x[4], r2d[5];
 #pragma unroll
         for (int q = 0; q < E::NQ; ++q) {
             if (E::skip(q, pair)) continue;
@@ -1025,7 +1027,14 @@ template <> struct HvpOp<float> {
 #pragma unroll
             for (int k = 0; k < 9; ++k) Jd[k] += Jx[k];
             E::grad(Fv, q, dJ);
-            ok &= qp_hvp(E::template weight<float>(), Jx, Jd, dJ, mu[E::sub(q)], lam[E::sub(q)], Q);
+            if constexpr (std::is_same<E, Tet4Pair>::value) {
+                if (q == 0)
+                    ok &= qp_hvp<float, 1>(E::template weight<float>(), Jx, Jd, dJ, mu[0], lam[0], Q, r2x, r2d);
+                else
+                    ok &= qp_hvp<float, 2>(E::template weight<float>(), Jx, Jd, dJ, mu[1], lam[1], Q, r2x, r2d);
+            } else {
+                ok &= qp_hvp(E::template weight<float>(), Jx, Jd, dJ, mu[E::sub(q)], lam[E::sub(q)], Q);
+            }
             E::template add_forces<true>(Q, q, A);
         }
         E::finish(A, f);
