@@ -35,9 +35,10 @@ struct CgLaunch {
     // the update kernel clears q for the next tangent action (only the
     // atomic scatter's single-launch form needs q = 0 on entry)
     bool clear_q = true;
-    // 3x3 block Jacobi: [n_nodes][6] inverse blocks (k_block_inv); when set,
-    // init / update / dir / scaled apply it and ignore dinv
-    const float *binv = nullptr;
+    // 3x3 block Jacobi: [n_nodes][6] inverse blocks in bfloat16
+    // (k_block_inv); when set, init / update / dir / scaled apply them and
+    // ignore dinv
+    const uint16_t *binv = nullptr;
 
     hipError_t init(const double *b, double sign, const T *dinv, const uint8_t *nmask, T *x, T *r,
                     T *p, T *q, CgScalars *sc, double eta2) const;
@@ -75,7 +76,7 @@ struct FcgLaunch {
 // binv [n_nodes][6] from the diagonal d [3 n_nodes] and the off-diagonals o
 // [n_nodes][3] of the nodes' 3x3 blocks of K (prescribed components removed)
 hipError_t launch_block_inv(hipStream_t s, int64_t n_nodes, const double *d, const double *o,
-                            const uint8_t *nmask, float *binv);
+                            const uint8_t *nmask, uint16_t *binv);
 hipError_t launch_bc_increment(hipStream_t s, int64_t n, const double *u, const double *u_bc,
                                double frac, const uint8_t *nmask, double *dc, double *u_old);
 hipError_t launch_dot64(hipStream_t s, const CgWorkspace &ws, int64_t n, const double *a,

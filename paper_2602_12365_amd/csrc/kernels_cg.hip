@@ -191,13 +191,24 @@ __global__ void __launch_bounds__(kThreads) k_cg_dir(int64_t n, T *__restrict__ 
 
 // ------------------------------------------------ 3x3 block Jacobi
 
+// bfloat16 storage of the inverse blocks (round to nearest even): the
+// preconditioner only has to stay symmetric positive definite, which a
+// relative perturbation of 2^-9 keeps, and the CG update and direction
+// kernels read the blocks every iteration (12 bytes per node instead of 24)
+__device__ __forceinline__ uint16_t to_bf16(float f)
+{
+    const uint32_t b = __float_as_uint(f);
+    return (uint16_t)((b + 0x7fffu + ((b >> 16) & 1u)) >> 16);
+}
+__device__ __forceinline__ float from_bf16(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
 // binv [n_nodes][6] = (B00, B11, B22, B01, B02, B12), the inverse of each
 // node's 3x3 diagonal block of K_ff: diagonal d [3 n_nodes], off-diagonals
 // o [n_nodes][3] = (K01, K02, K12).  Prescribed components leave the block
 // (their rows and columns of the inverse are 0).  A block that is not
 // positive definite (leading minors) falls back to its diagonal inverse.
 __global__ void k_block_inv(int64_t nn, const double *__restrict__ d, const double *__restrict__ o,
-                            const uint8_t *__restrict__ nmask, float *__restrict__ binv)
+                            const uint8_t *__restrict__ nmask, uint16_t *__restrict__ binv)
 {
     GRID_STRIDE(i, nn)
     {
@@ -223,17 +234,18 @@ __global__ void k_block_inv(int64_t nn, const double *__restrict__ d, const doub
         if (f1) b[1] = b[3] = b[5] = 0.0;
         if (f2) b[2] = b[4] = b[5] = 0.0;
 #pragma unroll
-        for (int k = 0; k < 6; ++k) binv[6 * i + k] = (float)b[k];
+        for (int k = 0; k < 6; ++k) binv[6 * i + k] = to_bf16((float)b[k]);
     }
 }
 
 // z = B r for node i's block
 template <class T>
-__device__ __forceinline__ void block_apply(const float *__restrict__ binv, int64_t i, T r0, T r1, T r2, T &z0,
+__device__ __forceinline__ void block_apply(const uint16_t *__restrict__ binv, int64_t i, T r0, T r1, T r2, T &z0,
                                             T &z1, T &z2)
 {
-    const T b00 = T(binv[6 * i]), b11 = T(binv[6 * i + 1]), b22 = T(binv[6 * i + 2]);
-    const T b01 = T(binv[6 * i + 3]), b02 = T(binv[6 * i + 4]), b12 = T(binv[6 * i + 5]);
+    const T b00 = T(from_bf16(binv[6 * i])), b11 = T(from_bf16(binv[6 * i + 1])), b22 = T(from_bf16(binv[6 * i + 2]));
+    const T b01 = T(from_bf16(binv[6 * i + 3])), b02 = T(from_bf16(binv[6 * i + 4]));
+    const T b12 = T(from_bf16(binv[6 * i + 5]));
     z0 = b00 * r0 + b01 * r1 + b02 * r2;
     z1 = b01 * r0 + b11 * r1 + b12 * r2;
     z2 = b02 * r0 + b12 * r1 + b22 * r2;
@@ -243,7 +255,7 @@ __device__ __forceinline__ void block_apply(const float *__restrict__ binv, int6
 // thread; their reductions and scalar logic are those of the DOF-wise ones.
 template <class T>
 __global__ void __launch_bounds__(kThreads) k_cgb_init(int64_t nn, const double *__restrict__ b, double sign,
-                                                       const float *__restrict__ binv,
+                                                       const uint16_t *__restrict__ binv,
                                                        const uint8_t *__restrict__ nmask, T *__restrict__ x,
                                                        T *__restrict__ r, T *__restrict__ p, T *__restrict__ q,
                                                        double *__restrict__ prr, double *__restrict__ prz)
@@ -277,7 +289,7 @@ __global__ void __launch_bounds__(kThreads) k_cgb_init(int64_t nn, const double 
 template <class T, bool CLEAR>
 __global__ void __launch_bounds__(kThreads) k_cgb_update(int64_t nn, T *__restrict__ x, T *__restrict__ r,
                                                          const T *__restrict__ p, T *__restrict__ q,
-                                                         const float *__restrict__ binv, CgScalars *sc,
+                                                         const uint16_t *__restrict__ binv, CgScalars *sc,
                                                          const double *__restrict__ ppq, int count,
                                                          double *__restrict__ prr, double *__restrict__ prz,
                                                          int par, int j)
@@ -329,7 +341,7 @@ __global__ void __launch_bounds__(kThreads) k_cgb_update(int64_t nn, T *__restri
 
 template <class T>
 __global__ void __launch_bounds__(kThreads) k_cgb_dir(int64_t nn, T *__restrict__ p, const T *__restrict__ r,
-                                                      const float *__restrict__ binv, CgScalars *sc,
+                                                      const uint16_t *__restrict__ binv, CgScalars *sc,
                                                       const double *__restrict__ prr,
                                                       const double *__restrict__ prz, int count, int par)
 {
@@ -361,7 +373,7 @@ __global__ void __launch_bounds__(kThreads) k_cgb_dir(int64_t nn, T *__restrict_
 }
 
 template <class T>
-__global__ void k_cgb_scaled(int64_t nn, const float *__restrict__ binv, const double *__restrict__ b,
+__global__ void k_cgb_scaled(int64_t nn, const uint16_t *__restrict__ binv, const double *__restrict__ b,
                              double sign, T *__restrict__ x)
 {
     GRID_STRIDE(i, nn)
@@ -766,7 +778,7 @@ hipError_t FcgLaunch<T>::dir(T *p, const T *z, CgScalars *sc, const double *prz,
 }
 
 hipError_t launch_block_inv(hipStream_t s, int64_t n_nodes, const double *d, const double *o,
-                            const uint8_t *nmask, float *binv)
+                            const uint8_t *nmask, uint16_t *binv)
 {
     hipLaunchKernelGGL(k_block_inv, dim3(red_grid(n_nodes)), dim3(kThreads), 0, s, n_nodes, d, o, nmask, binv);
     return hipGetLastError();

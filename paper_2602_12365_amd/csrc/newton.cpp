@@ -47,7 +47,7 @@ struct Solver {
            *kdc = nullptr, *dscal = nullptr;
     T *x = nullptr, *rv = nullptr, *p = nullptr, *q = nullptr, *dinv = nullptr;
     double *off = nullptr;   // precond = 2: off-diagonals of the nodes' 3x3 blocks
-    float *binv = nullptr;   // and their inverses [n_nodes][6]
+    uint16_t *binv = nullptr;   // and their inverses [n_nodes][6], bfloat16
     double load_s = 0.0;   // load factor of the current step
     CgScalars *sc = nullptr;
     CgWorkspace ws;
@@ -84,7 +84,7 @@ struct Solver {
             || (rc = alloc(&p, n)) || (rc = alloc(&q, n)) || (rc = alloc(&dinv, n))
             || (rc = alloc(&sc, 1)) || (rc = alloc(&ws.partials, 4 * kMaxRedBlocks)))
             return rc;
-        if (o.precond == 2 && ((rc = alloc(&off, n)) || (rc = alloc(&binv, 2 * n)))) return rc;
+        if (o.precond == 2 && ((rc = alloc(&off, n)) || (rc = alloc(&binv, 2 * n)))) return rc;   // 6 per node
         if (!c.xlin) {
             void *q_ = nullptr;
             TRY(hipMalloc(&q_, 2 * n * sizeof(double)));   // (X, X + u) per node
