@@ -601,7 +601,10 @@ struct Hex8 {
 // W20, W21 (the last row of Ad against the face's two edges of v).
 // ROW2 = 1: those go out to r2x = {Ae row 2, S22}, r2d = {Ad row 2, W20,
 // W21}; ROW2 = 2: they are taken from there, signs and columns swapped.
-template <class T, int ROW2 = 0>
+// FOLD: the scalars a, b, c enter the matrix products (S and W scaled
+// first, 12 fewer operations); the Hex8 kernels, whose register allocation
+// is tighter, keep the separate terms.
+template <class T, int ROW2 = 0, bool FOLD = true>
 __device__ __forceinline__ bool qp_hvp(T w, const T Jx[9], const T Jd[9], const T dJ[9], T mu,
                                        T lam, T Q[9], T *r2x = nullptr, T *r2d = nullptr)
 {
@@ -619,21 +622,24 @@ __device__ __forceinline__ bool qp_hvp(T w, const T Jx[9], const T Jd[9], const 
             for (int i = 0; i < 3; ++i) r2x[i] = Ae[6 + i], r2d[i] = Ad[6 + i];
         }
     }
-    // S = Ae Ae^T (symmetric)
-    const T S00 = Ae[0] * Ae[0] + Ae[1] * Ae[1] + Ae[2] * Ae[2];
-    const T S01 = Ae[0] * Ae[3] + Ae[1] * Ae[4] + Ae[2] * Ae[5];
-    const T S02 = Ae[0] * Ae[6] + Ae[1] * Ae[7] + Ae[2] * Ae[8];
-    const T S11 = Ae[3] * Ae[3] + Ae[4] * Ae[4] + Ae[5] * Ae[5];
-    const T S12 = Ae[3] * Ae[6] + Ae[4] * Ae[7] + Ae[5] * Ae[8];
-    T S22;
-    if constexpr (ROW2 == 2) S22 = r2x[3];
-    else S22 = Ae[6] * Ae[6] + Ae[7] * Ae[7] + Ae[8] * Ae[8];
-    if constexpr (ROW2 == 1) r2x[3] = S22;
     const T rDe = rcp(De), rDd = rcp(Dd);
     const T a = w * mu * rDe;
     const T s2 = w * De * rDd * rDd;
     const T lnJ = log_(Dd * rDe);
     const T c1 = mu - lam * lnJ;
+    // S = a Ae Ae^T (symmetric), the scale a folded in
+    T S22;
+    if constexpr (ROW2 == 2) S22 = r2x[3];
+    else S22 = Ae[6] * Ae[6] + Ae[7] * Ae[7] + Ae[8] * Ae[8];
+    if constexpr (ROW2 == 1) r2x[3] = S22;
+    const T sa = FOLD ? a : T(1);
+    const T S00 = sa * (Ae[0] * Ae[0] + Ae[1] * Ae[1] + Ae[2] * Ae[2]);
+    const T S01 = sa * (Ae[0] * Ae[3] + Ae[1] * Ae[4] + Ae[2] * Ae[5]);
+    const T S02 = sa * (Ae[0] * Ae[6] + Ae[1] * Ae[7] + Ae[2] * Ae[8]);
+    const T S11 = sa * (Ae[3] * Ae[3] + Ae[4] * Ae[4] + Ae[5] * Ae[5]);
+    const T S12 = sa * (Ae[3] * Ae[6] + Ae[4] * Ae[7] + Ae[5] * Ae[8]);
+    S22 = sa * S22;
+    const T S[9] = {S00, S01, S02, S01, S11, S12, S02, S12, S22};
     // W = Ad dJ
     T W[9];
 #pragma unroll
@@ -655,19 +661,32 @@ __device__ __forceinline__ bool qp_hvp(T w, const T Jx[9], const T Jd[9], const 
     const T tr = W[0] + W[4] + W[8];
     const T b = lam * tr * s2;
     const T c = c1 * s2;
+    if constexpr (FOLD) {
+        // V = c W + b I: the two Ad^T terms of dP become one product
+        T V[9];
 #pragma unroll
-    for (int i = 0; i < 3; ++i) {
-        const T d0 = dJ[i * 3 + 0], d1 = dJ[i * 3 + 1], d2 = dJ[i * 3 + 2];
-        const T dS0 = d0 * S00 + d1 * S01 + d2 * S02;
-        const T dS1 = d0 * S01 + d1 * S11 + d2 * S12;
-        const T dS2 = d0 * S02 + d1 * S12 + d2 * S22;
-        const T dS[3] = {dS0, dS1, dS2};
+        for (int k = 0; k < 9; ++k) V[k] = (k % 4 == 0) ? fma(c, W[k], b) : c * W[k];
+        // Q[i][J] = (dJ S)[i][J] + (V Ad)[J][i]
 #pragma unroll
-        for (int J = 0; J < 3; ++J) {
-            // M[J][i] = (W Ad)[J][i]
-            const T Mji = W[J * 3 + 0] * Ad[0 * 3 + i] + W[J * 3 + 1] * Ad[1 * 3 + i]
-                        + W[J * 3 + 2] * Ad[2 * 3 + i];
-            Q[i * 3 + J] = a * dS[J] + b * Ad[J * 3 + i] + c * Mji;
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int J = 0; J < 3; ++J)
+                Q[i * 3 + J] = dJ[i * 3 + 0] * S[0 * 3 + J] + dJ[i * 3 + 1] * S[1 * 3 + J]
+                             + dJ[i * 3 + 2] * S[2 * 3 + J] + V[J * 3 + 0] * Ad[0 * 3 + i]
+                             + V[J * 3 + 1] * Ad[1 * 3 + i] + V[J * 3 + 2] * Ad[2 * 3 + i];
+    } else {
+        // Q[i][J] = a (dJ S)[i][J] + b Ad[J][i] + c (W Ad)[J][i]
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            const T d0 = dJ[i * 3 + 0], d1 = dJ[i * 3 + 1], d2 = dJ[i * 3 + 2];
+            const T dS[3] = {d0 * S[0] + d1 * S[3] + d2 * S[6], d0 * S[1] + d1 * S[4] + d2 * S[7],
+                             d0 * S[2] + d1 * S[5] + d2 * S[8]};
+#pragma unroll
+            for (int J = 0; J < 3; ++J) {
+                const T Mji = W[J * 3 + 0] * Ad[0 * 3 + i] + W[J * 3 + 1] * Ad[1 * 3 + i]
+                            + W[J * 3 + 2] * Ad[2 * 3 + i];
+                Q[i * 3 + J] = a * dS[J] + b * Ad[J * 3 + i] + c * Mji;
+            }
         }
     }
     return Dd > T(0);
@@ -931,7 +950,7 @@ template <> struct HvpOp<double> {
                 E::grad(FX, q, Jx);
                 E::grad(Fx, q, Jd);
                 E::grad(Fv, q, dJ);
-                ok &= qp_hvp(E::template weight<double>(), Jx, Jd, dJ, mu[0], lam[0], Q);
+                ok &= qp_hvp<double, 0, false>(E::template weight<double>(), Jx, Jd, dJ, mu[0], lam[0], Q);
                 E::template add_forces<true>(Q, q, A);
             }
             E::finish(A, f);
@@ -1033,7 +1052,8 @@ template <> struct HvpOp<float> {
                 else
                     ok &= qp_hvp<float, 2>(E::template weight<float>(), Jx, Jd, dJ, mu[1], lam[1], Q, r2x, r2d);
             } else {
-                ok &= qp_hvp(E::template weight<float>(), Jx, Jd, dJ, mu[E::sub(q)], lam[E::sub(q)], Q);
+                ok &= qp_hvp<float, 0, !std::is_same<E, Hex8>::value>(E::template weight<float>(), Jx, Jd, dJ,
+                                                                      mu[E::sub(q)], lam[E::sub(q)], Q);
             }
             E::template add_forces<true>(Q, q, A);
         }
