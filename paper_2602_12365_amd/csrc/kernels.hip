@@ -257,6 +257,32 @@ struct Tet4Pair {
 #pragma unroll
             for (int i = 0; i < 3; ++i) out[a][i] = A.f[a][i];
     }
+    // The pair's forces on nodes 1..4, points in order 0, 1 (1 possibly
+    // skipped); node 0 is left to close0.  Each tetrahedron's nodal forces sum
+    // to zero (its shape functions sum to one), so node 0 carries minus the
+    // sum of the others, which saves each point its own node-0 sum.
+    template <class T>
+    __device__ static __forceinline__ void add_forces_open(const T Q[9], int q, T out[NEN][3])
+    {
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            if (q == 0) {
+                out[1][i] = Q[i * 3 + 0];
+                out[2][i] = Q[i * 3 + 1];
+                out[3][i] = Q[i * 3 + 2];
+                out[4][i] = T(0);
+            } else {   // tet 2 = (a, c, b, d2); only it touches node 4
+                out[2][i] += Q[i * 3 + 0];
+                out[1][i] += Q[i * 3 + 1];
+                out[4][i] = Q[i * 3 + 2];
+            }
+        }
+    }
+    template <class T> __device__ static __forceinline__ void close0(T out[NEN][3])
+    {
+#pragma unroll
+        for (int i = 0; i < 3; ++i) out[0][i] = -((out[1][i] + out[2][i]) + (out[3][i] + out[4][i]));
+    }
     // d N_a / d xi_J of pair node a at point q (0 for the node outside tet q)
     template <class T> __device__ static __forceinline__ T dN(int q, int a, int J)
     {
@@ -971,14 +997,15 @@ template <> struct HvpOp<double> {
             G::grad(Fx, 0, Jd);
             G::grad(Fv, 0, dJ);
             ok &= qp_hvp<double, 1>(E::template weight<double>(), Jx, Jd, dJ, mu[0], lam[0], Q, r2x, r2d);
-            G::template add_forces_to<true>(Q, 0, f);
+            E::add_forces_open(Q, 0, f);
             if (pair) {
                 G::grad(FX, 1, Jx);
                 G::grad(Fx, 1, Jd);
                 G::grad(Fv, 1, dJ);
                 ok &= qp_hvp<double, 2>(E::template weight<double>(), Jx, Jd, dJ, mu[1], lam[1], Q, r2x, r2d);
-                G::template add_forces_to<true>(Q, 1, f);
+                E::add_forces_open(Q, 1, f);
             }
+            E::close0(f);
             return ok;
         }
 #pragma unroll
@@ -1055,8 +1082,10 @@ template <> struct HvpOp<float> {
                 ok &= qp_hvp<float, 0, !std::is_same<E, Hex8>::value>(E::template weight<float>(), Jx, Jd, dJ,
                                                                       mu[E::sub(q)], lam[E::sub(q)], Q);
             }
-            E::template add_forces<true>(Q, q, A);
+            if constexpr (std::is_same<E, Tet4Pair>::value) E::add_forces_open(Q, q, A.f);
+            else E::template add_forces<true>(Q, q, A);
         }
+        if constexpr (std::is_same<E, Tet4Pair>::value) E::close0(A.f);
         E::finish(A, f);
         return ok;
     }
