@@ -286,7 +286,8 @@ typedef struct {
     int32_t hvp_prec;         /* EFEM_F64 or EFEM_F32 for the CG tangent actions */
     int32_t precond;          /* 0 = Jacobi, 1 = learned (efem_set_mlp) with Jacobi fallback,
                                  2 = 3x3 block Jacobi (the inverses of the nodes' diagonal
-                                 blocks of K_ff, rebuilt at every linearization) */
+                                 blocks of K_ff, stored in bfloat16 and rebuilt at every
+                                 linearization) */
     int32_t max_newton;       /* per load step */
     int32_t max_cg;           /* per linear solve */
     int32_t check_every;      /* CG iterations between host convergence checks (>= 1) */
