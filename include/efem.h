@@ -210,7 +210,8 @@ int efem_energy(efem_ctx *ctx, const double *u, double *psi);
  * on the context's stream, like efem_energy. */
 int efem_energy_noalloc(efem_ctx *ctx, const double *u, double *psi);
 
-/* r = grad Psi_h(u), Eq. (1): u, r DEVICE float64 [3*n_nodes]. */
+/* r = grad Psi_h(u), Eq. (1): u, r DEVICE float64 [3*n_nodes].  r must not
+ * be u (EFEM_ERR_INVALID): the elements read u while nodal sums are stored. */
 int efem_residual(efem_ctx *ctx, const double *u, double *r);
 
 /* Fix the linearization point u (DEVICE float64 [3*n_nodes]) of efem_hvp and

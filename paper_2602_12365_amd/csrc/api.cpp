@@ -965,6 +965,10 @@ int efem_energy_noalloc(efem_ctx *ctx, const double *u, double *psi)
 int efem_residual(efem_ctx *ctx, const double *u, double *r)
 {
     CHECK_ARGS(u && r, "efem_residual");
+    if (u == r) {
+        set_error("efem_residual: r aliases u");
+        return EFEM_ERR_INVALID;
+    }
     DeviceGuard dg(ctx->device);
     HIP_TRY(launch_residual(*ctx, u, r));
     return EFEM_OK;

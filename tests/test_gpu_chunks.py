@@ -141,7 +141,7 @@ def test_chunk_full_size_64cube_per_element_material():
     """64^3 Kuhn mesh in the benchmark's launch configuration (256 chunks of 4
     steps of 768 pairs) with the lognormal(0, 0.3) shear modulus field of the
     adjoint case and the clamped-top Dirichlet mask: every entry of the FP64
-    tangent action against the oracle."""
+    tangent action (and of the block pass's residual, Eq. 1) against the oracle."""
     from paper_2602_12365_amd import Operator
     n = 64
     m = I.tet_mesh(n)
@@ -157,8 +157,10 @@ def test_chunk_full_size_64cube_per_element_material():
     op.set_material(dev(mu), dev(lam))
     op.linearize(dev(u), "f64")
     assert rel(host(op.hvp(dev(v))), orc.hvp(u, v)) <= TOL64
+    assert rel(host(op.residual(dev(u))), orc.residual(u)) <= TOL64
     mask, _ = I.clamp_top_bottom(m.X, 0.05)
     op.set_dirichlet(dev(mask, torch.uint8))
     ref = F.masked(mask, orc.hvp(u, F.masked(mask, v)))
     assert rel(host(op.hvp(dev(v))), ref) <= TOL64
+    assert rel(host(op.residual(dev(u))), F.masked(mask, orc.residual(u))) <= TOL64
     op.close()

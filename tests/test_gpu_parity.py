@@ -260,6 +260,17 @@ def test_inverted_element_flags_and_inf():
     assert op.status() == 0          # cleared by the read
 
 
+def test_residual_rejects_aliased_output():
+    from paper_2602_12365_amd import Operator
+    from paper_2602_12365_amd import _lib as L
+    m = I.tet_mesh(2)
+    op = Operator(I.TET4, m.X, m.conn)
+    u = dev(np.zeros_like(m.X))
+    with pytest.raises(L.EfemError):
+        op.residual(u, out=u)
+    op.close()
+
+
 def test_error_codes():
     from paper_2602_12365_amd import Operator
     from paper_2602_12365_amd import _lib as L
