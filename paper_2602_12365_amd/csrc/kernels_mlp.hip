@@ -24,17 +24,18 @@ __device__ __forceinline__ float bfr(float f) { return bf2f(f2bf(f)); }
 // hardware base-2 exponential and logarithm (the exponent is <= 0 and the
 // logarithm's argument lies in [1, 2], so neither needs range reduction).
 // For x < 0 softplus is ln(1 + t) alone, so that term needs relative
-// accuracy: below t = 2^-7 it is the series t - t^2/2 + t^3/3 (the first
-// omitted term is below 2^-23 of the sum); above, the logarithm of the
-// rounded 1 + t is within 2^-17 relative.  (The logarithm of the rounded
-// 1 + t alone would be off by up to 2^-24 / t relative: several bfloat16
-// ulps once x < -12.)
+// accuracy, which the logarithm of the rounded u = 1 + t lacks for small t
+// (off by up to 2^-24 / t relative: several bfloat16 ulps once x < -12).
+// The rounding error e = (1 + t) - u = t - (u - 1) is exact (u - 1 is exact
+// for u in [1, 2], and t and u - 1 differ by at most an ulp of u), and
+// ln(1 + t) = ln u + ln(1 + e/u) = ln u + e to within 2^-24 relative
+// (|e| <= 2^-24, u >= 1); where 1 + t rounds to 1 this gives t itself.
 __device__ __forceinline__ float softplus(float x)
 {
     const float t = __builtin_amdgcn_exp2f(-fabsf(x) * 1.4426950408889634f);
-    const float series = t * fmaf(t, fmaf(t, 0.33333333f, -0.5f), 1.f);
-    const float l = t < 0.0078125f ? series : 0.6931471805599453f * __builtin_amdgcn_logf(1.f + t);
-    return fmaxf(x, 0.f) + l;
+    const float u = 1.f + t;
+    const float e = t - (u - 1.f);
+    return fmaxf(x, 0.f) + fmaf(0.6931471805599453f, __builtin_amdgcn_logf(u), e);
 }
 __device__ __forceinline__ float sigmoidf_(float x) { return 1.f / (1.f + __expf(-x)); }
 

@@ -84,9 +84,10 @@ def test_mlp_layers_match_oracle_within_one_bf16_ulp(scale):
     significands give a 16-bit product) and add the k products and the bias
     (k = 12, then 64) in FP32, so the pre-activation is within
     (k + 1) 2^-24 sum|terms| of its exact value.  Softplus has slope in
-    (0, 1), and its hardware exponential and logarithm (a series for
-    ln(1 + t) at small t) add a few FP32 ulps of relative error, also where
-    softplus is tiny (pre-activations down to about -40 at scale 2.5).
+    (0, 1), and its hardware exponential and logarithm (ln(1 + t) taken as
+    ln u plus the exact rounding error of u = 1 + t) add a few FP32 ulps of
+    relative error, also where softplus is tiny (pre-activations down to
+    about -40 at scale 2.5).
     For these weights that puts the FP32 activation within about 1e-4
     relative of the oracle's FP64 one, well under half a bf16 ulp (2^-9).
     Both sides then round to nearest even: they agree unless a rounding
