@@ -81,13 +81,18 @@ COUNTERS_MD = os.path.join(ROOT, "profiles", "hvp_tet4_f64_64cube_counters.md")
 
 
 def kernel_source_hash():
-    """Hash of the element-kernel sources; counter summaries record it so that
-    stale HBM-traffic figures are not reported for a changed kernel."""
+    """Hash of the element-kernel sources with comments and whitespace taken
+    out; counter summaries record it so that stale HBM-traffic figures are
+    not reported for a changed kernel (a comment edit changes no kernel)."""
     import hashlib
+    import re
     h = hashlib.sha256()
     for name in ("kernels.hip", "efem_internal.h"):
-        with open(os.path.join(ROOT, "paper_2602_12365_amd", "csrc", name), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(ROOT, "paper_2602_12365_amd", "csrc", name)) as f:
+            src = f.read()
+        src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)   # block comments
+        src = re.sub(r"//[^\n]*", " ", src)                 # line comments
+        h.update("".join(src.split()).encode())
     return h.hexdigest()[:16]
 
 

@@ -627,9 +627,10 @@ struct Hex8 {
 // W20, W21 (the last row of Ad against the face's two edges of v).
 // ROW2 = 1: those go out to r2x = {Ae row 2, S22}, r2d = {Ad row 2, W20,
 // W21}; ROW2 = 2: they are taken from there, signs and columns swapped.
-// FOLD: the scalars a, b, c enter the matrix products (S and W scaled
-// first, 12 fewer operations); the Hex8 kernels, whose register allocation
-// is tighter, keep the separate terms.
+// FOLD: the scalars a, b, c enter the matrix products (S scaled by a, W
+// replaced by c W + b I; 12 fewer operations, but each entry of Q becomes
+// one six-term chain).  The Hex8 kernels, at 1 or 2 waves per SIMD, keep
+// the separate terms: there the longer chains cost more than they save.
 template <class T, int ROW2 = 0, bool FOLD = true>
 __device__ __forceinline__ bool qp_hvp(T w, const T Jx[9], const T Jd[9], const T dJ[9], T mu,
                                        T lam, T Q[9], T *r2x = nullptr, T *r2d = nullptr)
@@ -653,7 +654,7 @@ __device__ __forceinline__ bool qp_hvp(T w, const T Jx[9], const T Jd[9], const 
     const T s2 = w * De * rDd * rDd;
     const T lnJ = log_(Dd * rDe);
     const T c1 = mu - lam * lnJ;
-    // S = a Ae Ae^T (symmetric), the scale a folded in
+    // S = Ae Ae^T (symmetric), times a when FOLD
     T S22;
     if constexpr (ROW2 == 2) S22 = r2x[3];
     else S22 = Ae[6] * Ae[6] + Ae[7] * Ae[7] + Ae[8] * Ae[8];
