@@ -69,13 +69,18 @@ def test_pins_catch_planted_mistake(name, tmp_path):
 # Mistakes in the oracle's Python layer (the loaded Newton solve): planted in a
 # copy of the oracle package placed in a scratch tree with the tests and the
 # input generators, and run there against the real C oracle.
+# name: (anchor, replacement, pin files that must catch it)
 PY_MUTATIONS = {
-    "load_residual_not_scaled_by_step": ("reshape(-1) - s * f)", "reshape(-1) - f)"),
-    "load_residual_sign": ("reshape(-1) - s * f)", "reshape(-1) + s * f)"),
-    "load_energy_not_scaled_by_step": ("- s * (f @ uu)", "- (f @ uu)"),
-    "load_energy_sign": ("- s * (f @ uu)", "+ s * (f @ uu)"),
+    "load_residual_not_scaled_by_step": ("reshape(-1) - s * f)", "reshape(-1) - f)", ["test_oracle_load.py"]),
+    "load_residual_sign": ("reshape(-1) - s * f)", "reshape(-1) + s * f)", ["test_oracle_load.py"]),
+    "load_energy_not_scaled_by_step": ("- s * (f @ uu)", "- (f @ uu)", ["test_oracle_load.py"]),
+    "load_energy_sign": ("- s * (f @ uu)", "+ s * (f @ uu)", ["test_oracle_load.py"]),
+    "predictor_rhs_sign": ("* f - fem.hvp(u, dc).reshape(-1))", "* f + fem.hvp(u, dc).reshape(-1))",
+                           ["test_oracle_newton.py"]),
+    "predictor_not_applied": ("u_try = u + dc + free * df", "u_try = u + dc", ["test_oracle_newton.py"]),
+    "forcing_held_at_eta_max": ("eta = opts.ew_gamma * (rn / rn_prev) ** opts.ew_alpha", "eta = opts.eta_max",
+                                ["test_oracle_newton.py"]),
 }
-PY_PIN_FILES = ["test_oracle_load.py"]
 
 
 @pytest.mark.parametrize("name", sorted(PY_MUTATIONS))
@@ -83,7 +88,7 @@ def test_pins_catch_planted_mistake_in_solve(name, tmp_path):
     import shutil
 
     from oracle import build as _build
-    old, new = PY_MUTATIONS[name]
+    old, new, pin_files = PY_MUTATIONS[name]
     for d in ("oracle", "tests", "paper_2602_12365_amd"):
         (tmp_path / d).mkdir()
         for f in os.listdir(os.path.join(ROOT, d)):
@@ -95,7 +100,7 @@ def test_pins_catch_planted_mistake_in_solve(name, tmp_path):
     fem_py.write_text(src.replace(old, new))
     env = dict(os.environ, EFEM_ORACLE_LIB=_build.build(), OMP_NUM_THREADS="2")
     res = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider"]
-                         + [str(tmp_path / "tests" / f) for f in PY_PIN_FILES],
+                         + [str(tmp_path / "tests" / f) for f in pin_files],
                          cwd=str(tmp_path), env=env, capture_output=True, text=True, timeout=300)
     assert "passed" in res.stdout or "failed" in res.stdout, res.stdout[-2000:] + res.stderr[-2000:]
     assert res.returncode != 0, f"pins did not catch mutation {name}:\n{res.stdout[-2000:]}"

@@ -83,3 +83,45 @@ def test_compression_needs_predictor_and_converges():
     u, st = F.newton_solve(f, mask, ubc, F.SolveOptions(n_steps=10))
     assert st.converged
     assert np.isfinite(f.energy(u))
+
+
+def test_predictor_solves_each_linear_load_step():
+    """With the linear-elastic density the tangent is constant, so a load
+    step's tangent predictor (K_ff d_f = -(K dc)_f, CG to predictor_rtol)
+    lands on that step's solution: the step starts from the predictor solve's
+    own CG residual, at most predictor_rtol times its right-hand side.  From
+    a solved previous step that right-hand side is the residual the plain lift
+    u + dc would leave, the same for every step (equal increments, constant
+    K).  Without the predictor the step would start at the plain lift's
+    residual; with the sign of its right-hand side flipped, at about twice
+    that."""
+    m = I.make_mesh(I.TET4, 4)
+    mu = I.lognormal_field(m.n_elems, 0.3, 3)
+    f = F.FEM(I.TET4, m.X, m.conn, mu, 1.5 * mu, "linear")
+    mask, ubc = I.clamp_top_bottom(m.X, 0.1)
+    opts = F.SolveOptions(n_steps=3)
+    _, st = F.newton_solve(f, mask, ubc, opts)
+    assert st.converged
+    free = mask.reshape(-1) == 0
+    lift = np.zeros(3 * m.n_nodes)
+    lift[~free] = ubc.reshape(-1)[~free] / opts.n_steps       # step 1's plain lift from u = 0
+    r_lift = np.linalg.norm(f.residual(lift.reshape(-1, 3)).ravel()[free])
+    assert r_lift > 0.0
+    for hist in st.residual_history:
+        assert hist[0] <= opts.predictor_rtol * r_lift * 1.001 + 1e-12
+
+
+def test_eisenstat_walker_forcing_gives_superlinear_steps():
+    """Choice 2 of Eisenstat and Walker sets the forcing term from the square
+    of the last residual ratio, so the CG tolerance tightens as Newton
+    converges and the iteration turns superlinear (the exact-solve limit is
+    pinned quadratic above).  On the cfg1 case every load step converges
+    within 8 iterations, and in each step some iteration cuts the residual by
+    at least 100x.  A forcing term held at eta_max = 0.5 converges linearly,
+    by about half per iteration, and would need some 27 iterations per step."""
+    m, f, mask, ubc = setup(8, 0.1)
+    _, st = F.newton_solve(f, mask, ubc, F.SolveOptions(n_steps=5))
+    assert st.converged
+    for nit, hist in zip(st.newton_iters, st.residual_history):
+        assert nit <= 8
+        assert min(b / a for a, b in zip(hist, hist[1:])) <= 1e-2
