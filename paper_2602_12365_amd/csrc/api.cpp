@@ -499,6 +499,91 @@ static bool build_chunks(const HostBlocks &hb, int64_t nn, int n_cu, HostChunks 
     }
 }
 
+// Item order within each block for the chunk pass.  Item k runs on lane
+// k / W of wave k % W (W = kChunkThreads / 64), so a wave's 64 lanes issue each
+// record read and each FP64 LDS atomic together, at the slots of one node
+// position of their 64 items.  An FP64 atomic at slot l occupies the LDS bank
+// pair (3 l + i) mod 32, one-to-one with l mod 32 for each component i, and a
+// 16-byte record piece the bank quad l mod 16; lanes on one bank pair or quad
+// are served one after another.  In Morton order the slots of a wave's items
+// are effectively random, several lanes to a bank.  Each block's items are
+// dealt to the waves greedily instead: an item goes to the wave, among those
+// with positions left, where its five slots' residues mod 32 have been taken
+// least often.  Pairs are dealt over the pair positions and single
+// tetrahedra over theirs (an item's position decides its pair flag); the
+// element order and both item arrays move with the items.  The slots
+// themselves do not depend on the item order.
+static void spread_items(HostBlocks &hb, HostChunks &hc)
+{
+    constexpr int W = kChunkThreads / 64;
+    const int nb = (int)hb.estart.size() - 1;
+    std::vector<uint32_t> bw, cw;
+    std::vector<int32_t> el, assign;
+    std::vector<std::vector<int32_t>> dealt(W);
+    for (int b = 0; b < nb; ++b) {
+        const int i0 = hb.istart[(size_t)b], ni = hb.istart[(size_t)b + 1] - i0;
+        const int e0 = hb.estart[(size_t)b], np = (hb.estart[(size_t)b + 1] - e0) - ni;
+        auto slots = [&](int k, int r[5]) {
+            const uint32_t w0 = hc.items[2 * (size_t)(i0 + k)], w1 = hc.items[2 * (size_t)(i0 + k) + 1];
+            r[0] = (int)(w0 & 2047u);
+            r[1] = (int)((w0 >> 11) & 2047u);
+            r[2] = (int)(w1 & 2047u);
+            r[3] = (int)((w0 >> 22) | ((w1 >> 22) << 10));
+            r[4] = (int)((w1 >> 11) & 2047u);
+        };
+        assign.assign((size_t)ni, 0);
+        for (int part = 0; part < 2; ++part) {
+            const int lo = part == 0 ? 0 : np, hi = part == 0 ? np : ni;
+            if (hi <= lo) continue;
+            int cap[W] = {};
+            for (int k = lo; k < hi; ++k) cap[k % W] += 1;
+            static thread_local int cnt[W][5][32];
+            std::memset(cnt, 0, sizeof(cnt));
+            for (auto &d : dealt) d.clear();
+            for (int k = lo; k < hi; ++k) {
+                int r[5];
+                slots(k, r);
+                int best = -1, best_cost = 0;
+                for (int w = 0; w < W; ++w) {
+                    if (cap[w] == 0) continue;
+                    int cost = 0;
+                    for (int a = 0; a < 5; ++a) cost += cnt[w][a][r[a] & 31];
+                    if (best < 0 || cost < best_cost || (cost == best_cost && cap[w] > cap[best])) {
+                        best = w;
+                        best_cost = cost;
+                    }
+                }
+                for (int a = 0; a < 5; ++a) cnt[best][a][r[a] & 31] += 1;
+                cap[best] -= 1;
+                dealt[(size_t)best].push_back(k);
+            }
+            // position k of the range takes the next item dealt to wave k % W
+            int next[W] = {};
+            for (int k = lo; k < hi; ++k) {
+                const int w = k % W;
+                assign[(size_t)k] = dealt[(size_t)w][(size_t)next[w]++];
+            }
+        }
+        // move the items (both word arrays) and their elements
+        bw.assign(hb.items.begin() + 2 * (size_t)i0, hb.items.begin() + 2 * (size_t)(i0 + ni));
+        cw.assign(hc.items.begin() + 2 * (size_t)i0, hc.items.begin() + 2 * (size_t)(i0 + ni));
+        el.assign(hb.order.begin() + e0, hb.order.begin() + hb.estart[(size_t)b + 1]);
+        for (int k = 0; k < ni; ++k) {
+            const int src = assign[(size_t)k];
+            for (int j = 0; j < 2; ++j) {
+                hb.items[2 * (size_t)(i0 + k) + j] = bw[2 * (size_t)src + j];
+                hc.items[2 * (size_t)(i0 + k) + j] = cw[2 * (size_t)src + j];
+            }
+            if (k < np) {
+                hb.order[(size_t)(e0 + 2 * k)] = el[2 * (size_t)src];
+                hb.order[(size_t)(e0 + 2 * k + 1)] = el[2 * (size_t)src + 1];
+            } else {
+                hb.order[(size_t)(e0 + np + k)] = el[(size_t)(np + src)];
+            }
+        }
+    }
+}
+
 // Halo layout of the shared nodes (HaloSegs): each node's entries take
 // consecutive slots in entry order (block or chunk order), nodes grouped by
 // entry count.  hslot[i] is the slot of entry i (-1 for unshared entries);
@@ -663,6 +748,16 @@ int efem_create(efem_ctx **out, int32_t elem, int64_t n_nodes, int64_t n_elems,
         efem_destroy(ctx);
         return rc;
     };
+    // chunks for the LDS-resident FP64 tangent action (Tet4 pairs, halo
+    // scatter), built before the uploads: the item order follows them
+    int lds_max = 0, n_cu = 0;
+    (void)hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, ctx->device);
+    (void)hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, ctx->device);
+    HostChunks hc;
+    const bool use_chunks = elem == EFEM_TET4 && ctx->scatter == Scatter::Halo && !(opts && opts->no_chunks)
+                            && n_nodes <= (int64_t)kStageGid && lds_max >= kChunkLds
+                            && build_chunks(hb, n_nodes, n_cu, hc);
+    if (use_chunks) spread_items(hb, hc);
     int rc;
     BlockMesh &m = ctx->m;
     m.n_blocks = (int32_t)hb.estart.size() - 1;
@@ -702,13 +797,7 @@ int efem_create(efem_ctx **out, int32_t elem, int64_t n_nodes, int64_t n_elems,
         m.hslot = p_hs;
     }
 
-    // chunks for the LDS-resident FP64 tangent action (Tet4 pairs, halo scatter)
-    int lds_max = 0, n_cu = 0;
-    (void)hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, ctx->device);
-    (void)hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, ctx->device);
-    HostChunks hc;
-    if (elem == EFEM_TET4 && ctx->scatter == Scatter::Halo && !(opts && opts->no_chunks)
-        && n_nodes <= (int64_t)kStageGid && lds_max >= kChunkLds && build_chunks(hb, n_nodes, n_cu, hc)) {
+    if (use_chunks) {
         ChunkMesh &ch = ctx->ch;
         ch.n_chunks = (int32_t)hc.bstart.size() - 1;
         ctx->max_chunk_slots = hc.max_slots;
