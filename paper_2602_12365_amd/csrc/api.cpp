@@ -500,26 +500,33 @@ static bool build_chunks(const HostBlocks &hb, int64_t nn, int n_cu, HostChunks 
 }
 
 // Item order within each block for the chunk pass.  Item k runs on lane
-// k / W of wave k % W (W = kChunkThreads / 64), so a wave's 64 lanes issue each
-// record read and each FP64 LDS atomic together, at the slots of one node
-// position of their 64 items.  An FP64 atomic at slot l occupies the LDS bank
-// pair (3 l + i) mod 32, one-to-one with l mod 32 for each component i, and a
-// 16-byte record piece the bank quad l mod 16; lanes on one bank pair or quad
-// are served one after another.  In Morton order the slots of a wave's items
-// are effectively random, several lanes to a bank.  Each block's items are
-// dealt to the waves greedily instead: an item goes to the wave, among those
-// with positions left, where its five slots' residues mod 32 have been taken
-// least often.  Pairs are dealt over the pair positions and single
-// tetrahedra over theirs (an item's position decides its pair flag); the
-// element order and both item arrays move with the items.  The slots
-// themselves do not depend on the item order.
+// L = k / W of wave k % W (W = kChunkThreads / 64), so a wave's 64 lanes issue
+// each record read and each FP64 LDS atomic together, at the slots of one node
+// position of their 64 items.  The LDS serves an FP64 atomic 16 lanes at a
+// time, the lanes of a group one after another where their slots l fall on
+// one bank pair, (3 l + i) mod 16 for component i (one-to-one with l mod 16),
+// and a 16-byte record read 8 lanes at a time, by bank quad l mod 8 (measured:
+// lanes paired on bank pairs within each 16-lane group cost as much as
+// random slots, lanes paired across groups nothing).  In Morton order a
+// group's slots are effectively random.  Each block's items are dealt to the
+// lane groups (16 lanes of one wave, 48 groups for 768 items) greedily
+// instead: an item goes to the group, among those with positions left, where
+// its five slots' residues mod 16 have been taken least often, counting also
+// the residues mod 8 in the 8-lane half it lands in.  Pairs are dealt over
+// the pair positions and single tetrahedra over theirs (an item's position
+// decides its pair flag); the element order and both item arrays move with
+// the items.  The slots do not depend on the item order.
 static void spread_items(HostBlocks &hb, HostChunks &hc)
 {
-    constexpr int W = kChunkThreads / 64;
+    constexpr int W = kChunkThreads / 64, G = 16, NG = W * (64 / G), M = 16, M2 = 8;
     const int nb = (int)hb.estart.size() - 1;
     std::vector<uint32_t> bw, cw;
     std::vector<int32_t> el, assign;
-    std::vector<std::vector<int32_t>> dealt(W);
+    std::vector<std::vector<int32_t>> dealt(NG);
+    // residue counts with the group index innermost, so that one item's cost
+    // over all groups is a few contiguous sweeps
+    std::vector<int32_t> cnt((size_t)5 * M * NG), cnt2((size_t)2 * 5 * M2 * NG);
+    auto group_of = [](int k) { return (k % W) * (64 / G) + (k / W) / G; };
     for (int b = 0; b < nb; ++b) {
         const int i0 = hb.istart[(size_t)b], ni = hb.istart[(size_t)b + 1] - i0;
         const int e0 = hb.estart[(size_t)b], np = (hb.estart[(size_t)b + 1] - e0) - ni;
@@ -535,33 +542,48 @@ static void spread_items(HostBlocks &hb, HostChunks &hc)
         for (int part = 0; part < 2; ++part) {
             const int lo = part == 0 ? 0 : np, hi = part == 0 ? np : ni;
             if (hi <= lo) continue;
-            int cap[W] = {};
-            for (int k = lo; k < hi; ++k) cap[k % W] += 1;
-            static thread_local int cnt[W][5][32];
-            std::memset(cnt, 0, sizeof(cnt));
+            int cap[NG] = {}, fill[NG] = {};
+            for (int k = lo; k < hi; ++k) cap[group_of(k)] += 1;
+            std::fill(cnt.begin(), cnt.end(), 0);
+            std::fill(cnt2.begin(), cnt2.end(), 0);
             for (auto &d : dealt) d.clear();
             for (int k = lo; k < hi; ++k) {
                 int r[5];
                 slots(k, r);
+                int c0[NG] = {}, c1[NG] = {}, c2[NG] = {};
+                for (int a = 0; a < 5; ++a) {
+                    const int32_t *p = &cnt[((size_t)a * M + (r[a] & (M - 1))) * NG];
+                    const int32_t *q0 = &cnt2[(((size_t)0 * 5 + a) * M2 + (r[a] & (M2 - 1))) * NG];
+                    const int32_t *q1 = &cnt2[(((size_t)1 * 5 + a) * M2 + (r[a] & (M2 - 1))) * NG];
+                    for (int g = 0; g < NG; ++g) {
+                        c0[g] += p[g];
+                        c1[g] += q0[g];
+                        c2[g] += q1[g];
+                    }
+                }
                 int best = -1, best_cost = 0;
-                for (int w = 0; w < W; ++w) {
-                    if (cap[w] == 0) continue;
-                    int cost = 0;
-                    for (int a = 0; a < 5; ++a) cost += cnt[w][a][r[a] & 31];
-                    if (best < 0 || cost < best_cost || (cost == best_cost && cap[w] > cap[best])) {
-                        best = w;
+                for (int g = 0; g < NG; ++g) {
+                    if (cap[g] == 0) continue;
+                    const int cost = c0[g] + (fill[g] >= G / 2 ? c2[g] : c1[g]);
+                    if (best < 0 || cost < best_cost || (cost == best_cost && cap[g] > cap[best])) {
+                        best = g;
                         best_cost = cost;
                     }
                 }
-                for (int a = 0; a < 5; ++a) cnt[best][a][r[a] & 31] += 1;
+                const int half = fill[best] >= G / 2 ? 1 : 0;
+                for (int a = 0; a < 5; ++a) {
+                    cnt[((size_t)a * M + (r[a] & (M - 1))) * NG + best] += 1;
+                    cnt2[(((size_t)half * 5 + a) * M2 + (r[a] & (M2 - 1))) * NG + best] += 1;
+                }
                 cap[best] -= 1;
+                fill[best] += 1;
                 dealt[(size_t)best].push_back(k);
             }
-            // position k of the range takes the next item dealt to wave k % W
-            int next[W] = {};
+            // the positions of a group, in lane order, take its items in the order dealt
+            int next[NG] = {};
             for (int k = lo; k < hi; ++k) {
-                const int w = k % W;
-                assign[(size_t)k] = dealt[(size_t)w][(size_t)next[w]++];
+                const int g = group_of(k);
+                assign[(size_t)k] = dealt[(size_t)g][(size_t)next[g]++];
             }
         }
         // move the items (both word arrays) and their elements
