@@ -499,37 +499,115 @@ static bool build_chunks(const HostBlocks &hb, int64_t nn, int n_cu, HostChunks 
     }
 }
 
-// Item order within each block for the chunk pass.  Item k runs on lane
-// L = k / W of wave k % W (W = kChunkThreads / 64), so a wave's 64 lanes issue
-// each record read and each FP64 LDS atomic together, at the slots of one node
-// position of their 64 items.  The LDS serves an FP64 atomic 16 lanes at a
-// time, the lanes of a group one after another where their slots l fall on
-// one bank pair, (3 l + i) mod 16 for component i (one-to-one with l mod 16),
-// and a 16-byte record read 8 lanes at a time, by bank quad l mod 8 (measured:
-// lanes paired on bank pairs within each 16-lane group cost as much as
-// random slots, lanes paired across groups nothing).  In Morton order a
-// group's slots are effectively random.  Each block's items are dealt to the
-// lane groups (16 lanes of one wave, 48 groups for 768 items) greedily
-// instead: an item goes to the group, among those with positions left, where
-// its five slots' residues mod 16 have been taken least often, counting also
-// the residues mod 8 in the 8-lane half it lands in.  Pairs are dealt over
-// the pair positions and single tetrahedra over theirs (an item's position
-// decides its pair flag); the element order and both item arrays move with
-// the items.  The slots do not depend on the item order.
-static void spread_items(HostBlocks &hb, HostChunks &hc)
+// Item order within each block, for the LDS.  The 64 lanes of a wave issue
+// each node-record read and each FP64 LDS atomic of their items together, at
+// the slots of one node position.  The LDS serves an FP64 atomic 16 lanes at a
+// time, the lanes of such a group one after another where their slots l fall
+// on one bank pair, (3 l + i) mod 16 for component i (one-to-one with
+// l mod 16), and a 16-byte record read 8 lanes at a time, by bank quad l mod 8
+// (measured: lanes paired on bank pairs within each 16-lane group cost as much
+// as random slots, lanes paired across groups nothing).  In Morton order a
+// group's slots are effectively random.  The items of a block are dealt to the
+// lane groups greedily instead: an item goes to the group, among those with
+// positions left, where its slots' residues mod 16 have been taken least
+// often, counting also the residues mod 8 in the 8-lane half it lands in.
+// Tetrahedron pairs are dealt over the pair positions and single tetrahedra
+// over theirs (an item's position decides its pair flag); the element order
+// and the item words move with the items.  Slots do not depend on the order
+// of the items within a block.
+
+// One block's items [lo, hi): slots(k, r) gives the NPOS slots of item k,
+// group_of(k) the lane group (of 16) of position k among ng groups.  On
+// return assign[k] is the item placed at position k.
+template <int NPOS, class Slots, class Group>
+static void deal_items(int lo, int hi, int ng, Group group_of, Slots slots, std::vector<int32_t> &assign)
 {
-    constexpr int W = kChunkThreads / 64, G = 16, NG = W * (64 / G), M = 16, M2 = 8;
-    const int nb = (int)hb.estart.size() - 1;
-    std::vector<uint32_t> bw, cw;
-    std::vector<int32_t> el, assign;
-    std::vector<std::vector<int32_t>> dealt(NG);
+    constexpr int G = 16, M = 16, M2 = 8;
+    if (hi <= lo) return;
     // residue counts with the group index innermost, so that one item's cost
     // over all groups is a few contiguous sweeps
-    std::vector<int32_t> cnt((size_t)5 * M * NG), cnt2((size_t)2 * 5 * M2 * NG);
-    auto group_of = [](int k) { return (k % W) * (64 / G) + (k / W) / G; };
+    std::vector<int32_t> cnt((size_t)NPOS * M * ng, 0), cnt2((size_t)2 * NPOS * M2 * ng, 0);
+    std::vector<int32_t> cap((size_t)ng, 0), fill((size_t)ng, 0), c0((size_t)ng), c1((size_t)ng), c2((size_t)ng);
+    std::vector<std::vector<int32_t>> dealt((size_t)ng);
+    for (int k = lo; k < hi; ++k) cap[(size_t)group_of(k)] += 1;
+    for (int k = lo; k < hi; ++k) {
+        int r[NPOS];
+        slots(k, r);
+        std::fill(c0.begin(), c0.end(), 0);
+        std::fill(c1.begin(), c1.end(), 0);
+        std::fill(c2.begin(), c2.end(), 0);
+        for (int a = 0; a < NPOS; ++a) {
+            const int32_t *p = &cnt[((size_t)a * M + (r[a] & (M - 1))) * ng];
+            const int32_t *q0 = &cnt2[(((size_t)0 * NPOS + a) * M2 + (r[a] & (M2 - 1))) * ng];
+            const int32_t *q1 = &cnt2[(((size_t)1 * NPOS + a) * M2 + (r[a] & (M2 - 1))) * ng];
+            for (int g = 0; g < ng; ++g) {
+                c0[(size_t)g] += p[g];
+                c1[(size_t)g] += q0[g];
+                c2[(size_t)g] += q1[g];
+            }
+        }
+        int best = -1, best_cost = 0;
+        for (int g = 0; g < ng; ++g) {
+            if (cap[(size_t)g] == 0) continue;
+            const int cost = c0[(size_t)g] + (fill[(size_t)g] >= G / 2 ? c2[(size_t)g] : c1[(size_t)g]);
+            if (best < 0 || cost < best_cost || (cost == best_cost && cap[(size_t)g] > cap[(size_t)best])) {
+                best = g;
+                best_cost = cost;
+            }
+        }
+        const int half = fill[(size_t)best] >= G / 2 ? 1 : 0;
+        for (int a = 0; a < NPOS; ++a) {
+            cnt[((size_t)a * M + (r[a] & (M - 1))) * ng + best] += 1;
+            cnt2[(((size_t)half * NPOS + a) * M2 + (r[a] & (M2 - 1))) * ng + best] += 1;
+        }
+        cap[(size_t)best] -= 1;
+        fill[(size_t)best] += 1;
+        dealt[(size_t)best].push_back(k);
+    }
+    // the positions of a group, in lane order, take its items in the order dealt
+    std::vector<int32_t> next((size_t)ng, 0);
+    for (int k = lo; k < hi; ++k) {
+        const int g = group_of(k);
+        assign[(size_t)k] = dealt[(size_t)g][(size_t)next[(size_t)g]++];
+    }
+}
+
+// Block b's items to the order assign: the item words (wpi per item) of the
+// block pass, the chunk pass's (two per item, if given) and the elements.
+static void permute_items(HostBlocks &hb, std::vector<uint32_t> *citems, int b, int wpi,
+                          const std::vector<int32_t> &assign)
+{
+    const int i0 = hb.istart[(size_t)b], ni = hb.istart[(size_t)b + 1] - i0;
+    const int e0 = hb.estart[(size_t)b], np = (hb.estart[(size_t)b + 1] - e0) - ni;
+    const std::vector<uint32_t> bw(hb.items.begin() + (size_t)wpi * i0, hb.items.begin() + (size_t)wpi * (i0 + ni));
+    std::vector<uint32_t> cw;
+    if (citems) cw.assign(citems->begin() + 2 * (size_t)i0, citems->begin() + 2 * (size_t)(i0 + ni));
+    const std::vector<int32_t> el(hb.order.begin() + e0, hb.order.begin() + hb.estart[(size_t)b + 1]);
+    for (int k = 0; k < ni; ++k) {
+        const int src = assign[(size_t)k];
+        for (int j = 0; j < wpi; ++j) hb.items[(size_t)wpi * (i0 + k) + j] = bw[(size_t)wpi * src + j];
+        if (citems)
+            for (int j = 0; j < 2; ++j) (*citems)[2 * (size_t)(i0 + k) + j] = cw[2 * (size_t)src + j];
+        if (k < np) {
+            hb.order[(size_t)(e0 + 2 * k)] = el[2 * (size_t)src];
+            hb.order[(size_t)(e0 + 2 * k + 1)] = el[2 * (size_t)src + 1];
+        } else {
+            hb.order[(size_t)(e0 + np + k)] = el[(size_t)(np + src)];
+        }
+    }
+}
+
+// For the chunk pass (Tet4 pairs): item k runs on lane k / W of wave k % W
+// (W = kChunkThreads / 64); the slots are the chunk's.
+static void spread_items_chunks(HostBlocks &hb, HostChunks &hc)
+{
+    constexpr int W = kChunkThreads / 64, NG = W * 4;
+    const int nb = (int)hb.estart.size() - 1;
+    std::vector<int32_t> assign;
+    auto group_of = [](int k) { return (k % W) * 4 + (k / W) / 16; };
     for (int b = 0; b < nb; ++b) {
         const int i0 = hb.istart[(size_t)b], ni = hb.istart[(size_t)b + 1] - i0;
-        const int e0 = hb.estart[(size_t)b], np = (hb.estart[(size_t)b + 1] - e0) - ni;
+        const int np = (hb.estart[(size_t)b + 1] - hb.estart[(size_t)b]) - ni;
         auto slots = [&](int k, int r[5]) {
             const uint32_t w0 = hc.items[2 * (size_t)(i0 + k)], w1 = hc.items[2 * (size_t)(i0 + k) + 1];
             r[0] = (int)(w0 & 2047u);
@@ -539,70 +617,55 @@ static void spread_items(HostBlocks &hb, HostChunks &hc)
             r[4] = (int)((w1 >> 11) & 2047u);
         };
         assign.assign((size_t)ni, 0);
-        for (int part = 0; part < 2; ++part) {
-            const int lo = part == 0 ? 0 : np, hi = part == 0 ? np : ni;
-            if (hi <= lo) continue;
-            int cap[NG] = {}, fill[NG] = {};
-            for (int k = lo; k < hi; ++k) cap[group_of(k)] += 1;
-            std::fill(cnt.begin(), cnt.end(), 0);
-            std::fill(cnt2.begin(), cnt2.end(), 0);
-            for (auto &d : dealt) d.clear();
-            for (int k = lo; k < hi; ++k) {
-                int r[5];
-                slots(k, r);
-                int c0[NG] = {}, c1[NG] = {}, c2[NG] = {};
-                for (int a = 0; a < 5; ++a) {
-                    const int32_t *p = &cnt[((size_t)a * M + (r[a] & (M - 1))) * NG];
-                    const int32_t *q0 = &cnt2[(((size_t)0 * 5 + a) * M2 + (r[a] & (M2 - 1))) * NG];
-                    const int32_t *q1 = &cnt2[(((size_t)1 * 5 + a) * M2 + (r[a] & (M2 - 1))) * NG];
-                    for (int g = 0; g < NG; ++g) {
-                        c0[g] += p[g];
-                        c1[g] += q0[g];
-                        c2[g] += q1[g];
-                    }
+        deal_items<5>(0, np, NG, group_of, slots, assign);
+        deal_items<5>(np, ni, NG, group_of, slots, assign);
+        permute_items(hb, &hc.items, b, 2, assign);
+    }
+}
+
+// For the block pass: item k runs on lane k / S in column k % S, S = ceil(ni
+// / 64), the 64 lanes of one column together; the slots are the block's node
+// ids.
+static void spread_items_blocks(HostBlocks &hb, int elem)
+{
+    const int nb = (int)hb.estart.size() - 1;
+    const int wpi = elem == EFEM_TET4 ? 2 : (elem == EFEM_TRI3 ? 1 : 4);
+    std::vector<int32_t> assign;
+    for (int b = 0; b < nb; ++b) {
+        const int i0 = hb.istart[(size_t)b], ni = hb.istart[(size_t)b + 1] - i0;
+        const int np = (hb.estart[(size_t)b + 1] - hb.estart[(size_t)b]) - ni;
+        const int S = (ni + 63) / 64;
+        auto group_of = [S](int k) { return (k % S) * 4 + (k / S) / 16; };
+        const uint32_t *w = hb.items.data() + (size_t)wpi * i0;
+        assign.assign((size_t)ni, 0);
+        if (elem == EFEM_TET4) {
+            auto slots = [&](int k, int r[5]) {
+                const uint32_t w0 = w[2 * (size_t)k], w1 = w[2 * (size_t)k + 1];
+                r[0] = (int)(w0 & 1023u);
+                r[1] = (int)((w0 >> 10) & 1023u);
+                r[2] = (int)((w0 >> 20) & 1023u);
+                r[3] = (int)(w1 & 1023u);
+                r[4] = (int)((w1 >> 10) & 1023u);
+            };
+            deal_items<5>(0, np, 4 * S, group_of, slots, assign);
+            deal_items<5>(np, ni, 4 * S, group_of, slots, assign);
+        } else if (elem == EFEM_TRI3) {
+            auto slots = [&](int k, int r[3]) {
+                r[0] = (int)(w[k] & 1023u);
+                r[1] = (int)((w[k] >> 10) & 1023u);
+                r[2] = (int)((w[k] >> 20) & 1023u);
+            };
+            deal_items<3>(0, ni, 4 * S, group_of, slots, assign);
+        } else {
+            auto slots = [&](int k, int r[8]) {
+                for (int j = 0; j < 4; ++j) {
+                    r[2 * j] = (int)(w[4 * (size_t)k + j] & 0xffffu);
+                    r[2 * j + 1] = (int)(w[4 * (size_t)k + j] >> 16);
                 }
-                int best = -1, best_cost = 0;
-                for (int g = 0; g < NG; ++g) {
-                    if (cap[g] == 0) continue;
-                    const int cost = c0[g] + (fill[g] >= G / 2 ? c2[g] : c1[g]);
-                    if (best < 0 || cost < best_cost || (cost == best_cost && cap[g] > cap[best])) {
-                        best = g;
-                        best_cost = cost;
-                    }
-                }
-                const int half = fill[best] >= G / 2 ? 1 : 0;
-                for (int a = 0; a < 5; ++a) {
-                    cnt[((size_t)a * M + (r[a] & (M - 1))) * NG + best] += 1;
-                    cnt2[(((size_t)half * 5 + a) * M2 + (r[a] & (M2 - 1))) * NG + best] += 1;
-                }
-                cap[best] -= 1;
-                fill[best] += 1;
-                dealt[(size_t)best].push_back(k);
-            }
-            // the positions of a group, in lane order, take its items in the order dealt
-            int next[NG] = {};
-            for (int k = lo; k < hi; ++k) {
-                const int g = group_of(k);
-                assign[(size_t)k] = dealt[(size_t)g][(size_t)next[g]++];
-            }
+            };
+            deal_items<8>(0, ni, 4 * S, group_of, slots, assign);
         }
-        // move the items (both word arrays) and their elements
-        bw.assign(hb.items.begin() + 2 * (size_t)i0, hb.items.begin() + 2 * (size_t)(i0 + ni));
-        cw.assign(hc.items.begin() + 2 * (size_t)i0, hc.items.begin() + 2 * (size_t)(i0 + ni));
-        el.assign(hb.order.begin() + e0, hb.order.begin() + hb.estart[(size_t)b + 1]);
-        for (int k = 0; k < ni; ++k) {
-            const int src = assign[(size_t)k];
-            for (int j = 0; j < 2; ++j) {
-                hb.items[2 * (size_t)(i0 + k) + j] = bw[2 * (size_t)src + j];
-                hc.items[2 * (size_t)(i0 + k) + j] = cw[2 * (size_t)src + j];
-            }
-            if (k < np) {
-                hb.order[(size_t)(e0 + 2 * k)] = el[2 * (size_t)src];
-                hb.order[(size_t)(e0 + 2 * k + 1)] = el[2 * (size_t)src + 1];
-            } else {
-                hb.order[(size_t)(e0 + np + k)] = el[(size_t)(np + src)];
-            }
-        }
+        permute_items(hb, nullptr, b, wpi, assign);
     }
 }
 
@@ -779,7 +842,8 @@ int efem_create(efem_ctx **out, int32_t elem, int64_t n_nodes, int64_t n_elems,
     const bool use_chunks = elem == EFEM_TET4 && ctx->scatter == Scatter::Halo && !(opts && opts->no_chunks)
                             && n_nodes <= (int64_t)kStageGid && lds_max >= kChunkLds
                             && build_chunks(hb, n_nodes, n_cu, hc);
-    if (use_chunks) spread_items(hb, hc);
+    if (use_chunks) spread_items_chunks(hb, hc);
+    else spread_items_blocks(hb, elem);
     int rc;
     BlockMesh &m = ctx->m;
     m.n_blocks = (int32_t)hb.estart.size() - 1;
