@@ -398,6 +398,7 @@ static void build_blocks(int elem, int64_t nn, int64_t ne, const double *X, cons
 struct HostChunks {
     std::vector<int32_t> bstart, sstart;
     std::vector<uint32_t> bnew, cnode, items;
+    std::vector<uint16_t> iperm;   // per chunk item: its position in the block pass's order
     std::vector<int32_t> shared_nodes;   // nodes in more than one chunk, increasing id
     // a chunk's slots in the order their sums become final (by the last of
     // its blocks that touches them): fin_slot[s0 + j] is a global slot
@@ -598,17 +599,24 @@ static void permute_items(HostBlocks &hb, std::vector<uint32_t> *citems, int b, 
 }
 
 // For the chunk pass (Tet4 pairs): item k runs on lane k / W of wave k % W
-// (W = kChunkThreads / 64); the slots are the chunk's.
+// (W = kChunkThreads / 64), with the chunk's slots.  The block pass over the
+// same blocks (the FP32 action, the residual, the energy) keys its groups on
+// the block's node ids, so each pass gets its own deal: the block order (and
+// with it the element order) is dealt for the block pass, the chunk items for
+// the chunk pass, and iperm gives each chunk item's block position, where the
+// per-element materials are found.
 static void spread_items_chunks(HostBlocks &hb, HostChunks &hc)
 {
     constexpr int W = kChunkThreads / 64, NG = W * 4;
     const int nb = (int)hb.estart.size() - 1;
-    std::vector<int32_t> assign;
-    auto group_of = [](int k) { return (k % W) * 4 + (k / W) / 16; };
+    std::vector<int32_t> ac, ab, inv;
+    std::vector<uint32_t> cw;
+    hc.iperm.assign(hc.items.size() / 2, 0);
+    auto group_c = [](int k) { return (k % W) * 4 + (k / W) / 16; };
     for (int b = 0; b < nb; ++b) {
         const int i0 = hb.istart[(size_t)b], ni = hb.istart[(size_t)b + 1] - i0;
         const int np = (hb.estart[(size_t)b + 1] - hb.estart[(size_t)b]) - ni;
-        auto slots = [&](int k, int r[5]) {
+        auto cslots = [&](int k, int r[5]) {
             const uint32_t w0 = hc.items[2 * (size_t)(i0 + k)], w1 = hc.items[2 * (size_t)(i0 + k) + 1];
             r[0] = (int)(w0 & 2047u);
             r[1] = (int)((w0 >> 11) & 2047u);
@@ -616,10 +624,34 @@ static void spread_items_chunks(HostBlocks &hb, HostChunks &hc)
             r[3] = (int)((w0 >> 22) | ((w1 >> 22) << 10));
             r[4] = (int)((w1 >> 11) & 2047u);
         };
-        assign.assign((size_t)ni, 0);
-        deal_items<5>(0, np, NG, group_of, slots, assign);
-        deal_items<5>(np, ni, NG, group_of, slots, assign);
-        permute_items(hb, &hc.items, b, 2, assign);
+        const uint32_t *w = hb.items.data() + 2 * (size_t)i0;
+        auto bslots = [&](int k, int r[5]) {
+            const uint32_t w0 = w[2 * (size_t)k], w1 = w[2 * (size_t)k + 1];
+            r[0] = (int)(w0 & 1023u);
+            r[1] = (int)((w0 >> 10) & 1023u);
+            r[2] = (int)((w0 >> 20) & 1023u);
+            r[3] = (int)(w1 & 1023u);
+            r[4] = (int)((w1 >> 10) & 1023u);
+        };
+        const int S = (ni + 63) / 64;
+        auto group_b = [S](int k) { return (k % S) * 4 + (k / S) / 16; };
+        ac.assign((size_t)ni, 0);
+        ab.assign((size_t)ni, 0);
+        deal_items<5>(0, np, NG, group_c, cslots, ac);
+        deal_items<5>(np, ni, NG, group_c, cslots, ac);
+        deal_items<5>(0, np, 4 * S, group_b, bslots, ab);
+        deal_items<5>(np, ni, 4 * S, group_b, bslots, ab);
+        // chunk items in their order, each with its block position
+        inv.assign((size_t)ni, 0);
+        for (int k = 0; k < ni; ++k) inv[(size_t)ab[(size_t)k]] = k;
+        cw.assign(hc.items.begin() + 2 * (size_t)i0, hc.items.begin() + 2 * (size_t)(i0 + ni));
+        for (int k = 0; k < ni; ++k) {
+            const int src = ac[(size_t)k];
+            hc.items[2 * (size_t)(i0 + k)] = cw[2 * (size_t)src];
+            hc.items[2 * (size_t)(i0 + k) + 1] = cw[2 * (size_t)src + 1];
+            hc.iperm[(size_t)(i0 + k)] = (uint16_t)inv[(size_t)src];
+        }
+        permute_items(hb, nullptr, b, 2, ab);
     }
 }
 
@@ -891,6 +923,7 @@ int efem_create(efem_ctx **out, int32_t elem, int64_t n_nodes, int64_t n_elems,
         ctx->n_ch_shared = (int64_t)hc.shared_nodes.size();
         int32_t *p_bs, *p_ss, *p_hs = nullptr, *p_hd;
         uint32_t *p_bw, *p_cn, *p_it;
+        uint16_t *p_ip;
         std::vector<int32_t> hdr((size_t)ch.n_chunks * 8, 0);
         for (int c = 0; c < ch.n_chunks; ++c) {
             const int b0 = hc.bstart[(size_t)c], b1 = hc.bstart[(size_t)c + 1];
@@ -905,7 +938,8 @@ int efem_create(efem_ctx **out, int32_t elem, int64_t n_nodes, int64_t n_elems,
         }
         if ((rc = upload(*ctx, &p_bs, hc.bstart)) || (rc = upload(*ctx, &p_ss, hc.sstart))
             || (rc = upload(*ctx, &p_bw, hc.bnew)) || (rc = upload(*ctx, &p_cn, hc.cnode))
-            || (rc = upload(*ctx, &p_it, hc.items)) || (rc = upload(*ctx, &p_hd, hdr)))
+            || (rc = upload(*ctx, &p_it, hc.items)) || (rc = upload(*ctx, &p_hd, hdr))
+            || (rc = upload(*ctx, &p_ip, hc.iperm)))
             return fail(rc);
         ch.hdr = reinterpret_cast<const int4 *>(p_hd);
         ch.bstart = p_bs;
@@ -913,6 +947,7 @@ int efem_create(efem_ctx **out, int32_t elem, int64_t n_nodes, int64_t n_elems,
         ch.bnew = p_bw;
         ch.cnode = p_cn;
         ch.items = p_it;
+        ch.iperm = p_ip;
         ch.halo = nullptr;
         if (ctx->n_ch_shared > 0) {
             std::vector<int32_t> order, gptr, hslot;

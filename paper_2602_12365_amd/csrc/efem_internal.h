@@ -72,6 +72,8 @@ struct ChunkMesh {
                               // {istart[b0], items of block b0, bnew[b0 + 1] (0 if none), 0}
     const uint32_t *items;    // chunk-slot connectivity, 2 words per item, 11-bit ids:
                               // a | b<<11 | (d1 & 1023)<<22,  c | d2<<11 | (d1 >> 10)<<22
+    const uint16_t *iperm;    // [items] each item's position in the block pass's order
+                              // (where the element arrays find it)
     const int32_t *hslot;     // [slots] halo entry of a shared slot, else -1
     double *halo;             // [3 * entries]
     // write-out in the order the slots' sums become final: the slots final

@@ -2087,7 +2087,13 @@ k_chunk_hvp64(BlockMesh m, ChunkMesh ch, const double *__restrict__ xrec, const 
     // lanes of one LDS atomic are W items apart in Morton order
     const int k = lane * W + wave;
     uint2 itw = make_uint2(0u, 0u);
-    if (k < h1.y) itw = *reinterpret_cast<const uint2 *>(ch.items + 2 * (int64_t)(h1.x + k));
+    // per-element materials: the item's position in the block pass's order,
+    // which the element arrays follow (the chunk pass orders items its own way)
+    int kb = 0;
+    if (k < h1.y) {
+        itw = *reinterpret_cast<const uint2 *>(ch.items + 2 * (int64_t)(h1.x + k));
+        if (!UNI) kb = ch.iperm[h1.x + k];
+    }
     if (nsteps > 1) {
         const int l1 = chunk_stage_slot((uint32_t)h1.z, wave, lane);
         if (l1 >= 0) load_to_lds4(cword + l1, wdst);
@@ -2143,9 +2149,12 @@ k_chunk_hvp64(BlockMesh m, ChunkMesh ch, const double *__restrict__ xrec, const 
             }
         }
         const uint2 cur = itw;
+        const int kbc = kb;
         const int i0 = t_istart[t], ni = t_istart[t + 1] - i0;
-        if (t + 1 < nsteps && k < t_istart[t + 2] - t_istart[t + 1])
+        if (t + 1 < nsteps && k < t_istart[t + 2] - t_istart[t + 1]) {
             itw = *reinterpret_cast<const uint2 *>(ch.items + 2 * (int64_t)(t_istart[t + 1] + k));
+            if (!UNI) kb = ch.iperm[t_istart[t + 1] + k];
+        }
 
         if (k < ni) {
             ItemRange r;
@@ -2176,7 +2185,7 @@ k_chunk_hvp64(BlockMesh m, ChunkMesh ch, const double *__restrict__ xrec, const 
                 mu[0] = mu[1] = m.mu0;
                 lam[0] = lam[1] = m.lam0;
             } else {
-                item_materials<Tet4Pair>(m, r, k, mu, lam);
+                item_materials<Tet4Pair>(m, r, kbc, mu, lam);
             }
             double f[5][3];
             bad |= !HvpOp<double>::compute<Tet4Pair>(Xe, xe, ve, mu, lam, k < r.np, f);
