@@ -573,22 +573,17 @@ static void deal_items(int lo, int hi, int ng, Group group_of, Slots slots, std:
     }
 }
 
-// Block b's items to the order assign: the item words (wpi per item) of the
-// block pass, the chunk pass's (two per item, if given) and the elements.
-static void permute_items(HostBlocks &hb, std::vector<uint32_t> *citems, int b, int wpi,
-                          const std::vector<int32_t> &assign)
+// Block b's items to the order assign: the block pass's item words (wpi per
+// item) and the elements.
+static void permute_items(HostBlocks &hb, int b, int wpi, const std::vector<int32_t> &assign)
 {
     const int i0 = hb.istart[(size_t)b], ni = hb.istart[(size_t)b + 1] - i0;
     const int e0 = hb.estart[(size_t)b], np = (hb.estart[(size_t)b + 1] - e0) - ni;
     const std::vector<uint32_t> bw(hb.items.begin() + (size_t)wpi * i0, hb.items.begin() + (size_t)wpi * (i0 + ni));
-    std::vector<uint32_t> cw;
-    if (citems) cw.assign(citems->begin() + 2 * (size_t)i0, citems->begin() + 2 * (size_t)(i0 + ni));
     const std::vector<int32_t> el(hb.order.begin() + e0, hb.order.begin() + hb.estart[(size_t)b + 1]);
     for (int k = 0; k < ni; ++k) {
         const int src = assign[(size_t)k];
         for (int j = 0; j < wpi; ++j) hb.items[(size_t)wpi * (i0 + k) + j] = bw[(size_t)wpi * src + j];
-        if (citems)
-            for (int j = 0; j < 2; ++j) (*citems)[2 * (size_t)(i0 + k) + j] = cw[2 * (size_t)src + j];
         if (k < np) {
             hb.order[(size_t)(e0 + 2 * k)] = el[2 * (size_t)src];
             hb.order[(size_t)(e0 + 2 * k + 1)] = el[2 * (size_t)src + 1];
@@ -651,7 +646,7 @@ static void spread_items_chunks(HostBlocks &hb, HostChunks &hc)
             hc.items[2 * (size_t)(i0 + k) + 1] = cw[2 * (size_t)src + 1];
             hc.iperm[(size_t)(i0 + k)] = (uint16_t)inv[(size_t)src];
         }
-        permute_items(hb, nullptr, b, 2, ab);
+        permute_items(hb, b, 2, ab);
     }
 }
 
@@ -697,7 +692,7 @@ static void spread_items_blocks(HostBlocks &hb, int elem)
             };
             deal_items<8>(0, ni, 4 * S, group_of, slots, assign);
         }
-        permute_items(hb, nullptr, b, wpi, assign);
+        permute_items(hb, b, wpi, assign);
     }
 }
 
