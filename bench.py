@@ -60,6 +60,24 @@ FLOPS_PER_PAIR_HVP = 2 * FLOPS_PER_TET_HVP - 18 - 18 - 5 - 10 - 6
 FLOPS_PER_HEX_HVP = 756 + 8 * 290 + 36 + 216 + 48
 
 
+def tet4_hvp_alg(n_elems, n_nodes, n_items):
+    """Algorithmic HBM bytes and FP64 operations of one FP64 Tet4 tangent
+    action (Eq. 3): int32 connectivity (16 bytes per tetrahedron), X, x and v
+    read and y written (24 bytes per node each); FLOPS_PER_PAIR_HVP per face
+    pair and FLOPS_PER_TET_HVP per single tetrahedron (n_items work items,
+    each a pair or a single)."""
+    n_pairs = n_elems - n_items
+    alg_bytes = n_elems * 4 * 4 + 4 * n_nodes * 3 * 8
+    alg_flops = n_pairs * FLOPS_PER_PAIR_HVP + (n_elems - 2 * n_pairs) * FLOPS_PER_TET_HVP
+    return alg_bytes, alg_flops
+
+
+def roofline_bound(alg_bytes, alg_flops):
+    """The bound of a kernel: the longer of its two ideal times at the MI355X
+    peaks, alg_bytes / 8 TB/s ("hbm") or alg_flops / 78.6 TFLOP/s ("alu")."""
+    return "hbm" if alg_bytes / (HBM_PEAK_GBS * 1e9) >= alg_flops / (FP64_PEAK_TFLOPS * 1e12) else "alu"
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -448,9 +466,7 @@ def main():
     t_acc = sum(a.elapsed_time(b) for a, b in hvp_events) * 1e-3 / (len(hvp_events) * N_DIRS)
     conn_b = mesh.n_elems * 4 * 4
     node_b = mesh.n_nodes * 3 * 8
-    alg_hvp = conn_b + 3 * node_b + node_b          # conn + X, x, v read + y write
-    n_pairs = mesh.n_elems - info["n_items"]            # items are pairs or single tets
-    alg_flops = n_pairs * FLOPS_PER_PAIR_HVP + (mesh.n_elems - 2 * n_pairs) * FLOPS_PER_TET_HVP
+    alg_hvp, alg_flops = tet4_hvp_alg(mesh.n_elems, mesh.n_nodes, info["n_items"])
     achieved = alg_hvp / t_acc / 1e9
     achieved_tf = alg_flops / t_acc / 1e12
     log(f"hvp chunk pass + gather in the timed steps {t_acc*1e6:.2f} us -> {achieved:.0f} GB/s, "
@@ -664,7 +680,7 @@ def main():
     # the roofline's bound is the longer of the formulation's two ideal
     # times, alg_bytes / 8 TB/s and alg_flops / 78.6 TFLOP/s; both fractions
     # are reported (hbm_frac is the metric's %HBM)
-    if alg_hvp / (HBM_PEAK_GBS * 1e9) >= alg_flops / (FP64_PEAK_TFLOPS * 1e12):
+    if roofline_bound(alg_hvp, alg_flops) == "hbm":
         roof_head = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4)}
     else:
