@@ -8,7 +8,7 @@
  *
  * The calls follow the paper's statement of the problem (arXiv 2602.12365):
  *   - an operator object built from a mesh, an element type and a batch
- *     (block) size, Sec. 4 ("Geometric Context");
+ *     (block) size, Sec. 4 (the geometric context of an operator);
  *   - the discrete energy Psi_h of a flat DOF vector, Eq. (2) and Alg. 1;
  *   - the residual r = grad Psi_h, Eq. (1);
  *   - the tangent action dr = K du, Eq. (3);

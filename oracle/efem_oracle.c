@@ -8,7 +8,7 @@
  * What it computes is the plain definition of the discrete energy of Eq. (2)
  * of the paper and of its exact first and second derivatives, Eq. (1) and the
  * tangent action of Eq. (3).  The paper obtains these derivatives by automatic
- * differentiation "up to machine precision" (Sec. 1); here they are written
+ * differentiation, exact to rounding (Sec. 1); here they are written
  * out in closed form, element by element and quadrature point by quadrature
  * point, with no blocking, fusion or reordering:
  *
